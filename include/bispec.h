@@ -1,0 +1,169 @@
+/*
+ * bispec.h -- C ABI of the MI355X (gfx950) FFT-based binned bispectrum estimator.
+ *
+ * The estimator (Shaw et al., "A fast estimator for quantifying the shape
+ * dependence of the 3D bispectrum", arXiv:2107.14564, Section 2) takes a real
+ * field delta(x) on a periodic N_g^3 grid in a cube of side L and returns, for
+ * every selected triangle bin (a1 >= a2 >= a3) of spherical k-shells,
+ *
+ *     B(a1,a2,a3) = [V N_tri N_g^3]^-1 sum_x D_a1(x) D_a2(x) D_a3(x)     (eq. bsfin)
+ *     D_n(x)      = sum_{k in shell n} Z(k) Delta(k) e^{ik.x}             (eq. iFT)
+ *     N_tri       = N_g^-3 sum_x I_a1(x) I_a2(x) I_a3(x)                  (eq. Ntri2)
+ *     I_n(x)      = sum_{k in shell n} e^{ik.x}                           (eq. 2FT)
+ *
+ * which equals the direct closed-triangle sum of eq. binbs exactly while every
+ * mode satisfies k < 2 pi N_g / (3 L) (Section 2.2, eq. 3FT).  Here
+ * Delta(k) = dV sum_x delta(x) e^{-ik.x} (the convention under which eq. bs reads
+ * <Delta Delta Delta> = V B), V = L^3, dV = V / N_g^3, and Z(k) = 1 + beta (k_z/|k|)^2
+ * is the optional linear redshift-space factor of eq. RSD (line of sight = z).
+ * Bins are labelled (k1, mu, t) by eq. shape from the shells' mean |k|.
+ *
+ * Conventions shared by every entry point
+ *   - k = k_f m, k_f = 2 pi / L, m integer.  Shells have width dk = w k_f with
+ *     w >= 1 (Section 2.1: widths below one grid spacing are not meaningful);
+ *     shell n (1..n_shells) holds the modes with (n - 1/2) w <= |m| < (n + 1/2) w,
+ *     decided exactly on the integer |m|^2 as
+ *         (2n-1)^2 w^2 <= 4 |m|^2 < (2n+1)^2 w^2   (evaluated in IEEE double).
+ *   - A bin is closable when a2 + a3 >= a1; only closable bins are selected.
+ *   - Every used mode must lie below the aliasing cutoff: (n_shells + 1/2) w <= N_g/3,
+ *     else BISPEC_ECUTOFF.
+ *   - delta is float32 [N_g][N_g][N_g], z fastest (C order), on the device.
+ *   - B is float64 [n_tri] on the device, ordered like bispec_triangles().
+ *
+ * Threading / streams: calls on different plans may run concurrently; calls on
+ * one plan must be serialised by the caller.  bispec_run and bispec_grad are
+ * asynchronous on the given HIP stream and allocate nothing; only bispec_plan
+ * allocates device memory and synchronises.
+ *
+ * Errors: every call returns BISPEC_OK (0) or a negative status and never
+ * throws; bispec_last_error() returns the calling thread's last message.
+ */
+#ifndef BISPEC_H
+#define BISPEC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bispec_plan_s* bispec_plan_t;
+
+enum bispec_status {
+  BISPEC_OK = 0,
+  BISPEC_EINVAL = -1,   /* bad argument or configuration                         */
+  BISPEC_ECUTOFF = -2,  /* a shell reaches k >= 2 pi N_g / (3 L) (eq. 3FT)        */
+  BISPEC_ENOMEM = -3,   /* workspace exceeds free device memory or BISPEC_MAX_BYTES */
+  BISPEC_EHIP = -4,     /* HIP runtime error (message holds hipGetErrorString)    */
+  BISPEC_ESTATE = -5,   /* call out of order (e.g. grad before any run)           */
+  BISPEC_EPREC = -6     /* an N_tri sum was not within 1e-3 of an integer         */
+};
+
+/* Triangle selection rules. */
+enum bispec_tri_mode {
+  BISPEC_TRI_ALL = 0,      /* every closable shell triple                               */
+  BISPEC_TRI_K1SET = 1,    /* closable triples with a1 in k1_shells[0..n_k1)            */
+  BISPEC_TRI_MUT_GRID = 2, /* per a1 in k1_shells, the triples nearest a (mu,t) grid:   */
+                           /*   mu_g, t_g = linspace(0.5,1,n_mu) x linspace(0.5,1,n_t), */
+                           /*   t_g mu_g >= 0.5 - 1e-12 (eq. cond),                     */
+                           /*   a2 = clamp(floor(t_g a1 + 1/2), 1, a1),                 */
+                           /*   a3 = clamp(floor(a1 sqrt(1 + t_g^2 - 2 mu_g t_g) + 1/2), 1, a2); */
+                           /*   unique closable triples kept                            */
+  BISPEC_TRI_LIST = 3      /* the n_list rows (a1,a2,a3) of list (each closable, distinct) */
+};
+
+/* Arithmetic of the triple contraction (step c); FFTs are float32 in both. */
+enum bispec_precision {
+  BISPEC_PREC_SPLITBF16 = 0, /* bf16 MFMA on hi+lo split operands, fp32 accumulate  */
+  BISPEC_PREC_FP32 = 1       /* plain fp32 vector FMAs                               */
+};
+
+enum bispec_flags {
+  BISPEC_FLAG_GRAD = 1u,         /* allocate the workspace for bispec_grad            */
+  BISPEC_FLAG_STAGE_TIMING = 2u  /* record HIP events around each stage of run       */
+};
+
+typedef struct bispec_config {
+  int32_t n_g;            /* grid points per side: even, 8..1024, factors 2,3,5     */
+  int32_t n_shells;       /* shells 1..n_shells                                     */
+  double box_l;           /* box side L (> 0); k in units of 1/L's unit             */
+  double dk;              /* shell width w in units of k_f (w >= 1)                  */
+  double rsd_beta;        /* linear RSD beta (0 = none), line of sight z            */
+  int32_t tri_mode;       /* enum bispec_tri_mode                                   */
+  int32_t n_k1;           /* K1SET / MUT_GRID: number of a1 shells                  */
+  const int32_t* k1_shells; /* host array [n_k1], read only during the call        */
+  int32_t n_mu, n_t;      /* MUT_GRID grid sizes (>= 2)                              */
+  int64_t n_list;         /* LIST: number of rows                                   */
+  const int32_t* list;    /* LIST: host array [n_list][3] (a1,a2,a3), a1>=a2>=a3>=1 */
+  int32_t precision;      /* enum bispec_precision                                  */
+  uint32_t flags;         /* enum bispec_flags                                      */
+} bispec_config;
+
+/* ---- host-only queries (no GPU needed) ------------------------------------ */
+
+/* Selected triangles for cfg, ordered by (a1,a2,a3) ascending.  Writes n_tri;
+ * if abc (host, [capacity][3]) and/or k1_mu_t (host, [capacity][3]: k1 in 1/L
+ * units of k, mu, t from eq. shape) are non-null, fills min(n_tri, capacity)
+ * rows.  Errors: EINVAL, ECUTOFF. */
+int bispec_query_triangles(const bispec_config* cfg, int64_t* n_tri, int32_t* abc,
+                           double* k1_mu_t, int64_t capacity);
+
+/* Per-shell mode counts (host int64 [n_shells], both halves of k-space) and
+ * mean |k| (host double [n_shells], in k units), Section 2.1's k_n. */
+int bispec_shell_stats(const bispec_config* cfg, int64_t* counts, double* mean_k);
+
+/* Device bytes the plan keeps (run_bytes) and its peak during planning
+ * (plan_peak_bytes, which includes the float64 unit shells). */
+int bispec_workspace_bytes(const bispec_config* cfg, int64_t* run_bytes, int64_t* plan_peak_bytes);
+
+/* ---- plan / run ------------------------------------------------------------ */
+
+/* Validate cfg, build shell and triangle tables, allocate the workspace on the
+ * current device, compute N_tri on the GPU in float64 from the unit shells
+ * (eqs. 2FT, Ntri2), round and check them (EPREC), then free the unit shells.
+ * hip_stream: a hipStream_t (null = default stream); the call synchronises it.
+ * *out receives the plan (owned by the caller; release with bispec_destroy).
+ * Errors: EINVAL, ECUTOFF, ENOMEM (checked before any allocation against
+ * hipMemGetInfo and the env var BISPEC_MAX_BYTES), EHIP, EPREC. */
+int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out);
+
+int bispec_num_triangles(bispec_plan_t plan, int64_t* n_tri);
+
+/* Host copies of the plan's triangles: abc [n_tri][3] int32, k1_mu_t [n_tri][3]
+ * double, ntri [n_tri] int64 (the exact triangle counts).  Any may be null. */
+int bispec_triangles(bispec_plan_t plan, int32_t* abc, double* k1_mu_t, int64_t* ntri);
+
+/* One pass of the estimator: forward R2C FFT of delta (a), per-shell masked
+ * inverse FFTs to the data shells D_n (b), the triple contraction (c) and the
+ * float64 normalisation B = T / (V N_tri N_g^3) (d).
+ * delta: device float32 [N_g^3]; B: device float64 [n_tri].  Both caller-owned,
+ * must not alias the plan's memory.  Asynchronous on hip_stream. */
+int bispec_run(bispec_plan_t plan, const float* delta, double* B, void* hip_stream);
+
+/* Vector-Jacobian product of the last bispec_run on this plan (needs
+ * BISPEC_FLAG_GRAD): gdelta(x) = sum_t gB_t dB_t/d delta(x).
+ * gB: device float64 [n_tri]; gdelta: device float32 [N_g^3] (overwritten).
+ * Errors: ESTATE when no run preceded or the plan lacks BISPEC_FLAG_GRAD. */
+int bispec_grad(bispec_plan_t plan, const double* gB, float* gdelta, void* hip_stream);
+
+/* Switch the contraction arithmetic of an existing plan (enum bispec_precision). */
+int bispec_set_precision(bispec_plan_t plan, int32_t precision);
+
+/* Stage times in ms of the last run (needs BISPEC_FLAG_STAGE_TIMING; the
+ * caller synchronises the stream first): ms[0] forward FFT, ms[1] inverse
+ * shell FFTs, ms[2] contraction, ms[3] normalisation.  n = entries wanted (<= 4). */
+int bispec_stage_times(bispec_plan_t plan, float* ms, int32_t n);
+
+/* Inspection (tests): copy the data shell D_n of the last run, divided by
+ * dV N_g^{3/2} (the plan's internal scale), into dst (device float32 [N_g^3]). */
+int bispec_copy_field(bispec_plan_t plan, int32_t shell, float* dst, void* hip_stream);
+
+int bispec_destroy(bispec_plan_t plan);
+
+/* Last error message of the calling thread ("" if none). */
+const char* bispec_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BISPEC_H */

@@ -1,0 +1,180 @@
+"""ctypes binding of libbispec.so (include/bispec.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  All arithmetic
+runs in the HIP library; if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbispec.so")
+
+BISPEC_OK, BISPEC_EINVAL, BISPEC_ECUTOFF, BISPEC_ENOMEM = 0, -1, -2, -3
+BISPEC_EHIP, BISPEC_ESTATE, BISPEC_EPREC = -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECUTOFF", -3: "ENOMEM", -4: "EHIP", -5: "ESTATE", -6: "EPREC"}
+TRI_ALL, TRI_K1SET, TRI_MUT_GRID, TRI_LIST = 0, 1, 2, 3
+PREC_SPLITBF16, PREC_FP32 = 0, 1
+FLAG_GRAD, FLAG_STAGE_TIMING = 1, 2
+
+
+class BispecError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__("%s failed with %s: %s" % (where, STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+class bispec_config(C.Structure):
+    _fields_ = [
+        ("n_g", C.c_int32), ("n_shells", C.c_int32), ("box_l", C.c_double), ("dk", C.c_double),
+        ("rsd_beta", C.c_double), ("tri_mode", C.c_int32), ("n_k1", C.c_int32),
+        ("k1_shells", C.POINTER(C.c_int32)), ("n_mu", C.c_int32), ("n_t", C.c_int32),
+        ("n_list", C.c_int64), ("list", C.POINTER(C.c_int32)), ("precision", C.c_int32),
+        ("flags", C.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded HIP library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libbispec.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2107_14564_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        cfgp = C.POINTER(bispec_config)
+        sig = {
+            "bispec_query_triangles": [cfgp, C.POINTER(I64), C.POINTER(I32), C.POINTER(D), I64],
+            "bispec_shell_stats": [cfgp, C.POINTER(I64), C.POINTER(D)],
+            "bispec_workspace_bytes": [cfgp, C.POINTER(I64), C.POINTER(I64)],
+            "bispec_plan": [cfgp, P, C.POINTER(P)],
+            "bispec_num_triangles": [P, C.POINTER(I64)],
+            "bispec_triangles": [P, C.POINTER(I32), C.POINTER(D), C.POINTER(I64)],
+            "bispec_run": [P, P, P, P],
+            "bispec_grad": [P, P, P, P],
+            "bispec_set_precision": [P, I32],
+            "bispec_stage_times": [P, C.POINTER(C.c_float), I32],
+            "bispec_copy_field": [P, I32, P, P],
+            "bispec_destroy": [P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.bispec_last_error.argtypes = []
+        L.bispec_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != BISPEC_OK:
+        raise BispecError(status, where, lib().bispec_last_error().decode())
+
+
+def _i32_array(values):
+    if values is None:
+        return None, 0
+    vals = [int(v) for v in values]
+    arr = (C.c_int32 * max(1, len(vals)))(*vals)
+    return arr, len(vals)
+
+
+def make_config(n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=TRI_ALL, k1_shells=None, n_mu=0, n_t=0,
+                triangles=None, precision=PREC_SPLITBF16, flags=0):
+    """A bispec_config plus the ctypes arrays it points into (keep both alive)."""
+    k1, nk1 = _i32_array(k1_shells)
+    flat = None if triangles is None else [int(v) for row in triangles for v in row]
+    lst, nflat = _i32_array(flat)
+    cfg = bispec_config(n_g=int(n_g), n_shells=int(n_shells), box_l=float(box_l), dk=float(dk),
+                        rsd_beta=float(rsd_beta), tri_mode=int(tri_mode), n_k1=nk1,
+                        k1_shells=C.cast(k1, C.POINTER(C.c_int32)) if k1 is not None else None,
+                        n_mu=int(n_mu), n_t=int(n_t), n_list=nflat // 3,
+                        list=C.cast(lst, C.POINTER(C.c_int32)) if lst is not None else None,
+                        precision=int(precision), flags=int(flags))
+    return cfg, (k1, lst)
+
+
+def bispec_query_triangles(cfg):
+    """(abc int32 [n][3], k1_mu_t float64 [n][3]) as Python lists of tuples."""
+    n = C.c_int64(0)
+    _check(lib().bispec_query_triangles(C.byref(cfg), C.byref(n), None, None, 0), "bispec_query_triangles")
+    abc = (C.c_int32 * (3 * n.value))()
+    lab = (C.c_double * (3 * n.value))()
+    _check(lib().bispec_query_triangles(C.byref(cfg), C.byref(n), abc, lab, n.value), "bispec_query_triangles")
+    return ([tuple(abc[3 * t:3 * t + 3]) for t in range(n.value)],
+            [tuple(lab[3 * t:3 * t + 3]) for t in range(n.value)])
+
+
+def bispec_shell_stats(cfg):
+    ns = cfg.n_shells
+    counts = (C.c_int64 * ns)()
+    means = (C.c_double * ns)()
+    _check(lib().bispec_shell_stats(C.byref(cfg), counts, means), "bispec_shell_stats")
+    return list(counts), list(means)
+
+
+def bispec_workspace_bytes(cfg):
+    run, peak = C.c_int64(0), C.c_int64(0)
+    _check(lib().bispec_workspace_bytes(C.byref(cfg), C.byref(run), C.byref(peak)), "bispec_workspace_bytes")
+    return run.value, peak.value
+
+
+def bispec_plan(cfg, stream: int = 0) -> int:
+    h = C.c_void_p()
+    _check(lib().bispec_plan(C.byref(cfg), C.c_void_p(stream), C.byref(h)), "bispec_plan")
+    return h.value
+
+
+def bispec_num_triangles(plan: int) -> int:
+    n = C.c_int64(0)
+    _check(lib().bispec_num_triangles(C.c_void_p(plan), C.byref(n)), "bispec_num_triangles")
+    return n.value
+
+
+def bispec_triangles(plan: int):
+    n = bispec_num_triangles(plan)
+    abc = (C.c_int32 * (3 * n))()
+    lab = (C.c_double * (3 * n))()
+    ntri = (C.c_int64 * n)()
+    _check(lib().bispec_triangles(C.c_void_p(plan), abc, lab, ntri), "bispec_triangles")
+    return ([tuple(abc[3 * t:3 * t + 3]) for t in range(n)],
+            [tuple(lab[3 * t:3 * t + 3]) for t in range(n)], list(ntri))
+
+
+def bispec_run(plan: int, delta_ptr: int, b_ptr: int, stream: int = 0):
+    _check(lib().bispec_run(C.c_void_p(plan), C.c_void_p(delta_ptr), C.c_void_p(b_ptr), C.c_void_p(stream)),
+           "bispec_run")
+
+
+def bispec_grad(plan: int, gb_ptr: int, gdelta_ptr: int, stream: int = 0):
+    _check(lib().bispec_grad(C.c_void_p(plan), C.c_void_p(gb_ptr), C.c_void_p(gdelta_ptr), C.c_void_p(stream)),
+           "bispec_grad")
+
+
+def bispec_set_precision(plan: int, precision: int):
+    _check(lib().bispec_set_precision(C.c_void_p(plan), int(precision)), "bispec_set_precision")
+
+
+def bispec_stage_times(plan: int, n: int = 4):
+    ms = (C.c_float * n)()
+    _check(lib().bispec_stage_times(C.c_void_p(plan), ms, n), "bispec_stage_times")
+    return list(ms)
+
+
+def bispec_copy_field(plan: int, shell: int, dst_ptr: int, stream: int = 0):
+    _check(lib().bispec_copy_field(C.c_void_p(plan), int(shell), C.c_void_p(dst_ptr), C.c_void_p(stream)),
+           "bispec_copy_field")
+
+
+def bispec_destroy(plan: int):
+    _check(lib().bispec_destroy(C.c_void_p(plan)), "bispec_destroy")
+
+
+def bispec_last_error() -> str:
+    return lib().bispec_last_error().decode()

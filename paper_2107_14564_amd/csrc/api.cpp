@@ -1,0 +1,457 @@
+// C ABI of the estimator (bispec.h): plan construction, memory management,
+// the N_tri computation at plan time and the asynchronous run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bispec.h"
+#include "geometry.h"
+#include "kernels.h"
+
+using namespace bispec;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return set_err(BISPEC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+hipError_t dalloc(DevBuf& b, size_t bytes) {
+  b.release();
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e == hipSuccess) b.bytes = bytes;
+  return e;
+}
+
+template <typename T> hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+  hipError_t e = dalloc(b, v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+int n_krange_for(long long groups, long long n_vox) {
+  long long k = (1024 + groups - 1) / groups;
+  k = ((k + 7) / 8) * 8;
+  long long cap = std::max(8LL, (n_vox / 64) / 8 * 8);
+  if (k > cap) k = cap;
+  if (k < 8) k = 8;
+  return (int)k;
+}
+
+struct Sizes {
+  long long n_vox = 0, n_tri = 0;
+  size_t spec = 0, fields32 = 0, a1_32 = 0, a2_32 = 0, fields64 = 0, a1_64 = 0, a2_64 = 0, grad = 0;
+  size_t tables = 0, partial_run = 0, partial_plan = 0;
+  size_t run_total() const { return spec + fields32 + a1_32 + a2_32 + grad + tables + partial_run; }
+  size_t plan_peak() const {
+    size_t p1 = fields64 + a1_64 + a2_64 + tables + partial_plan;
+    return std::max(p1, run_total());
+  }
+};
+
+}  // namespace
+
+struct bispec_plan_s {
+  bispec_config cfg{};
+  ShellGeometry geo;
+  Selection sel;
+  TilePlan tiles;
+  ShellPassPlan pass32;
+  Sizes sz;
+  std::vector<int64_t> ntri;
+  int precision = BISPEC_PREC_SPLITBF16;
+  int n_krange_vec = 8, n_krange_mfma = 8;
+  bool ran = false;
+  int device = 0;
+  // device memory
+  DevBuf spec, F, a1, a2, partial, norm, tri_index, rows, tile_list, task_off, shells, x_tiles, y_off, z_off, tw32;
+  DevBuf G;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  ~bispec_plan_s() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int build_host(const bispec_config* cfg, bispec_plan_s& p) {
+  if (!cfg) return set_err(BISPEC_EINVAL, "null config");
+  std::string err;
+  p.cfg = *cfg;
+  p.cfg.k1_shells = nullptr;
+  p.cfg.list = nullptr;
+  int st = build_shells(*cfg, p.geo, err);
+  if (st) return set_err(st, err);
+  if (p.geo.n_s > 256) return set_err(BISPEC_EINVAL, "n_shells > 256 is not supported by the contraction kernels");
+  if (cfg->precision == BISPEC_PREC_SPLITBF16 && p.geo.n_s > 112)
+    return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 112");
+  st = select_triangles(*cfg, p.geo, p.sel, err);
+  if (st) return set_err(st, err);
+  build_tiles(p.sel, p.tiles);
+  plan_shell_passes(p.geo, false, p.pass32);
+  const long long n = p.geo.n_g;
+  Sizes& s = p.sz;
+  s.n_vox = n * n * n;
+  s.n_tri = (long long)p.sel.tri.size();
+  s.spec = (size_t)n * n * (n / 2 + 1) * sizeof(float2);
+  s.fields32 = (size_t)p.geo.n_s * s.n_vox * sizeof(float);
+  s.a1_32 = (size_t)p.pass32.a1_elems * sizeof(float2);
+  s.a2_32 = (size_t)p.pass32.a2_elems * sizeof(float2);
+  ShellPassPlan p64;
+  plan_shell_passes(p.geo, true, p64);
+  s.fields64 = (size_t)p.geo.n_s * s.n_vox * sizeof(double);
+  s.a1_64 = (size_t)p64.a1_elems * sizeof(double2);
+  s.a2_64 = (size_t)p64.a2_elems * sizeof(double2);
+  s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 : 0;
+  const long long ntasks = (long long)p.tiles.task_off.size() - 1;
+  p.n_krange_vec = n_krange_for(ntasks, s.n_vox);
+  p.n_krange_mfma = n_krange_for((ntasks + 3) / 4, s.n_vox);
+  s.partial_run = (size_t)std::max(p.n_krange_vec, p.n_krange_mfma) * s.n_tri * sizeof(double);
+  s.partial_plan = (size_t)p.n_krange_vec * s.n_tri * sizeof(double);
+  s.tables = (size_t)p.geo.n_s * p.geo.n_s * p.geo.n_s * sizeof(int32_t) + p.tiles.rows.size() * sizeof(RowBlock) +
+             p.tiles.tiles.size() * sizeof(Tile) + p.pass32.x_tiles.size() * sizeof(int4) + (size_t)s.n_tri * 8 +
+             (size_t)n * 16 + 4096 * 4;
+  p.precision = cfg->precision;
+  return BISPEC_OK;
+}
+
+ContractArgs contract_args(bispec_plan_s& p, int n_krange) {
+  ContractArgs a;
+  a.rows = p.rows.as<RowBlock>();
+  a.tiles = p.tile_list.as<Tile>();
+  a.task_off = p.task_off.as<int32_t>();
+  a.n_tasks = (int)p.tiles.task_off.size() - 1;
+  a.tri_index = p.tri_index.as<int32_t>();
+  a.n_s = p.geo.n_s;
+  a.n_vox = p.sz.n_vox;
+  a.n_krange = n_krange;
+  a.partial = p.partial.as<double>();
+  a.n_tri = p.sz.n_tri;
+  return a;
+}
+
+ShellLaunch shell_launch(const ShellPassPlan& pp, const DevBuf& shells, const DevBuf& xt, const DevBuf& yo,
+                         const DevBuf& zo, int n_s) {
+  ShellLaunch L;
+  L.n_shells = n_s;
+  L.shells = shells.as<ShellDev>();
+  L.x_tiles = xt.as<int4>();
+  L.n_x_tiles = (long long)pp.x_tiles.size();
+  L.y_off = yo.as<long long>();
+  L.n_y_blocks = pp.y_off.back();
+  L.z_off = zo.as<long long>();
+  L.n_z_blocks = pp.z_off.back();
+  return L;
+}
+
+size_t max_bytes_env() {
+  const char* s = std::getenv("BISPEC_MAX_BYTES");
+  if (!s || !*s) return 0;
+  return (size_t)std::strtoull(s, nullptr, 10);
+}
+
+// N_tri from the float64 unit shells (eqs. 2FT, Ntri2) on the GPU.
+int compute_ntri(bispec_plan_s& p, hipStream_t st) {
+  const int n = p.geo.n_g;
+  ShellPassPlan pp;
+  plan_shell_passes(p.geo, true, pp);
+  DevBuf I, a1, a2, shells, xt, yo, zo, tw;
+  HIP_TRY(dalloc(I, p.sz.fields64));
+  HIP_TRY(dalloc(a1, p.sz.a1_64));
+  HIP_TRY(dalloc(a2, p.sz.a2_64));
+  HIP_TRY(upload(shells, pp.shells, st));
+  HIP_TRY(upload(xt, pp.x_tiles, st));
+  HIP_TRY(upload(yo, pp.y_off, st));
+  HIP_TRY(upload(zo, pp.z_off, st));
+  std::vector<double2> t64(n);
+  for (int k = 0; k < n; ++k) {
+    const double ang = 2.0 * M_PI * (double)k / (double)n;
+    t64[k] = make_double2(std::cos(ang), -std::sin(ang));
+  }
+  HIP_TRY(upload(tw, t64, st));
+  ShellLaunch L = shell_launch(pp, shells, xt, yo, zo, p.geo.n_s);
+  HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), p.sz.n_vox, L, n,
+                             tw.as<double2>(), st));
+  a1.release();
+  a2.release();
+  ContractArgs ca = contract_args(p, p.n_krange_vec);
+  HIP_TRY(launch_contract_fp64(I.as<double>(), ca, st));
+  DevBuf sums;
+  HIP_TRY(dalloc(sums, (size_t)p.sz.n_tri * sizeof(double)));
+  HIP_TRY(launch_reduce(p.partial.as<double>(), p.n_krange_vec, p.sz.n_tri, nullptr, sums.as<double>(), st));
+  std::vector<double> h(p.sz.n_tri);
+  HIP_TRY(hipMemcpyAsync(h.data(), sums.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double nv = (double)p.sz.n_vox;
+  p.ntri.resize(p.sz.n_tri);
+  double worst = 0.0;
+  long long worst_t = -1;
+  for (long long t = 0; t < p.sz.n_tri; ++t) {
+    const double v = h[t] / nv;
+    const double r = std::nearbyint(v);
+    if (std::fabs(v - r) > worst) { worst = std::fabs(v - r); worst_t = t; }
+    p.ntri[t] = (int64_t)r;
+  }
+  if (worst > 1e-3) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "N_tri sum of triangle %lld is %.6f from an integer", worst_t, worst);
+    return set_err(BISPEC_EPREC, buf);
+  }
+  return BISPEC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bispec_last_error(void) { return g_err.c_str(); }
+
+int bispec_query_triangles(const bispec_config* cfg, int64_t* n_tri, int32_t* abc, double* k1_mu_t,
+                           int64_t capacity) {
+  if (!cfg || !n_tri) return set_err(BISPEC_EINVAL, "null argument");
+  std::string err;
+  ShellGeometry g;
+  int st = build_shells(*cfg, g, err);
+  if (st) return set_err(st, err);
+  Selection s;
+  st = select_triangles(*cfg, g, s, err);
+  if (st) return set_err(st, err);
+  *n_tri = (int64_t)s.tri.size();
+  const int64_t m = std::min<int64_t>(*n_tri, capacity);
+  for (int64_t t = 0; t < m; ++t) {
+    if (abc) {
+      abc[3 * t] = s.tri[t].a1;
+      abc[3 * t + 1] = s.tri[t].a2;
+      abc[3 * t + 2] = s.tri[t].a3;
+    }
+    if (k1_mu_t)
+      for (int q = 0; q < 3; ++q) k1_mu_t[3 * t + q] = s.k1_mu_t[3 * t + q];
+  }
+  return BISPEC_OK;
+}
+
+int bispec_shell_stats(const bispec_config* cfg, int64_t* counts, double* mean_k) {
+  if (!cfg) return set_err(BISPEC_EINVAL, "null config");
+  std::string err;
+  ShellGeometry g;
+  int st = build_shells(*cfg, g, err);
+  if (st) return set_err(st, err);
+  for (int n = 0; n < g.n_s; ++n) {
+    if (counts) counts[n] = g.counts[n];
+    if (mean_k) mean_k[n] = g.mean_k[n];
+  }
+  return BISPEC_OK;
+}
+
+int bispec_workspace_bytes(const bispec_config* cfg, int64_t* run_bytes, int64_t* plan_peak_bytes) {
+  bispec_plan_s p;
+  int st = build_host(cfg, p);
+  if (st) return st;
+  if (run_bytes) *run_bytes = (int64_t)p.sz.run_total();
+  if (plan_peak_bytes) *plan_peak_bytes = (int64_t)p.sz.plan_peak();
+  return BISPEC_OK;
+}
+
+int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) {
+  if (!out) return set_err(BISPEC_EINVAL, "null output");
+  *out = nullptr;
+  bispec_plan_s* p = new (std::nothrow) bispec_plan_s();
+  if (!p) return set_err(BISPEC_ENOMEM, "host allocation failed");
+  auto fail = [&](int code) {
+    delete p;
+    return code;
+  };
+  int st = build_host(cfg, *p);
+  if (st) return fail(st);
+  hipStream_t s = (hipStream_t)hip_stream;
+  {
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e)));
+    size_t free_b = 0, total_b = 0;
+    e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("hipMemGetInfo: ") + hipGetErrorString(e)));
+    const size_t need = p->sz.plan_peak();
+    const size_t cap = max_bytes_env();
+    if (need > free_b || (cap && need > cap)) {
+      char buf[256];
+      std::snprintf(buf, sizeof buf, "plan needs %.3f GB of device memory; %.3f GB free%s", need / 1e9, free_b / 1e9,
+                    cap ? " (or above BISPEC_MAX_BYTES)" : "");
+      return fail(set_err(BISPEC_ENOMEM, buf));
+    }
+  }
+  const int ns = p->geo.n_s;
+  // triangle index table (i-1, j-1, l-1) -> t
+  {
+    std::vector<int32_t> idx((size_t)ns * ns * ns, -1);
+    for (size_t t = 0; t < p->sel.tri.size(); ++t) {
+      const Tri& q = p->sel.tri[t];
+      idx[((size_t)(q.a1 - 1) * ns + (q.a2 - 1)) * ns + (q.a3 - 1)] = (int32_t)t;
+    }
+    hipError_t e = upload(p->tri_index, idx, s);
+    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, hipGetErrorString(e)));
+  }
+#define PLAN_HIP(expr)                                                                                     \
+  do {                                                                                                     \
+    hipError_t e_ = (expr);                                                                                \
+    if (e_ != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+  PLAN_HIP(upload(p->rows, p->tiles.rows, s));
+  PLAN_HIP(upload(p->tile_list, p->tiles.tiles, s));
+  PLAN_HIP(upload(p->task_off, p->tiles.task_off, s));
+  PLAN_HIP(dalloc(p->partial, p->sz.partial_run));
+  // N_tri first (largest memory phase), then the run workspace
+  st = compute_ntri(*p, s);
+  if (st) return fail(st);
+  PLAN_HIP(upload(p->shells, p->pass32.shells, s));
+  PLAN_HIP(upload(p->x_tiles, p->pass32.x_tiles, s));
+  PLAN_HIP(upload(p->y_off, p->pass32.y_off, s));
+  PLAN_HIP(upload(p->z_off, p->pass32.z_off, s));
+  {
+    const int n = p->geo.n_g;
+    std::vector<float2> t32(n);
+    for (int k = 0; k < n; ++k) {
+      const double ang = 2.0 * M_PI * (double)k / (double)n;
+      t32[k] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+    }
+    PLAN_HIP(upload(p->tw32, t32, s));
+    // B = dV^3 N^{3/2} T_s / (V N_tri), T_s the triple sum of the scaled fields
+    const double V = p->geo.box_l * p->geo.box_l * p->geo.box_l;
+    const double dV = V / ((double)n * n * n);
+    const double c = dV * dV * dV * std::pow((double)n, 1.5) / V;
+    std::vector<double> norm(p->sz.n_tri);
+    for (long long t = 0; t < p->sz.n_tri; ++t) norm[t] = p->ntri[t] > 0 ? c / (double)p->ntri[t] : NAN;
+    PLAN_HIP(upload(p->norm, norm, s));
+  }
+  PLAN_HIP(dalloc(p->spec, p->sz.spec));
+  PLAN_HIP(dalloc(p->a1, p->sz.a1_32));
+  PLAN_HIP(dalloc(p->a2, p->sz.a2_32));
+  PLAN_HIP(dalloc(p->F, p->sz.fields32));
+  if (p->cfg.flags & BISPEC_FLAG_GRAD) PLAN_HIP(dalloc(p->G, p->sz.grad));
+  if (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING)
+    for (auto& e : p->ev) PLAN_HIP(hipEventCreate(&e));
+  PLAN_HIP(hipStreamSynchronize(s));
+#undef PLAN_HIP
+  *out = p;
+  return BISPEC_OK;
+}
+
+int bispec_num_triangles(bispec_plan_t p, int64_t* n_tri) {
+  if (!p || !n_tri) return set_err(BISPEC_EINVAL, "null argument");
+  *n_tri = p->sz.n_tri;
+  return BISPEC_OK;
+}
+
+int bispec_triangles(bispec_plan_t p, int32_t* abc, double* k1_mu_t, int64_t* ntri) {
+  if (!p) return set_err(BISPEC_EINVAL, "null plan");
+  for (long long t = 0; t < p->sz.n_tri; ++t) {
+    if (abc) {
+      abc[3 * t] = p->sel.tri[t].a1;
+      abc[3 * t + 1] = p->sel.tri[t].a2;
+      abc[3 * t + 2] = p->sel.tri[t].a3;
+    }
+    if (k1_mu_t)
+      for (int q = 0; q < 3; ++q) k1_mu_t[3 * t + q] = p->sel.k1_mu_t[3 * t + q];
+    if (ntri) ntri[t] = p->ntri[t];
+  }
+  return BISPEC_OK;
+}
+
+int bispec_set_precision(bispec_plan_t p, int32_t precision) {
+  if (!p) return set_err(BISPEC_EINVAL, "null plan");
+  if (precision != BISPEC_PREC_SPLITBF16 && precision != BISPEC_PREC_FP32)
+    return set_err(BISPEC_EINVAL, "unknown precision");
+  if (precision == BISPEC_PREC_SPLITBF16 && p->geo.n_s > 112)
+    return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 112");
+  p->precision = precision;
+  return BISPEC_OK;
+}
+
+int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream) {
+  if (!p || !delta || !B) return set_err(BISPEC_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool timing = (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING) != 0;
+  const int n = p->geo.n_g;
+  if (timing) HIP_TRY(hipEventRecord(p->ev[0], s));
+  HIP_TRY(launch_forward(delta, p->spec.as<float2>(), n, (float)p->geo.beta, p->tw32.as<float2>(), s));
+  if (timing) HIP_TRY(hipEventRecord(p->ev[1], s));
+  ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s);
+  HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), p->F.as<float>(),
+                             p->sz.n_vox, L, n, p->tw32.as<float2>(), s));
+  if (timing) HIP_TRY(hipEventRecord(p->ev[2], s));
+  int nk;
+  if (p->precision == BISPEC_PREC_FP32) {
+    nk = p->n_krange_vec;
+    HIP_TRY(launch_contract_fp32(p->F.as<float>(), contract_args(*p, nk), s));
+  } else {
+    nk = p->n_krange_mfma;
+    HIP_TRY(launch_contract_bf16x3(p->F.as<float>(), contract_args(*p, nk), s));
+  }
+  if (timing) HIP_TRY(hipEventRecord(p->ev[3], s));
+  HIP_TRY(launch_reduce(p->partial.as<double>(), nk, p->sz.n_tri, p->norm.as<double>(), B, s));
+  if (timing) HIP_TRY(hipEventRecord(p->ev[4], s));
+  p->ran = true;
+  return BISPEC_OK;
+}
+
+int bispec_grad(bispec_plan_t p, const double* gB, float* gdelta, void* hip_stream) {
+  if (!p || !gB || !gdelta) return set_err(BISPEC_EINVAL, "null argument");
+  (void)hip_stream;
+  if (!(p->cfg.flags & BISPEC_FLAG_GRAD)) return set_err(BISPEC_ESTATE, "plan was made without BISPEC_FLAG_GRAD");
+  if (!p->ran) return set_err(BISPEC_ESTATE, "bispec_grad needs a preceding bispec_run");
+  return set_err(BISPEC_ESTATE, "gradient not available in this build");
+}
+
+int bispec_stage_times(bispec_plan_t p, float* ms, int32_t n) {
+  if (!p || !ms || n < 0 || n > 4) return set_err(BISPEC_EINVAL, "bad argument");
+  if (!(p->cfg.flags & BISPEC_FLAG_STAGE_TIMING)) return set_err(BISPEC_ESTATE, "plan was made without stage timing");
+  if (!p->ran) return set_err(BISPEC_ESTATE, "no run recorded");
+  for (int q = 0; q < n; ++q) HIP_TRY(hipEventElapsedTime(&ms[q], p->ev[q], p->ev[q + 1]));
+  return BISPEC_OK;
+}
+
+int bispec_copy_field(bispec_plan_t p, int32_t shell, float* dst, void* hip_stream) {
+  if (!p || !dst) return set_err(BISPEC_EINVAL, "null argument");
+  if (shell < 1 || shell > p->geo.n_s) return set_err(BISPEC_EINVAL, "shell out of range");
+  if (!p->ran) return set_err(BISPEC_ESTATE, "no run recorded");
+  HIP_TRY(hipMemcpyAsync(dst, p->F.as<float>() + (size_t)(shell - 1) * p->sz.n_vox, p->sz.n_vox * sizeof(float),
+                         hipMemcpyDeviceToDevice, (hipStream_t)hip_stream));
+  return BISPEC_OK;
+}
+
+int bispec_destroy(bispec_plan_t p) {
+  delete p;
+  return BISPEC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+// Plan geometry on the host (see geometry.h).  Compiled without floating-point
+// contraction so the double-precision shell and grid rules evaluate exactly as
+// written in bispec.h.
+#include "geometry.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <set>
+
+namespace bispec {
+
+static int fail(std::string& err, int code, const char* msg) {
+  err = msg;
+  return code;
+}
+
+std::vector<int> fft_radices(int n) {
+  std::vector<int> r;
+  if (n < 2) return r;
+  while (n % 8 == 0 && n > 8) { r.push_back(8); n /= 8; }
+  for (int p : {8, 4, 2, 3, 5})
+    while (n % p == 0) { r.push_back(p); n /= p; }
+  if (n != 1) r.clear();
+  return r;
+}
+
+int validate(const bispec_config& c, std::string& err) {
+  if (c.n_g < 8 || c.n_g > 1024 || (c.n_g & 1))
+    return fail(err, BISPEC_EINVAL, "n_g must be even and in [8, 1024]");
+  if (fft_radices(c.n_g).empty() || fft_radices(c.n_g / 2).empty())
+    return fail(err, BISPEC_EINVAL, "n_g must factor into 2, 3 and 5");
+  if (!(c.box_l > 0) || !std::isfinite(c.box_l)) return fail(err, BISPEC_EINVAL, "box_l must be > 0");
+  if (!(c.dk >= 1.0) || !std::isfinite(c.dk)) return fail(err, BISPEC_EINVAL, "dk (shell width in k_f) must be >= 1");
+  if (c.n_shells < 1 || c.n_shells > 1024) return fail(err, BISPEC_EINVAL, "n_shells must be in [1, 1024]");
+  if (!std::isfinite(c.rsd_beta)) return fail(err, BISPEC_EINVAL, "rsd_beta must be finite");
+  if (c.precision != BISPEC_PREC_SPLITBF16 && c.precision != BISPEC_PREC_FP32)
+    return fail(err, BISPEC_EINVAL, "unknown precision");
+  // eq. 3FT: all shell modes below 2 pi N_g / (3 L)  <=>  (n_s + 1/2) w <= N_g / 3
+  if ((c.n_shells + 0.5) * c.dk * 3.0 > (double)c.n_g)
+    return fail(err, BISPEC_ECUTOFF, "shells reach k >= 2 pi N_g/(3L): need (n_shells + 1/2) dk <= n_g/3");
+  switch (c.tri_mode) {
+    case BISPEC_TRI_ALL: break;
+    case BISPEC_TRI_K1SET:
+    case BISPEC_TRI_MUT_GRID:
+      if (c.n_k1 < 1 || !c.k1_shells) return fail(err, BISPEC_EINVAL, "k1_shells required");
+      for (int q = 0; q < c.n_k1; ++q)
+        if (c.k1_shells[q] < 1 || c.k1_shells[q] > c.n_shells) return fail(err, BISPEC_EINVAL, "k1 shell out of range");
+      if (c.tri_mode == BISPEC_TRI_MUT_GRID && (c.n_mu < 2 || c.n_t < 2 || c.n_mu > 4096 || c.n_t > 4096))
+        return fail(err, BISPEC_EINVAL, "n_mu and n_t must be in [2, 4096]");
+      break;
+    case BISPEC_TRI_LIST:
+      if (c.n_list < 1 || !c.list) return fail(err, BISPEC_EINVAL, "list required");
+      break;
+    default: return fail(err, BISPEC_EINVAL, "unknown tri_mode");
+  }
+  if (c.flags & ~(uint32_t)(BISPEC_FLAG_GRAD | BISPEC_FLAG_STAGE_TIMING))
+    return fail(err, BISPEC_EINVAL, "unknown flag bits");
+  return BISPEC_OK;
+}
+
+// smallest integer q >= 0 with 4 q >= (2n-1)^2 w^2 (the exact rule of bispec.h)
+static int64_t edge_m2(int64_t two_n_pm1, double w) {
+  const double rhs = (double)(two_n_pm1 * two_n_pm1) * (w * w);
+  int64_t q = (int64_t)std::floor(rhs / 4.0) - 2;
+  if (q < 0) q = 0;
+  while (!(4.0 * (double)q >= rhs)) ++q;
+  return q;
+}
+
+int build_shells(const bispec_config& c, ShellGeometry& g, std::string& err) {
+  int st = validate(c, err);
+  if (st) return st;
+  g.n_g = c.n_g;
+  g.n_s = c.n_shells;
+  g.box_l = c.box_l;
+  g.w = c.dk;
+  g.beta = c.rsd_beta;
+  g.lo2.resize(g.n_s);
+  g.hi2.resize(g.n_s);
+  g.rad.resize(g.n_s);
+  for (int n = 1; n <= g.n_s; ++n) {
+    g.lo2[n - 1] = edge_m2(2 * n - 1, g.w);
+    g.hi2[n - 1] = edge_m2(2 * n + 1, g.w);
+    int64_t r = (int64_t)std::floor(std::sqrt((double)(g.hi2[n - 1] - 1)));
+    while (r * r > g.hi2[n - 1] - 1) --r;
+    while ((r + 1) * (r + 1) <= g.hi2[n - 1] - 1) ++r;
+    g.rad[n - 1] = (int32_t)r;
+  }
+  // mode counts and mean |m| over the full lattice ball
+  const int64_t top = g.hi2[g.n_s - 1];
+  const int R = g.rad[g.n_s - 1];
+  std::vector<double> sum(g.n_s, 0.0);
+  g.counts.assign(g.n_s, 0);
+  // shell lookup by |m|^2
+  std::vector<int32_t> shell_of(top, 0);
+  for (int n = 1; n <= g.n_s; ++n)
+    for (int64_t q = g.lo2[n - 1]; q < g.hi2[n - 1]; ++q) shell_of[q] = n;
+  for (int x = -R; x <= R; ++x)
+    for (int y = -R; y <= R; ++y)
+      for (int z = -R; z <= R; ++z) {
+        int64_t q = (int64_t)x * x + (int64_t)y * y + (int64_t)z * z;
+        if (q >= top || q == 0) continue;
+        int n = shell_of[q];
+        if (!n) continue;
+        g.counts[n - 1] += 1;
+        sum[n - 1] += std::sqrt((double)q);
+      }
+  const double kf = 2.0 * M_PI / g.box_l;
+  g.mean_k.resize(g.n_s);
+  for (int n = 0; n < g.n_s; ++n) {
+    if (g.counts[n] == 0) return fail(err, BISPEC_EINVAL, "empty shell");
+    g.mean_k[n] = kf * (sum[n] / (double)g.counts[n]);
+  }
+  return BISPEC_OK;
+}
+
+static std::vector<double> linspace_half_one(int n) {
+  // numpy.linspace(0.5, 1.0, n): start + i*step, last point exactly 1.0
+  std::vector<double> v(n);
+  const double step = (1.0 - 0.5) / (double)(n - 1);
+  for (int i = 0; i < n; ++i) v[i] = (double)i * step + 0.5;
+  v[n - 1] = 1.0;
+  return v;
+}
+
+int select_triangles(const bispec_config& c, const ShellGeometry& g, Selection& s, std::string& err) {
+  std::set<std::tuple<int, int, int>> pick;
+  const int ns = g.n_s;
+  auto closable = [](int a1, int a2, int a3) { return a1 >= a2 && a2 >= a3 && a3 >= 1 && a2 + a3 >= a1; };
+  if (c.tri_mode == BISPEC_TRI_ALL || c.tri_mode == BISPEC_TRI_K1SET) {
+    std::vector<char> use(ns + 1, c.tri_mode == BISPEC_TRI_ALL);
+    if (c.tri_mode == BISPEC_TRI_K1SET)
+      for (int q = 0; q < c.n_k1; ++q) use[c.k1_shells[q]] = 1;
+    for (int a1 = 1; a1 <= ns; ++a1) {
+      if (!use[a1]) continue;
+      for (int a2 = 1; a2 <= a1; ++a2)
+        for (int a3 = 1; a3 <= a2; ++a3)
+          if (a2 + a3 >= a1) pick.insert({a1, a2, a3});
+    }
+  } else if (c.tri_mode == BISPEC_TRI_MUT_GRID) {
+    const std::vector<double> mus = linspace_half_one(c.n_mu), ts = linspace_half_one(c.n_t);
+    for (int q = 0; q < c.n_k1; ++q) {
+      const int a1 = c.k1_shells[q];
+      for (double t : ts)
+        for (double mu : mus) {
+          if (t * mu < 0.5 - 1e-12) continue;
+          int a2 = (int)std::floor(t * a1 + 0.5);
+          a2 = std::min(std::max(a2, 1), a1);
+          double r = 1.0 + t * t - 2.0 * mu * t;
+          if (r < 0.0) r = 0.0;
+          int a3 = (int)std::floor(a1 * std::sqrt(r) + 0.5);
+          a3 = std::min(std::max(a3, 1), a2);
+          if (closable(a1, a2, a3)) pick.insert({a1, a2, a3});
+        }
+    }
+  } else {  // LIST
+    for (int64_t r = 0; r < c.n_list; ++r) {
+      int a1 = c.list[3 * r], a2 = c.list[3 * r + 1], a3 = c.list[3 * r + 2];
+      if (a1 > ns || !closable(a1, a2, a3)) return fail(err, BISPEC_EINVAL, "list row is not a closable triple within n_shells");
+      if (!pick.insert({a1, a2, a3}).second) return fail(err, BISPEC_EINVAL, "duplicate list row");
+    }
+  }
+  if (pick.empty()) return fail(err, BISPEC_EINVAL, "no triangle selected");
+  s.tri.clear();
+  s.k1_mu_t.clear();
+  for (auto& p : pick) {
+    Tri t{std::get<0>(p), std::get<1>(p), std::get<2>(p)};
+    s.tri.push_back(t);
+    const double k1 = g.mean_k[t.a1 - 1], k2 = g.mean_k[t.a2 - 1], k3 = g.mean_k[t.a3 - 1];
+    // eq. shape
+    s.k1_mu_t.push_back(k1);
+    s.k1_mu_t.push_back(0.5 * (k1 / k2 + k2 / k1 - (k3 / k1) * (k3 / k2)));
+    s.k1_mu_t.push_back(k2 / k1);
+  }
+  return BISPEC_OK;
+}
+
+void build_tiles(const Selection& s, TilePlan& tp) {
+  // pairs (i, j) with their selected l values
+  std::map<std::pair<int, int>, std::vector<int>> pl;
+  for (const Tri& t : s.tri) pl[{t.a1, t.a2}].push_back(t.a3);
+  struct P { int i, j, lo, hi; };
+  std::vector<P> pairs;
+  for (auto& kv : pl) {
+    auto mm = std::minmax_element(kv.second.begin(), kv.second.end());
+    pairs.push_back({kv.first.first, kv.first.second, *mm.first, *mm.second});
+  }
+  // rows with similar column ranges share a block: order by (hi, lo, i, j)
+  std::sort(pairs.begin(), pairs.end(), [](const P& a, const P& b) {
+    if (a.hi != b.hi) return a.hi < b.hi;
+    if (a.lo != b.lo) return a.lo < b.lo;
+    if (a.i != b.i) return a.i < b.i;
+    return a.j < b.j;
+  });
+  tp.rows.clear();
+  tp.tiles.clear();
+  tp.task_off.clear();
+  std::vector<std::vector<Tile>> per_rb;
+  for (size_t p0 = 0; p0 < pairs.size(); p0 += kRows) {
+    RowBlock rb{};
+    int lo = 1 << 30, hi = 0;
+    for (int r = 0; r < kRows; ++r) {
+      if (p0 + r < pairs.size()) {
+        rb.i[r] = (int16_t)pairs[p0 + r].i;
+        rb.j[r] = (int16_t)pairs[p0 + r].j;
+        lo = std::min(lo, pairs[p0 + r].lo);
+        hi = std::max(hi, pairs[p0 + r].hi);
+      } else {
+        rb.i[r] = 0;
+        rb.j[r] = 0;
+      }
+    }
+    const int id = (int)tp.rows.size();
+    tp.rows.push_back(rb);
+    std::vector<Tile> ts;
+    for (int c0 = lo; c0 <= hi; c0 += kCols) {
+      // keep the tile only if some selected (i, j, l) falls in it
+      bool any = false;
+      for (int r = 0; r < kRows && !any; ++r) {
+        if (!rb.j[r]) continue;
+        for (int l : pl[{rb.i[r], rb.j[r]}])
+          if (l >= c0 && l < c0 + kCols) { any = true; break; }
+      }
+      if (any) ts.push_back({id, c0});
+    }
+    per_rb.push_back(ts);
+  }
+  // tasks: consecutive row blocks; a row block with more than kMaxTilesPerTask
+  // tiles is split across tasks (its products are then formed once per task)
+  tp.task_off.push_back(0);
+  int in_task = 0;
+  for (auto& ts : per_rb) {
+    if (in_task > 0 && in_task + (int)ts.size() > kMaxTilesPerTask) {
+      tp.task_off.push_back((int32_t)tp.tiles.size());
+      in_task = 0;
+    }
+    for (auto& t : ts) {
+      if (in_task == kMaxTilesPerTask) {
+        tp.task_off.push_back((int32_t)tp.tiles.size());
+        in_task = 0;
+      }
+      tp.tiles.push_back(t);
+      ++in_task;
+    }
+  }
+  if ((int)tp.tiles.size() > tp.task_off.back()) tp.task_off.push_back((int32_t)tp.tiles.size());
+  tp.useful = (int64_t)s.tri.size();
+  tp.slots = (int64_t)tp.tiles.size() * kRows * kCols;
+}
+
+}  // namespace bispec

@@ -1,0 +1,80 @@
+// Host-side plan geometry: configuration checks, k-shells, triangle selection,
+// bin labels and the contraction tile lists.  Pure C++ (no HIP), so the
+// host-only queries of the C ABI work without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bispec.h"
+
+namespace bispec {
+
+struct Tri {
+  int32_t a1, a2, a3;
+};
+
+struct ShellGeometry {
+  int32_t n_g = 0, n_s = 0;
+  double box_l = 0, w = 0, beta = 0;
+  // integer |m|^2 bounds: shell n (1-based) holds lo2[n-1] <= |m|^2 < hi2[n-1]
+  std::vector<int64_t> lo2, hi2;
+  // largest |m_y| (and |m_z|) of a mode below hi2 of shell n: floor(sqrt(hi2-1))
+  std::vector<int32_t> rad;
+  std::vector<int64_t> counts;   // modes per shell over the whole lattice
+  std::vector<double> mean_k;    // mean |k| per shell (k units)
+};
+
+struct Selection {
+  std::vector<Tri> tri;          // ascending (a1,a2,a3)
+  std::vector<double> k1_mu_t;   // [n_tri][3]
+};
+
+// Validates cfg (everything except memory).  Returns a bispec_status.
+int validate(const bispec_config& cfg, std::string& err);
+int build_shells(const bispec_config& cfg, ShellGeometry& g, std::string& err);
+int select_triangles(const bispec_config& cfg, const ShellGeometry& g, Selection& s, std::string& err);
+
+// FFT radix schedule of a length (product of 8,4,2,3,5); empty if unsupported.
+std::vector<int> fft_radices(int n);
+
+// ---- contraction work decomposition -------------------------------------
+//
+// The triple sums T(i,j,l) = sum_x F_i F_j F_l for the selected triangles are
+// grouped as a GEMM whose rows are shell pairs (i >= j) and whose columns are
+// single shells l: row (i,j) x column l contributes to triangle (i,j,l) when
+// l <= j.  Rows are packed in blocks of kRows pairs; each row block meets the
+// columns it needs in consecutive blocks of kCols shells.  A tile is one
+// (row block, column block) product; every selected triangle lies in exactly
+// one tile.
+constexpr int kRows = 32;
+constexpr int kCols = 32;
+
+struct RowBlock {
+  int16_t i[kRows];
+  int16_t j[kRows];   // 0 = padding row
+};
+
+struct Tile {
+  int32_t rb;     // row block
+  int32_t col0;   // first column shell (1-based)
+};
+
+// A task is at most kMaxTilesPerTask tiles handled together over a voxel
+// range (by one wavefront in the MFMA kernel, one work group in the vector
+// kernel); a row block's tiles stay in one task so its pair products are
+// formed once.
+constexpr int kMaxTilesPerTask = 8;
+
+struct TilePlan {
+  std::vector<RowBlock> rows;
+  std::vector<Tile> tiles;       // task-major
+  std::vector<int32_t> task_off; // task q owns tiles [task_off[q], task_off[q+1])
+  int64_t useful = 0;            // selected triangles
+  int64_t slots = 0;             // tiles * kRows * kCols
+};
+
+void build_tiles(const Selection& s, TilePlan& tp);
+
+}  // namespace bispec

@@ -1,0 +1,92 @@
+"""Plan objects and the autograd entry point (marshalling only)."""
+from __future__ import annotations
+
+import torch
+
+from . import _abi
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """A bispectrum plan on the current device.
+
+    Arguments follow bispec_config: grid size n_g, box side box_l, shell width
+    dk (units of 2 pi / box_l), n_shells, optional RSD beta, a triangle
+    selection (tri_mode with k1_shells / n_mu / n_t / triangles), the
+    contraction precision and flags.
+    """
+
+    def __init__(self, n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=_abi.TRI_ALL, k1_shells=None, n_mu=0,
+                 n_t=0, triangles=None, precision=_abi.PREC_SPLITBF16, flags=0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Plan needs a HIP device")
+        self.cfg, self._keep = _abi.make_config(n_g, box_l, dk, n_shells, rsd_beta, tri_mode, k1_shells, n_mu, n_t,
+                                                triangles, precision, flags)
+        self.n_g = int(n_g)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.handle = _abi.bispec_plan(self.cfg, _stream())
+        abc, lab, ntri = _abi.bispec_triangles(self.handle)
+        self.triangles = torch.tensor(abc, dtype=torch.int32)
+        self.labels = torch.tensor(lab, dtype=torch.float64)
+        self.ntri = torch.tensor(ntri, dtype=torch.int64)
+        self.n_tri = len(abc)
+
+    def run(self, delta: torch.Tensor) -> torch.Tensor:
+        self._check_field(delta)
+        out = torch.empty(self.n_tri, dtype=torch.float64, device=delta.device)
+        _abi.bispec_run(self.handle, delta.data_ptr(), out.data_ptr(), _stream())
+        return out
+
+    def grad(self, g_b: torch.Tensor) -> torch.Tensor:
+        g_b = g_b.to(dtype=torch.float64, device=self.device).contiguous()
+        if g_b.numel() != self.n_tri:
+            raise ValueError("gradient of B has the wrong length")
+        out = torch.empty((self.n_g,) * 3, dtype=torch.float32, device=self.device)
+        _abi.bispec_grad(self.handle, g_b.data_ptr(), out.data_ptr(), _stream())
+        return out
+
+    def set_precision(self, precision: int):
+        _abi.bispec_set_precision(self.handle, precision)
+
+    def stage_times(self):
+        return _abi.bispec_stage_times(self.handle, 4)
+
+    def field(self, shell: int) -> torch.Tensor:
+        out = torch.empty((self.n_g,) * 3, dtype=torch.float32, device=self.device)
+        _abi.bispec_copy_field(self.handle, shell, out.data_ptr(), _stream())
+        return out
+
+    def _check_field(self, delta):
+        if (delta.dtype != torch.float32 or not delta.is_cuda or not delta.is_contiguous()
+                or tuple(delta.shape) != (self.n_g,) * 3):
+            raise ValueError("delta must be a contiguous float32 CUDA tensor of shape (n_g, n_g, n_g)")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _abi.bispec_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _BispecFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, delta, plan):
+        ctx.plan = plan
+        return plan.run(delta.contiguous())
+
+    @staticmethod
+    def backward(ctx, g_b):
+        return ctx.plan.grad(g_b), None
+
+
+def bispectrum(delta: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """B (float64 [n_tri]) of delta; differentiable when the plan has FLAG_GRAD."""
+    return _BispecFn.apply(delta, plan)

@@ -1,0 +1,118 @@
+"""HIP path against the FP64 oracle, element by element, through the C ABI.
+
+Tolerance (relative error against the float64 oracle, per the precision target
+of 1e-5): every B satisfies e_cond = |B - B_ref| / S <= 1e-5 with
+S = sum_x |D_a1 D_a2 D_a3| / (V N_tri N^3), the rounding scale of the triple
+sum (a float32 FFT leaves ~1e-7 relative error in each D_n, the split-bf16
+products ~2^-17, float32 accumulation ~1e-7 times that scale), and the
+normwise error |B - B_ref|/|B_ref| <= 1e-5.  N_tri must be exact."""
+import numpy as np
+import pytest
+
+from gpu_util import gpu_ok, metrics, say, to_gpu
+from oracle import fbe, geometry
+from synth import PowerLaw, gaussian_field, quadratic_ng_field
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
+
+TOL = 1e-5
+
+
+def _field(n_g, box, seed, index=-1.0, f_ng=1.0):
+    return quadratic_ng_field(gaussian_field(n_g, box, PowerLaw(index), seed), f_ng)
+
+
+def _check(n_g, box, dk, n_s, beta, seed, precision, tri_kw=None, tol=TOL):
+    import paper_2107_14564_amd as P
+    tri_kw = tri_kw or {}
+    say("case n_g=%d box=%g dk=%g n_s=%d beta=%g seed=%d prec=%d %s" % (n_g, box, dk, n_s, beta, seed, precision,
+                                                                        tri_kw))
+    delta_gpu, delta64 = to_gpu(_field(n_g, box, seed))
+    plan = P.Plan(n_g, box, dk, n_s, rsd_beta=beta, precision=precision, **tri_kw)
+    B = plan.run(delta_gpu).cpu().numpy()
+    tri = plan.triangles.numpy()
+    ref = fbe.estimate(delta64, box, dk, tri, rsd_beta=beta, with_abs=True)
+    assert np.array_equal(plan.ntri.numpy(), ref["ntri"]), "N_tri differs"
+    m = metrics(B, ref["B"], ref["S"])
+    say("  n_tri=%d %s" % (len(tri), m))
+    assert m["e_cond"] <= tol and m["e_norm"] <= tol, m
+    plan.close()
+    return m
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("n_g,box,dk,n_s,beta", [
+    (16, 100.0, 1.0, 4, 0.0),
+    (16, 100.0, 1.0, 4, 0.5),
+    (32, 300.0, 1.0, 10, 0.0),
+    (64, 300.0, 1.0, 20, 0.5),
+    (64, 500.0, 2.0, 10, 0.0),
+    (48, 200.0, 1.5, 9, 1.0),      # mixed radix 3 (48 = 8*2*3, 24 = 8*3)
+    (40, 200.0, 1.0, 12, 0.0),     # mixed radix 5 (40 = 8*5, 20 = 4*5)
+])
+def test_all_triangles(n_g, box, dk, n_s, beta, precision):
+    _check(n_g, box, dk, n_s, beta, 100 + n_g, precision)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_shape_grid_ng32(precision):
+    """The oracle-sized workload: N_g = 32, L = 300, shells of one grid spacing,
+    k1 shells 5..10, 10 x 10 (mu, t) grid."""
+    _check(32, 300.0, 1.0, 10, 0.0, 1001, precision,
+           dict(tri_mode=2, k1_shells=list(range(5, 11)), n_mu=10, n_t=10))
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_single_triangle_and_single_shell(precision):
+    _check(16, 100.0, 1.0, 4, 0.0, 7, precision, dict(tri_mode=3, triangles=[(4, 3, 2)]))
+    _check(16, 100.0, 1.0, 1, 0.0, 8, precision)
+
+
+def test_fields_match_oracle():
+    """Steps a and b alone: the data shell fields D_n against float64 FFTs."""
+    import paper_2107_14564_amd as P
+    for n_g, box, dk, n_s, beta in [(32, 300.0, 1.0, 10, 0.5), (128, 600.0, 2.0, 20, 0.0)]:
+        say("fields n_g=%d n_s=%d" % (n_g, n_s))
+        delta_gpu, delta64 = to_gpu(_field(n_g, box, 11))
+        plan = P.Plan(n_g, box, dk, n_s, rsd_beta=beta, precision=1)
+        plan.run(delta_gpu)
+        spec = fbe.spectrum(delta64, box, beta)
+        masks = fbe.shell_masks(n_g, dk, list(range(1, n_s + 1)))
+        scale = (box / n_g) ** 3 * n_g ** 1.5
+        for n in (1, n_s // 2, n_s):
+            ref = fbe.shell_field(spec, masks[n]) / scale
+            got = plan.field(n).cpu().numpy().astype(np.float64)
+            err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+            say("  shell %d max err / max %.3g" % (n, err))
+            assert err < 2e-6
+        plan.close()
+
+
+def test_kronecker_delta_gpu():
+    """delta = 1 at one voxel gives B = dV^3 / V in every bin (both precisions)."""
+    import torch
+    import paper_2107_14564_amd as P
+    n_g, box = 32, 300.0
+    d = np.zeros((n_g,) * 3, dtype=np.float32)
+    d[5, 17, 3] = 1.0
+    dv = (box / n_g) ** 3
+    for prec in (1, 0):
+        plan = P.Plan(n_g, box, 1.0, 10, precision=prec)
+        B = plan.run(torch.from_numpy(d).cuda()).cpu().numpy()
+        err = np.max(np.abs(B / (dv ** 3 / box ** 3) - 1))
+        say("kronecker prec=%d max rel err %.3g" % (prec, err))
+        assert err < 1e-5
+        plan.close()
+
+
+def test_deterministic_and_precision_switch():
+    import paper_2107_14564_amd as P
+    delta_gpu, _ = to_gpu(_field(64, 300.0, 5))
+    plan = P.Plan(64, 300.0, 1.0, 20, precision=0)
+    b1 = plan.run(delta_gpu).cpu().numpy()
+    b2 = plan.run(delta_gpu).cpu().numpy()
+    assert np.array_equal(b1, b2)
+    plan.set_precision(1)
+    b3 = plan.run(delta_gpu).cpu().numpy()
+    assert np.linalg.norm(b3 - b1) / np.linalg.norm(b1) < 1e-5
+    plan.close()
