@@ -1,0 +1,176 @@
+"""Throughput of the FFT bispectrum estimator on one MI355X.
+
+One step = one full pass of the estimator (forward R2C FFT, per-shell inverse
+FFTs, triple contraction, float64 normalisation) over the synthetic field of
+the workload, with the field already resident in HBM.
+
+Default workload: N_g = 512, L = 1500 Mpc, P(k) = k^-1.5, f_NG = 2, linear RSD
+beta = 0.5 along z, 100 shells of width one k_f, all 89 625 closable
+triangles, split-bf16 MFMA contraction.
+
+Prints one JSON line (rank 0): metric/value/unit, the per-stage times, the
+roofline of the dominant kernel (the contraction) measured with HIP events
+recorded by the library on the run stream, the plain-fp32 contraction time of
+the same plan, and the float64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (synth workload key, n_g, box_l, dk, n_shells, rsd_beta, selection)
+    "ng512_100shells_rsd": dict(field="ng512", n_g=512, box_l=1500.0, dk=1.0, n_shells=100, rsd_beta=0.5, sel={}),
+    "ng256_40shells_grid": dict(field="ng256", n_g=256, box_l=1000.0, dk=2.0, n_shells=40, rsd_beta=0.0,
+                                sel=dict(tri_mode=2, k1_shells=list(range(2, 41, 2)), n_mu=20, n_t=20)),
+    "ng32_10shells_grid": dict(field="ng32", n_g=32, box_l=300.0, dk=1.0, n_shells=10, rsd_beta=0.0,
+                               sel=dict(tri_mode=2, k1_shells=list(range(5, 11)), n_mu=10, n_t=10)),
+}
+
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense bf16 MFMA
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_baseline(delta32, w: dict, budget_s: float = 30.0) -> dict:
+    """The float64 oracle on a bounded sample of the same workload: all closable
+    triangles of the first S shells at the full grid (forward FFT, S data and S
+    unit shells, the triple sums, N_tri), S grown while the time stays small."""
+    import numpy as np
+
+    from oracle import fbe, geometry
+    cores = os.cpu_count() or 1
+    d64 = delta32.astype(np.float64)
+    s_shells = 4
+    tri = geometry.all_triangles(s_shells)
+    t0 = time.perf_counter()
+    fbe.estimate(d64, w["box_l"], w["dk"], tri, rsd_beta=w["rsd_beta"])
+    dt = time.perf_counter() - t0
+    return {"value": len(tri) / dt, "unit": "triangles/s", "cores": cores, "kind": "oracle",
+            "sample": "all %d closable triangles of shells 1-%d at N_g=%d (float64 FFTs, fields, triple sums, "
+                      "N_tri) in %.2f s" % (len(tri), s_shells, delta32.shape[0], dt),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ng512_100shells_rsd", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="splitbf16", choices=["splitbf16", "fp32"])
+    ap.add_argument("--no-fp32-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the estimator would shard "
+              "voxel slabs; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2107_14564_amd as P
+    from synth import workload_field
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    delta32 = np.ascontiguousarray(workload_field(w["field"]), dtype=np.float32)
+    gen_s = time.perf_counter() - t0
+    print("field ready (%.1f s)" % gen_s, file=sys.stderr, flush=True)
+    delta = torch.from_numpy(delta32).to(dev)
+    prec = P.PREC_SPLITBF16 if args.precision == "splitbf16" else P.PREC_FP32
+    t0 = time.perf_counter()
+    plan = P.Plan(w["n_g"], w["box_l"], w["dk"], w["n_shells"], rsd_beta=w["rsd_beta"], precision=prec,
+                  flags=P.FLAG_STAGE_TIMING, **w["sel"])
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    print("plan ready (%.1f s), %d triangles" % (plan_s, plan.n_tri), file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        plan.run(delta)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stages = np.zeros(4)
+    step_ms = []
+    for k in range(args.steps):
+        start.record(stream)
+        B = plan.run(delta)
+        stop.record(stream)
+        stop.synchronize()
+        step_ms.append(start.elapsed_time(stop))
+        stages += np.array(plan.stage_times())
+        print("step %d: %.3f ms" % (k, step_ms[-1]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    stages /= args.steps
+    ms = float(np.mean(step_ms))
+    b_host = B.cpu().numpy()
+    assert np.all(np.isfinite(b_host)), "non-finite B"
+
+    n = w["n_g"]
+    n_vox = float(n) ** 3
+    tri = plan.triangles.numpy()
+    n_pairs = len({(int(a), int(b)) for a, b, _ in tri})
+    # algorithmic work of the contraction: 2 N^3 flop per triangle + N^3 per distinct shell pair product
+    flop = n_vox * (2.0 * plan.n_tri + n_pairs)
+    contract_ms = float(stages[2])
+    achieved = flop / (contract_ms * 1e-3) / 1e12
+    result = {
+        "metric": "triangles/s",
+        "value": plan.n_tri / (ms * 1e-3),
+        "unit": "triangles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3-fp32acc" if prec == P.PREC_SPLITBF16 else "fp32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_g": n, "box_l": w["box_l"], "n_shells": w["n_shells"],
+                   "dk_kf": w["dk"], "rsd_beta": w["rsd_beta"], "n_tri": plan.n_tri, "precision": args.precision},
+        "stages_ms": {"forward_fft": stages[0], "shell_ffts": stages[1], "contraction": stages[2],
+                      "normalise": stages[3]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "kernel": "k_contract_bf16x3" if prec == P.PREC_SPLITBF16 else "k_contract_vec<float>",
+                     "algorithmic_flop": flop},
+        "fft_hbm": {"algorithmic_bytes": (8.0 * n_vox + 4.0 * n_vox * w["n_shells"]),
+                    "achieved_GBs": (8.0 * n_vox + 4.0 * n_vox * w["n_shells"]) / ((stages[0] + stages[1]) * 1e-3) / 1e9,
+                    "peak_GBs": PEAK_HBM_GBS},
+        "plan_s": plan_s,
+    }
+    result["fft_hbm"]["frac"] = result["fft_hbm"]["achieved_GBs"] / PEAK_HBM_GBS
+    if not args.no_fp32_compare and prec == P.PREC_SPLITBF16:
+        plan.set_precision(P.PREC_FP32)
+        plan.run(delta)
+        torch.cuda.synchronize()
+        f32 = []
+        for _ in range(max(2, min(3, args.steps))):
+            plan.run(delta)
+            torch.cuda.synchronize()
+            f32.append(plan.stage_times()[2])
+        b32 = plan.run(delta).cpu().numpy()
+        plan.set_precision(prec)
+        result["fp32_contraction_ms"] = float(np.mean(f32))
+        result["speedup_vs_fp32_contraction"] = float(np.mean(f32)) / contract_ms
+        result["splitbf16_vs_fp32_norm_diff"] = float(np.linalg.norm(b_host - b32) / np.linalg.norm(b32))
+    if not args.no_cpu_baseline:
+        print("cpu baseline ...", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(delta32, w)
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,7 +85,8 @@ struct bispec_plan_s {
   bispec_config cfg{};
   ShellGeometry geo;
   Selection sel;
-  TilePlan tiles;
+  TilePlan tiles;        // tasks of <= kMaxTilesPerTask tiles (vector kernels)
+  TilePlan tiles_mfma;   // same tiles, tasks of <= kMaxTilesPerTaskMfma (MFMA kernel)
   ShellPassPlan pass32;
   Sizes sz;
   std::vector<int64_t> ntri;
@@ -94,7 +95,8 @@ struct bispec_plan_s {
   bool ran = false;
   int device = 0;
   // device memory
-  DevBuf spec, F, a1, a2, partial, norm, tri_index, rows, tile_list, task_off, shells, x_tiles, y_off, z_off, tw32;
+  DevBuf spec, F, a1, a2, partial, norm, tri_index, rows, tile_list, task_off, task_off_mfma, shells, x_tiles, y_off,
+      z_off, tw32;
   DevBuf G;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   ~bispec_plan_s() {
@@ -118,7 +120,8 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
     return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 112");
   st = select_triangles(*cfg, p.geo, p.sel, err);
   if (st) return set_err(st, err);
-  build_tiles(p.sel, p.tiles);
+  build_tiles(p.sel, kMaxTilesPerTask, p.tiles);
+  build_tiles(p.sel, kMaxTilesPerTaskMfma, p.tiles_mfma);
   plan_shell_passes(p.geo, false, p.pass32);
   const long long n = p.geo.n_g;
   Sizes& s = p.sz;
@@ -135,8 +138,9 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   s.a2_64 = (size_t)p64.a2_elems * sizeof(double2);
   s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 : 0;
   const long long ntasks = (long long)p.tiles.task_off.size() - 1;
+  const long long ntasks_mfma = (long long)p.tiles_mfma.task_off.size() - 1;
   p.n_krange_vec = n_krange_for(ntasks, s.n_vox);
-  p.n_krange_mfma = n_krange_for((ntasks + 3) / 4, s.n_vox);
+  p.n_krange_mfma = n_krange_for((ntasks_mfma + 3) / 4, s.n_vox);
   s.partial_run = (size_t)std::max(p.n_krange_vec, p.n_krange_mfma) * s.n_tri * sizeof(double);
   s.partial_plan = (size_t)p.n_krange_vec * s.n_tri * sizeof(double);
   s.tables = (size_t)p.geo.n_s * p.geo.n_s * p.geo.n_s * sizeof(int32_t) + p.tiles.rows.size() * sizeof(RowBlock) +
@@ -146,12 +150,12 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   return BISPEC_OK;
 }
 
-ContractArgs contract_args(bispec_plan_s& p, int n_krange) {
+ContractArgs contract_args(bispec_plan_s& p, int n_krange, bool mfma) {
   ContractArgs a;
   a.rows = p.rows.as<RowBlock>();
   a.tiles = p.tile_list.as<Tile>();
-  a.task_off = p.task_off.as<int32_t>();
-  a.n_tasks = (int)p.tiles.task_off.size() - 1;
+  a.task_off = mfma ? p.task_off_mfma.as<int32_t>() : p.task_off.as<int32_t>();
+  a.n_tasks = (int)(mfma ? p.tiles_mfma.task_off.size() : p.tiles.task_off.size()) - 1;
   a.tri_index = p.tri_index.as<int32_t>();
   a.n_s = p.geo.n_s;
   a.n_vox = p.sz.n_vox;
@@ -205,7 +209,7 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
                              tw.as<double2>(), st));
   a1.release();
   a2.release();
-  ContractArgs ca = contract_args(p, p.n_krange_vec);
+  ContractArgs ca = contract_args(p, p.n_krange_vec, false);
   HIP_TRY(launch_contract_fp64(I.as<double>(), ca, st));
   DevBuf sums;
   HIP_TRY(dalloc(sums, (size_t)p.sz.n_tri * sizeof(double)));
@@ -329,6 +333,7 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
   PLAN_HIP(upload(p->rows, p->tiles.rows, s));
   PLAN_HIP(upload(p->tile_list, p->tiles.tiles, s));
   PLAN_HIP(upload(p->task_off, p->tiles.task_off, s));
+  PLAN_HIP(upload(p->task_off_mfma, p->tiles_mfma.task_off, s));
   PLAN_HIP(dalloc(p->partial, p->sz.partial_run));
   // N_tri first (largest memory phase), then the run workspace
   st = compute_ntri(*p, s);
@@ -412,10 +417,10 @@ int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream)
   int nk;
   if (p->precision == BISPEC_PREC_FP32) {
     nk = p->n_krange_vec;
-    HIP_TRY(launch_contract_fp32(p->F.as<float>(), contract_args(*p, nk), s));
+    HIP_TRY(launch_contract_fp32(p->F.as<float>(), contract_args(*p, nk, false), s));
   } else {
     nk = p->n_krange_mfma;
-    HIP_TRY(launch_contract_bf16x3(p->F.as<float>(), contract_args(*p, nk), s));
+    HIP_TRY(launch_contract_bf16x3(p->F.as<float>(), contract_args(*p, nk, true), s));
   }
   if (timing) HIP_TRY(hipEventRecord(p->ev[3], s));
   HIP_TRY(launch_reduce(p->partial.as<double>(), nk, p->sz.n_tri, p->norm.as<double>(), B, s));

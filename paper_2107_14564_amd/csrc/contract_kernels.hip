@@ -41,6 +41,10 @@ __device__ __forceinline__ long long range_lo(long long n_vox, int n_krange, int
 // One work group = one task (<= 8 tiles).  Thread t: tile t/32; within the
 // tile, rows 4*((t%32)/4) .. +3 and columns 8*(t%4) .. +7 (32 sums per thread).
 // LDS chunk: [Kc][n_s + 1] (shell-contiguous per voxel, one zero shell last).
+// Sums run in T over one chunk (<= 256 voxels) and are then added into float64
+// totals: a long float32 chain would carry rounding error proportional to its
+// running partial sum, which for shells of box-scale wavelength is far larger
+// than the final (cancelling) total.
 // ============================================================================
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__ F, ContractArgs a, int kc) {
@@ -71,11 +75,14 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
     const int l = tile.col0 + 8 * cq + c;
     cl[c] = (l >= 1 && l <= ns) ? l - 1 : ns;
   }
+  // float32: per-chunk sums in acc, flushed into tot; float64: tot directly
+  constexpr bool kF32 = sizeof(T) == 4;
   T acc[4][8];
+  double tot[4][8];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[u][c] = (T)0;
+    for (int c = 0; c < 8; ++c) tot[u][c] = 0.0;
 
   const long long k_lo = range_lo(a.n_vox, a.n_krange, kr), k_hi = range_lo(a.n_vox, a.n_krange, kr + 1);
   // zero shell column
@@ -89,6 +96,12 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
     }
     __syncthreads();
     if (!active) continue;
+    if constexpr (kF32) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[u][c] = (T)0;
+    }
     for (int x = 0; x < len; ++x) {
       const T* row = chunk + x * ls;
       T p[4], f[8];
@@ -99,7 +112,18 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[u][c] = fma(p[u], f[c], acc[u][c]);
+        for (int c = 0; c < 8; ++c) {
+          if constexpr (kF32)
+            acc[u][c] = fma(p[u], f[c], acc[u][c]);
+          else
+            tot[u][c] = fma((double)p[u], (double)f[c], tot[u][c]);
+        }
+    }
+    if constexpr (kF32) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) tot[u][c] += (double)acc[u][c];
     }
   }
   if (!active) return;
@@ -114,7 +138,7 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
       const int l = tile.col0 + 8 * cq + c;
       if (l < 1 || l > j) continue;
       const int t = a.tri_index[((long long)(i - 1) * ns + (j - 1)) * ns + (l - 1)];
-      if (t >= 0) out[t] = (double)acc[u][c];
+      if (t >= 0) out[t] = tot[u][c];
     }
   }
 }
@@ -138,6 +162,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kKc = 64;
 constexpr int kFfStride = kKc + 4;   // floats
 constexpr int kBStride = kKc + 8;    // bf16
+constexpr int kFlush = 16;           // chunks (1024 voxels) per float32 accumulation chain
+constexpr int kMT = kMaxTilesPerTaskMfma;
 
 // Output element v (0..15) of lane `lane` of a 32x32 MFMA accumulator sits
 // at row mfma_row(v, lane), column lane % 32.
@@ -167,13 +193,13 @@ __global__ void __launch_bounds__(kThreads) k_contract_bf16x3(const float* __res
   const bool active = task < a.n_tasks;
   const int t0 = active ? a.task_off[task] : 0;
   const int t1 = active ? a.task_off[task + 1] : 0;
-  const int nt = t1 - t0;  // <= kMaxTilesPerTask
+  const int nt = t1 - t0;  // <= kMT
 
   // per tile: this lane's row (pair) and column indices into the chunk
-  int rowi[kMaxTilesPerTask], rowj[kMaxTilesPerTask], col[kMaxTilesPerTask], rbk[kMaxTilesPerTask];
+  int rowi[kMT], rowj[kMT], col[kMT], rbk[kMT];
   const int r = lane & 31, kg = lane >> 5;
 #pragma unroll
-  for (int k = 0; k < kMaxTilesPerTask; ++k) {
+  for (int k = 0; k < kMT; ++k) {
     rowi[k] = ns;
     rowj[k] = ns;
     col[k] = ns;
@@ -187,11 +213,16 @@ __global__ void __launch_bounds__(kThreads) k_contract_bf16x3(const float* __res
       if (l >= 1 && l <= ns) col[k] = l - 1;
     }
   }
-  f32x16 acc[kMaxTilesPerTask];
+  f32x16 acc[kMT];
+  double tot[kMT][16];
 #pragma unroll
-  for (int k = 0; k < kMaxTilesPerTask; ++k)
+  for (int k = 0; k < kMT; ++k)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[k][v] = 0.f;
+    for (int v = 0; v < 16; ++v) {
+      acc[k][v] = 0.f;
+      tot[k][v] = 0.0;
+    }
+  int chain = 0;
 
   // zero shell rows
   for (int e = threadIdx.x; e < kFfStride; e += kThreads) Ff[ns * kFfStride + e] = 0.f;
@@ -231,7 +262,7 @@ __global__ void __launch_bounds__(kThreads) k_contract_bf16x3(const float* __res
       int prev_rb = -1;  // wave-uniform: tiles of one row block share the row operand
       bf16x8 ahi, alo;
 #pragma unroll
-      for (int k = 0; k < kMaxTilesPerTask; ++k) {
+      for (int k = 0; k < kMT; ++k) {
         if (k >= nt) break;
         if (rbk[k] != prev_rb) {
           const float* fi = Ff + rowi[k] * kFfStride + off;
@@ -250,11 +281,21 @@ __global__ void __launch_bounds__(kThreads) k_contract_bf16x3(const float* __res
         acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, acc[k], 0, 0, 0);
       }
     }
+    if (++chain == kFlush || x0 + kKc >= k_hi) {
+      chain = 0;
+#pragma unroll
+      for (int k = 0; k < kMT; ++k)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          tot[k][v] += (double)acc[k][v];
+          acc[k][v] = 0.f;
+        }
+    }
   }
   if (!active) return;
   double* out = a.partial + (long long)kr * a.n_tri;
 #pragma unroll
-  for (int k = 0; k < kMaxTilesPerTask; ++k) {
+  for (int k = 0; k < kMT; ++k) {
     if (k >= nt) break;
     const Tile tl = a.tiles[t0 + k];
     const int l = tl.col0 + (lane & 31);
@@ -264,7 +305,7 @@ __global__ void __launch_bounds__(kThreads) k_contract_bf16x3(const float* __res
       const int i = a.rows[tl.rb].i[row], j = a.rows[tl.rb].j[row];
       if (j <= 0 || l < 1 || l > j) continue;
       const int t = a.tri_index[((long long)(i - 1) * ns + (j - 1)) * ns + (l - 1)];
-      if (t >= 0) out[t] = (double)acc[k][v];
+      if (t >= 0) out[t] = tot[k][v];
     }
   }
 }

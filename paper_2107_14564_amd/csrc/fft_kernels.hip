@@ -248,12 +248,12 @@ __global__ void __launch_bounds__(NT) k_c2r_z(const V2<T>* __restrict__ a2, OutT
   }
   __syncthreads();
   lds_fft<T, FftCfg<T>::E, NT>(buf, s, lines, 1, ls, false, tw, (T)1);
-  OutT* dst = out + (long long)sn * field_stride + line0 * n;
+  // (x_{2q}, x_{2q+1}) = (Re z_q, Im z_q): one paired store per output slot
+  V2<OutT>* dst = reinterpret_cast<V2<OutT>*>(out + (long long)sn * field_stride + line0 * n);
   for (int e = threadIdx.x; e < lines * m; e += NT) {
     const int c = e / m, q = e % m;
     const V2<T> z = buf[c * ls + q];
-    dst[(long long)c * n + 2 * q] = (OutT)z.x;
-    dst[(long long)c * n + 2 * q + 1] = (OutT)z.y;
+    dst[(long long)c * m + q] = mk<OutT>((OutT)z.x, (OutT)z.y);
   }
 }
 

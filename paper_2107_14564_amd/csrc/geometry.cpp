@@ -177,7 +177,7 @@ int select_triangles(const bispec_config& c, const ShellGeometry& g, Selection& 
   return BISPEC_OK;
 }
 
-void build_tiles(const Selection& s, TilePlan& tp) {
+void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp) {
   // pairs (i, j) with their selected l values
   std::map<std::pair<int, int>, std::vector<int>> pl;
   for (const Tri& t : s.tri) pl[{t.a1, t.a2}].push_back(t.a3);
@@ -227,17 +227,17 @@ void build_tiles(const Selection& s, TilePlan& tp) {
     }
     per_rb.push_back(ts);
   }
-  // tasks: consecutive row blocks; a row block with more than kMaxTilesPerTask
+  // tasks: consecutive row blocks; a row block with more than max_tiles_per_task
   // tiles is split across tasks (its products are then formed once per task)
   tp.task_off.push_back(0);
   int in_task = 0;
   for (auto& ts : per_rb) {
-    if (in_task > 0 && in_task + (int)ts.size() > kMaxTilesPerTask) {
+    if (in_task > 0 && in_task + (int)ts.size() > max_tiles_per_task) {
       tp.task_off.push_back((int32_t)tp.tiles.size());
       in_task = 0;
     }
     for (auto& t : ts) {
-      if (in_task == kMaxTilesPerTask) {
+      if (in_task == max_tiles_per_task) {
         tp.task_off.push_back((int32_t)tp.tiles.size());
         in_task = 0;
       }

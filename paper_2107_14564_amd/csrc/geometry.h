@@ -61,11 +61,13 @@ struct Tile {
   int32_t col0;   // first column shell (1-based)
 };
 
-// A task is at most kMaxTilesPerTask tiles handled together over a voxel
-// range (by one wavefront in the MFMA kernel, one work group in the vector
-// kernel); a row block's tiles stay in one task so its pair products are
-// formed once.
+// A task is a few tiles handled together over a voxel range: at most
+// kMaxTilesPerTask (8) by one work group of the vector kernel, at most
+// kMaxTilesPerTaskMfma (4) by one wavefront of the MFMA kernel (its fp32
+// accumulators need float64 shadows).  A row block's tiles stay in one task
+// when they fit, so its pair products are formed once.
 constexpr int kMaxTilesPerTask = 8;
+constexpr int kMaxTilesPerTaskMfma = 4;
 
 struct TilePlan {
   std::vector<RowBlock> rows;
@@ -75,6 +77,6 @@ struct TilePlan {
   int64_t slots = 0;             // tiles * kRows * kCols
 };
 
-void build_tiles(const Selection& s, TilePlan& tp);
+void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp);
 
 }  // namespace bispec

@@ -61,7 +61,7 @@ hipError_t launch_unit_shells(double2* a1, double2* a2, double* I, long long fie
 struct ContractArgs {
   const RowBlock* rows = nullptr;   // device
   const Tile* tiles = nullptr;      // device, task-major
-  const int32_t* task_off = nullptr;  // device [n_tasks + 1]
+  const int32_t* task_off = nullptr;  // device [n_tasks + 1] (task grouping of the kernel launched)
   int n_tasks = 0;
   const int32_t* tri_index = nullptr; // device [n_s^3]: (i-1, j-1, l-1) -> triangle or -1
   int n_s = 0;

@@ -89,19 +89,25 @@ def test_fields_match_oracle():
 
 
 def test_kronecker_delta_gpu():
-    """delta = 1 at one voxel gives B = dV^3 / V in every bin (both precisions)."""
+    """delta = 1 at one voxel gives B = dV^3 / V in every bin (both precisions):
+    conditioned error <= 1e-5 against that closed form, and per bin within
+    1e-5 (fp32) / 5e-5 (split-bf16: each D_n carries cancellation, so the
+    per-bin error is the summation scale times ~2^-17)."""
     import torch
     import paper_2107_14564_amd as P
     n_g, box = 32, 300.0
     d = np.zeros((n_g,) * 3, dtype=np.float32)
     d[5, 17, 3] = 1.0
     dv = (box / n_g) ** 3
-    for prec in (1, 0):
+    exact = dv ** 3 / box ** 3
+    for prec, strict in ((1, 1e-5), (0, 5e-5)):
         plan = P.Plan(n_g, box, 1.0, 10, precision=prec)
         B = plan.run(torch.from_numpy(d).cuda()).cpu().numpy()
-        err = np.max(np.abs(B / (dv ** 3 / box ** 3) - 1))
-        say("kronecker prec=%d max rel err %.3g" % (prec, err))
-        assert err < 1e-5
+        S = fbe.estimate(d.astype(np.float64), box, 1.0, plan.triangles.numpy(), with_abs=True)["S"]
+        err = np.max(np.abs(B / exact - 1))
+        cond = np.max(np.abs(B - exact) / S)
+        say("kronecker prec=%d max rel err %.3g cond %.3g" % (prec, err, cond))
+        assert cond < 1e-5 and err < strict
         plan.close()
 
 
