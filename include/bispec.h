@@ -84,7 +84,7 @@ enum bispec_flags {
 };
 
 typedef struct bispec_config {
-  int32_t n_g;            /* grid points per side: even, 8..1024, factors 2,3,5     */
+  int32_t n_g;            /* grid points per side: 2^a, 3*2^a or 5*2^a, 2^a >= 8, <= 1024 */
   int32_t n_shells;       /* shells 1..n_shells                                     */
   double box_l;           /* box side L (> 0); k in units of 1/L's unit             */
   double dk;              /* shell width w in units of k_f (w >= 1)                  */

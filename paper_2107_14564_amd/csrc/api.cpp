@@ -59,6 +59,15 @@ template <typename T> hipError_t upload(DevBuf& b, const std::vector<T>& v, hipS
   return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
 }
 
+// voxel ranges of the MFMA kernel: about 1024 work groups overall, a multiple
+// of 8 (all work groups of a range on one XCD)
+int n_krange_mfma_for(long long groups, long long n_vox) {
+  long long k = (1024 + groups - 1) / groups;
+  k = ((k + 7) / 8) * 8;
+  const long long cap = std::max(8LL, (n_vox / 64) / 8 * 8);
+  return (int)std::min(std::max(k, 8LL), cap);
+}
+
 int n_krange_for(long long groups, long long n_vox) {
   long long k = (1024 + groups - 1) / groups;
   k = ((k + 7) / 8) * 8;
@@ -72,7 +81,7 @@ struct Sizes {
   long long n_vox = 0, n_tri = 0;
   size_t spec = 0, fields32 = 0, a1_32 = 0, a2_32 = 0, fields64 = 0, a1_64 = 0, a2_64 = 0, grad = 0;
   size_t tables = 0, partial_run = 0, partial_plan = 0;
-  size_t run_total() const { return spec + fields32 + a1_32 + a2_32 + grad + tables + partial_run; }
+  size_t run_total() const { return spec + 2 * fields32 + a1_32 + a2_32 + grad + tables + partial_run; }
   size_t plan_peak() const {
     size_t p1 = fields64 + a1_64 + a2_64 + tables + partial_plan;
     return std::max(p1, run_total());
@@ -86,7 +95,7 @@ struct bispec_plan_s {
   ShellGeometry geo;
   Selection sel;
   TilePlan tiles;        // tasks of <= kMaxTilesPerTask tiles (vector kernels)
-  TilePlan tiles_mfma;   // same tiles, tasks of <= kMaxTilesPerTaskMfma (MFMA kernel)
+  MfmaTiling mfma;       // span-grouped row blocks (MFMA kernel)
   ShellPassPlan pass32;
   Sizes sz;
   std::vector<int64_t> ntri;
@@ -95,8 +104,9 @@ struct bispec_plan_s {
   bool ran = false;
   int device = 0;
   // device memory
-  DevBuf spec, F, a1, a2, partial, norm, tri_index, rows, tile_list, task_off, task_off_mfma, shells, x_tiles, y_off,
-      z_off, tw32;
+  DevBuf spec, F, a1, a2, partial, norm, tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols, shells, x_tiles,
+      y_off, z_off, tw32;
+  DevBuf Fh, Fl;   // bf16 hi/lo planes of F (column operands of the split-bf16 contraction)
   DevBuf G;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   ~bispec_plan_s() {
@@ -116,46 +126,61 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   int st = build_shells(*cfg, p.geo, err);
   if (st) return set_err(st, err);
   if (p.geo.n_s > 256) return set_err(BISPEC_EINVAL, "n_shells > 256 is not supported by the contraction kernels");
-  if (cfg->precision == BISPEC_PREC_SPLITBF16 && p.geo.n_s > 112)
-    return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 112");
+  if (cfg->precision == BISPEC_PREC_SPLITBF16 && p.geo.n_s > kCols * kMaxColTiles)
+    return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 128");
   st = select_triangles(*cfg, p.geo, p.sel, err);
   if (st) return set_err(st, err);
   build_tiles(p.sel, kMaxTilesPerTask, p.tiles);
-  build_tiles(p.sel, kMaxTilesPerTaskMfma, p.tiles_mfma);
+  build_mfma_tiles(p.sel, p.mfma);
   plan_shell_passes(p.geo, false, p.pass32);
   const long long n = p.geo.n_g;
   Sizes& s = p.sz;
   s.n_vox = n * n * n;
   s.n_tri = (long long)p.sel.tri.size();
   s.spec = (size_t)n * n * (n / 2 + 1) * sizeof(float2);
-  s.fields32 = (size_t)p.geo.n_s * s.n_vox * sizeof(float);
+  s.fields32 = (size_t)blocked_elems(s.n_vox, p.geo.n_s) * sizeof(float);
   s.a1_32 = (size_t)p.pass32.a1_elems * sizeof(float2);
   s.a2_32 = (size_t)p.pass32.a2_elems * sizeof(float2);
   ShellPassPlan p64;
   plan_shell_passes(p.geo, true, p64);
-  s.fields64 = (size_t)p.geo.n_s * s.n_vox * sizeof(double);
+  s.fields64 = (size_t)blocked_elems(s.n_vox, p.geo.n_s) * sizeof(double);
   s.a1_64 = (size_t)p64.a1_elems * sizeof(double2);
   s.a2_64 = (size_t)p64.a2_elems * sizeof(double2);
   s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 : 0;
   const long long ntasks = (long long)p.tiles.task_off.size() - 1;
-  const long long ntasks_mfma = (long long)p.tiles_mfma.task_off.size() - 1;
+  const long long n_wg_mfma = (long long)p.mfma.rows.size() / kRbPerWg;
   p.n_krange_vec = n_krange_for(ntasks, s.n_vox);
-  p.n_krange_mfma = n_krange_for((ntasks_mfma + 3) / 4, s.n_vox);
+  p.n_krange_mfma = n_krange_mfma_for(n_wg_mfma, s.n_vox);
   s.partial_run = (size_t)std::max(p.n_krange_vec, p.n_krange_mfma) * s.n_tri * sizeof(double);
   s.partial_plan = (size_t)p.n_krange_vec * s.n_tri * sizeof(double);
   s.tables = (size_t)p.geo.n_s * p.geo.n_s * p.geo.n_s * sizeof(int32_t) + p.tiles.rows.size() * sizeof(RowBlock) +
-             p.tiles.tiles.size() * sizeof(Tile) + p.pass32.x_tiles.size() * sizeof(int4) + (size_t)s.n_tri * 8 +
+             p.tiles.tiles.size() * sizeof(Tile) + p.mfma.rows.size() * (sizeof(RowBlock) + sizeof(RbCols)) +
+             p.pass32.x_tiles.size() * sizeof(int4) + (size_t)s.n_tri * 8 +
              (size_t)n * 16 + 4096 * 4;
   p.precision = cfg->precision;
   return BISPEC_OK;
 }
 
-ContractArgs contract_args(bispec_plan_s& p, int n_krange, bool mfma) {
+WsArgs ws_args(bispec_plan_s& p) {
+  WsArgs a;
+  a.rows = p.mfma_rows.as<RowBlock>();
+  a.cols = p.mfma_cols.as<RbCols>();
+  a.n_wg = (int)(p.mfma.rows.size() / kRbPerWg);
+  a.tri_index = p.tri_index.as<int32_t>();
+  a.n_s = p.geo.n_s;
+  a.n_vox = p.sz.n_vox;
+  a.n_krange = p.n_krange_mfma;
+  a.partial = p.partial.as<double>();
+  a.n_tri = p.sz.n_tri;
+  return a;
+}
+
+ContractArgs contract_args(bispec_plan_s& p, int n_krange) {
   ContractArgs a;
   a.rows = p.rows.as<RowBlock>();
   a.tiles = p.tile_list.as<Tile>();
-  a.task_off = mfma ? p.task_off_mfma.as<int32_t>() : p.task_off.as<int32_t>();
-  a.n_tasks = (int)(mfma ? p.tiles_mfma.task_off.size() : p.tiles.task_off.size()) - 1;
+  a.task_off = p.task_off.as<int32_t>();
+  a.n_tasks = (int)p.tiles.task_off.size() - 1;
   a.tri_index = p.tri_index.as<int32_t>();
   a.n_s = p.geo.n_s;
   a.n_vox = p.sz.n_vox;
@@ -205,11 +230,10 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
   }
   HIP_TRY(upload(tw, t64, st));
   ShellLaunch L = shell_launch(pp, shells, xt, yo, zo, p.geo.n_s);
-  HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), p.sz.n_vox, L, n,
-                             tw.as<double2>(), st));
+  HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), L, n, tw.as<double2>(), st));
   a1.release();
   a2.release();
-  ContractArgs ca = contract_args(p, p.n_krange_vec, false);
+  ContractArgs ca = contract_args(p, p.n_krange_vec);
   HIP_TRY(launch_contract_fp64(I.as<double>(), ca, st));
   DevBuf sums;
   HIP_TRY(dalloc(sums, (size_t)p.sz.n_tri * sizeof(double)));
@@ -333,7 +357,8 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
   PLAN_HIP(upload(p->rows, p->tiles.rows, s));
   PLAN_HIP(upload(p->tile_list, p->tiles.tiles, s));
   PLAN_HIP(upload(p->task_off, p->tiles.task_off, s));
-  PLAN_HIP(upload(p->task_off_mfma, p->tiles_mfma.task_off, s));
+  PLAN_HIP(upload(p->mfma_rows, p->mfma.rows, s));
+  PLAN_HIP(upload(p->mfma_cols, p->mfma.cols, s));
   PLAN_HIP(dalloc(p->partial, p->sz.partial_run));
   // N_tri first (largest memory phase), then the run workspace
   st = compute_ntri(*p, s);
@@ -362,6 +387,8 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
   PLAN_HIP(dalloc(p->a1, p->sz.a1_32));
   PLAN_HIP(dalloc(p->a2, p->sz.a2_32));
   PLAN_HIP(dalloc(p->F, p->sz.fields32));
+  PLAN_HIP(dalloc(p->Fh, p->sz.fields32 / 2));
+  PLAN_HIP(dalloc(p->Fl, p->sz.fields32 / 2));
   if (p->cfg.flags & BISPEC_FLAG_GRAD) PLAN_HIP(dalloc(p->G, p->sz.grad));
   if (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING)
     for (auto& e : p->ev) PLAN_HIP(hipEventCreate(&e));
@@ -396,8 +423,8 @@ int bispec_set_precision(bispec_plan_t p, int32_t precision) {
   if (!p) return set_err(BISPEC_EINVAL, "null plan");
   if (precision != BISPEC_PREC_SPLITBF16 && precision != BISPEC_PREC_FP32)
     return set_err(BISPEC_EINVAL, "unknown precision");
-  if (precision == BISPEC_PREC_SPLITBF16 && p->geo.n_s > 112)
-    return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 112");
+  if (precision == BISPEC_PREC_SPLITBF16 && p->geo.n_s > kCols * kMaxColTiles)
+    return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 128");
   p->precision = precision;
   return BISPEC_OK;
 }
@@ -411,16 +438,18 @@ int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream)
   HIP_TRY(launch_forward(delta, p->spec.as<float2>(), n, (float)p->geo.beta, p->tw32.as<float2>(), s));
   if (timing) HIP_TRY(hipEventRecord(p->ev[1], s));
   ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s);
-  HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), p->F.as<float>(),
-                             p->sz.n_vox, L, n, p->tw32.as<float2>(), s));
+  const bool split = p->precision == BISPEC_PREC_SPLITBF16;
+  HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), p->F.as<float>(), L, n,
+                             p->tw32.as<float2>(), split ? p->Fh.as<__bf16>() : nullptr,
+                             split ? p->Fl.as<__bf16>() : nullptr, s));
   if (timing) HIP_TRY(hipEventRecord(p->ev[2], s));
   int nk;
   if (p->precision == BISPEC_PREC_FP32) {
     nk = p->n_krange_vec;
-    HIP_TRY(launch_contract_fp32(p->F.as<float>(), contract_args(*p, nk, false), s));
+    HIP_TRY(launch_contract_fp32(p->F.as<float>(), contract_args(*p, nk), s));
   } else {
     nk = p->n_krange_mfma;
-    HIP_TRY(launch_contract_bf16x3(p->F.as<float>(), contract_args(*p, nk, true), s));
+    HIP_TRY(launch_contract_bf16x3(p->F.as<float>(), p->Fh.as<__bf16>(), p->Fl.as<__bf16>(), ws_args(*p), s));
   }
   if (timing) HIP_TRY(hipEventRecord(p->ev[3], s));
   HIP_TRY(launch_reduce(p->partial.as<double>(), nk, p->sz.n_tri, p->norm.as<double>(), B, s));
@@ -449,8 +478,7 @@ int bispec_copy_field(bispec_plan_t p, int32_t shell, float* dst, void* hip_stre
   if (!p || !dst) return set_err(BISPEC_EINVAL, "null argument");
   if (shell < 1 || shell > p->geo.n_s) return set_err(BISPEC_EINVAL, "shell out of range");
   if (!p->ran) return set_err(BISPEC_ESTATE, "no run recorded");
-  HIP_TRY(hipMemcpyAsync(dst, p->F.as<float>() + (size_t)(shell - 1) * p->sz.n_vox, p->sz.n_vox * sizeof(float),
-                         hipMemcpyDeviceToDevice, (hipStream_t)hip_stream));
+  HIP_TRY(launch_unblock(p->F.as<float>(), shell - 1, p->geo.n_s, p->sz.n_vox, dst, (hipStream_t)hip_stream));
   return BISPEC_OK;
 }
 

@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
     __syncthreads();
     for (int e = threadIdx.x; e < ns * kc; e += kThreads) {
       const int s = e / kc, x = e % kc;
-      chunk[x * ls + s] = x < len ? F[(long long)s * a.n_vox + x0 + x] : (T)0;
+      chunk[x * ls + s] = x < len ? F[vox_index(x0 + x, s, ns)] : (T)0;
     }
     __syncthreads();
     if (!active) continue;
@@ -145,29 +145,52 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 
 // ============================================================================
 // Split-BF16 MFMA form (step c).  Each fp32 operand v is written as
-// v = hi + lo with hi = bf16(v), lo = bf16(v - hi); the product of two
-// operands is accumulated as hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-16
-// relative, is dropped) by three v_mfma_f32_32x32x16_bf16 per 16 voxels.
-// Row operand: the pair product F_i F_j formed in fp32 then split; column
-// operand: F_l split once per chunk into LDS.
+// v = hi + lo with hi = bf16(v), lo = bf16(v - hi); a product of two operands
+// is accumulated as hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-16 relative, is
+// dropped) by three v_mfma_f32_32x32x16_bf16 per 16 voxels.  The row operand
+// is the pair product F_i F_j formed in fp32 and then split; the column
+// operand is F_l split.
 //
-// One work group = 4 wavefronts = up to 4 tasks; wavefront w runs task 4g + w.
-// LDS chunk (Kc = 64 voxels): Ff [n_s + 1][Kc + 4] fp32, Bh/Bl [n_s + 1][Kc + 8]
-// bf16 (row n_s is the zero shell; the pads stagger rows across banks).
+// Work group = 8 wavefronts (512 threads), one per SIMD pair:
+//   consumers (waves 0-3): wave w owns row block 4q + w of the work group and
+//     its <= 4 column tiles; it only reads operand fragments from LDS and
+//     issues MFMAs (fp32 accumulators, added into float64 every kFlush chunks);
+//   producers (waves 4-7): copy F (fp32) of chunk c+2 and the column planes
+//     (bf16 hi/lo written by the C2R pass) of chunk c+1 from registers loaded
+//     two chunks earlier, and form + split the pair products of chunk c+1.
+// LDS holds two buffers of everything (one barrier per chunk):
+//   F32 [2][n_s + 1][kC2 + 4] fp32     (row n_s = zero shell)
+//   Bh, Bl [2][n_s + 1][kC2 + 8] bf16
+//   Ah, Al [2][kRbPerWg][32][kC2 + 8] bf16
 // ============================================================================
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kKc = 64;
-constexpr int kFfStride = kKc + 4;   // floats
-constexpr int kBStride = kKc + 8;    // bf16
-constexpr int kFlush = 16;           // chunks (1024 voxels) per float32 accumulation chain
-constexpr int kMT = kMaxTilesPerTaskMfma;
+constexpr int kC2 = 32;              // voxels per chunk
+constexpr int kF32S = kC2 + 4;       // fp32 row stride (floats)
+constexpr int kBS = kC2 + 8;         // bf16 row stride (elements)
+constexpr int kFlush = 32;           // chunks (1024 voxels) per float32 accumulation chain
+constexpr int kWsThreads = 512;
+constexpr int kProd = 256;           // producer threads
+constexpr int kNV = 4;               // float4 staging slots per producer thread (n_s * kC2 / 4 <= kProd * kNV)
 
 // Output element v (0..15) of lane `lane` of a 32x32 MFMA accumulator sits
 // at row mfma_row(v, lane), column lane % 32.
 __device__ __forceinline__ int mfma_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+struct WsLds {
+  float* f32;      // [2][ns1][kF32S]
+  __bf16* bh;      // [2][ns1][kBS]
+  __bf16* bl;
+  __bf16* ah;      // [2][kRbPerWg][32][kBS]
+  __bf16* al;
+  int ns1;
+  __device__ float* F(int buf, int s) const { return f32 + (buf * ns1 + s) * kF32S; }
+  __device__ __bf16* Bh(int buf, int s) const { return bh + (buf * ns1 + s) * kBS; }
+  __device__ __bf16* Bl(int buf, int s) const { return bl + (buf * ns1 + s) * kBS; }
+  __device__ __bf16* Ah(int buf, int rb, int r) const { return ah + ((buf * kRbPerWg + rb) * 32 + r) * kBS; }
+  __device__ __bf16* Al(int buf, int rb, int r) const { return al + ((buf * kRbPerWg + rb) * 32 + r) * kBS; }
+};
 
 __device__ __forceinline__ void split8(const float* p, bf16x8& hi, bf16x8& lo) {
 #pragma unroll
@@ -178,136 +201,263 @@ __device__ __forceinline__ void split8(const float* p, bf16x8& hi, bf16x8& lo) {
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_contract_bf16x3(const float* __restrict__ F, ContractArgs a,
-                                                              int n_groups) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int ns = a.n_s;
-  float* Ff = reinterpret_cast<float*>(smem_raw);
-  __bf16* Bh = reinterpret_cast<__bf16*>(Ff + (ns + 1) * kFfStride);
-  __bf16* Bl = Bh + (ns + 1) * kBStride;
-  int g, kr;
-  xcd_map(n_groups, g, kr);
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int task = 4 * g + wave;
-  const bool active = task < a.n_tasks;
-  const int t0 = active ? a.task_off[task] : 0;
-  const int t1 = active ? a.task_off[task + 1] : 0;
-  const int nt = t1 - t0;  // <= kMT
+struct WsRange {
+  long long k_lo, k_hi;
+  int n_chunks;
+};
 
-  // per tile: this lane's row (pair) and column indices into the chunk
-  int rowi[kMT], rowj[kMT], col[kMT], rbk[kMT];
-  const int r = lane & 31, kg = lane >> 5;
+// ---- producers ---------------------------------------------------------------
+// Per chunk: F (fp32, for the pair products) n_s x kC2 floats = n_s * kC2/4 float4;
+// column planes hi/lo n_s x kC2 bf16 each = n_s * kC2/8 uint4 per plane.
+struct WsPf {
+  float4 f[kNV];
+  uint4 b[kNV];    // slots [0, n_s*kC2/8) hold hi, [n_s*kC2/8, n_s*kC2/4) hold lo
+};
+
+// A chunk (kC2 = kVoxBlock voxels) of every shell is one contiguous block of
+// the voxel-blocked layout; ranges start on multiples of 64 voxels and the
+// supported grids have N^3 divisible by 512, so every chunk is full.
+static_assert(kC2 == kVoxBlock, "chunks are voxel blocks");
+
+__device__ __forceinline__ void ws_load_f(const float* __restrict__ F, const WsArgs& a, const WsRange& R, int c,
+                                          WsPf& pf, int tid) {
+  if (c >= R.n_chunks) return;
+  const float4* base = reinterpret_cast<const float4*>(F + ((R.k_lo / kC2) + c) * (long long)a.n_s * kC2);
+  const int n4 = a.n_s * (kC2 / 4);
 #pragma unroll
-  for (int k = 0; k < kMT; ++k) {
-    rowi[k] = ns;
-    rowj[k] = ns;
-    col[k] = ns;
-    rbk[k] = -1;
-    if (k < nt) {
-      const Tile tl = a.tiles[t0 + k];
-      rbk[k] = tl.rb;
-      const int i = a.rows[tl.rb].i[r], j = a.rows[tl.rb].j[r];
-      if (j > 0) { rowi[k] = i - 1; rowj[k] = j - 1; }
-      const int l = tl.col0 + r;
-      if (l >= 1 && l <= ns) col[k] = l - 1;
+  for (int u = 0; u < kNV; ++u) {
+    const int idx = tid + u * kProd;
+    if (idx < n4) pf.f[u] = base[idx];
+  }
+}
+
+__device__ __forceinline__ void ws_load_b(const __bf16* __restrict__ fh, const __bf16* __restrict__ fl,
+                                          const WsArgs& a, const WsRange& R, int c, WsPf& pf, int tid) {
+  if (c >= R.n_chunks) return;
+  const long long off = ((R.k_lo / kC2) + c) * (long long)a.n_s * kC2;
+  const uint4* bh = reinterpret_cast<const uint4*>(fh + off);
+  const uint4* bl = reinterpret_cast<const uint4*>(fl + off);
+  const int per_plane = a.n_s * (kC2 / 8);
+#pragma unroll
+  for (int u = 0; u < kNV; ++u) {
+    const int idx = tid + u * kProd;
+    if (idx < per_plane)
+      pf.b[u] = bh[idx];
+    else if (idx < 2 * per_plane)
+      pf.b[u] = bl[idx - per_plane];
+  }
+}
+
+__device__ __forceinline__ void ws_store_f(const WsLds& L, const WsArgs& a, int buf, const WsPf& pf, int tid) {
+#pragma unroll
+  for (int u = 0; u < kNV; ++u) {
+    const int idx = tid + u * kProd;
+    if (idx < a.n_s * (kC2 / 4)) {
+      const int s = idx / (kC2 / 4), q4 = idx % (kC2 / 4);
+      *reinterpret_cast<float4*>(L.F(buf, s) + 4 * q4) = pf.f[u];
     }
   }
-  f32x16 acc[kMT];
-  double tot[kMT][16];
+}
+
+__device__ __forceinline__ void ws_store_b(const WsLds& L, const WsArgs& a, int buf, const WsPf& pf, int tid) {
+  const int per_plane = a.n_s * (kC2 / 8);
 #pragma unroll
-  for (int k = 0; k < kMT; ++k)
+  for (int u = 0; u < kNV; ++u) {
+    const int idx = tid + u * kProd;
+    if (idx < 2 * per_plane) {
+      const int plane = idx >= per_plane;
+      const int k = idx - plane * per_plane;
+      const int s = k / (kC2 / 8), q8 = k % (kC2 / 8);
+      __bf16* dst = (plane ? L.Bl(buf, s) : L.Bh(buf, s)) + 8 * q8;
+      *reinterpret_cast<uint4*>(dst) = pf.b[u];
+    }
+  }
+}
+
+// pair products of the chunk held in F32 buffer buf, split into A[buf]
+__device__ __forceinline__ void ws_products(const WsLds& L, int buf, const int (&pi)[2], const int (&pj)[2],
+                                            int tid) {
+  // kRbPerWg * 32 pairs x 4 groups of 8 voxels = 512 groups, 2 per thread
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int g = tid + u * kProd;
+    const int rbr = g >> 2, xg = (g & 3) * 8;  // rbr = rb * 32 + row
+    const float* fi = L.F(buf, pi[u]) + xg;
+    const float* fj = L.F(buf, pj[u]) + xg;
+    const float4 i0 = *reinterpret_cast<const float4*>(fi), i1 = *reinterpret_cast<const float4*>(fi + 4);
+    const float4 j0 = *reinterpret_cast<const float4*>(fj), j1 = *reinterpret_cast<const float4*>(fj + 4);
+    const float p[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
+                        i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
+    bf16x8 hi, lo;
+    split8(p, hi, lo);
+    *reinterpret_cast<bf16x8*>(L.Ah(buf, rbr >> 5, rbr & 31) + xg) = hi;
+    *reinterpret_cast<bf16x8*>(L.Al(buf, rbr >> 5, rbr & 31) + xg) = lo;
+  }
+}
+
+// Iteration c: products of chunk c+1 (F32[(c+1)%2] -> A[(c+1)%2]); F32[c%2] <- F of
+// chunk c+2 and B[(c+1)%2] <- planes of chunk c+1, both from registers loaded two
+// iterations earlier; then the loads of chunks c+4 (F) and c+3 (planes) are issued.
+__device__ __forceinline__ void ws_producer(const float* __restrict__ F, const __bf16* __restrict__ fh,
+                            const __bf16* __restrict__ fl, const WsArgs& a, const WsLds& L, const WsRange& R, int wg,
+                            int tid) {
+  int pi[2], pj[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int g = tid + u * kProd;
+    const int rb = wg * kRbPerWg + ((g >> 2) >> 5), r = (g >> 2) & 31;
+    const int i = a.rows[rb].i[r], j = a.rows[rb].j[r];
+    pi[u] = j > 0 ? i - 1 : a.n_s;
+    pj[u] = j > 0 ? j - 1 : a.n_s;
+  }
+  WsPf p0, p1;
+  // prologue: F of chunks 0, 1 and planes of chunk 0 into LDS
+  ws_load_f(F, a, R, 0, p0, tid);
+  ws_load_f(F, a, R, 1, p1, tid);
+  ws_load_b(fh, fl, a, R, 0, p0, tid);
+  ws_store_f(L, a, 0, p0, tid);
+  ws_store_f(L, a, 1, p1, tid);
+  ws_store_b(L, a, 0, p0, tid);
+  // in flight: F of chunks 2, 3; planes of chunks 1, 2
+  ws_load_f(F, a, R, 2, p0, tid);
+  ws_load_f(F, a, R, 3, p1, tid);
+  ws_load_b(fh, fl, a, R, 1, p0, tid);
+  ws_load_b(fh, fl, a, R, 2, p1, tid);
+  __syncthreads();                 // barrier P1
+  ws_products(L, 0, pi, pj, tid);  // chunk 0 -> A[0]
+  __syncthreads();                 // barrier P2
+  for (int c = 0; c < R.n_chunks; c += 2) {
+    if (c + 1 < R.n_chunks) ws_products(L, 1, pi, pj, tid);
+    ws_store_f(L, a, 0, p0, tid);    // F of chunk c+2
+    ws_store_b(L, a, 1, p0, tid);    // planes of chunk c+1
+    ws_load_f(F, a, R, c + 4, p0, tid);
+    ws_load_b(fh, fl, a, R, c + 3, p0, tid);
+    __syncthreads();
+    if (c + 1 >= R.n_chunks) break;
+    if (c + 2 < R.n_chunks) ws_products(L, 0, pi, pj, tid);
+    ws_store_f(L, a, 1, p1, tid);    // F of chunk c+3
+    ws_store_b(L, a, 0, p1, tid);    // planes of chunk c+2
+    ws_load_f(F, a, R, c + 5, p1, tid);
+    ws_load_b(fh, fl, a, R, c + 4, p1, tid);
+    __syncthreads();
+  }
+}
+
+// ---- consumers ---------------------------------------------------------------
+// NT = column tiles of this wavefront's row block (constant over the run).
+template <int NT>
+__device__ __forceinline__ void ws_consumer_nt(const WsArgs& a, const WsLds& L, const WsRange& R, int rb, const RbCols& rc,
+                               int wave, int lane, int kr) {
+  const int kg = lane >> 5;
+  int cs[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int l = rc.col0[t] + (lane & 31);
+    cs[t] = (l >= 1 && l <= a.n_s) ? l - 1 : a.n_s;
+  }
+  f32x16 acc[NT];
+  double tot[NT][16];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      acc[k][v] = 0.f;
-      tot[k][v] = 0.0;
+      acc[t][v] = 0.f;
+      tot[t][v] = 0.0;
     }
+  __syncthreads();  // matches producer barrier P1
+  __syncthreads();  // matches producer barrier P2
   int chain = 0;
-
-  // zero shell rows
-  for (int e = threadIdx.x; e < kFfStride; e += kThreads) Ff[ns * kFfStride + e] = 0.f;
-  for (int e = threadIdx.x; e < kBStride; e += kThreads) {
-    Bh[ns * kBStride + e] = (__bf16)0.f;
-    Bl[ns * kBStride + e] = (__bf16)0.f;
-  }
-  const long long k_lo = range_lo(a.n_vox, a.n_krange, kr), k_hi = range_lo(a.n_vox, a.n_krange, kr + 1);
-  for (long long x0 = k_lo; x0 < k_hi; x0 += kKc) {
-    const int len = (int)min((long long)kKc, k_hi - x0);
-    __syncthreads();
-    // stage the chunk: 4 voxels per thread step
-    for (int e = threadIdx.x; e < ns * (kKc / 4); e += kThreads) {
-      const int s = e / (kKc / 4), x4 = (e % (kKc / 4)) * 4;
-      float v[4];
-      const float* src = F + (long long)s * a.n_vox + x0 + x4;
-      if (x4 + 4 <= len && ((((uintptr_t)src) & 15) == 0)) {
-        const float4 q = *reinterpret_cast<const float4*>(src);
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-      } else {
+  for (int c = 0; c < R.n_chunks; ++c) {
+    const int buf = c & 1;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = (x4 + u < len) ? src[u] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        Ff[s * kFfStride + x4 + u] = v[u];
-        const __bf16 h = (__bf16)v[u];
-        Bh[s * kBStride + x4 + u] = h;
-        Bl[s * kBStride + x4 + u] = (__bf16)(v[u] - (float)h);
-      }
-    }
-    __syncthreads();
-    if (!active) continue;
-#pragma unroll
-    for (int ks = 0; ks < kKc / 16; ++ks) {
+    for (int ks = 0; ks < kC2 / 16; ++ks) {
       const int off = ks * 16 + kg * 8;
-      int prev_rb = -1;  // wave-uniform: tiles of one row block share the row operand
-      bf16x8 ahi, alo;
+      const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(L.Ah(buf, wave, lane & 31) + off);
+      const bf16x8 alo = *reinterpret_cast<const bf16x8*>(L.Al(buf, wave, lane & 31) + off);
+      bf16x8 bhi[NT], blo[NT];
 #pragma unroll
-      for (int k = 0; k < kMT; ++k) {
-        if (k >= nt) break;
-        if (rbk[k] != prev_rb) {
-          const float* fi = Ff + rowi[k] * kFfStride + off;
-          const float* fj = Ff + rowj[k] * kFfStride + off;
-          const float4 i0 = *reinterpret_cast<const float4*>(fi), i1 = *reinterpret_cast<const float4*>(fi + 4);
-          const float4 j0 = *reinterpret_cast<const float4*>(fj), j1 = *reinterpret_cast<const float4*>(fj + 4);
-          float p[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
-                        i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
-          split8(p, ahi, alo);
-          prev_rb = rbk[k];
-        }
-        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(Bh + col[k] * kBStride + off);
-        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(Bl + col[k] * kBStride + off);
-        acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, acc[k], 0, 0, 0);
-        acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, acc[k], 0, 0, 0);
-        acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, acc[k], 0, 0, 0);
+      for (int t = 0; t < NT; ++t) {
+        bhi[t] = *reinterpret_cast<const bf16x8*>(L.Bh(buf, cs[t]) + off);
+        blo[t] = *reinterpret_cast<const bf16x8*>(L.Bl(buf, cs[t]) + off);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[t], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[t], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[t], acc[t], 0, 0, 0);
       }
     }
-    if (++chain == kFlush || x0 + kKc >= k_hi) {
+    if (++chain == kFlush || c + 1 == R.n_chunks) {
       chain = 0;
 #pragma unroll
-      for (int k = 0; k < kMT; ++k)
+      for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          tot[k][v] += (double)acc[k][v];
-          acc[k][v] = 0.f;
+          tot[t][v] += (double)acc[t][v];
+          acc[t][v] = 0.f;
         }
     }
+    __syncthreads();  // matches the producer's per-chunk barrier
   }
-  if (!active) return;
   double* out = a.partial + (long long)kr * a.n_tri;
+  const RowBlock& rw = a.rows[rb];
 #pragma unroll
-  for (int k = 0; k < kMT; ++k) {
-    if (k >= nt) break;
-    const Tile tl = a.tiles[t0 + k];
-    const int l = tl.col0 + (lane & 31);
+  for (int t = 0; t < NT; ++t) {
+    const int l = rc.col0[t] + (lane & 31);
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int row = mfma_row(v, lane);
-      const int i = a.rows[tl.rb].i[row], j = a.rows[tl.rb].j[row];
+      const int i = rw.i[row], j = rw.j[row];
       if (j <= 0 || l < 1 || l > j) continue;
-      const int t = a.tri_index[((long long)(i - 1) * ns + (j - 1)) * ns + (l - 1)];
-      if (t >= 0) out[t] = tot[k][v];
+      const int tt = a.tri_index[((long long)(i - 1) * a.n_s + (j - 1)) * a.n_s + (l - 1)];
+      if (tt >= 0) out[tt] = tot[t][v];
     }
   }
+}
+
+__device__ __forceinline__ void ws_consumer(const WsArgs& a, const WsLds& L, const WsRange& R, int wg, int wave, int lane, int kr) {
+  const int rb = wg * kRbPerWg + wave;
+  const RbCols rc = a.cols[rb];
+  switch (rc.n) {
+    case 1: ws_consumer_nt<1>(a, L, R, rb, rc, wave, lane, kr); break;
+    case 2: ws_consumer_nt<2>(a, L, R, rb, rc, wave, lane, kr); break;
+    case 3: ws_consumer_nt<3>(a, L, R, rb, rc, wave, lane, kr); break;
+    case 4: ws_consumer_nt<4>(a, L, R, rb, rc, wave, lane, kr); break;
+    default:  // padding row block: keep the barrier count of the work group
+      for (int c = 0; c < R.n_chunks + 2; ++c) __syncthreads();
+      break;
+  }
+}
+
+__global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __restrict__ F,
+                                                                const __bf16* __restrict__ fh,
+                                                                const __bf16* __restrict__ fl, WsArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  WsLds L;
+  L.ns1 = a.n_s + 1;
+  L.f32 = reinterpret_cast<float*>(smem_raw);
+  L.bh = reinterpret_cast<__bf16*>(L.f32 + 2 * L.ns1 * kF32S);
+  L.bl = L.bh + 2 * L.ns1 * kBS;
+  L.ah = L.bl + 2 * L.ns1 * kBS;
+  L.al = L.ah + 2 * kRbPerWg * 32 * kBS;
+  int wg, kr;
+  xcd_map(a.n_wg, wg, kr);
+  // zero shell rows of both buffers (never overwritten afterwards)
+  for (int e = threadIdx.x; e < 2 * kF32S; e += kWsThreads) L.F(e / kF32S, a.n_s)[e % kF32S] = 0.f;
+  for (int e = threadIdx.x; e < 2 * kBS; e += kWsThreads) {
+    L.Bh(e / kBS, a.n_s)[e % kBS] = (__bf16)0.f;
+    L.Bl(e / kBS, a.n_s)[e % kBS] = (__bf16)0.f;
+  }
+  __syncthreads();
+  WsRange R;
+  R.k_lo = range_lo(a.n_vox, a.n_krange, kr);
+  R.k_hi = range_lo(a.n_vox, a.n_krange, kr + 1);
+  R.n_chunks = (int)((R.k_hi - R.k_lo + kC2 - 1) / kC2);
+  const int wave = threadIdx.x >> 6;
+  if (wave < 4)
+    ws_consumer(a, L, R, wg, wave, threadIdx.x & 63, kr);
+  else
+    ws_producer(F, fh, fl, a, L, R, wg, threadIdx.x - 256);
 }
 
 __global__ void k_reduce(const double* __restrict__ partial, int n_krange, long long n_tri,
@@ -334,18 +484,22 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
 }  // namespace
 
 size_t bf16x3_lds_bytes(int n_s) {
-  return (size_t)(n_s + 1) * kFfStride * sizeof(float) + 2 * (size_t)(n_s + 1) * kBStride * sizeof(__bf16);
+  return 2 * (size_t)(n_s + 1) * kF32S * sizeof(float) + 4 * (size_t)(n_s + 1) * kBS * sizeof(__bf16) +
+         4 * (size_t)kRbPerWg * 32 * kBS * sizeof(__bf16);
 }
 
 hipError_t launch_contract_fp32(const float* F, const ContractArgs& a, hipStream_t st) { return launch_vec<float>(F, a, st); }
 hipError_t launch_contract_fp64(const double* F, const ContractArgs& a, hipStream_t st) { return launch_vec<double>(F, a, st); }
 
-hipError_t launch_contract_bf16x3(const float* F, const ContractArgs& a, hipStream_t st) {
-  const int n_groups = (a.n_tasks + 3) / 4;
+hipError_t launch_contract_bf16x3(const float* F, const __bf16* f_hi, const __bf16* f_lo, const WsArgs& a,
+                                  hipStream_t st) {
+  if (a.n_s * (kC2 / 4) > kProd * kNV) return hipErrorInvalidValue;
   const size_t lds = bf16x3_lds_bytes(a.n_s);
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)n_groups * (unsigned)a.n_krange;
-  hipLaunchKernelGGL(k_contract_bf16x3, dim3(blocks), dim3(kThreads), lds, st, F, a, n_groups);
+  hipError_t e = hipFuncSetAttribute((const void*)k_contract_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)a.n_wg * (unsigned)a.n_krange;
+  hipLaunchKernelGGL(k_contract_bf16x3, dim3(blocks), dim3(kWsThreads), lds, st, F, f_hi, f_lo, a);
   return hipGetLastError();
 }
 

@@ -8,7 +8,9 @@
 // R-point DFT and writes it to y[(j div ns) ns R + (j mod ns) + r ns].  After
 // the last pass ns = n and y holds the DFT in natural order.  Each pass is done
 // in place: every thread first loads all elements of its butterflies into
-// registers, the work group synchronises, then all threads store.
+// registers, the work group synchronises, then all threads store.  Line
+// length, radix schedule and tile shape are compile-time constants, so all
+// index arithmetic reduces to shifts and constant multiplies.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -112,80 +114,74 @@ template <typename T> struct Dft<T, 5> {
   }
 };
 
-// Radix schedule of one line length, passed by value to kernels.
-struct FftSched {
-  int n;       // line length
-  int npass;
-  int r[12];   // radices, applied in order
-  int tw_stride;  // table index step: table holds exp(-2 pi i k / Nt), Nt = n * tw_stride
-};
+// Radix of the next pass for a remaining length rem: 8 while it divides, then
+// 4, 2, 3, 5 (any order of the factors gives a correct Stockham FFT).
+__host__ __device__ constexpr int next_radix(int rem) {
+  return (rem % 8 == 0) ? 8 : (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3 : 5;
+}
 
-// Lines in LDS: element q of line c sits at buf[c * ls + q * es].  With
-// interleaved = true, consecutive threads walk lines first (good when es == 1
-// is false, i.e. lines are interleaved); otherwise butterflies first.
-template <typename T, int R, int E, int NT>
-__device__ __forceinline__ void stockham_pass(V2<T>* buf, int n, int ns, int nl, int es, int ls, bool interleaved,
-                                              const V2<T>* __restrict__ tw, int tw_stride, T sign) {
-  constexpr int BPT = (E + R - 1) / R;
-  const int nb = n / R;
-  const int total = nb * nl;
-  const int step = (n / (ns * R)) * tw_stride;
+// One radix-R pass on NL lines of length N held in LDS, all sizes known at
+// compile time.  Layout: interleaved (element q of line c at q*NL + c; the
+// strided-axis tiles) or line-major (at c*LSX + q; contiguous lines, LSX >= N).
+// Twiddles come from a table tw[k] = exp(-2 pi i k / (N * TWS)).
+template <typename T, int R, int N, int NS, int NL, int NT, bool INTERLEAVED, int LSX, int TWS>
+__device__ __forceinline__ void ct_pass(V2<T>* buf, const V2<T>* __restrict__ tw, T sign) {
+  constexpr int NB = N / R;
+  constexpr int TOTAL = NB * NL;
+  constexpr int BPT = (TOTAL + NT - 1) / NT;
+  constexpr int STEP = (N / (NS * R)) * TWS;
+  constexpr int ES = INTERLEAVED ? NL : 1;
+  constexpr int LS = INTERLEAVED ? 1 : LSX;
   V2<T> v[BPT][R];
-  int jj[BPT], cc[BPT];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     const int w = threadIdx.x + b * NT;
-    int j, c;
-    if (interleaved) { c = w % nl; j = w / nl; } else { j = w % nb; c = w / nb; }
-    jj[b] = j;
-    cc[b] = c;
-    if (w < total) {
+    if (TOTAL % NT == 0 || w < TOTAL) {
+      const int c = INTERLEAVED ? w % NL : w / NB;
+      const int j = INTERLEAVED ? w / NL : w % NB;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = buf[c * ls + (j + r * nb) * es];
+      for (int r = 0; r < R; ++r) v[b][r] = buf[c * LS + (j + r * NB) * ES];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     const int w = threadIdx.x + b * NT;
-    if (w < total) {
-      const int j = jj[b], c = cc[b];
-      const int jm = j % ns;
-      if (ns > 1) {
+    if (TOTAL % NT == 0 || w < TOTAL) {
+      const int c = INTERLEAVED ? w % NL : w / NB;
+      const int j = INTERLEAVED ? w / NL : w % NB;
+      const int jm = j % NS;
+      if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          V2<T> t = tw[r * jm * step];
-          t.y *= -sign;  // table is exp(-i...); sign = -1 keeps it, +1 conjugates
+          V2<T> t = tw[r * jm * STEP];
+          t.y *= -sign;  // table holds exp(-i...); sign = +1 conjugates
           v[b][r] = mul<T>(v[b][r], t);
         }
       }
       Dft<T, R>::run(v[b], sign);
-      const int base = (j / ns) * ns * R + jm;
+      const int base = (j / NS) * NS * R + jm;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[c * ls + (base + r * ns) * es] = v[b][r];
+      for (int r = 0; r < R; ++r) buf[c * LS + (base + r * NS) * ES] = v[b][r];
     }
   }
   __syncthreads();
 }
 
-// Full FFT of nl lines of length s.n in LDS.  sign = -1 forward, +1 inverse
-// (unnormalised).  Requires s.n * nl <= NT * E.  Ends with a barrier.
-template <typename T, int E, int NT>
-__device__ void lds_fft(V2<T>* buf, const FftSched& s, int nl, int es, int ls, bool interleaved,
-                        const V2<T>* __restrict__ tw, T sign) {
-  int ns = 1;
-  for (int p = 0; p < s.npass; ++p) {
-    const int R = s.r[p];
-    switch (R) {
-      case 8: stockham_pass<T, 8, E, NT>(buf, s.n, ns, nl, es, ls, interleaved, tw, s.tw_stride, sign); break;
-      case 4: stockham_pass<T, 4, E, NT>(buf, s.n, ns, nl, es, ls, interleaved, tw, s.tw_stride, sign); break;
-      case 2: stockham_pass<T, 2, E, NT>(buf, s.n, ns, nl, es, ls, interleaved, tw, s.tw_stride, sign); break;
-      case 3: stockham_pass<T, 3, E, NT>(buf, s.n, ns, nl, es, ls, interleaved, tw, s.tw_stride, sign); break;
-      case 5: stockham_pass<T, 5, E, NT>(buf, s.n, ns, nl, es, ls, interleaved, tw, s.tw_stride, sign); break;
-      default: break;
-    }
-    ns *= R;
+template <typename T, int N, int NS, int NL, int NT, bool INTERLEAVED, int LSX, int TWS>
+__device__ __forceinline__ void ct_passes(V2<T>* buf, const V2<T>* __restrict__ tw, T sign) {
+  if constexpr (NS < N) {
+    constexpr int R = next_radix(N / NS);
+    ct_pass<T, R, N, NS, NL, NT, INTERLEAVED, LSX, TWS>(buf, tw, sign);
+    ct_passes<T, N, NS * R, NL, NT, INTERLEAVED, LSX, TWS>(buf, tw, sign);
   }
+}
+
+// Full FFT (sign -1 forward, +1 inverse, unnormalised) of NL lines of length N
+// in LDS; starts and ends with the block synchronised.
+template <typename T, int N, int NL, int NT, bool INTERLEAVED, int LSX, int TWS>
+__device__ __forceinline__ void ct_fft(V2<T>* buf, const V2<T>* __restrict__ tw, T sign) {
+  ct_passes<T, N, 1, NL, NT, INTERLEAVED, LSX, TWS>(buf, tw, sign);
 }
 
 }  // namespace bispec

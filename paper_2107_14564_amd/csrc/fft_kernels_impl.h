@@ -1,0 +1,262 @@
+// FFT pass kernels of the estimator (steps a, b and b2), templated on the line
+// length N so every index computation is compile-time.  Instantiated for the
+// supported grid sizes by fft_forward.hip, fft_inv_x.hip, fft_inv_y.hip and
+// fft_c2r.hip.
+//
+// Grid layout (all C order, z fastest):
+//   delta  float32 [N][N][N]
+//   spec   complex [N (kx)][N (ky)][M+1 (kz)], M = N/2     (half spectrum, in place)
+//   A1_n   complex [N (x)][2R+1 (ky + R)][R+1 (kz)]        (shell n after the x pass)
+//   A2_n   complex [N (x)][N (y)][R+1 (kz)]                (shell n after the y pass)
+//   F_n    real, voxel-blocked (vox_index)                 (shell field)
+// R = rad[n] is the largest |m_y| of any mode of shell n, so the inverse
+// passes of shell n only touch the ball |m| <= R: the x pass runs only the
+// (ky, kz) columns inside the disc ky^2 + kz^2 < hi2[n], the y pass only the
+// kz <= R planes, and the z pass reads R+1 of the M+1 half-spectrum planes.
+//
+// Strided passes stage a tile of TW consecutive kz columns times the whole
+// line in LDS (interleaved layout); contiguous passes stage whole lines.
+#pragma once
+
+#include "fft_core.h"
+#include "kernels.h"
+
+namespace bispec {
+namespace fftk {
+
+constexpr int kThrAxis = 512;  // threads of a strided-pass block
+constexpr int kThrZ = 256;     // threads of a contiguous-pass block
+
+__device__ __forceinline__ int freq(int q, int n) { return q < n / 2 ? q : q - n; }
+
+// ---- (a) forward: real z lines -> half spectrum ------------------------------
+// Two real samples per complex slot: z_m = x_{2m} + i x_{2m+1}, M-point FFT,
+// then X_k = (Z_k + Z*_{M-k})/2 + W_N^k (Z_k - Z*_{M-k})/(2i), k = 0..M.
+template <int N>
+__global__ void __launch_bounds__(kThrZ) k_r2c_z(const float* __restrict__ in, float2* __restrict__ out,
+                                                 const float2* __restrict__ tw, float scale) {
+  constexpr int M = N / 2;
+  constexpr int NL = fft_z_lines(M, false);
+  constexpr int LS = M + 1;
+  __shared__ float2 buf[NL * LS];
+  const long long n_lines = (long long)N * N;
+  const long long line0 = (long long)blockIdx.x * NL;
+  const int lines = (int)min((long long)NL, n_lines - line0);
+  const float2* src = reinterpret_cast<const float2*>(in) + line0 * M;
+  for (int e = threadIdx.x; e < NL * M; e += kThrZ) {
+    const int c = e / M, q = e % M;
+    if (c < lines) buf[c * LS + q] = src[(long long)c * M + q];
+  }
+  __syncthreads();
+  ct_fft<float, M, NL, kThrZ, false, LS, 2>(buf, tw, -1.0f);
+  float2* dst = out + line0 * (M + 1);
+  for (int e = threadIdx.x; e < NL * (M + 1); e += kThrZ) {
+    const int c = e / (M + 1), k = e % (M + 1);
+    if (c >= lines) continue;
+    const float2 zk = buf[c * LS + (k == M ? 0 : k)];
+    const float2 zc = conjv<float>(buf[c * LS + (k == 0 ? 0 : M - k)]);
+    const float2 a = scl<float>(add<float>(zk, zc), 0.5f);
+    const float2 d = scl<float>(sub<float>(zk, zc), 0.5f);  // (Z_k - Z*_{M-k}) / 2
+    const float2 w = tw[k];
+    const float2 bi = mk<float>(d.y, -d.x);                 // d / i
+    dst[(long long)c * (M + 1) + k] = scl<float>(add<float>(a, mul<float>(w, bi)), scale);
+  }
+}
+
+// ---- (a) forward: strided complex axis, in place -----------------------------
+// Lines along an axis of length N with element stride `stride`; n_cols
+// consecutive columns; planes at outer_stride.  rsd_pass (the final x pass):
+// multiply by 1 + beta kz^2/|m|^2.
+template <int N>
+__global__ void __launch_bounds__(kThrAxis) k_fft_axis(float2* __restrict__ data, long long stride, int n_cols,
+                                                       long long outer_stride, const float2* __restrict__ tw,
+                                                       float sign, float scale, int rsd_pass, float beta) {
+  constexpr int TW = fft_tile_cols(N, false);
+  __shared__ float2 buf[N * TW];
+  const int n_ct = (n_cols + TW - 1) / TW;
+  const int o = blockIdx.x / n_ct;
+  const int c0 = (blockIdx.x % n_ct) * TW;
+  const int cols = min(TW, n_cols - c0);
+  float2* base = data + (long long)o * outer_stride + c0;
+  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
+    const int q = e / TW, c = e % TW;
+    buf[e] = c < cols ? base[(long long)q * stride + c] : mk<float>(0.f, 0.f);
+  }
+  __syncthreads();
+  ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, tw, sign);
+  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
+    const int q = e / TW, c = e % TW;
+    if (c >= cols) continue;
+    float f = scale;
+    if (rsd_pass) {
+      // data layout [kx][ky][kz]: this pass runs along kx (q), o = ky, column = kz
+      const long long mx = freq(q, N), my = freq(o, N), mz = c0 + c;
+      const long long m2 = mx * mx + my * my + mz * mz;
+      if (m2 > 0) f *= 1.0f + beta * (float)((double)(mz * mz) / (double)m2);
+    }
+    base[(long long)q * stride + c] = scl<float>(buf[e], f);
+  }
+}
+
+// ---- (b) inverse x pass of every shell ----------------------------------------
+// Tile (shell, ky, kz0) of TW columns: Delta (or 1 for the unit shells) on the
+// modes of shell n in those columns, inverse FFT along x, into A1_n.
+template <typename T, bool UNIT, int N>
+__global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ spec, V2<T>* __restrict__ a1,
+                                                    const int4* __restrict__ tiles, const ShellDev* __restrict__ sh,
+                                                    const V2<T>* __restrict__ tw) {
+  constexpr int M = N / 2;
+  constexpr int TW = fft_tile_cols(N, sizeof(T) == 8);
+  __shared__ V2<T> buf[N * TW];
+  const int4 td = tiles[blockIdx.x];
+  const int sn = td.x, ky = td.y, kz0 = td.z;
+  const ShellDev d = sh[sn];
+  const int R = d.rad;
+  const int cols = min(TW, R + 1 - kz0);
+  const int yrow = ky < 0 ? ky + N : ky;
+  const long long ky2 = (long long)ky * ky;
+  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
+    const int q = e / TW, c = e % TW;
+    V2<T> v = mk<T>((T)0, (T)0);
+    if (c < cols) {
+      const long long mx = freq(q, N), kz = kz0 + c;
+      const long long m2 = mx * mx + ky2 + kz * kz;
+      if (m2 >= d.lo2 && m2 < d.hi2) {
+        if (UNIT) {
+          v = mk<T>((T)1, (T)0);
+        } else {
+          const float2 x = spec[((long long)q * N + yrow) * (M + 1) + kz];
+          v = mk<T>((T)x.x, (T)x.y);
+        }
+      }
+    }
+    buf[e] = v;
+  }
+  __syncthreads();
+  ct_fft<T, N, TW, kThrAxis, true, 1, 1>(buf, tw, (T)1);
+  V2<T>* dst = a1 + d.a1_off;
+  const int wy = 2 * R + 1, wz = R + 1;
+  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
+    const int q = e / TW, c = e % TW;
+    if (c < cols) dst[((long long)q * wy + (ky + R)) * wz + kz0 + c] = buf[e];
+  }
+}
+
+// ---- (b) inverse y pass of every shell ----------------------------------------
+// Block -> (shell, x, kz tile) through the per-shell prefix sums tile_off.
+template <typename T, int N>
+__global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1, V2<T>* __restrict__ a2,
+                                                    const long long* __restrict__ tile_off, int n_shells,
+                                                    const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw) {
+  constexpr int TW = fft_tile_cols(N, sizeof(T) == 8);
+  __shared__ V2<T> buf[N * TW];
+  const long long b = blockIdx.x;
+  int lo = 0, hi = n_shells;  // sn with tile_off[sn] <= b < tile_off[sn+1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (tile_off[mid] <= b) lo = mid; else hi = mid;
+  }
+  const int sn = lo;
+  const ShellDev d = sh[sn];
+  const int R = d.rad;
+  const int n_ct = (R + 1 + TW - 1) / TW;
+  const long long local = b - tile_off[sn];
+  const int x = (int)(local / n_ct);
+  const int kz0 = (int)(local % n_ct) * TW;
+  const int cols = min(TW, R + 1 - kz0);
+  const int wy = 2 * R + 1, wz = R + 1;
+  const V2<T>* src = a1 + d.a1_off + (long long)x * wy * wz;
+  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
+    const int q = e / TW, c = e % TW;
+    V2<T> v = mk<T>((T)0, (T)0);
+    if (c < cols) {
+      const long long my = freq(q, N), kz = kz0 + c;
+      if (my >= -R && my <= R && my * my + kz * kz < d.hi2) v = src[(my + R) * wz + kz];
+    }
+    buf[e] = v;
+  }
+  __syncthreads();
+  ct_fft<T, N, TW, kThrAxis, true, 1, 1>(buf, tw, (T)1);
+  V2<T>* dst = a2 + d.a2_off + (long long)x * N * wz;
+  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
+    const int q = e / TW, c = e % TW;
+    if (c < cols) dst[(long long)q * wz + kz0 + c] = buf[e];
+  }
+}
+
+// ---- (b) inverse z pass (C2R) of every shell -----------------------------------
+// Per (x, y) line: X_k (k = 0..M, zero beyond R), Z'_k = (X_k + X*_{M-k})
+// + i W_N^{-k} (X_k - X*_{M-k}) for k < M, M-point inverse FFT; the
+// unnormalised real line is (Re z_m, Im z_m) at (2m, 2m+1), written
+// voxel-blocked; with SPLIT also as bf16 planes hi = bf16(v), lo = bf16(v - hi).
+template <typename T, typename OutT, bool SPLIT, int N>
+__global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, OutT* __restrict__ out,
+                                                 const long long* __restrict__ blk_off, int n_shells,
+                                                 const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw,
+                                                 __bf16* __restrict__ out_hi, __bf16* __restrict__ out_lo) {
+  constexpr int M = N / 2;
+  constexpr int NL = fft_z_lines(M, sizeof(T) == 8);
+  constexpr int LS = M + 1;
+  __shared__ V2<T> buf[NL * LS];
+  const long long b = blockIdx.x;
+  int lo = 0, hi = n_shells;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (blk_off[mid] <= b) lo = mid; else hi = mid;
+  }
+  const int sn = lo;
+  const ShellDev d = sh[sn];
+  const int wz = d.rad + 1;
+  const long long n_lines = (long long)N * N;
+  const long long line0 = (b - blk_off[sn]) * NL;
+  const int lines = (int)min((long long)NL, n_lines - line0);
+  const V2<T>* src = a2 + d.a2_off + line0 * wz;
+  for (int e = threadIdx.x; e < NL * LS; e += kThrZ) {
+    const int c = e / LS, k = e % LS;
+    buf[e] = (c < lines && k < wz) ? src[(long long)c * wz + k] : mk<T>((T)0, (T)0);
+  }
+  __syncthreads();
+  // pairs (k, M-k), k = 0..M/2, one thread each, in place
+  constexpr int HALF = M / 2 + 1;
+  for (int e = threadIdx.x; e < NL * HALF; e += kThrZ) {
+    const int c = e / HALF, k = e % HALF;
+    V2<T>* L = buf + c * LS;
+    const V2<T> xk = L[k], xmk = L[M - k];
+    const V2<T> sp = add<T>(xk, conjv<T>(xmk));
+    const V2<T> t = mul<T>(conjv<T>(tw[k]), sub<T>(xk, conjv<T>(xmk)));
+    if (k > 0 && k < M - k) {
+      const V2<T> sp2 = add<T>(xmk, conjv<T>(xk));
+      const V2<T> t2 = mul<T>(conjv<T>(tw[M - k]), sub<T>(xmk, conjv<T>(xk)));
+      L[M - k] = mk<T>(sp2.x - t2.y, sp2.y + t2.x);
+    }
+    if (k < M) L[k] = mk<T>(sp.x - t.y, sp.y + t.x);
+  }
+  __syncthreads();
+  ct_fft<T, M, NL, kThrZ, false, LS, 2>(buf, tw, (T)1);
+  for (int e = threadIdx.x; e < NL * M; e += kThrZ) {
+    const int c = e / M, q = e % M;
+    if (c >= lines) continue;
+    const V2<T> z = buf[c * LS + q];
+    const OutT x0 = (OutT)z.x, x1 = (OutT)z.y;
+    const long long at = vox_index((line0 + c) * N + 2 * q, sn, n_shells);  // even: pair stays in one block
+    *reinterpret_cast<V2<OutT>*>(out + at) = mk<OutT>(x0, x1);
+    if constexpr (SPLIT) {
+      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+      bf16x2 h, l;
+      h[0] = (__bf16)x0;
+      h[1] = (__bf16)x1;
+      l[0] = (__bf16)(x0 - (float)h[0]);
+      l[1] = (__bf16)(x1 - (float)h[1]);
+      *reinterpret_cast<bf16x2*>(out_hi + at) = h;
+      *reinterpret_cast<bf16x2*>(out_lo + at) = l;
+    }
+  }
+}
+
+}  // namespace fftk
+}  // namespace bispec
+
+// X-macro over the supported grid sizes N = 2^a * {1, 3, 5}, 8 <= N <= 1024.
+#define BISPEC_FOR_EACH_N(X) \
+  X(8) X(16) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512) X(640) \
+  X(768) X(1024)

@@ -27,10 +27,13 @@ std::vector<int> fft_radices(int n) {
 }
 
 int validate(const bispec_config& c, std::string& err) {
-  if (c.n_g < 8 || c.n_g > 1024 || (c.n_g & 1))
-    return fail(err, BISPEC_EINVAL, "n_g must be even and in [8, 1024]");
-  if (fft_radices(c.n_g).empty() || fft_radices(c.n_g / 2).empty())
-    return fail(err, BISPEC_EINVAL, "n_g must factor into 2, 3 and 5");
+  {
+    // n_g = 2^a * {1, 3, 5} with 2^a >= 8, n_g <= 1024
+    int m = c.n_g;
+    while (m > 1 && m % 2 == 0) m /= 2;
+    if (c.n_g < 8 || c.n_g > 1024 || !(m == 1 || m == 3 || m == 5) || c.n_g / m < 8)
+      return fail(err, BISPEC_EINVAL, "n_g must be 2^a, 3*2^a or 5*2^a with 2^a >= 8, at most 1024");
+  }
   if (!(c.box_l > 0) || !std::isfinite(c.box_l)) return fail(err, BISPEC_EINVAL, "box_l must be > 0");
   if (!(c.dk >= 1.0) || !std::isfinite(c.dk)) return fail(err, BISPEC_EINVAL, "dk (shell width in k_f) must be >= 1");
   if (c.n_shells < 1 || c.n_shells > 1024) return fail(err, BISPEC_EINVAL, "n_shells must be in [1, 1024]");
@@ -248,6 +251,57 @@ void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp) {
   if ((int)tp.tiles.size() > tp.task_off.back()) tp.task_off.push_back((int32_t)tp.tiles.size());
   tp.useful = (int64_t)s.tri.size();
   tp.slots = (int64_t)tp.tiles.size() * kRows * kCols;
+}
+
+void build_mfma_tiles(const Selection& s, MfmaTiling& mt) {
+  std::map<std::pair<int, int>, std::vector<int>> pl;
+  for (const Tri& t : s.tri) pl[{t.a1, t.a2}].push_back(t.a3);
+  struct P { int i, j, lo, hi; };
+  std::map<std::pair<int, int>, std::vector<P>> spans;  // (first, last column block) -> pairs
+  for (auto& kv : pl) {
+    auto mm = std::minmax_element(kv.second.begin(), kv.second.end());
+    const int c0 = (*mm.first - 1) / kCols, c1 = (*mm.second - 1) / kCols;
+    spans[{c0, c1}].push_back({kv.first.first, kv.first.second, *mm.first, *mm.second});
+  }
+  mt.rows.clear();
+  mt.cols.clear();
+  mt.tiles = 0;
+  for (auto& sp : spans) {
+    auto& ps = sp.second;
+    std::sort(ps.begin(), ps.end(), [](const P& a, const P& b) {
+      if (a.hi != b.hi) return a.hi < b.hi;
+      if (a.lo != b.lo) return a.lo < b.lo;
+      if (a.i != b.i) return a.i < b.i;
+      return a.j < b.j;
+    });
+    for (size_t p0 = 0; p0 < ps.size(); p0 += kRows) {
+      RowBlock rb{};
+      for (int r = 0; r < kRows; ++r) {
+        const bool in = p0 + r < ps.size();
+        rb.i[r] = in ? (int16_t)ps[p0 + r].i : 0;
+        rb.j[r] = in ? (int16_t)ps[p0 + r].j : 0;
+      }
+      RbCols rc{};
+      rc.n = 0;
+      for (int c = sp.first.first; c <= sp.first.second; ++c) {
+        const int col0 = c * kCols + 1;
+        bool any = false;
+        for (int r = 0; r < kRows && !any; ++r) {
+          if (!rb.j[r]) continue;
+          for (int l : pl[{rb.i[r], rb.j[r]}])
+            if (l >= col0 && l < col0 + kCols) { any = true; break; }
+        }
+        if (any) rc.col0[rc.n++] = col0;
+      }
+      mt.rows.push_back(rb);
+      mt.cols.push_back(rc);
+      mt.tiles += rc.n;
+    }
+  }
+  while (mt.rows.size() % kRbPerWg) {
+    mt.rows.push_back(RowBlock{});
+    mt.cols.push_back(RbCols{});
+  }
 }
 
 }  // namespace bispec

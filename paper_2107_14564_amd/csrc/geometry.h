@@ -61,13 +61,10 @@ struct Tile {
   int32_t col0;   // first column shell (1-based)
 };
 
-// A task is a few tiles handled together over a voxel range: at most
-// kMaxTilesPerTask (8) by one work group of the vector kernel, at most
-// kMaxTilesPerTaskMfma (4) by one wavefront of the MFMA kernel (its fp32
-// accumulators need float64 shadows).  A row block's tiles stay in one task
-// when they fit, so its pair products are formed once.
+// A task is at most kMaxTilesPerTask tiles handled together over a voxel range
+// by one work group of the vector kernels.  A row block's tiles stay in one
+// task when they fit, so its pair products are formed once.
 constexpr int kMaxTilesPerTask = 8;
-constexpr int kMaxTilesPerTaskMfma = 4;
 
 struct TilePlan {
   std::vector<RowBlock> rows;
@@ -78,5 +75,26 @@ struct TilePlan {
 };
 
 void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp);
+
+// Tiling of the MFMA kernel.  Pairs are grouped by the span of column blocks
+// (aligned blocks of kCols shells) that their selected l fall in; each row
+// block of kRows pairs of one span meets every column block of that span, so
+// row blocks are whole rectangles of at most kMaxColTiles tiles.  Work group q
+// owns row blocks [kRbPerWg q, kRbPerWg (q+1)).
+constexpr int kMaxColTiles = 4;   // n_shells <= kCols * kMaxColTiles
+constexpr int kRbPerWg = 4;
+
+struct RbCols {
+  int32_t n;                      // column tiles of this row block (0 = padding)
+  int32_t col0[kMaxColTiles];     // first shell (1-based) of each column tile
+};
+
+struct MfmaTiling {
+  std::vector<RowBlock> rows;
+  std::vector<RbCols> cols;       // one per row block, padded to a multiple of kRbPerWg
+  int64_t tiles = 0;
+};
+
+void build_mfma_tiles(const Selection& s, MfmaTiling& mt);
 
 }  // namespace bispec

@@ -10,17 +10,33 @@
 
 namespace bispec {
 
-constexpr int kFftThreads = 256;
-constexpr int kFftElemsF32 = 32;  // LDS tile of an fp32 FFT block = 32 * 256 complex (64 KB)
-constexpr int kFftElemsF64 = 16;  // LDS tile of an fp64 FFT block = 16 * 256 complex (64 KB)
-
-// columns per block of a strided pass over lines of length n
-__host__ __device__ inline int fft_tile_cols(int n, bool f64) {
-  return (kFftThreads * (f64 ? kFftElemsF64 : kFftElemsF32)) / n;
+// Tile shapes of the FFT passes (shared by kernels and host planning).
+// Strided passes: TW columns x N rows per block (<= 64 KB of LDS).
+__host__ __device__ constexpr int fft_tile_cols(int n, bool f64) {
+  return ((f64 ? 4096 : 8192) / n) < 64 ? ((f64 ? 4096 : 8192) / n) : 64;
 }
-// lines per block of a contiguous pass over lines of length len (LDS stride len + 1)
-__host__ __device__ inline int fft_tile_lines(int len, bool f64) {
-  return (kFftThreads * (f64 ? kFftElemsF64 : kFftElemsF32)) / (len + 1);
+// Contiguous passes over lines of length len (LDS stride len + 1): lines per block.
+__host__ __device__ constexpr int fft_z_lines(int len, bool f64) { return (f64 ? 2048 : 2048) / (len + 1); }
+
+// Supported grid sizes: N = 2^a * {1, 3, 5}, 8 <= N <= 1024.
+inline bool fft_size_supported(int n) {
+  if (n < 8 || n > 1024) return false;
+  int m = n;
+  while (m % 2 == 0) m /= 2;
+  return (m == 1 || m == 3 || m == 5) && (n / m) >= 8;
+}
+
+// Shell fields (F, its bf16 planes, the float64 unit shells) are stored
+// voxel-blocked: value of shell n at voxel v sits at
+//   (v / kVoxBlock) * n_s * kVoxBlock + n * kVoxBlock + v % kVoxBlock,
+// so one block of kVoxBlock voxels of every shell is contiguous (the unit the
+// contraction streams), and a chunk touches one memory page instead of n_s.
+constexpr int kVoxBlock = 32;
+__host__ __device__ inline long long vox_index(long long v, int n, int n_s) {
+  return (v / kVoxBlock) * (long long)n_s * kVoxBlock + (long long)n * kVoxBlock + (v % kVoxBlock);
+}
+__host__ inline long long blocked_elems(long long n_vox, int n_s) {
+  return (n_vox + kVoxBlock - 1) / kVoxBlock * (long long)n_s * kVoxBlock;
 }
 
 struct ShellDev {
@@ -52,10 +68,26 @@ struct ShellPassPlan {
 void plan_shell_passes(const ShellGeometry& g, bool f64, ShellPassPlan& p);
 
 hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, const float2* tw, hipStream_t st);
-hipError_t launch_data_shells(const float2* spec, float2* a1, float2* a2, float* F, long long field_stride,
-                              const ShellLaunch& L, int n, const float2* tw, hipStream_t st);
-hipError_t launch_unit_shells(double2* a1, double2* a2, double* I, long long field_stride, const ShellLaunch& L, int n,
-                              const double2* tw, hipStream_t st);
+// the three inverse passes of every shell (fft_inv_x.hip, fft_inv_y.hip, fft_c2r.hip)
+hipError_t launch_inv_x_f32(const float2* spec, float2* a1, const ShellLaunch& L, int n, const float2* tw,
+                            hipStream_t st);
+hipError_t launch_inv_x_unit_f64(double2* a1, const ShellLaunch& L, int n, const double2* tw, hipStream_t st);
+hipError_t launch_inv_y_f32(const float2* a1, float2* a2, const ShellLaunch& L, int n, const float2* tw,
+                            hipStream_t st);
+hipError_t launch_inv_y_f64(const double2* a1, double2* a2, const ShellLaunch& L, int n, const double2* tw,
+                            hipStream_t st);
+hipError_t launch_c2r_f32(const float2* a2, float* F, __bf16* f_hi, __bf16* f_lo, const ShellLaunch& L, int n,
+                          const float2* tw, hipStream_t st);
+hipError_t launch_c2r_f64(const double2* a2, double* I, const ShellLaunch& L, int n, const double2* tw,
+                          hipStream_t st);
+// F_hi/F_lo (optional, both or neither): bf16 planes hi = bf16(F), lo = bf16(F - hi)
+// Fields are written voxel-blocked (vox_index).
+hipError_t launch_data_shells(const float2* spec, float2* a1, float2* a2, float* F, const ShellLaunch& L, int n,
+                              const float2* tw, __bf16* f_hi, __bf16* f_lo, hipStream_t st);
+hipError_t launch_unit_shells(double2* a1, double2* a2, double* I, const ShellLaunch& L, int n, const double2* tw,
+                              hipStream_t st);
+// dst[v] = F[vox_index(v, shell, n_s)] for v < n_vox (float32)
+hipError_t launch_unblock(const float* F, int shell, int n_s, long long n_vox, float* dst, hipStream_t st);
 
 // ---- contraction ---------------------------------------------------------------
 struct ContractArgs {
@@ -73,7 +105,21 @@ struct ContractArgs {
 
 hipError_t launch_contract_fp32(const float* F, const ContractArgs& a, hipStream_t st);
 hipError_t launch_contract_fp64(const double* F, const ContractArgs& a, hipStream_t st);
-hipError_t launch_contract_bf16x3(const float* F, const ContractArgs& a, hipStream_t st);
+
+struct WsArgs {
+  const RowBlock* rows = nullptr;     // device [n_wg * kRbPerWg]
+  const RbCols* cols = nullptr;       // device [n_wg * kRbPerWg]
+  int n_wg = 0;                       // work groups per voxel range
+  const int32_t* tri_index = nullptr; // device [n_s^3]
+  int n_s = 0;
+  long long n_vox = 0;
+  int n_krange = 0;                   // multiple of 8
+  double* partial = nullptr;          // device [n_krange][n_tri]
+  long long n_tri = 0;
+};
+size_t bf16x3_lds_bytes(int n_s);
+hipError_t launch_contract_bf16x3(const float* F, const __bf16* f_hi, const __bf16* f_lo, const WsArgs& a,
+                                  hipStream_t st);
 // B[t] = norm[t] * sum_k partial[k][t] (fixed order, float64)
 hipError_t launch_reduce(const double* partial, int n_krange, long long n_tri, const double* norm, double* out,
                          hipStream_t st);
