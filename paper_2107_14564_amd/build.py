@@ -27,7 +27,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLU
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", INCLUDE, "-I", CSRC, "-Wall"]
 
-HIP_SOURCES = ["fft_forward.hip", "fft_inv_x.hip", "fft_inv_y.hip", "fft_c2r.hip", "contract_kernels.hip", "api.cpp"]
+HIP_SOURCES = ["fft_forward.hip", "fft_inv_x.hip", "fft_inv_y.hip", "fft_c2r.hip", "fft_adjoint.hip", "contract_kernels.hip", "api.cpp"]
 HOST_SOURCES = ["geometry.cpp"]
 
 

@@ -107,7 +107,10 @@ struct bispec_plan_s {
   DevBuf spec, F, a1, a2, partial, norm, tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols, shells, x_tiles,
       y_off, z_off, tw32;
   DevBuf Fh, Fl;   // bf16 hi/lo planes of F (column operands of the split-bf16 contraction)
-  DevBuf G;
+  // gradient workspace (BISPEC_FLAG_GRAD)
+  DevBuf G, g_terms, g_term_off, g_w, ball_shells, ball_x, ball_y, ball_z;
+  long long n_terms = 0;
+  ShellPassPlan pass_ball;   // one pseudo-shell covering every shell mode (inverse of the gathered spectrum)
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   ~bispec_plan_s() {
     for (auto& e : ev)
@@ -146,7 +149,7 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   s.fields64 = (size_t)blocked_elems(s.n_vox, p.geo.n_s) * sizeof(double);
   s.a1_64 = (size_t)p64.a1_elems * sizeof(double2);
   s.a2_64 = (size_t)p64.a2_elems * sizeof(double2);
-  s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 : 0;
+  s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 + (size_t)3 * s.n_tri * (sizeof(int4) + sizeof(float)) : 0;
   const long long ntasks = (long long)p.tiles.task_off.size() - 1;
   const long long n_wg_mfma = (long long)p.mfma.rows.size() / kRbPerWg;
   p.n_krange_vec = n_krange_for(ntasks, s.n_vox);
@@ -389,7 +392,39 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
   PLAN_HIP(dalloc(p->F, p->sz.fields32));
   PLAN_HIP(dalloc(p->Fh, p->sz.fields32 / 2));
   PLAN_HIP(dalloc(p->Fl, p->sz.fields32 / 2));
-  if (p->cfg.flags & BISPEC_FLAG_GRAD) PLAN_HIP(dalloc(p->G, p->sz.grad));
+  if (p->cfg.flags & BISPEC_FLAG_GRAD) {
+    PLAN_HIP(dalloc(p->G, p->sz.fields32));
+    // terms (t, j, l) of every shell n: d(F_a1 F_a2 F_a3)/dF_n
+    std::vector<std::vector<int4>> per(ns);
+    for (size_t t = 0; t < p->sel.tri.size(); ++t) {
+      const Tri& q = p->sel.tri[t];
+      per[q.a1 - 1].push_back(make_int4((int)t, q.a2 - 1, q.a3 - 1, 0));
+      per[q.a2 - 1].push_back(make_int4((int)t, q.a1 - 1, q.a3 - 1, 0));
+      per[q.a3 - 1].push_back(make_int4((int)t, q.a1 - 1, q.a2 - 1, 0));
+    }
+    std::vector<int4> terms;
+    std::vector<int32_t> off(1, 0);
+    for (int n = 0; n < ns; ++n) {
+      terms.insert(terms.end(), per[n].begin(), per[n].end());
+      off.push_back((int32_t)terms.size());
+    }
+    p->n_terms = (long long)terms.size();
+    PLAN_HIP(upload(p->g_terms, terms, s));
+    PLAN_HIP(upload(p->g_term_off, off, s));
+    PLAN_HIP(dalloc(p->g_w, terms.size() * sizeof(float)));
+    // the gathered spectrum S lives on the modes of shells 1..n_s: one pseudo-shell
+    ShellGeometry ball;
+    ball.n_g = p->geo.n_g;
+    ball.n_s = 1;
+    ball.lo2 = {p->geo.lo2[0]};
+    ball.hi2 = {p->geo.hi2[ns - 1]};
+    ball.rad = {p->geo.rad[ns - 1]};
+    plan_shell_passes(ball, false, p->pass_ball);
+    PLAN_HIP(upload(p->ball_shells, p->pass_ball.shells, s));
+    PLAN_HIP(upload(p->ball_x, p->pass_ball.x_tiles, s));
+    PLAN_HIP(upload(p->ball_y, p->pass_ball.y_off, s));
+    PLAN_HIP(upload(p->ball_z, p->pass_ball.z_off, s));
+  }
   if (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING)
     for (auto& e : p->ev) PLAN_HIP(hipEventCreate(&e));
   PLAN_HIP(hipStreamSynchronize(s));
@@ -460,10 +495,24 @@ int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream)
 
 int bispec_grad(bispec_plan_t p, const double* gB, float* gdelta, void* hip_stream) {
   if (!p || !gB || !gdelta) return set_err(BISPEC_EINVAL, "null argument");
-  (void)hip_stream;
   if (!(p->cfg.flags & BISPEC_FLAG_GRAD)) return set_err(BISPEC_ESTATE, "plan was made without BISPEC_FLAG_GRAD");
   if (!p->ran) return set_err(BISPEC_ESTATE, "bispec_grad needs a preceding bispec_run");
-  return set_err(BISPEC_ESTATE, "gradient not available in this build");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int n = p->geo.n_g;
+  // G_n = sum_t gB_t norm_t d(F_a1 F_a2 F_a3)/dF_n on the (scaled) fields of the last run
+  HIP_TRY(launch_gbuild(p->F.as<float>(), gB, p->norm.as<double>(), p->g_terms.as<int4>(), p->n_terms,
+                        p->g_term_off.as<int32_t>(), p->geo.n_s, p->sz.n_vox, p->g_w.as<float>(), p->G.as<float>(),
+                        s));
+  // S = sum_n mask_n Z DFT(G_n) * N^{-3/2}, gathered into the spectrum buffer
+  ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s);
+  const float scale = (float)std::pow((double)n, -1.5);
+  HIP_TRY(launch_adjoint_shells(p->G.as<float>(), p->a1.as<float2>(), p->a2.as<float2>(), p->spec.as<float2>(), L, n,
+                                p->tw32.as<float2>(), scale, (float)p->geo.beta, s));
+  // gdelta = unnormalised inverse transform of S (one pseudo-shell: natural layout)
+  ShellLaunch B = shell_launch(p->pass_ball, p->ball_shells, p->ball_x, p->ball_y, p->ball_z, 1);
+  HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), gdelta, B, n,
+                             p->tw32.as<float2>(), nullptr, nullptr, s));
+  return BISPEC_OK;
 }
 
 int bispec_stage_times(bispec_plan_t p, float* ms, int32_t n) {

@@ -460,6 +460,50 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
     ws_producer(F, fh, fl, a, L, R, wg, threadIdx.x - 256);
 }
 
+// ============================================================================
+// Adjoint field build (gradient of L = sum_t gB_t B_t with respect to the
+// scaled shell fields): for every shell n and voxel x
+//   G_n(x) = sum over the terms (t, j, l) of n of w_t F_j(x) F_l(x),
+// where each selected triangle (a1, a2, a3) contributes the terms (t, a2, a3)
+// to G_a1, (t, a1, a3) to G_a2 and (t, a1, a2) to G_a3 (the three factors of
+// d(F_a1 F_a2 F_a3)), and w_t = gB_t * norm_t.  Thread = voxel; the F block
+// of kGbVox voxels x n_s shells is staged in LDS; G is written voxel-blocked.
+// ============================================================================
+constexpr int kGbVox = 128;
+
+__global__ void k_gweights(const double* __restrict__ gB, const double* __restrict__ norm,
+                           const int4* __restrict__ terms, long long n_terms, float* __restrict__ w) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_terms) w[k] = (float)(gB[terms[k].x] * norm[terms[k].x]);
+}
+
+__global__ void __launch_bounds__(kGbVox) k_gbuild(const float* __restrict__ F, const int4* __restrict__ terms,
+                                                   const float* __restrict__ w,
+                                                   const int32_t* __restrict__ term_off, int n_s,
+                                                   float* __restrict__ G) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* f = reinterpret_cast<float*>(smem_raw);  // [n_s][kGbVox]
+  const long long blk0 = (long long)blockIdx.x * (kGbVox / kVoxBlock);
+  // stage: kGbVox/32 voxel blocks, each n_s x 32 contiguous
+  for (int e = threadIdx.x; e < n_s * kGbVox; e += kGbVox) {
+    const int b = e / (n_s * kVoxBlock), r = e % (n_s * kVoxBlock);
+    const int sh = r / kVoxBlock, v = r % kVoxBlock;
+    f[sh * kGbVox + b * kVoxBlock + v] = F[(blk0 + b) * (long long)n_s * kVoxBlock + r];
+  }
+  __syncthreads();
+  const int v = threadIdx.x;
+  float* g = G + (blk0 + v / kVoxBlock) * (long long)n_s * kVoxBlock + (v % kVoxBlock);
+  for (int n = 0; n < n_s; ++n) {
+    float acc = 0.f;
+    const int k1 = term_off[n + 1];
+    for (int k = term_off[n]; k < k1; ++k) {
+      const int4 tm = terms[k];
+      acc = fmaf(w[k] * f[tm.y * kGbVox + v], f[tm.z * kGbVox + v], acc);
+    }
+    g[n * kVoxBlock] = acc;
+  }
+}
+
 __global__ void k_reduce(const double* __restrict__ partial, int n_krange, long long n_tri,
                          const double* __restrict__ norm, double* __restrict__ out) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -500,6 +544,19 @@ hipError_t launch_contract_bf16x3(const float* F, const __bf16* f_hi, const __bf
   if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)a.n_wg * (unsigned)a.n_krange;
   hipLaunchKernelGGL(k_contract_bf16x3, dim3(blocks), dim3(kWsThreads), lds, st, F, f_hi, f_lo, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, const int4* terms, long long n_terms,
+                        const int32_t* term_off, int n_s, long long n_vox, float* w, float* G, hipStream_t st) {
+  if (n_vox % kGbVox) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gweights, dim3((unsigned)((n_terms + 255) / 256)), dim3(256), 0, st, gB, norm, terms, n_terms,
+                     w);
+  const size_t lds = (size_t)n_s * kGbVox * sizeof(float);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gbuild, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gbuild, dim3((unsigned)(n_vox / kGbVox)), dim3(kGbVox), lds, st, F, terms, w, term_off, n_s,
+                     G);
   return hipGetLastError();
 }
 

@@ -260,3 +260,131 @@ __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, O
 #define BISPEC_FOR_EACH_N(X) \
   X(8) X(16) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512) X(640) \
   X(768) X(1024)
+
+// ============================================================================
+// Adjoint passes (gradient of sum_t gB_t B_t): the forward transform of every
+// G_n, pruned to the modes of shell n, scattered into one half spectrum S.
+// They mirror the inverse passes: z (R2C, keep kz <= R) -> A2_n, y (keep
+// |ky| <= R) -> A1_n, x (keep the modes of shell n) -> S.
+// ============================================================================
+namespace bispec {
+namespace fftk {
+
+// z: G_n line (x, y) (voxel-blocked) -> A2_n[x][y][0..R] (forward R2C, unnormalised)
+template <int N>
+__global__ void __launch_bounds__(kThrZ) k_g_r2c_z(const float* __restrict__ G, float2* __restrict__ a2,
+                                                   const long long* __restrict__ blk_off, int n_shells,
+                                                   const ShellDev* __restrict__ sh, const float2* __restrict__ tw) {
+  constexpr int M = N / 2;
+  constexpr int NL = fft_z_lines(M, false);
+  constexpr int LS = M + 1;
+  __shared__ float2 buf[NL * LS];
+  const long long b = blockIdx.x;
+  int lo = 0, hi = n_shells;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (blk_off[mid] <= b) lo = mid; else hi = mid;
+  }
+  const int sn = lo;
+  const ShellDev d = sh[sn];
+  const int wz = d.rad + 1;
+  const long long n_lines = (long long)N * N;
+  const long long line0 = (b - blk_off[sn]) * NL;
+  const int lines = (int)min((long long)NL, n_lines - line0);
+  for (int e = threadIdx.x; e < NL * M; e += kThrZ) {
+    const int c = e / M, q = e % M;
+    if (c < lines) {
+      const long long at = vox_index((line0 + c) * N + 2 * q, sn, n_shells);
+      buf[c * LS + q] = *reinterpret_cast<const float2*>(G + at);
+    }
+  }
+  __syncthreads();
+  ct_fft<float, M, NL, kThrZ, false, LS, 2>(buf, tw, -1.0f);
+  float2* dst = a2 + d.a2_off + line0 * wz;
+  for (int e = threadIdx.x; e < NL * wz; e += kThrZ) {
+    const int c = e / wz, k = e % wz;
+    if (c >= lines) continue;
+    const float2 zk = buf[c * LS + (k == M ? 0 : k)];
+    const float2 zc = conjv<float>(buf[c * LS + (k == 0 ? 0 : M - k)]);
+    const float2 a = scl<float>(add<float>(zk, zc), 0.5f);
+    const float2 dd = scl<float>(sub<float>(zk, zc), 0.5f);
+    const float2 bi = mk<float>(dd.y, -dd.x);
+    dst[(long long)c * wz + k] = add<float>(a, mul<float>(tw[k], bi));
+  }
+}
+
+// y: A2_n[x][.][kz] (kz <= R) -> forward FFT along y -> A1_n[x][ky + R][kz], |ky| <= R
+template <int N>
+__global__ void __launch_bounds__(kThrAxis) k_g_fwd_y(const float2* __restrict__ a2, float2* __restrict__ a1,
+                                                      const long long* __restrict__ tile_off, int n_shells,
+                                                      const ShellDev* __restrict__ sh,
+                                                      const float2* __restrict__ tw) {
+  constexpr int TW = fft_tile_cols(N, false);
+  __shared__ float2 buf[N * TW];
+  const long long b = blockIdx.x;
+  int lo = 0, hi = n_shells;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (tile_off[mid] <= b) lo = mid; else hi = mid;
+  }
+  const int sn = lo;
+  const ShellDev d = sh[sn];
+  const int R = d.rad;
+  const int n_ct = (R + 1 + TW - 1) / TW;
+  const long long local = b - tile_off[sn];
+  const int x = (int)(local / n_ct);
+  const int kz0 = (int)(local % n_ct) * TW;
+  const int cols = min(TW, R + 1 - kz0);
+  const int wy = 2 * R + 1, wz = R + 1;
+  const float2* src = a2 + d.a2_off + (long long)x * N * wz;
+  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
+    const int q = e / TW, c = e % TW;
+    buf[e] = c < cols ? src[(long long)q * wz + kz0 + c] : mk<float>(0.f, 0.f);
+  }
+  __syncthreads();
+  ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, tw, -1.0f);
+  float2* dst = a1 + d.a1_off + (long long)x * wy * wz;
+  for (int e = threadIdx.x; e < wy * TW; e += kThrAxis) {
+    const int ky = e / TW - R, c = e % TW;
+    if (c < cols) dst[(long long)(ky + R) * wz + kz0 + c] = buf[(ky < 0 ? ky + N : ky) * TW + c];
+  }
+}
+
+// x: tile (shell, ky, kz0): A1_n[.][ky + R][kz] -> forward FFT along x -> for the
+// modes of shell n: S[kx][ky][kz] = scale * Z(k) * value (shells are disjoint)
+template <int N>
+__global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__ a1, float2* __restrict__ S,
+                                                      const int4* __restrict__ tiles,
+                                                      const ShellDev* __restrict__ sh,
+                                                      const float2* __restrict__ tw, float scale, float beta) {
+  constexpr int M = N / 2;
+  constexpr int TW = fft_tile_cols(N, false);
+  __shared__ float2 buf[N * TW];
+  const int4 td = tiles[blockIdx.x];
+  const int sn = td.x, ky = td.y, kz0 = td.z;
+  const ShellDev d = sh[sn];
+  const int R = d.rad;
+  const int cols = min(TW, R + 1 - kz0);
+  const int wy = 2 * R + 1, wz = R + 1;
+  const float2* src = a1 + d.a1_off;
+  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
+    const int q = e / TW, c = e % TW;
+    buf[e] = c < cols ? src[((long long)q * wy + (ky + R)) * wz + kz0 + c] : mk<float>(0.f, 0.f);
+  }
+  __syncthreads();
+  ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, tw, -1.0f);
+  const int yrow = ky < 0 ? ky + N : ky;
+  const long long ky2 = (long long)ky * ky;
+  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
+    const int q = e / TW, c = e % TW;
+    if (c >= cols) continue;
+    const long long mx = freq(q, N), kz = kz0 + c;
+    const long long m2 = mx * mx + ky2 + kz * kz;
+    if (m2 < d.lo2 || m2 >= d.hi2) continue;
+    const float z = 1.0f + beta * (float)((double)(kz * kz) / (double)m2);
+    S[((long long)q * N + yrow) * (M + 1) + kz] = scl<float>(buf[e], scale * z);
+  }
+}
+
+}  // namespace fftk
+}  // namespace bispec

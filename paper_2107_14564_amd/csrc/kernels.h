@@ -120,6 +120,14 @@ struct WsArgs {
 size_t bf16x3_lds_bytes(int n_s);
 hipError_t launch_contract_bf16x3(const float* F, const __bf16* f_hi, const __bf16* f_lo, const WsArgs& a,
                                   hipStream_t st);
+// Gradient: w_k = gB[t_k] norm[t_k]; G_n = sum_{terms (t, j, l) of n} w F_j F_l
+// (terms: int4 (t, j, l, 0) with 0-based shells, grouped by n via term_off[n_s + 1])
+hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, const int4* terms, long long n_terms,
+                        const int32_t* term_off, int n_s, long long n_vox, float* w, float* G, hipStream_t st);
+// pruned forward transforms of every G_n, scattered (times scale * Z) into the half spectrum S
+hipError_t launch_adjoint_shells(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, int n,
+                                 const float2* tw, float scale, float beta, hipStream_t st);
+
 // B[t] = norm[t] * sum_k partial[k][t] (fixed order, float64)
 hipError_t launch_reduce(const double* partial, int n_krange, long long n_tri, const double* norm, double* out,
                          hipStream_t st);

@@ -1,0 +1,118 @@
+"""Gradient (vector-Jacobian product) of the HIP path against the FP64 oracle.
+
+dL/d delta for L = sum_t v_t B_t is linear in v; the GPU computes it in
+float32 (fields, adjoint fields, FFTs) and is compared normwise with the
+oracle's float64 adjoint (itself pinned to the direct-sum gradient and to
+finite differences).  Tolerance: 1e-5 normwise and in max-norm relative to
+max|g| (float32 FFTs leave ~3e-7 per field value)."""
+import numpy as np
+import pytest
+
+from gpu_util import gpu_ok, say, to_gpu
+from oracle import adjoint, analytic, fbe, geometry
+from synth import PowerLaw, gaussian_field, quadratic_ng_field, workload_field
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ok(), reason="needs a GPU")]
+
+TOL = 1e-5
+
+
+def _cmp(g_gpu, g_ref, tol=TOL):
+    e_norm = float(np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref))
+    e_max = float(np.max(np.abs(g_gpu - g_ref)) / np.max(np.abs(g_ref)))
+    say("  grad e_norm %.3g e_max %.3g" % (e_norm, e_max))
+    assert e_norm <= tol and e_max <= tol
+    return e_norm
+
+
+@pytest.mark.parametrize("n_g,box,dk,n_s,beta", [(16, 100.0, 1.0, 4, 0.0), (16, 100.0, 1.0, 4, 0.5),
+                                                 (32, 300.0, 1.0, 10, 0.0), (48, 200.0, 1.5, 9, 1.0)])
+def test_vjp_matches_oracle(n_g, box, dk, n_s, beta):
+    import torch
+    import paper_2107_14564_amd as P
+    say("vjp n_g=%d n_s=%d beta=%g" % (n_g, n_s, beta))
+    d = quadratic_ng_field(gaussian_field(n_g, box, PowerLaw(-1.0), 300 + n_g), 1.0)
+    dg, d64 = to_gpu(d)
+    plan = P.Plan(n_g, box, dk, n_s, rsd_beta=beta, flags=P.FLAG_GRAD)
+    plan.run(dg)
+    v = np.random.default_rng(7).standard_normal(plan.n_tri)
+    g = plan.grad(torch.from_numpy(v).cuda()).cpu().numpy().astype(np.float64)
+    ref = adjoint.gradient(d64, box, dk, plan.triangles.numpy(), v, rsd_beta=beta, ntri=plan.ntri.numpy())
+    _cmp(g, ref)
+    plan.close()
+
+
+def test_grad_requires_flag_and_run():
+    import torch
+    import paper_2107_14564_amd as P
+    plan = P.Plan(16, 100.0, 1.0, 3)
+    with pytest.raises(P.BispecError) as e:
+        plan.grad(torch.zeros(plan.n_tri, dtype=torch.float64))
+    assert e.value.status == -5
+    plan2 = P.Plan(16, 100.0, 1.0, 3, flags=P.FLAG_GRAD)
+    with pytest.raises(P.BispecError) as e:
+        plan2.grad(torch.zeros(plan2.n_tri, dtype=torch.float64))
+    assert e.value.status == -5
+    plan.close()
+    plan2.close()
+
+
+def test_autograd_function():
+    import torch
+    import paper_2107_14564_amd as P
+    d = quadratic_ng_field(gaussian_field(32, 300.0, PowerLaw(-1.0), 41), 1.0)
+    dg, _ = to_gpu(d)
+    plan = P.Plan(32, 300.0, 1.0, 8, flags=P.FLAG_GRAD)
+    x = dg.clone().requires_grad_(True)
+    B = P.bispectrum(x, plan)
+    w = torch.linspace(-1, 1, plan.n_tri, dtype=torch.float64, device=B.device)
+    (B * w).sum().backward()
+    direct = plan.grad(w)
+    assert torch.equal(x.grad, direct)
+    plan.close()
+
+
+@pytest.mark.timeout(600)
+def test_chi2_gradient_ng256_30_shells():
+    """The differentiation workload: N_g = 256, L = 1000 Mpc, P = k^-1, f_NG = 1,
+    30 shells of one k_f, a1 in {29, 30} (494 triangles); loss
+    chi^2 = sum (B - B_target)^2 / sigma^2 with B_target the tree-level B at the
+    bin labels and sigma = 0.1 |B_target|.  GPU gradient vs the float64 oracle
+    gradient, and a central directional difference of the GPU loss."""
+    import torch
+    import paper_2107_14564_amd as P
+    n_g, box = 256, 1000.0
+    d = workload_field("ng256_grad")
+    dg, d64 = to_gpu(d)
+    plan = P.Plan(n_g, box, 1.0, 30, tri_mode=P.TRI_K1SET, k1_shells=[29, 30], flags=P.FLAG_GRAD,
+                  precision=P.PREC_FP32)
+    assert plan.n_tri == 494
+    lab = plan.labels.numpy()
+    k1 = lab[:, 0]
+    k2 = lab[:, 2] * k1
+    mu = lab[:, 1]
+    k3 = k1 * np.sqrt(np.maximum(0.0, 1 + (k2 / k1) ** 2 - 2 * mu * (k2 / k1)))
+    b_t = analytic.b_tree(k1, k2, k3, PowerLaw(-1.0), 1.0)
+    sig = 0.1 * np.abs(b_t)
+    B = plan.run(dg).cpu().numpy()
+    gB = 2.0 * (B - b_t) / sig ** 2
+    g = plan.grad(torch.from_numpy(gB).cuda()).cpu().numpy().astype(np.float64)
+    say("  chi2 = %.6g" % float(np.sum((B - b_t) ** 2 / sig ** 2)))
+    ref = adjoint.gradient(d64, box, 1.0, plan.triangles.numpy(), gB, ntri=plan.ntri.numpy())
+    _cmp(g, ref)
+
+    # directional derivative along a smooth random direction, by central differences of the GPU loss
+    u = gaussian_field(n_g, box, PowerLaw(-2.0), 5003)
+    u /= np.sqrt(np.mean(u * u))
+    eps = 1e-2 * np.sqrt(np.mean(d * d))
+
+    def chi2(field):
+        t, _ = to_gpu(field)
+        b = plan.run(t).cpu().numpy()
+        return float(np.sum((b - b_t) ** 2 / sig ** 2))
+    # five-point stencil: exact through degree 4, truncation O(eps^4) for the degree-6 loss
+    fd = (8.0 * (chi2(d + eps * u) - chi2(d - eps * u)) - (chi2(d + 2 * eps * u) - chi2(d - 2 * eps * u))) / (12 * eps)
+    an = float(np.sum(g * u))
+    say("  directional: fd %.8g adjoint %.8g" % (fd, an))
+    assert abs(fd - an) <= 1e-4 * abs(an)
+    plan.close()
