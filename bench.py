@@ -117,10 +117,11 @@ def main():
     assert np.all(np.isfinite(b_host)), "non-finite B"
 
     n = w["n_g"]
-    n_vox = float(n) ** 3
+    g = plan.n_est
+    n_vox = float(g) ** 3       # the triple sums run over the estimator grid
     tri = plan.triangles.numpy()
     n_pairs = len({(int(a), int(b)) for a, b, _ in tri})
-    # algorithmic work of the contraction: 2 N^3 flop per triangle + N^3 per distinct shell pair product
+    # algorithmic work of the contraction: 2 G^3 flop per triangle + G^3 per distinct shell pair product
     flop = n_vox * (2.0 * plan.n_tri + n_pairs)
     contract_ms = float(stages[2])
     achieved = flop / (contract_ms * 1e-3) / 1e12
@@ -137,7 +138,7 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16x3-fp32acc" if prec == P.PREC_SPLITBF16 else "fp32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_g": n, "box_l": w["box_l"], "n_shells": w["n_shells"],
+        "config": {"workload": args.workload, "n_g": n, "n_est": g, "box_l": w["box_l"], "n_shells": w["n_shells"],
                    "dk_kf": w["dk"], "rsd_beta": w["rsd_beta"], "n_tri": plan.n_tri, "precision": args.precision},
         "stages_ms": {"forward_fft": stages[0], "shell_ffts": stages[1], "contraction": stages[2],
                       "normalise": stages[3]},
@@ -145,8 +146,8 @@ def main():
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
                      "kernel": "k_contract_bf16x3" if prec == P.PREC_SPLITBF16 else "k_contract_vec<float>",
                      "algorithmic_flop": flop},
-        "fft_hbm": {"algorithmic_bytes": (8.0 * n_vox + 4.0 * n_vox * w["n_shells"]),
-                    "achieved_GBs": (8.0 * n_vox + 4.0 * n_vox * w["n_shells"]) / ((stages[0] + stages[1]) * 1e-3) / 1e9,
+        "fft_hbm": {"algorithmic_bytes": (8.0 * n ** 3 + 4.0 * n_vox * w["n_shells"]),
+                    "achieved_GBs": (8.0 * n ** 3 + 4.0 * n_vox * w["n_shells"]) / ((stages[0] + stages[1]) * 1e-3) / 1e9,
                     "peak_GBs": PEAK_HBM_GBS},
         "plan_s": plan_s,
     }

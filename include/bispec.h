@@ -27,6 +27,12 @@
  *   - A bin is closable when a2 + a3 >= a1; only closable bins are selected.
  *   - Every used mode must lie below the aliasing cutoff: (n_shells + 1/2) w <= N_g/3,
  *     else BISPEC_ECUTOFF.
+ *   - The shell fields and the triple sums live on an estimator grid of G <= N_g
+ *     points per side with G > 3 max|m_i| over every shell mode: Section 2.2's
+ *     aliasing argument applied to G shows that the G^3-point sums of
+ *     eqs. bsfin and Ntri2 (with N_g^3 replaced by G^3) pick exactly the same
+ *     closed triangles, so B and N_tri do not depend on G.  Only the forward
+ *     transform (and the last inverse of bispec_grad) runs at N_g.
  *   - delta is float32 [N_g][N_g][N_g], z fastest (C order), on the device.
  *   - B is float64 [n_tri] on the device, ordered like bispec_triangles().
  *
@@ -97,6 +103,9 @@ typedef struct bispec_config {
   const int32_t* list;    /* LIST: host array [n_list][3] (a1,a2,a3), a1>=a2>=a3>=1 */
   int32_t precision;      /* enum bispec_precision                                  */
   uint32_t flags;         /* enum bispec_flags                                      */
+  int32_t n_est;          /* estimator grid G for the shell fields and triple sums:  */
+                          /*   0 = the smallest supported size above 3 max|m_i|;    */
+                          /*   else a supported size with 3 max|m_i| < n_est <= n_g */
 } bispec_config;
 
 /* ---- host-only queries (no GPU needed) ------------------------------------ */
@@ -111,6 +120,9 @@ int bispec_query_triangles(const bispec_config* cfg, int64_t* n_tri, int32_t* ab
 /* Per-shell mode counts (host int64 [n_shells], both halves of k-space) and
  * mean |k| (host double [n_shells], in k units), Section 2.1's k_n. */
 int bispec_shell_stats(const bispec_config* cfg, int64_t* counts, double* mean_k);
+
+/* The estimator grid G that a plan of cfg would use (see n_est). */
+int bispec_estimator_grid(const bispec_config* cfg, int32_t* n_est);
 
 /* Device bytes the plan keeps (run_bytes) and its peak during planning
  * (plan_peak_bytes, which includes the float64 unit shells). */
@@ -154,8 +166,9 @@ int bispec_set_precision(bispec_plan_t plan, int32_t precision);
  * shell FFTs, ms[2] contraction, ms[3] normalisation.  n = entries wanted (<= 4). */
 int bispec_stage_times(bispec_plan_t plan, float* ms, int32_t n);
 
-/* Inspection (tests): copy the data shell D_n of the last run, divided by
- * dV N_g^{3/2} (the plan's internal scale), into dst (device float32 [N_g^3]). */
+/* Inspection (tests): copy the data shell D_n of the last run on the estimator
+ * grid, divided by dV N_g^{3/2} (the plan's internal scale), into dst
+ * (device float32 [G^3], G from bispec_estimator_grid). */
 int bispec_copy_field(bispec_plan_t plan, int32_t shell, float* dst, void* hip_stream);
 
 int bispec_destroy(bispec_plan_t plan);

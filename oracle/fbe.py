@@ -83,6 +83,22 @@ def shell_field(spec: np.ndarray, mask: np.ndarray) -> np.ndarray:
     return _irfftn(np.where(mask, spec, 0.0), s=(n_g, n_g, n_g)) * float(n_g) ** 3
 
 
+def shell_field_at(spec: np.ndarray, mask: np.ndarray, n_eval: int) -> np.ndarray:
+    """D_n at the points x_j = L j / n_eval (j in [0, n_eval)^3) of a grid other
+    than the input one: the same mode sum, sum_{k in shell} Delta(k) e^{ik.x_j},
+    evaluated by placing each shell mode at its signed frequency in an n_eval
+    half spectrum (every mode must satisfy |m_i| < n_eval / 2)."""
+    n_g = spec.shape[0]
+    mx, my, mz = half_grid_m(n_g)
+    sel = np.nonzero(mask)
+    fx, fy, fz = mx.ravel()[sel[0]], my.ravel()[sel[1]], mz.ravel()[sel[2]]
+    if len(fx) and max(np.abs(fx).max(), np.abs(fy).max(), fz.max()) * 2 >= n_eval:
+        raise ValueError("shell modes do not fit the evaluation grid")
+    out = np.zeros((n_eval, n_eval, n_eval // 2 + 1), dtype=np.complex128)
+    out[fx % n_eval, fy % n_eval, fz] = spec[sel]
+    return _irfftn(out, s=(n_eval,) * 3) * float(n_eval) ** 3
+
+
 def unit_field(mask: np.ndarray) -> np.ndarray:
     """I_n(x) = sum_{k in shell} e^{ik.x} = N^3 irfftn(mask)."""
     n_g = mask.shape[0]

@@ -31,7 +31,7 @@ class bispec_config(C.Structure):
         ("rsd_beta", C.c_double), ("tri_mode", C.c_int32), ("n_k1", C.c_int32),
         ("k1_shells", C.POINTER(C.c_int32)), ("n_mu", C.c_int32), ("n_t", C.c_int32),
         ("n_list", C.c_int64), ("list", C.POINTER(C.c_int32)), ("precision", C.c_int32),
-        ("flags", C.c_uint32),
+        ("flags", C.c_uint32), ("n_est", C.c_int32),
     ]
 
 
@@ -52,6 +52,7 @@ def lib() -> C.CDLL:
             "bispec_query_triangles": [cfgp, C.POINTER(I64), C.POINTER(I32), C.POINTER(D), I64],
             "bispec_shell_stats": [cfgp, C.POINTER(I64), C.POINTER(D)],
             "bispec_workspace_bytes": [cfgp, C.POINTER(I64), C.POINTER(I64)],
+            "bispec_estimator_grid": [cfgp, C.POINTER(I32)],
             "bispec_plan": [cfgp, P, C.POINTER(P)],
             "bispec_num_triangles": [P, C.POINTER(I64)],
             "bispec_triangles": [P, C.POINTER(I32), C.POINTER(D), C.POINTER(I64)],
@@ -86,7 +87,7 @@ def _i32_array(values):
 
 
 def make_config(n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=TRI_ALL, k1_shells=None, n_mu=0, n_t=0,
-                triangles=None, precision=PREC_SPLITBF16, flags=0):
+                triangles=None, precision=PREC_SPLITBF16, flags=0, n_est=0):
     """A bispec_config plus the ctypes arrays it points into (keep both alive)."""
     k1, nk1 = _i32_array(k1_shells)
     flat = None if triangles is None else [int(v) for row in triangles for v in row]
@@ -96,7 +97,7 @@ def make_config(n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=TRI_ALL, k1_she
                         k1_shells=C.cast(k1, C.POINTER(C.c_int32)) if k1 is not None else None,
                         n_mu=int(n_mu), n_t=int(n_t), n_list=nflat // 3,
                         list=C.cast(lst, C.POINTER(C.c_int32)) if lst is not None else None,
-                        precision=int(precision), flags=int(flags))
+                        precision=int(precision), flags=int(flags), n_est=int(n_est))
     return cfg, (k1, lst)
 
 
@@ -123,6 +124,12 @@ def bispec_workspace_bytes(cfg):
     run, peak = C.c_int64(0), C.c_int64(0)
     _check(lib().bispec_workspace_bytes(C.byref(cfg), C.byref(run), C.byref(peak)), "bispec_workspace_bytes")
     return run.value, peak.value
+
+
+def bispec_estimator_grid(cfg) -> int:
+    n = C.c_int32(0)
+    _check(lib().bispec_estimator_grid(C.byref(cfg), C.byref(n)), "bispec_estimator_grid")
+    return n.value
 
 
 def bispec_plan(cfg, stream: int = 0) -> int:

@@ -97,6 +97,7 @@ struct bispec_plan_s {
   TilePlan tiles;        // tasks of <= kMaxTilesPerTask tiles (vector kernels)
   MfmaTiling mfma;       // span-grouped row blocks (MFMA kernel)
   ShellPassPlan pass32;
+  ShellPassPlan pass_ball;   // one pseudo-shell covering every shell mode at n_g (last inverse of grad)
   Sizes sz;
   std::vector<int64_t> ntri;
   int precision = BISPEC_PREC_SPLITBF16;
@@ -104,13 +105,13 @@ struct bispec_plan_s {
   bool ran = false;
   int device = 0;
   // device memory
-  DevBuf spec, F, a1, a2, partial, norm, tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols, shells, x_tiles,
-      y_off, z_off, tw32;
+  DevBuf spec, F, a1, a2, partial, partial_mfma, norm, tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols,
+      mfma_wgrows, mfma_slot, shells, x_tiles,
+      y_off, z_off, tw32, tw32e;
   DevBuf Fh, Fl;   // bf16 hi/lo planes of F (column operands of the split-bf16 contraction)
   // gradient workspace (BISPEC_FLAG_GRAD)
   DevBuf G, g_terms, g_term_off, g_w, ball_shells, ball_x, ball_y, ball_z;
   long long n_terms = 0;
-  ShellPassPlan pass_ball;   // one pseudo-shell covering every shell mode (inverse of the gathered spectrum)
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   ~bispec_plan_s() {
     for (auto& e : ev)
@@ -129,37 +130,52 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   int st = build_shells(*cfg, p.geo, err);
   if (st) return set_err(st, err);
   if (p.geo.n_s > 256) return set_err(BISPEC_EINVAL, "n_shells > 256 is not supported by the contraction kernels");
-  if (cfg->precision == BISPEC_PREC_SPLITBF16 && p.geo.n_s > kCols * kMaxColTiles)
+  if (cfg->precision == BISPEC_PREC_SPLITBF16 && p.geo.n_s > 128)
     return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 128");
   st = select_triangles(*cfg, p.geo, p.sel, err);
   if (st) return set_err(st, err);
   build_tiles(p.sel, kMaxTilesPerTask, p.tiles);
-  build_mfma_tiles(p.sel, p.mfma);
-  plan_shell_passes(p.geo, false, p.pass32);
-  const long long n = p.geo.n_g;
+  build_mfma_tiles(p.sel, p.geo.n_s, p.mfma);
+  const long long n = p.geo.n_g, ne = p.geo.n_est;
+  plan_shell_passes(p.geo, (int)ne, false, p.pass32);
   Sizes& s = p.sz;
-  s.n_vox = n * n * n;
+  s.n_vox = ne * ne * ne;
   s.n_tri = (long long)p.sel.tri.size();
   s.spec = (size_t)n * n * (n / 2 + 1) * sizeof(float2);
   s.fields32 = (size_t)blocked_elems(s.n_vox, p.geo.n_s) * sizeof(float);
   s.a1_32 = (size_t)p.pass32.a1_elems * sizeof(float2);
   s.a2_32 = (size_t)p.pass32.a2_elems * sizeof(float2);
+  if (cfg->flags & BISPEC_FLAG_GRAD) {
+    // the gathered spectrum S lives on the modes of shells 1..n_s: one pseudo-shell at n_g
+    ShellGeometry ball;
+    ball.n_g = p.geo.n_g;
+    ball.n_est = p.geo.n_g;
+    ball.n_s = 1;
+    ball.lo2 = {p.geo.lo2[0]};
+    ball.hi2 = {p.geo.hi2[p.geo.n_s - 1]};
+    ball.rad = {p.geo.rad[p.geo.n_s - 1]};
+    plan_shell_passes(ball, (int)n, false, p.pass_ball);
+    s.a1_32 = std::max(s.a1_32, (size_t)p.pass_ball.a1_elems * sizeof(float2));
+    s.a2_32 = std::max(s.a2_32, (size_t)p.pass_ball.a2_elems * sizeof(float2));
+  }
   ShellPassPlan p64;
-  plan_shell_passes(p.geo, true, p64);
+  plan_shell_passes(p.geo, (int)ne, true, p64);
   s.fields64 = (size_t)blocked_elems(s.n_vox, p.geo.n_s) * sizeof(double);
   s.a1_64 = (size_t)p64.a1_elems * sizeof(double2);
   s.a2_64 = (size_t)p64.a2_elems * sizeof(double2);
   s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 + (size_t)3 * s.n_tri * (sizeof(int4) + sizeof(float)) : 0;
   const long long ntasks = (long long)p.tiles.task_off.size() - 1;
-  const long long n_wg_mfma = (long long)p.mfma.rows.size() / kRbPerWg;
   p.n_krange_vec = n_krange_for(ntasks, s.n_vox);
-  p.n_krange_mfma = n_krange_mfma_for(n_wg_mfma, s.n_vox);
-  s.partial_run = (size_t)std::max(p.n_krange_vec, p.n_krange_mfma) * s.n_tri * sizeof(double);
+  p.n_krange_mfma = n_krange_mfma_for(p.mfma.n_wg, s.n_vox);
+  s.partial_run = (size_t)p.n_krange_vec * s.n_tri * sizeof(double) +
+                  (size_t)p.n_krange_mfma * p.mfma.n_wg * kTilesPerWg * 1024 * sizeof(double);
   s.partial_plan = (size_t)p.n_krange_vec * s.n_tri * sizeof(double);
   s.tables = (size_t)p.geo.n_s * p.geo.n_s * p.geo.n_s * sizeof(int32_t) + p.tiles.rows.size() * sizeof(RowBlock) +
-             p.tiles.tiles.size() * sizeof(Tile) + p.mfma.rows.size() * (sizeof(RowBlock) + sizeof(RbCols)) +
+             p.tiles.tiles.size() * sizeof(Tile) + p.mfma.rows.size() * sizeof(RowBlock) +
+             p.mfma.cols.size() * sizeof(SlotCols) + p.mfma.wg_rows.size() * sizeof(WgRows) +
+             p.mfma.slot_of.size() * sizeof(int32_t) +
              p.pass32.x_tiles.size() * sizeof(int4) + (size_t)s.n_tri * 8 +
-             (size_t)n * 16 + 4096 * 4;
+             (size_t)(n + ne) * 16 + 4096 * 4;
   p.precision = cfg->precision;
   return BISPEC_OK;
 }
@@ -167,14 +183,15 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
 WsArgs ws_args(bispec_plan_s& p) {
   WsArgs a;
   a.rows = p.mfma_rows.as<RowBlock>();
-  a.cols = p.mfma_cols.as<RbCols>();
-  a.n_wg = (int)(p.mfma.rows.size() / kRbPerWg);
-  a.tri_index = p.tri_index.as<int32_t>();
+  a.cols = p.mfma_cols.as<SlotCols>();
+  a.wg_rows = p.mfma_wgrows.as<WgRows>();
+  a.n_wg = p.mfma.n_wg;
   a.n_s = p.geo.n_s;
+  a.max_f = p.mfma.max_f;
+  a.max_b = p.mfma.max_b;
   a.n_vox = p.sz.n_vox;
   a.n_krange = p.n_krange_mfma;
-  a.partial = p.partial.as<double>();
-  a.n_tri = p.sz.n_tri;
+  a.partial = p.partial_mfma.as<double>();
   return a;
 }
 
@@ -194,9 +211,10 @@ ContractArgs contract_args(bispec_plan_s& p, int n_krange) {
 }
 
 ShellLaunch shell_launch(const ShellPassPlan& pp, const DevBuf& shells, const DevBuf& xt, const DevBuf& yo,
-                         const DevBuf& zo, int n_s) {
+                         const DevBuf& zo, int n_s, int spec_n) {
   ShellLaunch L;
   L.n_shells = n_s;
+  L.spec_n = spec_n;
   L.shells = shells.as<ShellDev>();
   L.x_tiles = xt.as<int4>();
   L.n_x_tiles = (long long)pp.x_tiles.size();
@@ -213,11 +231,12 @@ size_t max_bytes_env() {
   return (size_t)std::strtoull(s, nullptr, 10);
 }
 
-// N_tri from the float64 unit shells (eqs. 2FT, Ntri2) on the GPU.
+// N_tri from the float64 unit shells (eqs. 2FT, Ntri2) on the GPU, on the
+// estimator grid: N_tri = G^-3 sum_y I_a1 I_a2 I_a3.
 int compute_ntri(bispec_plan_s& p, hipStream_t st) {
-  const int n = p.geo.n_g;
+  const int n = p.geo.n_est;
   ShellPassPlan pp;
-  plan_shell_passes(p.geo, true, pp);
+  plan_shell_passes(p.geo, n, true, pp);
   DevBuf I, a1, a2, shells, xt, yo, zo, tw;
   HIP_TRY(dalloc(I, p.sz.fields64));
   HIP_TRY(dalloc(a1, p.sz.a1_64));
@@ -232,7 +251,7 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
     t64[k] = make_double2(std::cos(ang), -std::sin(ang));
   }
   HIP_TRY(upload(tw, t64, st));
-  ShellLaunch L = shell_launch(pp, shells, xt, yo, zo, p.geo.n_s);
+  ShellLaunch L = shell_launch(pp, shells, xt, yo, zo, p.geo.n_s, p.geo.n_g);
   HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), L, n, tw.as<double2>(), st));
   a1.release();
   a2.release();
@@ -240,7 +259,8 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
   HIP_TRY(launch_contract_fp64(I.as<double>(), ca, st));
   DevBuf sums;
   HIP_TRY(dalloc(sums, (size_t)p.sz.n_tri * sizeof(double)));
-  HIP_TRY(launch_reduce(p.partial.as<double>(), p.n_krange_vec, p.sz.n_tri, nullptr, sums.as<double>(), st));
+  HIP_TRY(launch_reduce(p.partial.as<double>(), p.n_krange_vec, p.sz.n_tri, p.sz.n_tri, nullptr, nullptr,
+                        sums.as<double>(), st));
   std::vector<double> h(p.sz.n_tri);
   HIP_TRY(hipMemcpyAsync(h.data(), sums.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -305,6 +325,16 @@ int bispec_shell_stats(const bispec_config* cfg, int64_t* counts, double* mean_k
   return BISPEC_OK;
 }
 
+int bispec_estimator_grid(const bispec_config* cfg, int32_t* n_est) {
+  if (!cfg || !n_est) return set_err(BISPEC_EINVAL, "null argument");
+  std::string err;
+  ShellGeometry g;
+  int st = build_shells(*cfg, g, err);
+  if (st) return set_err(st, err);
+  *n_est = g.n_est;
+  return BISPEC_OK;
+}
+
 int bispec_workspace_bytes(const bispec_config* cfg, int64_t* run_bytes, int64_t* plan_peak_bytes) {
   bispec_plan_s p;
   int st = build_host(cfg, p);
@@ -362,7 +392,10 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
   PLAN_HIP(upload(p->task_off, p->tiles.task_off, s));
   PLAN_HIP(upload(p->mfma_rows, p->mfma.rows, s));
   PLAN_HIP(upload(p->mfma_cols, p->mfma.cols, s));
-  PLAN_HIP(dalloc(p->partial, p->sz.partial_run));
+  PLAN_HIP(upload(p->mfma_wgrows, p->mfma.wg_rows, s));
+  PLAN_HIP(upload(p->mfma_slot, p->mfma.slot_of, s));
+  PLAN_HIP(dalloc(p->partial_mfma, (size_t)p->n_krange_mfma * p->mfma.n_wg * kTilesPerWg * 1024 * sizeof(double)));
+  PLAN_HIP(dalloc(p->partial, (size_t)p->n_krange_vec * p->sz.n_tri * sizeof(double)));
   // N_tri first (largest memory phase), then the run workspace
   st = compute_ntri(*p, s);
   if (st) return fail(st);
@@ -371,17 +404,23 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
   PLAN_HIP(upload(p->y_off, p->pass32.y_off, s));
   PLAN_HIP(upload(p->z_off, p->pass32.z_off, s));
   {
-    const int n = p->geo.n_g;
-    std::vector<float2> t32(n);
-    for (int k = 0; k < n; ++k) {
-      const double ang = 2.0 * M_PI * (double)k / (double)n;
-      t32[k] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
-    }
-    PLAN_HIP(upload(p->tw32, t32, s));
-    // B = dV^3 N^{3/2} T_s / (V N_tri), T_s the triple sum of the scaled fields
+    const int n = p->geo.n_g, ne = p->geo.n_est;
+    auto twiddles = [](int m) {
+      std::vector<float2> t(m);
+      for (int k = 0; k < m; ++k) {
+        const double ang = 2.0 * M_PI * (double)k / (double)m;
+        t[k] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+      }
+      return t;
+    };
+    PLAN_HIP(upload(p->tw32, twiddles(n), s));
+    PLAN_HIP(upload(p->tw32e, twiddles(ne), s));
+    // The fields are F_s = D / (dV N^{3/2}) on G^3 points (forward transform
+    // scaled by N^{-3/2}); eq. bsfin with the sum over the G grid:
+    //   B = (dV N^{3/2})^3 sum_y F_s F_s F_s / (V N_tri G^3)
     const double V = p->geo.box_l * p->geo.box_l * p->geo.box_l;
     const double dV = V / ((double)n * n * n);
-    const double c = dV * dV * dV * std::pow((double)n, 1.5) / V;
+    const double c = dV * dV * dV * std::pow((double)n, 4.5) / (V * (double)ne * ne * ne);
     std::vector<double> norm(p->sz.n_tri);
     for (long long t = 0; t < p->sz.n_tri; ++t) norm[t] = p->ntri[t] > 0 ? c / (double)p->ntri[t] : NAN;
     PLAN_HIP(upload(p->norm, norm, s));
@@ -412,14 +451,6 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
     PLAN_HIP(upload(p->g_terms, terms, s));
     PLAN_HIP(upload(p->g_term_off, off, s));
     PLAN_HIP(dalloc(p->g_w, terms.size() * sizeof(float)));
-    // the gathered spectrum S lives on the modes of shells 1..n_s: one pseudo-shell
-    ShellGeometry ball;
-    ball.n_g = p->geo.n_g;
-    ball.n_s = 1;
-    ball.lo2 = {p->geo.lo2[0]};
-    ball.hi2 = {p->geo.hi2[ns - 1]};
-    ball.rad = {p->geo.rad[ns - 1]};
-    plan_shell_passes(ball, false, p->pass_ball);
     PLAN_HIP(upload(p->ball_shells, p->pass_ball.shells, s));
     PLAN_HIP(upload(p->ball_x, p->pass_ball.x_tiles, s));
     PLAN_HIP(upload(p->ball_y, p->pass_ball.y_off, s));
@@ -458,7 +489,7 @@ int bispec_set_precision(bispec_plan_t p, int32_t precision) {
   if (!p) return set_err(BISPEC_EINVAL, "null plan");
   if (precision != BISPEC_PREC_SPLITBF16 && precision != BISPEC_PREC_FP32)
     return set_err(BISPEC_EINVAL, "unknown precision");
-  if (precision == BISPEC_PREC_SPLITBF16 && p->geo.n_s > kCols * kMaxColTiles)
+  if (precision == BISPEC_PREC_SPLITBF16 && p->geo.n_s > 128)
     return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 128");
   p->precision = precision;
   return BISPEC_OK;
@@ -472,22 +503,24 @@ int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream)
   if (timing) HIP_TRY(hipEventRecord(p->ev[0], s));
   HIP_TRY(launch_forward(delta, p->spec.as<float2>(), n, (float)p->geo.beta, p->tw32.as<float2>(), s));
   if (timing) HIP_TRY(hipEventRecord(p->ev[1], s));
-  ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s);
+  ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s, n);
   const bool split = p->precision == BISPEC_PREC_SPLITBF16;
-  HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), p->F.as<float>(), L, n,
-                             p->tw32.as<float2>(), split ? p->Fh.as<__bf16>() : nullptr,
+  HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), p->F.as<float>(), L,
+                             p->geo.n_est, p->tw32e.as<float2>(), split ? p->Fh.as<__bf16>() : nullptr,
                              split ? p->Fl.as<__bf16>() : nullptr, s));
   if (timing) HIP_TRY(hipEventRecord(p->ev[2], s));
-  int nk;
   if (p->precision == BISPEC_PREC_FP32) {
-    nk = p->n_krange_vec;
-    HIP_TRY(launch_contract_fp32(p->F.as<float>(), contract_args(*p, nk), s));
+    HIP_TRY(launch_contract_fp32(p->F.as<float>(), contract_args(*p, p->n_krange_vec), s));
+    if (timing) HIP_TRY(hipEventRecord(p->ev[3], s));
+    HIP_TRY(launch_reduce(p->partial.as<double>(), p->n_krange_vec, p->sz.n_tri, p->sz.n_tri, nullptr,
+                          p->norm.as<double>(), B, s));
   } else {
-    nk = p->n_krange_mfma;
     HIP_TRY(launch_contract_bf16x3(p->F.as<float>(), p->Fh.as<__bf16>(), p->Fl.as<__bf16>(), ws_args(*p), s));
+    if (timing) HIP_TRY(hipEventRecord(p->ev[3], s));
+    HIP_TRY(launch_reduce(p->partial_mfma.as<double>(), p->n_krange_mfma,
+                          (long long)p->mfma.n_wg * kTilesPerWg * 1024, p->sz.n_tri, p->mfma_slot.as<int32_t>(),
+                          p->norm.as<double>(), B, s));
   }
-  if (timing) HIP_TRY(hipEventRecord(p->ev[3], s));
-  HIP_TRY(launch_reduce(p->partial.as<double>(), nk, p->sz.n_tri, p->norm.as<double>(), B, s));
   if (timing) HIP_TRY(hipEventRecord(p->ev[4], s));
   p->ran = true;
   return BISPEC_OK;
@@ -503,13 +536,13 @@ int bispec_grad(bispec_plan_t p, const double* gB, float* gdelta, void* hip_stre
   HIP_TRY(launch_gbuild(p->F.as<float>(), gB, p->norm.as<double>(), p->g_terms.as<int4>(), p->n_terms,
                         p->g_term_off.as<int32_t>(), p->geo.n_s, p->sz.n_vox, p->g_w.as<float>(), p->G.as<float>(),
                         s));
-  // S = sum_n mask_n Z DFT(G_n) * N^{-3/2}, gathered into the spectrum buffer
-  ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s);
+  // S = sum_n mask_n Z DFT_G(G_n) * N^{-3/2}, gathered into the n_g spectrum buffer
+  ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s, n);
   const float scale = (float)std::pow((double)n, -1.5);
-  HIP_TRY(launch_adjoint_shells(p->G.as<float>(), p->a1.as<float2>(), p->a2.as<float2>(), p->spec.as<float2>(), L, n,
-                                p->tw32.as<float2>(), scale, (float)p->geo.beta, s));
-  // gdelta = unnormalised inverse transform of S (one pseudo-shell: natural layout)
-  ShellLaunch B = shell_launch(p->pass_ball, p->ball_shells, p->ball_x, p->ball_y, p->ball_z, 1);
+  HIP_TRY(launch_adjoint_shells(p->G.as<float>(), p->a1.as<float2>(), p->a2.as<float2>(), p->spec.as<float2>(), L,
+                                p->geo.n_est, p->tw32e.as<float2>(), scale, (float)p->geo.beta, s));
+  // gdelta = unnormalised inverse transform of S on the n_g grid (one pseudo-shell: natural layout)
+  ShellLaunch B = shell_launch(p->pass_ball, p->ball_shells, p->ball_x, p->ball_y, p->ball_z, 1, n);
   HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), gdelta, B, n,
                              p->tw32.as<float2>(), nullptr, nullptr, s));
   return BISPEC_OK;

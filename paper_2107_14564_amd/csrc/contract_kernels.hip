@@ -149,45 +149,46 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 // is accumulated as hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-16 relative, is
 // dropped) by three v_mfma_f32_32x32x16_bf16 per 16 voxels.  The row operand
 // is the pair product F_i F_j formed in fp32 and then split; the column
-// operand is F_l split.
+// operand comes pre-split as bf16 planes written by the C2R pass.
 //
-// Work group = 8 wavefronts (512 threads), one per SIMD pair:
-//   consumers (waves 0-3): wave w owns row block 4q + w of the work group and
-//     its <= 4 column tiles; it only reads operand fragments from LDS and
-//     issues MFMAs (fp32 accumulators, added into float64 every kFlush chunks);
-//   producers (waves 4-7): copy F (fp32) of chunk c+2 and the column planes
-//     (bf16 hi/lo written by the C2R pass) of chunk c+1 from registers loaded
-//     two chunks earlier, and form + split the pair products of chunk c+1.
-// LDS holds two buffers of everything (one barrier per chunk):
-//   F32 [2][n_s + 1][kC2 + 4] fp32     (row n_s = zero shell)
-//   Bh, Bl [2][n_s + 1][kC2 + 8] bf16
-//   Ah, Al [2][kRbPerWg][32][kC2 + 8] bf16
+// Work group = 8 wavefronts (512 threads), two per SIMD:
+//   consumers (waves 0-3): slot w = kRbPerSlot row blocks of one span and
+//     their <= kMaxColTiles column tiles; per 16 voxels it reads the row fragments of its
+//     row blocks and each column fragment once (shared by both row blocks) and
+//     issues 3 MFMAs per (row block, tile);
+//   producers (waves 4-7): copy the work group's F rows (chunk c+2) and column
+//     plane rows (chunk c+1) from registers loaded two chunks earlier, and
+//     form + split the pair products of chunk c+1 for all kRbPerWg row blocks.
+// Only the shell rows the work group needs are staged (WgRows).  LDS holds two
+// buffers of everything (one barrier per chunk of kC2 = 32 voxels):
+//   F32 [2][max_f + 1][kC2 + 4] fp32, Bh/Bl [2][max_b + 1][kC2 + 8] bf16,
+//   Ah/Al [2][kRbPerWg][32][kC2 + 8] bf16      (the extra row is all zero).
+// Accumulation: fp32 MFMA chains of kFlushChunks chunks, added in float64 into
+// partial[range][tile][element] (tile-major, coalesced); the reduction maps
+// elements to triangles.
 // ============================================================================
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kC2 = 32;              // voxels per chunk
+constexpr int kC2 = 32;              // voxels per chunk (= one voxel block)
 constexpr int kF32S = kC2 + 4;       // fp32 row stride (floats)
 constexpr int kBS = kC2 + 8;         // bf16 row stride (elements)
-constexpr int kFlush = 32;           // chunks (1024 voxels) per float32 accumulation chain
+constexpr int kFlushChunks = 256;    // 8192 voxels per float32 accumulation chain
 constexpr int kWsThreads = 512;
 constexpr int kProd = 256;           // producer threads
-constexpr int kNV = 4;               // float4 staging slots per producer thread (n_s * kC2 / 4 <= kProd * kNV)
-
-// Output element v (0..15) of lane `lane` of a 32x32 MFMA accumulator sits
-// at row mfma_row(v, lane), column lane % 32.
-__device__ __forceinline__ int mfma_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+constexpr int kNV = 4;               // float4 / uint4 staging slots per producer thread
+static_assert(kC2 == kVoxBlock, "chunks are voxel blocks");
 
 struct WsLds {
-  float* f32;      // [2][ns1][kF32S]
-  __bf16* bh;      // [2][ns1][kBS]
+  float* f32;      // [2][nf1][kF32S]
+  __bf16* bh;      // [2][nb1][kBS]
   __bf16* bl;
   __bf16* ah;      // [2][kRbPerWg][32][kBS]
   __bf16* al;
-  int ns1;
-  __device__ float* F(int buf, int s) const { return f32 + (buf * ns1 + s) * kF32S; }
-  __device__ __bf16* Bh(int buf, int s) const { return bh + (buf * ns1 + s) * kBS; }
-  __device__ __bf16* Bl(int buf, int s) const { return bl + (buf * ns1 + s) * kBS; }
+  int nf1, nb1;    // rows per buffer including the zero row
+  __device__ float* F(int buf, int r) const { return f32 + (buf * nf1 + r) * kF32S; }
+  __device__ __bf16* Bh(int buf, int r) const { return bh + (buf * nb1 + r) * kBS; }
+  __device__ __bf16* Bl(int buf, int r) const { return bl + (buf * nb1 + r) * kBS; }
   __device__ __bf16* Ah(int buf, int rb, int r) const { return ah + ((buf * kRbPerWg + rb) * 32 + r) * kBS; }
   __device__ __bf16* Al(int buf, int rb, int r) const { return al + ((buf * kRbPerWg + rb) * 32 + r) * kBS; }
 };
@@ -207,23 +208,17 @@ struct WsRange {
 };
 
 // ---- producers ---------------------------------------------------------------
-// Per chunk: F (fp32, for the pair products) n_s x kC2 floats = n_s * kC2/4 float4;
-// column planes hi/lo n_s x kC2 bf16 each = n_s * kC2/8 uint4 per plane.
 struct WsPf {
   float4 f[kNV];
-  uint4 b[kNV];    // slots [0, n_s*kC2/8) hold hi, [n_s*kC2/8, n_s*kC2/4) hold lo
+  uint4 b[kNV];    // slots [0, 4 b_n) hi plane rows, [4 b_n, 8 b_n) lo plane rows
 };
 
-// A chunk (kC2 = kVoxBlock voxels) of every shell is one contiguous block of
-// the voxel-blocked layout; ranges start on multiples of 64 voxels and the
-// supported grids have N^3 divisible by 512, so every chunk is full.
-static_assert(kC2 == kVoxBlock, "chunks are voxel blocks");
-
-__device__ __forceinline__ void ws_load_f(const float* __restrict__ F, const WsArgs& a, const WsRange& R, int c,
-                                          WsPf& pf, int tid) {
+__device__ __forceinline__ void ws_load_f(const float* __restrict__ F, const WsArgs& a, const WgRows& wr,
+                                          const WsRange& R, int c, WsPf& pf, int tid) {
   if (c >= R.n_chunks) return;
-  const float4* base = reinterpret_cast<const float4*>(F + ((R.k_lo / kC2) + c) * (long long)a.n_s * kC2);
-  const int n4 = a.n_s * (kC2 / 4);
+  const float4* base = reinterpret_cast<const float4*>(F + ((R.k_lo / kC2) + c) * (long long)a.n_s * kC2 +
+                                                       (long long)wr.f_lo * kC2);
+  const int n4 = wr.f_n * (kC2 / 4);
 #pragma unroll
   for (int u = 0; u < kNV; ++u) {
     const int idx = tid + u * kProd;
@@ -232,12 +227,13 @@ __device__ __forceinline__ void ws_load_f(const float* __restrict__ F, const WsA
 }
 
 __device__ __forceinline__ void ws_load_b(const __bf16* __restrict__ fh, const __bf16* __restrict__ fl,
-                                          const WsArgs& a, const WsRange& R, int c, WsPf& pf, int tid) {
+                                          const WsArgs& a, const WgRows& wr, const WsRange& R, int c, WsPf& pf,
+                                          int tid) {
   if (c >= R.n_chunks) return;
-  const long long off = ((R.k_lo / kC2) + c) * (long long)a.n_s * kC2;
+  const long long off = ((R.k_lo / kC2) + c) * (long long)a.n_s * kC2 + (long long)wr.b_lo * kC2;
   const uint4* bh = reinterpret_cast<const uint4*>(fh + off);
   const uint4* bl = reinterpret_cast<const uint4*>(fl + off);
-  const int per_plane = a.n_s * (kC2 / 8);
+  const int per_plane = wr.b_n * (kC2 / 8);
 #pragma unroll
   for (int u = 0; u < kNV; ++u) {
     const int idx = tid + u * kProd;
@@ -248,38 +244,36 @@ __device__ __forceinline__ void ws_load_b(const __bf16* __restrict__ fh, const _
   }
 }
 
-__device__ __forceinline__ void ws_store_f(const WsLds& L, const WsArgs& a, int buf, const WsPf& pf, int tid) {
+__device__ __forceinline__ void ws_store_f(const WsLds& L, const WgRows& wr, int buf, const WsPf& pf, int tid) {
 #pragma unroll
   for (int u = 0; u < kNV; ++u) {
     const int idx = tid + u * kProd;
-    if (idx < a.n_s * (kC2 / 4)) {
-      const int s = idx / (kC2 / 4), q4 = idx % (kC2 / 4);
-      *reinterpret_cast<float4*>(L.F(buf, s) + 4 * q4) = pf.f[u];
-    }
+    if (idx < wr.f_n * (kC2 / 4)) *reinterpret_cast<float4*>(L.F(buf, idx >> 3) + 4 * (idx & 7)) = pf.f[u];
   }
 }
 
-__device__ __forceinline__ void ws_store_b(const WsLds& L, const WsArgs& a, int buf, const WsPf& pf, int tid) {
-  const int per_plane = a.n_s * (kC2 / 8);
+__device__ __forceinline__ void ws_store_b(const WsLds& L, const WgRows& wr, int buf, const WsPf& pf, int tid) {
+  const int per_plane = wr.b_n * (kC2 / 8);
 #pragma unroll
   for (int u = 0; u < kNV; ++u) {
     const int idx = tid + u * kProd;
     if (idx < 2 * per_plane) {
       const int plane = idx >= per_plane;
       const int k = idx - plane * per_plane;
-      const int s = k / (kC2 / 8), q8 = k % (kC2 / 8);
-      __bf16* dst = (plane ? L.Bl(buf, s) : L.Bh(buf, s)) + 8 * q8;
+      __bf16* dst = (plane ? L.Bl(buf, k >> 2) : L.Bh(buf, k >> 2)) + 8 * (k & 3);
       *reinterpret_cast<uint4*>(dst) = pf.b[u];
     }
   }
 }
 
-// pair products of the chunk held in F32 buffer buf, split into A[buf]
-__device__ __forceinline__ void ws_products(const WsLds& L, int buf, const int (&pi)[2], const int (&pj)[2],
+// pair products of the chunk in F32 buffer buf, split into A[buf]:
+// kRbPerWg * 32 pairs x 4 groups of 8 voxels, 4 groups per thread
+__device__ __forceinline__ void ws_products(const WsLds& L, int buf, const int (&pi)[4], const int (&pj)[4],
                                             int tid) {
-  // kRbPerWg * 32 pairs x 4 groups of 8 voxels = 512 groups, 2 per thread
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
+  for (int u = 0; u < 4; ++u) {
+    // two groups in flight at a time (bounds the producer's register use)
+    if (u == 2) asm volatile("" ::: "memory");
     const int g = tid + u * kProd;
     const int rbr = g >> 2, xg = (g & 3) * 8;  // rbr = rb * 32 + row
     const float* fi = L.F(buf, pi[u]) + xg;
@@ -295,75 +289,75 @@ __device__ __forceinline__ void ws_products(const WsLds& L, int buf, const int (
   }
 }
 
-// Iteration c: products of chunk c+1 (F32[(c+1)%2] -> A[(c+1)%2]); F32[c%2] <- F of
-// chunk c+2 and B[(c+1)%2] <- planes of chunk c+1, both from registers loaded two
+// Iteration c: products of chunk c+1 (F32[(c+1)%2] -> A[(c+1)%2]); F32[c%2] <- F rows
+// of chunk c+2 and B[(c+1)%2] <- plane rows of chunk c+1 from registers loaded two
 // iterations earlier; then the loads of chunks c+4 (F) and c+3 (planes) are issued.
 __device__ __forceinline__ void ws_producer(const float* __restrict__ F, const __bf16* __restrict__ fh,
-                            const __bf16* __restrict__ fl, const WsArgs& a, const WsLds& L, const WsRange& R, int wg,
-                            int tid) {
-  int pi[2], pj[2];
+                                            const __bf16* __restrict__ fl, const WsArgs& a, const WsLds& L,
+                                            const WsRange& R, int wg, int tid) {
+  const WgRows wr = a.wg_rows[wg];
+  int pi[4], pj[4];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
+  for (int u = 0; u < 4; ++u) {
     const int g = tid + u * kProd;
     const int rb = wg * kRbPerWg + ((g >> 2) >> 5), r = (g >> 2) & 31;
     const int i = a.rows[rb].i[r], j = a.rows[rb].j[r];
-    pi[u] = j > 0 ? i - 1 : a.n_s;
-    pj[u] = j > 0 ? j - 1 : a.n_s;
+    pi[u] = j > 0 ? i - 1 - wr.f_lo : wr.f_n;  // row f_n of the buffer is zero
+    pj[u] = j > 0 ? j - 1 - wr.f_lo : wr.f_n;
   }
   WsPf p0, p1;
-  // prologue: F of chunks 0, 1 and planes of chunk 0 into LDS
-  ws_load_f(F, a, R, 0, p0, tid);
-  ws_load_f(F, a, R, 1, p1, tid);
-  ws_load_b(fh, fl, a, R, 0, p0, tid);
-  ws_store_f(L, a, 0, p0, tid);
-  ws_store_f(L, a, 1, p1, tid);
-  ws_store_b(L, a, 0, p0, tid);
-  // in flight: F of chunks 2, 3; planes of chunks 1, 2
-  ws_load_f(F, a, R, 2, p0, tid);
-  ws_load_f(F, a, R, 3, p1, tid);
-  ws_load_b(fh, fl, a, R, 1, p0, tid);
-  ws_load_b(fh, fl, a, R, 2, p1, tid);
+  ws_load_f(F, a, wr, R, 0, p0, tid);
+  ws_load_f(F, a, wr, R, 1, p1, tid);
+  ws_load_b(fh, fl, a, wr, R, 0, p0, tid);
+  ws_store_f(L, wr, 0, p0, tid);
+  ws_store_f(L, wr, 1, p1, tid);
+  ws_store_b(L, wr, 0, p0, tid);
+  ws_load_f(F, a, wr, R, 2, p0, tid);
+  ws_load_f(F, a, wr, R, 3, p1, tid);
+  ws_load_b(fh, fl, a, wr, R, 1, p0, tid);
+  ws_load_b(fh, fl, a, wr, R, 2, p1, tid);
   __syncthreads();                 // barrier P1
   ws_products(L, 0, pi, pj, tid);  // chunk 0 -> A[0]
   __syncthreads();                 // barrier P2
   for (int c = 0; c < R.n_chunks; c += 2) {
     if (c + 1 < R.n_chunks) ws_products(L, 1, pi, pj, tid);
-    ws_store_f(L, a, 0, p0, tid);    // F of chunk c+2
-    ws_store_b(L, a, 1, p0, tid);    // planes of chunk c+1
-    ws_load_f(F, a, R, c + 4, p0, tid);
-    ws_load_b(fh, fl, a, R, c + 3, p0, tid);
+    ws_store_f(L, wr, 0, p0, tid);   // F of chunk c+2
+    ws_store_b(L, wr, 1, p0, tid);   // planes of chunk c+1
+    ws_load_f(F, a, wr, R, c + 4, p0, tid);
+    ws_load_b(fh, fl, a, wr, R, c + 3, p0, tid);
     __syncthreads();
     if (c + 1 >= R.n_chunks) break;
     if (c + 2 < R.n_chunks) ws_products(L, 0, pi, pj, tid);
-    ws_store_f(L, a, 1, p1, tid);    // F of chunk c+3
-    ws_store_b(L, a, 0, p1, tid);    // planes of chunk c+2
-    ws_load_f(F, a, R, c + 5, p1, tid);
-    ws_load_b(fh, fl, a, R, c + 4, p1, tid);
+    ws_store_f(L, wr, 1, p1, tid);   // F of chunk c+3
+    ws_store_b(L, wr, 0, p1, tid);   // planes of chunk c+2
+    ws_load_f(F, a, wr, R, c + 5, p1, tid);
+    ws_load_b(fh, fl, a, wr, R, c + 4, p1, tid);
     __syncthreads();
   }
 }
 
 // ---- consumers ---------------------------------------------------------------
-// NT = column tiles of this wavefront's row block (constant over the run).
+// NT = column tiles of this slot (constant over the run).
 template <int NT>
-__device__ __forceinline__ void ws_consumer_nt(const WsArgs& a, const WsLds& L, const WsRange& R, int rb, const RbCols& rc,
-                               int wave, int lane, int kr) {
+__device__ __forceinline__ void ws_consumer_nt(const WsArgs& a, const WsLds& L, const WsRange& R, int wg, int w,
+                                               const SlotCols& sc, const WgRows& wr, int lane, int kr) {
   const int kg = lane >> 5;
   int cs[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int l = rc.col0[t] + (lane & 31);
-    cs[t] = (l >= 1 && l <= a.n_s) ? l - 1 : a.n_s;
+    const int l = sc.col0[t] + (lane & 31);  // 1-based column shell
+    cs[t] = (l <= a.n_s) ? l - 1 - wr.b_lo : wr.b_n;  // row b_n of the buffer is zero
   }
-  f32x16 acc[NT];
-  double tot[NT][16];
+  f32x16 acc[kRbPerSlot][NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int q = 0; q < kRbPerSlot; ++q)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      acc[t][v] = 0.f;
-      tot[t][v] = 0.0;
-    }
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[q][t][v] = 0.f;
+  // partial[kr][tile][element] with tile = wg*kTilesPerWg + (slot rows)*kMaxColTiles + t
+  double* out = a.partial + ((long long)kr * a.n_wg * kTilesPerWg + (long long)wg * kTilesPerWg) * 1024 + lane;
+  bool first = true;
   __syncthreads();  // matches producer barrier P1
   __syncthreads();  // matches producer barrier P2
   int chain = 0;
@@ -372,58 +366,62 @@ __device__ __forceinline__ void ws_consumer_nt(const WsArgs& a, const WsLds& L, 
 #pragma unroll
     for (int ks = 0; ks < kC2 / 16; ++ks) {
       const int off = ks * 16 + kg * 8;
-      const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(L.Ah(buf, wave, lane & 31) + off);
-      const bf16x8 alo = *reinterpret_cast<const bf16x8*>(L.Al(buf, wave, lane & 31) + off);
-      bf16x8 bhi[NT], blo[NT];
+      bf16x8 ahi[kRbPerSlot], alo[kRbPerSlot];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        bhi[t] = *reinterpret_cast<const bf16x8*>(L.Bh(buf, cs[t]) + off);
-        blo[t] = *reinterpret_cast<const bf16x8*>(L.Bl(buf, cs[t]) + off);
+      for (int q = 0; q < kRbPerSlot; ++q) {
+        ahi[q] = *reinterpret_cast<const bf16x8*>(L.Ah(buf, w * kRbPerSlot + q, lane & 31) + off);
+        alo[q] = *reinterpret_cast<const bf16x8*>(L.Al(buf, w * kRbPerSlot + q, lane & 31) + off);
       }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[t], acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[t], acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[t], acc[t], 0, 0, 0);
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(L.Bh(buf, cs[t]) + off);
+        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(L.Bl(buf, cs[t]) + off);
+#pragma unroll
+        for (int q = 0; q < kRbPerSlot; ++q) {
+          acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[q], bhi, acc[q][t], 0, 0, 0);
+          acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[q], blo, acc[q][t], 0, 0, 0);
+          acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[q], bhi, acc[q][t], 0, 0, 0);
+        }
       }
     }
-    if (++chain == kFlush || c + 1 == R.n_chunks) {
+    if (++chain == kFlushChunks || c + 1 == R.n_chunks) {
       chain = 0;
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+      for (int q = 0; q < kRbPerSlot; ++q)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          tot[t][v] += (double)acc[t][v];
-          acc[t][v] = 0.f;
+        for (int t = 0; t < NT; ++t) {
+          double* o = out + (long long)((w * kRbPerSlot + q) * kMaxColTiles + t) * 1024;
+          // one tile at a time: keeps the float64 read-modify-write of the
+          // partials from being hoisted across tiles (register pressure)
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            o[v * 64] = first ? (double)acc[q][t][v] : o[v * 64] + (double)acc[q][t][v];
+            acc[q][t][v] = 0.f;
+          }
         }
+      first = false;
     }
     __syncthreads();  // matches the producer's per-chunk barrier
   }
-  double* out = a.partial + (long long)kr * a.n_tri;
-  const RowBlock& rw = a.rows[rb];
+  if (R.n_chunks == 0) {  // empty range: its partials are zero
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int l = rc.col0[t] + (lane & 31);
+    for (int q = 0; q < kRbPerSlot; ++q)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int row = mfma_row(v, lane);
-      const int i = rw.i[row], j = rw.j[row];
-      if (j <= 0 || l < 1 || l > j) continue;
-      const int tt = a.tri_index[((long long)(i - 1) * a.n_s + (j - 1)) * a.n_s + (l - 1)];
-      if (tt >= 0) out[tt] = tot[t][v];
-    }
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) out[(long long)((w * kRbPerSlot + q) * kMaxColTiles + t) * 1024 + v * 64] = 0.0;
   }
 }
 
-__device__ __forceinline__ void ws_consumer(const WsArgs& a, const WsLds& L, const WsRange& R, int wg, int wave, int lane, int kr) {
-  const int rb = wg * kRbPerWg + wave;
-  const RbCols rc = a.cols[rb];
-  switch (rc.n) {
-    case 1: ws_consumer_nt<1>(a, L, R, rb, rc, wave, lane, kr); break;
-    case 2: ws_consumer_nt<2>(a, L, R, rb, rc, wave, lane, kr); break;
-    case 3: ws_consumer_nt<3>(a, L, R, rb, rc, wave, lane, kr); break;
-    case 4: ws_consumer_nt<4>(a, L, R, rb, rc, wave, lane, kr); break;
-    default:  // padding row block: keep the barrier count of the work group
+__device__ __forceinline__ void ws_consumer(const WsArgs& a, const WsLds& L, const WsRange& R, int wg, int w,
+                                            int lane, int kr) {
+  const SlotCols sc = a.cols[wg * kSlotsPerWg + w];
+  const WgRows wr = a.wg_rows[wg];
+  switch (sc.n) {
+    case 1: ws_consumer_nt<1>(a, L, R, wg, w, sc, wr, lane, kr); break;
+    case 2: ws_consumer_nt<2>(a, L, R, wg, w, sc, wr, lane, kr); break;
+    default:  // idle slot: keep the barrier count of the work group
       for (int c = 0; c < R.n_chunks + 2; ++c) __syncthreads();
       break;
   }
@@ -434,19 +432,21 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
                                                                 const __bf16* __restrict__ fl, WsArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   WsLds L;
-  L.ns1 = a.n_s + 1;
+  L.nf1 = a.max_f + 1;
+  L.nb1 = a.max_b + 1;
   L.f32 = reinterpret_cast<float*>(smem_raw);
-  L.bh = reinterpret_cast<__bf16*>(L.f32 + 2 * L.ns1 * kF32S);
-  L.bl = L.bh + 2 * L.ns1 * kBS;
-  L.ah = L.bl + 2 * L.ns1 * kBS;
+  L.bh = reinterpret_cast<__bf16*>(L.f32 + 2 * L.nf1 * kF32S);
+  L.bl = L.bh + 2 * L.nb1 * kBS;
+  L.ah = L.bl + 2 * L.nb1 * kBS;
   L.al = L.ah + 2 * kRbPerWg * 32 * kBS;
   int wg, kr;
   xcd_map(a.n_wg, wg, kr);
-  // zero shell rows of both buffers (never overwritten afterwards)
-  for (int e = threadIdx.x; e < 2 * kF32S; e += kWsThreads) L.F(e / kF32S, a.n_s)[e % kF32S] = 0.f;
+  const WgRows wr = a.wg_rows[wg];
+  // zero rows (index f_n / b_n of each buffer), never overwritten afterwards
+  for (int e = threadIdx.x; e < 2 * kF32S; e += kWsThreads) L.F(e / kF32S, wr.f_n)[e % kF32S] = 0.f;
   for (int e = threadIdx.x; e < 2 * kBS; e += kWsThreads) {
-    L.Bh(e / kBS, a.n_s)[e % kBS] = (__bf16)0.f;
-    L.Bl(e / kBS, a.n_s)[e % kBS] = (__bf16)0.f;
+    L.Bh(e / kBS, wr.b_n)[e % kBS] = (__bf16)0.f;
+    L.Bl(e / kBS, wr.b_n)[e % kBS] = (__bf16)0.f;
   }
   __syncthreads();
   WsRange R;
@@ -454,7 +454,7 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
   R.k_hi = range_lo(a.n_vox, a.n_krange, kr + 1);
   R.n_chunks = (int)((R.k_hi - R.k_lo + kC2 - 1) / kC2);
   const int wave = threadIdx.x >> 6;
-  if (wave < 4)
+  if (wave < kSlotsPerWg)
     ws_consumer(a, L, R, wg, wave, threadIdx.x & 63, kr);
   else
     ws_producer(F, fh, fl, a, L, R, wg, threadIdx.x - 256);
@@ -504,12 +504,14 @@ __global__ void __launch_bounds__(kGbVox) k_gbuild(const float* __restrict__ F, 
   }
 }
 
-__global__ void k_reduce(const double* __restrict__ partial, int n_krange, long long n_tri,
-                         const double* __restrict__ norm, double* __restrict__ out) {
+__global__ void k_reduce(const double* __restrict__ partial, int n_krange, long long stride, long long n_tri,
+                         const int32_t* __restrict__ slot, const double* __restrict__ norm,
+                         double* __restrict__ out) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
+  const long long at = slot ? slot[t] : t;
   double s = 0.0;
-  for (int k = 0; k < n_krange; ++k) s += partial[(long long)k * n_tri + t];
+  for (int k = 0; k < n_krange; ++k) s += partial[(long long)k * stride + at];
   out[t] = norm ? s * norm[t] : s;
 }
 
@@ -527,8 +529,8 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
 
 }  // namespace
 
-size_t bf16x3_lds_bytes(int n_s) {
-  return 2 * (size_t)(n_s + 1) * kF32S * sizeof(float) + 4 * (size_t)(n_s + 1) * kBS * sizeof(__bf16) +
+size_t bf16x3_lds_bytes(int max_f, int max_b) {
+  return 2 * (size_t)(max_f + 1) * kF32S * sizeof(float) + 4 * (size_t)(max_b + 1) * kBS * sizeof(__bf16) +
          4 * (size_t)kRbPerWg * 32 * kBS * sizeof(__bf16);
 }
 
@@ -537,8 +539,8 @@ hipError_t launch_contract_fp64(const double* F, const ContractArgs& a, hipStrea
 
 hipError_t launch_contract_bf16x3(const float* F, const __bf16* f_hi, const __bf16* f_lo, const WsArgs& a,
                                   hipStream_t st) {
-  if (a.n_s * (kC2 / 4) > kProd * kNV) return hipErrorInvalidValue;
-  const size_t lds = bf16x3_lds_bytes(a.n_s);
+  if (a.max_f * (kC2 / 4) > kProd * kNV || 2 * a.max_b * (kC2 / 8) > kProd * kNV) return hipErrorInvalidValue;
+  const size_t lds = bf16x3_lds_bytes(a.max_f, a.max_b);
   hipError_t e = hipFuncSetAttribute((const void*)k_contract_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -560,10 +562,10 @@ hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, c
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* partial, int n_krange, long long n_tri, const double* norm, double* out,
-                         hipStream_t st) {
+hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
+                         const double* norm, double* out, hipStream_t st) {
   const unsigned blocks = (unsigned)((n_tri + 255) / 256);
-  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(256), 0, st, partial, n_krange, n_tri, norm, out);
+  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(256), 0, st, partial, n_krange, stride, n_tri, slot, norm, out);
   return hipGetLastError();
 }
 

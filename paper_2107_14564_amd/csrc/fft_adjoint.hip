@@ -16,8 +16,8 @@ __global__ void k_zero(float2* __restrict__ p, long long n) {
 template <int N>
 hipError_t adjoint_n(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, const float2* tw,
                      float scale, float beta, hipStream_t st) {
-  constexpr int M = N / 2;
-  const long long n_spec = (long long)N * N * (M + 1);
+  const long long sn = L.spec_n;
+  const long long n_spec = sn * sn * (sn / 2 + 1);
   hipLaunchKernelGGL(k_zero, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, S, n_spec);
   if (L.n_z_blocks > 0)
     hipLaunchKernelGGL(k_g_r2c_z<N>, dim3((unsigned)L.n_z_blocks), dim3(kThrZ), 0, st, G, a2, L.z_off, L.n_shells,
@@ -26,7 +26,7 @@ hipError_t adjoint_n(const float* G, float2* a1, float2* a2, float2* S, const Sh
     hipLaunchKernelGGL(k_g_fwd_y<N>, dim3((unsigned)L.n_y_blocks), dim3(kThrAxis), 0, st, a2, a1, L.y_off,
                        L.n_shells, L.shells, tw);
   if (L.n_x_tiles > 0)
-    hipLaunchKernelGGL(k_g_fwd_x<N>, dim3((unsigned)L.n_x_tiles), dim3(kThrAxis), 0, st, a1, S, L.x_tiles,
+    hipLaunchKernelGGL(k_g_fwd_x<N>, dim3((unsigned)L.n_x_tiles), dim3(kThrAxis), 0, st, a1, S, L.spec_n, L.x_tiles,
                        L.shells, tw, scale, beta);
   return hipGetLastError();
 }

@@ -46,8 +46,7 @@ hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, c
   }
 }
 
-void plan_shell_passes(const ShellGeometry& g, bool f64, ShellPassPlan& p) {
-  const int n = g.n_g;
+void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p) {
   const int twc = fft_tile_cols(n, f64);
   const int nl = fft_z_lines(n / 2, f64);
   p.shells.resize(g.n_s);

@@ -13,7 +13,7 @@ static hipError_t inv_x(const float2* spec, V2<T>* a1, const ShellLaunch& L, int
   switch (n) {
 #define BISPEC_CASE(NN)                                                                                     \
   case NN:                                                                                                  \
-    hipLaunchKernelGGL((k_inv_x<T, UNIT, NN>), grid, dim3(kThrAxis), 0, st, spec, a1, L.x_tiles, L.shells, tw); \
+    hipLaunchKernelGGL((k_inv_x<T, UNIT, NN>), grid, dim3(kThrAxis), 0, st, spec, L.spec_n, a1, L.x_tiles, L.shells, tw); \
     break;
     BISPEC_FOR_EACH_N(BISPEC_CASE)
 #undef BISPEC_CASE

@@ -1,18 +1,24 @@
 // FFT pass kernels of the estimator (steps a, b and b2), templated on the line
-// length N so every index computation is compile-time.  Instantiated for the
+// length so every index computation is compile-time.  Instantiated for the
 // supported grid sizes by fft_forward.hip, fft_inv_x.hip, fft_inv_y.hip and
 // fft_c2r.hip.
 //
-// Grid layout (all C order, z fastest):
+// Two grids: the input grid N (delta and its half spectrum) and the estimator
+// grid G <= N on which the shell fields live.  Every shell mode has
+// |m_i| < G/2, so a mode sits at the same signed frequency on both grids, and
+// the triple sums over G^3 points pick exactly the closed triangles when
+// G > 3 max|m_i| (the aliasing argument of Section 2.2 applied to G).
+//
+// Layouts (all C order, z fastest):
 //   delta  float32 [N][N][N]
-//   spec   complex [N (kx)][N (ky)][M+1 (kz)], M = N/2     (half spectrum, in place)
-//   A1_n   complex [N (x)][2R+1 (ky + R)][R+1 (kz)]        (shell n after the x pass)
-//   A2_n   complex [N (x)][N (y)][R+1 (kz)]                (shell n after the y pass)
-//   F_n    real, voxel-blocked (vox_index)                 (shell field)
+//   spec   complex [N (kx)][N (ky)][N/2+1 (kz)]              (half spectrum, in place)
+//   A1_n   complex [G (x)][2R+1 (ky + R)][R+1 (kz)]          (shell n after the x pass)
+//   A2_n   complex [G (x)][G (y)][R+1 (kz)]                  (shell n after the y pass)
+//   F_n    real, voxel-blocked (vox_index) over G^3          (shell field)
 // R = rad[n] is the largest |m_y| of any mode of shell n, so the inverse
 // passes of shell n only touch the ball |m| <= R: the x pass runs only the
 // (ky, kz) columns inside the disc ky^2 + kz^2 < hi2[n], the y pass only the
-// kz <= R planes, and the z pass reads R+1 of the M+1 half-spectrum planes.
+// kz <= R planes, and the z pass reads R+1 of the G/2+1 half-spectrum planes.
 //
 // Strided passes stage a tile of TW consecutive kz columns times the whole
 // line in LDS (interleaved layout); contiguous passes stage whole lines.
@@ -102,10 +108,9 @@ __global__ void __launch_bounds__(kThrAxis) k_fft_axis(float2* __restrict__ data
 // Tile (shell, ky, kz0) of TW columns: Delta (or 1 for the unit shells) on the
 // modes of shell n in those columns, inverse FFT along x, into A1_n.
 template <typename T, bool UNIT, int N>
-__global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ spec, V2<T>* __restrict__ a1,
-                                                    const int4* __restrict__ tiles, const ShellDev* __restrict__ sh,
-                                                    const V2<T>* __restrict__ tw) {
-  constexpr int M = N / 2;
+__global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ spec, int spec_n,
+                                                    V2<T>* __restrict__ a1, const int4* __restrict__ tiles,
+                                                    const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw) {
   constexpr int TW = fft_tile_cols(N, sizeof(T) == 8);
   __shared__ V2<T> buf[N * TW];
   const int4 td = tiles[blockIdx.x];
@@ -113,7 +118,7 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ s
   const ShellDev d = sh[sn];
   const int R = d.rad;
   const int cols = min(TW, R + 1 - kz0);
-  const int yrow = ky < 0 ? ky + N : ky;
+  const int yrow = ky < 0 ? ky + spec_n : ky;
   const long long ky2 = (long long)ky * ky;
   for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
     const int q = e / TW, c = e % TW;
@@ -125,7 +130,8 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ s
         if (UNIT) {
           v = mk<T>((T)1, (T)0);
         } else {
-          const float2 x = spec[((long long)q * N + yrow) * (M + 1) + kz];
+          const long long xrow = mx < 0 ? mx + spec_n : mx;
+          const float2 x = spec[(xrow * spec_n + yrow) * (spec_n / 2 + 1) + kz];
           v = mk<T>((T)x.x, (T)x.y);
         }
       }
@@ -351,13 +357,13 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_y(const float2* __restrict__
 }
 
 // x: tile (shell, ky, kz0): A1_n[.][ky + R][kz] -> forward FFT along x -> for the
-// modes of shell n: S[kx][ky][kz] = scale * Z(k) * value (shells are disjoint)
+// modes of shell n: S[kx][ky][kz] = scale * Z(k) * value (shells are disjoint);
+// S is the half spectrum of the spec_n grid
 template <int N>
 __global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__ a1, float2* __restrict__ S,
-                                                      const int4* __restrict__ tiles,
+                                                      int spec_n, const int4* __restrict__ tiles,
                                                       const ShellDev* __restrict__ sh,
                                                       const float2* __restrict__ tw, float scale, float beta) {
-  constexpr int M = N / 2;
   constexpr int TW = fft_tile_cols(N, false);
   __shared__ float2 buf[N * TW];
   const int4 td = tiles[blockIdx.x];
@@ -373,7 +379,7 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__
   }
   __syncthreads();
   ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, tw, -1.0f);
-  const int yrow = ky < 0 ? ky + N : ky;
+  const int yrow = ky < 0 ? ky + spec_n : ky;
   const long long ky2 = (long long)ky * ky;
   for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
     const int q = e / TW, c = e % TW;
@@ -382,7 +388,8 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__
     const long long m2 = mx * mx + ky2 + kz * kz;
     if (m2 < d.lo2 || m2 >= d.hi2) continue;
     const float z = 1.0f + beta * (float)((double)(kz * kz) / (double)m2);
-    S[((long long)q * N + yrow) * (M + 1) + kz] = scl<float>(buf[e], scale * z);
+    const long long xrow = mx < 0 ? mx + spec_n : mx;
+    S[(xrow * spec_n + yrow) * (spec_n / 2 + 1) + kz] = scl<float>(buf[e], scale * z);
   }
 }
 

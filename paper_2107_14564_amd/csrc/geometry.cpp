@@ -26,14 +26,18 @@ std::vector<int> fft_radices(int n) {
   return r;
 }
 
+bool grid_size_supported(int n) {
+  if (n < 8 || n > 1024) return false;
+  int m = n;
+  while (m > 1 && m % 2 == 0) m /= 2;
+  return (m == 1 || m == 3 || m == 5) && n / m >= 8;
+}
+
 int validate(const bispec_config& c, std::string& err) {
-  {
-    // n_g = 2^a * {1, 3, 5} with 2^a >= 8, n_g <= 1024
-    int m = c.n_g;
-    while (m > 1 && m % 2 == 0) m /= 2;
-    if (c.n_g < 8 || c.n_g > 1024 || !(m == 1 || m == 3 || m == 5) || c.n_g / m < 8)
-      return fail(err, BISPEC_EINVAL, "n_g must be 2^a, 3*2^a or 5*2^a with 2^a >= 8, at most 1024");
-  }
+  if (!grid_size_supported(c.n_g))
+    return fail(err, BISPEC_EINVAL, "n_g must be 2^a, 3*2^a or 5*2^a with 2^a >= 8, at most 1024");
+  if (c.n_est != 0 && !grid_size_supported(c.n_est))
+    return fail(err, BISPEC_EINVAL, "n_est must be 0 or a supported grid size");
   if (!(c.box_l > 0) || !std::isfinite(c.box_l)) return fail(err, BISPEC_EINVAL, "box_l must be > 0");
   if (!(c.dk >= 1.0) || !std::isfinite(c.dk)) return fail(err, BISPEC_EINVAL, "dk (shell width in k_f) must be >= 1");
   if (c.n_shells < 1 || c.n_shells > 1024) return fail(err, BISPEC_EINVAL, "n_shells must be in [1, 1024]");
@@ -91,9 +95,21 @@ int build_shells(const bispec_config& c, ShellGeometry& g, std::string& err) {
     while ((r + 1) * (r + 1) <= g.hi2[n - 1] - 1) ++r;
     g.rad[n - 1] = (int32_t)r;
   }
+  // estimator grid: the triple sums over G^3 points are exact when no sum of
+  // three mode components can reach +-G, i.e. G > 3 max|m_i| (Section 2.2)
+  const int R = g.rad[g.n_s - 1];
+  const int need = 3 * R + 1;
+  if (c.n_est != 0) {
+    if (c.n_est < need || c.n_est > c.n_g)
+      return fail(err, BISPEC_EINVAL, "n_est must satisfy 3 max|m_i| < n_est <= n_g");
+    g.n_est = c.n_est;
+  } else {
+    g.n_est = c.n_g;
+    for (int q = need; q <= c.n_g; ++q)
+      if (grid_size_supported(q)) { g.n_est = q; break; }
+  }
   // mode counts and mean |m| over the full lattice ball
   const int64_t top = g.hi2[g.n_s - 1];
-  const int R = g.rad[g.n_s - 1];
   std::vector<double> sum(g.n_s, 0.0);
   g.counts.assign(g.n_s, 0);
   // shell lookup by |m|^2
@@ -253,19 +269,30 @@ void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp) {
   tp.slots = (int64_t)tp.tiles.size() * kRows * kCols;
 }
 
-void build_mfma_tiles(const Selection& s, MfmaTiling& mt) {
+void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
   std::map<std::pair<int, int>, std::vector<int>> pl;
   for (const Tri& t : s.tri) pl[{t.a1, t.a2}].push_back(t.a3);
   struct P { int i, j, lo, hi; };
-  std::map<std::pair<int, int>, std::vector<P>> spans;  // (first, last column block) -> pairs
+  // (window, first block, last block) -> pairs with selected l in that window
+  std::map<std::tuple<int, int, int>, std::vector<P>> groups;
   for (auto& kv : pl) {
-    auto mm = std::minmax_element(kv.second.begin(), kv.second.end());
-    const int c0 = (*mm.first - 1) / kCols, c1 = (*mm.second - 1) / kCols;
-    spans[{c0, c1}].push_back({kv.first.first, kv.first.second, *mm.first, *mm.second});
+    std::map<int, std::pair<int, int>> per_window;  // window -> (min l, max l)
+    for (int l : kv.second) {
+      const int wdw = ((l - 1) / kCols) / kMaxColTiles;
+      auto it = per_window.find(wdw);
+      if (it == per_window.end()) per_window[wdw] = {l, l};
+      else it->second = {std::min(it->second.first, l), std::max(it->second.second, l)};
+    }
+    for (auto& pw : per_window) {
+      const int lo = pw.second.first, hi = pw.second.second;
+      groups[{pw.first, (lo - 1) / kCols, (hi - 1) / kCols}].push_back({kv.first.first, kv.first.second, lo, hi});
+    }
   }
-  mt.rows.clear();
-  mt.cols.clear();
-  mt.tiles = 0;
+  std::map<std::pair<int, int>, std::vector<P>> spans;  // (first, last column block) -> pairs
+  for (auto& g : groups) spans[{std::get<1>(g.first), std::get<2>(g.first)}] = g.second;
+  // slots: kRbPerSlot row blocks of one span + that span's non-empty column tiles
+  struct Slot { RowBlock rb[kRbPerSlot]; SlotCols sc; };
+  std::vector<Slot> slots;
   for (auto& sp : spans) {
     auto& ps = sp.second;
     std::sort(ps.begin(), ps.end(), [](const P& a, const P& b) {
@@ -274,34 +301,80 @@ void build_mfma_tiles(const Selection& s, MfmaTiling& mt) {
       if (a.i != b.i) return a.i < b.i;
       return a.j < b.j;
     });
-    for (size_t p0 = 0; p0 < ps.size(); p0 += kRows) {
-      RowBlock rb{};
-      for (int r = 0; r < kRows; ++r) {
-        const bool in = p0 + r < ps.size();
-        rb.i[r] = in ? (int16_t)ps[p0 + r].i : 0;
-        rb.j[r] = in ? (int16_t)ps[p0 + r].j : 0;
-      }
-      RbCols rc{};
-      rc.n = 0;
+    const size_t per_slot = (size_t)kRows * kRbPerSlot;
+    for (size_t p0 = 0; p0 < ps.size(); p0 += per_slot) {
+      Slot sl{};
+      for (int q = 0; q < kRbPerSlot; ++q)
+        for (int r = 0; r < kRows; ++r) {
+          const size_t k = p0 + (size_t)q * kRows + r;
+          sl.rb[q].i[r] = k < ps.size() ? (int16_t)ps[k].i : 0;
+          sl.rb[q].j[r] = k < ps.size() ? (int16_t)ps[k].j : 0;
+        }
+      sl.sc.n = 0;
       for (int c = sp.first.first; c <= sp.first.second; ++c) {
         const int col0 = c * kCols + 1;
         bool any = false;
-        for (int r = 0; r < kRows && !any; ++r) {
-          if (!rb.j[r]) continue;
-          for (int l : pl[{rb.i[r], rb.j[r]}])
-            if (l >= col0 && l < col0 + kCols) { any = true; break; }
-        }
-        if (any) rc.col0[rc.n++] = col0;
+        for (int q = 0; q < kRbPerSlot && !any; ++q)
+          for (int r = 0; r < kRows && !any; ++r) {
+            if (!sl.rb[q].j[r]) continue;
+            for (int l : pl[{sl.rb[q].i[r], sl.rb[q].j[r]}])
+              if (l >= col0 && l < col0 + kCols) { any = true; break; }
+          }
+        if (any) sl.sc.col0[sl.sc.n++] = col0;
       }
-      mt.rows.push_back(rb);
-      mt.cols.push_back(rc);
-      mt.tiles += rc.n;
+      slots.push_back(sl);
     }
   }
-  while (mt.rows.size() % kRbPerWg) {
-    mt.rows.push_back(RowBlock{});
-    mt.cols.push_back(RbCols{});
+  while (slots.size() % kSlotsPerWg) slots.push_back(Slot{});
+  mt.n_wg = (int32_t)(slots.size() / kSlotsPerWg);
+  mt.rows.assign((size_t)mt.n_wg * kRbPerWg, RowBlock{});
+  mt.cols.assign((size_t)mt.n_wg * kSlotsPerWg, SlotCols{});
+  mt.wg_rows.assign(mt.n_wg, WgRows{});
+  mt.tiles = 0;
+  mt.max_f = mt.max_b = 0;
+  std::map<std::tuple<int, int, int>, int32_t> where;
+  for (int w = 0; w < mt.n_wg; ++w) {
+    int f_lo = 1 << 30, f_hi = -1, b_lo = 1 << 30, b_hi = -1;
+    for (int sidx = 0; sidx < kSlotsPerWg; ++sidx) {
+      const Slot& sl = slots[(size_t)w * kSlotsPerWg + sidx];
+      mt.cols[(size_t)w * kSlotsPerWg + sidx] = sl.sc;
+      mt.tiles += (int64_t)sl.sc.n * kRbPerSlot;
+      for (int t = 0; t < sl.sc.n; ++t) {
+        b_lo = std::min(b_lo, sl.sc.col0[t] - 1);
+        b_hi = std::max(b_hi, std::min(sl.sc.col0[t] - 1 + kCols - 1, n_shells - 1));
+      }
+      for (int q = 0; q < kRbPerSlot; ++q) {
+        const int rbi = sidx * kRbPerSlot + q;  // row block within the work group
+        mt.rows[(size_t)w * kRbPerWg + rbi] = sl.rb[q];
+        for (int r = 0; r < kRows; ++r) {
+          const int i = sl.rb[q].i[r], j = sl.rb[q].j[r];
+          if (!j) continue;
+          f_lo = std::min(f_lo, std::min(i, j) - 1);
+          f_hi = std::max(f_hi, std::max(i, j) - 1);
+          // element of the 32x32 accumulator: row r, column c -> (v, lane)
+          for (int t = 0; t < sl.sc.n; ++t)
+            for (int l : pl[{i, j}]) {
+              const int c = l - sl.sc.col0[t];
+              if (c < 0 || c >= kCols) continue;
+              const int lane = c + 32 * ((r >> 2) & 1), v = 4 * (r >> 3) + (r & 3);
+              const int tile = w * kTilesPerWg + rbi * kMaxColTiles + t;
+              where[{i, j, l}] = tile * (kRows * kCols) + v * 64 + lane;
+            }
+        }
+      }
+    }
+    WgRows& wr = mt.wg_rows[w];
+    if (f_hi < 0) { f_lo = 0; f_hi = -1; }
+    if (b_hi < 0) { b_lo = 0; b_hi = -1; }
+    wr.f_lo = f_lo;
+    wr.f_n = f_hi - f_lo + 1;
+    wr.b_lo = b_lo;
+    wr.b_n = b_hi - b_lo + 1;
+    mt.max_f = std::max(mt.max_f, wr.f_n);
+    mt.max_b = std::max(mt.max_b, wr.b_n);
   }
+  mt.slot_of.resize(s.tri.size());
+  for (size_t t = 0; t < s.tri.size(); ++t) mt.slot_of[t] = where.at({s.tri[t].a1, s.tri[t].a2, s.tri[t].a3});
 }
 
 }  // namespace bispec

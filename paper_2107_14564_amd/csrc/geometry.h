@@ -17,6 +17,7 @@ struct Tri {
 
 struct ShellGeometry {
   int32_t n_g = 0, n_s = 0;
+  int32_t n_est = 0;             // estimator grid G (shell fields, triple sums)
   double box_l = 0, w = 0, beta = 0;
   // integer |m|^2 bounds: shell n (1-based) holds lo2[n-1] <= |m|^2 < hi2[n-1]
   std::vector<int64_t> lo2, hi2;
@@ -35,6 +36,9 @@ struct Selection {
 int validate(const bispec_config& cfg, std::string& err);
 int build_shells(const bispec_config& cfg, ShellGeometry& g, std::string& err);
 int select_triangles(const bispec_config& cfg, const ShellGeometry& g, Selection& s, std::string& err);
+
+// Grid sizes the FFT kernels are built for: 2^a, 3*2^a, 5*2^a with 2^a >= 8, <= 1024.
+bool grid_size_supported(int n);
 
 // FFT radix schedule of a length (product of 8,4,2,3,5); empty if unsupported.
 std::vector<int> fft_radices(int n);
@@ -76,25 +80,40 @@ struct TilePlan {
 
 void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp);
 
-// Tiling of the MFMA kernel.  Pairs are grouped by the span of column blocks
-// (aligned blocks of kCols shells) that their selected l fall in; each row
-// block of kRows pairs of one span meets every column block of that span, so
-// row blocks are whole rectangles of at most kMaxColTiles tiles.  Work group q
-// owns row blocks [kRbPerWg q, kRbPerWg (q+1)).
-constexpr int kMaxColTiles = 4;   // n_shells <= kCols * kMaxColTiles
-constexpr int kRbPerWg = 4;
+// Tiling of the MFMA kernel.  Column blocks (aligned blocks of kCols shells)
+// are taken in windows of kMaxColTiles blocks; within a window, pairs are
+// grouped by the span of column blocks their selected l fall in, so each row
+// block of kRows pairs meets the column blocks of one span as whole rectangles
+// of at most kMaxColTiles tiles.  A consumer slot holds kRbPerSlot row blocks
+// of one span (they share the column operands); a work group has kSlotsPerWg
+// slots.  A pair whose l reach several windows appears once per window.
+constexpr int kMaxColTiles = 2;
+constexpr int kRbPerSlot = 2;
+constexpr int kSlotsPerWg = 4;
+constexpr int kRbPerWg = kRbPerSlot * kSlotsPerWg;
+constexpr int kTilesPerWg = kRbPerWg * kMaxColTiles;
 
-struct RbCols {
-  int32_t n;                      // column tiles of this row block (0 = padding)
+struct SlotCols {
+  int32_t n;                      // column tiles of this slot (0 = idle slot)
   int32_t col0[kMaxColTiles];     // first shell (1-based) of each column tile
 };
 
-struct MfmaTiling {
-  std::vector<RowBlock> rows;
-  std::vector<RbCols> cols;       // one per row block, padded to a multiple of kRbPerWg
-  int64_t tiles = 0;
+struct WgRows {
+  int32_t f_lo, f_n;   // F (fp32) rows staged: shells f_lo .. f_lo + f_n - 1 (0-based)
+  int32_t b_lo, b_n;   // column-plane rows staged
 };
 
-void build_mfma_tiles(const Selection& s, MfmaTiling& mt);
+struct MfmaTiling {
+  std::vector<RowBlock> rows;     // kRbPerWg per work group
+  std::vector<SlotCols> cols;     // kSlotsPerWg per work group
+  std::vector<WgRows> wg_rows;    // one per work group
+  // triangle t sits in partial slot slot_of[t] = tile * kRows*kCols + element
+  std::vector<int32_t> slot_of;
+  int32_t n_wg = 0;
+  int64_t tiles = 0;              // non-empty tiles
+  int32_t max_f = 0, max_b = 0;   // largest staged row counts (LDS sizing)
+};
+
+void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt);
 
 }  // namespace bispec

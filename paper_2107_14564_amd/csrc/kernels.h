@@ -49,6 +49,7 @@ struct ShellDev {
 
 struct ShellLaunch {
   int n_shells = 0;
+  int spec_n = 0;                     // grid of the half spectrum read (x pass) or written (adjoint)
   const ShellDev* shells = nullptr;   // device [n_shells]
   const int4* x_tiles = nullptr;      // device (shell, ky, kz0, 0)
   long long n_x_tiles = 0;
@@ -65,7 +66,8 @@ struct ShellPassPlan {
   std::vector<long long> y_off, z_off;
   long long a1_elems = 0, a2_elems = 0;
 };
-void plan_shell_passes(const ShellGeometry& g, bool f64, ShellPassPlan& p);
+// passes of every shell of g on a grid of n points per side
+void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p);
 
 hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, const float2* tw, hipStream_t st);
 // the three inverse passes of every shell (fft_inv_x.hip, fft_inv_y.hip, fft_c2r.hip)
@@ -80,6 +82,7 @@ hipError_t launch_c2r_f32(const float2* a2, float* F, __bf16* f_hi, __bf16* f_lo
                           const float2* tw, hipStream_t st);
 hipError_t launch_c2r_f64(const double2* a2, double* I, const ShellLaunch& L, int n, const double2* tw,
                           hipStream_t st);
+// n: the grid of the passes (the estimator grid); the spectrum grid is L.spec_n.
 // F_hi/F_lo (optional, both or neither): bf16 planes hi = bf16(F), lo = bf16(F - hi)
 // Fields are written voxel-blocked (vox_index).
 hipError_t launch_data_shells(const float2* spec, float2* a1, float2* a2, float* F, const ShellLaunch& L, int n,
@@ -108,16 +111,16 @@ hipError_t launch_contract_fp64(const double* F, const ContractArgs& a, hipStrea
 
 struct WsArgs {
   const RowBlock* rows = nullptr;     // device [n_wg * kRbPerWg]
-  const RbCols* cols = nullptr;       // device [n_wg * kRbPerWg]
+  const SlotCols* cols = nullptr;     // device [n_wg * kSlotsPerWg]
+  const WgRows* wg_rows = nullptr;    // device [n_wg]
   int n_wg = 0;                       // work groups per voxel range
-  const int32_t* tri_index = nullptr; // device [n_s^3]
   int n_s = 0;
+  int max_f = 0, max_b = 0;           // staged rows (LDS sizing)
   long long n_vox = 0;
   int n_krange = 0;                   // multiple of 8
-  double* partial = nullptr;          // device [n_krange][n_tri]
-  long long n_tri = 0;
+  double* partial = nullptr;          // device [n_krange][n_wg * kTilesPerWg][1024]
 };
-size_t bf16x3_lds_bytes(int n_s);
+size_t bf16x3_lds_bytes(int max_f, int max_b);
 hipError_t launch_contract_bf16x3(const float* F, const __bf16* f_hi, const __bf16* f_lo, const WsArgs& a,
                                   hipStream_t st);
 // Gradient: w_k = gB[t_k] norm[t_k]; G_n = sum_{terms (t, j, l) of n} w F_j F_l
@@ -128,8 +131,8 @@ hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, c
 hipError_t launch_adjoint_shells(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, int n,
                                  const float2* tw, float scale, float beta, hipStream_t st);
 
-// B[t] = norm[t] * sum_k partial[k][t] (fixed order, float64)
-hipError_t launch_reduce(const double* partial, int n_krange, long long n_tri, const double* norm, double* out,
-                         hipStream_t st);
+// out[t] = norm[t] * sum_k partial[k * stride + (slot ? slot[t] : t)] (fixed order, float64; norm may be null)
+hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
+                         const double* norm, double* out, hipStream_t st);
 
 }  // namespace bispec

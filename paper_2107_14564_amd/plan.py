@@ -16,16 +16,18 @@ class Plan:
     Arguments follow bispec_config: grid size n_g, box side box_l, shell width
     dk (units of 2 pi / box_l), n_shells, optional RSD beta, a triangle
     selection (tri_mode with k1_shells / n_mu / n_t / triangles), the
-    contraction precision and flags.
+    contraction precision, flags and the estimator grid n_est (0 = automatic:
+    the smallest supported size above three times the largest mode component).
     """
 
     def __init__(self, n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=_abi.TRI_ALL, k1_shells=None, n_mu=0,
-                 n_t=0, triangles=None, precision=_abi.PREC_SPLITBF16, flags=0):
+                 n_t=0, triangles=None, precision=_abi.PREC_SPLITBF16, flags=0, n_est=0):
         if not torch.cuda.is_available():
             raise RuntimeError("Plan needs a HIP device")
         self.cfg, self._keep = _abi.make_config(n_g, box_l, dk, n_shells, rsd_beta, tri_mode, k1_shells, n_mu, n_t,
-                                                triangles, precision, flags)
+                                                triangles, precision, flags, n_est)
         self.n_g = int(n_g)
+        self.n_est = _abi.bispec_estimator_grid(self.cfg)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.handle = _abi.bispec_plan(self.cfg, _stream())
         abc, lab, ntri = _abi.bispec_triangles(self.handle)
@@ -55,7 +57,8 @@ class Plan:
         return _abi.bispec_stage_times(self.handle, 4)
 
     def field(self, shell: int) -> torch.Tensor:
-        out = torch.empty((self.n_g,) * 3, dtype=torch.float32, device=self.device)
+        """Shell field D_n / (dV n_g^{3/2}) on the estimator grid (n_est^3 points)."""
+        out = torch.empty((self.n_est,) * 3, dtype=torch.float32, device=self.device)
         _abi.bispec_copy_field(self.handle, shell, out.data_ptr(), _stream())
         return out
 

@@ -105,7 +105,34 @@ def test_known_counts():
 
 def test_workspace_bytes():
     run, peak = abi.bispec_workspace_bytes(abi.make_config(512, 1500.0, 1.0, 100, rsd_beta=0.5)[0])
-    # float32 shells are 100 * 512^3 * 4 B and their bf16 hi/lo planes as much again;
-    # the float64 unit shells of the planning phase are 100 * 512^3 * 8 B
-    assert run > 2 * 100 * 512 ** 3 * 4 and peak > 100 * 512 ** 3 * 8
-    assert run < 130e9 and peak < 150e9
+    # shells live on the 320^3 estimator grid: float32 fields 100 * 320^3 * 4 B and
+    # their bf16 hi/lo planes as much again; float64 unit shells 100 * 320^3 * 8 B
+    assert run > 2 * 100 * 320 ** 3 * 4 and peak > 100 * 320 ** 3 * 8
+    assert run < 40e9 and peak < 40e9
+    run512, peak512 = abi.bispec_workspace_bytes(abi.make_config(512, 1500.0, 1.0, 100, rsd_beta=0.5, n_est=512)[0])
+    assert run512 > 2 * 100 * 512 ** 3 * 4 and peak512 > 100 * 512 ** 3 * 8
+    assert run512 < 130e9 and peak512 < 150e9
+
+
+def test_estimator_grid():
+    """G is the smallest supported size above 3 max|m_i| (the largest mode
+    component is floor(sqrt(hi2 - 1)) of the outermost shell), at most n_g."""
+    def grid(*a, **kw):
+        return abi.bispec_estimator_grid(abi.make_config(*a, **kw)[0])
+    # 100 shells of width 1: max component 100 -> G > 300 -> 320 (5 * 64)
+    assert grid(512, 1500.0, 1.0, 100) == 320
+    assert grid(1024, 1500.0, 1.0, 100) == 320
+    # 10 shells of width 1: max 10 -> G > 30 -> 32
+    assert grid(64, 300.0, 1.0, 10) == 32
+    assert grid(32, 300.0, 1.0, 10) == 32
+    # 40 shells of width 2: top edge 81, max component 80 -> G > 240 -> 256
+    assert grid(256, 1000.0, 2.0, 40) == 256
+    # 4 shells of width 1 (max 4): G > 12 -> 16; 2 shells (max 2): the smallest grid, 8
+    assert grid(96, 100.0, 1.0, 4) == 16
+    assert grid(96, 100.0, 1.0, 2) == 8
+    assert grid(512, 1500.0, 1.0, 100, n_est=384) == 384
+    assert grid(512, 1500.0, 1.0, 100, n_est=512) == 512
+    for bad in (256, 300, 640):   # too small, unsupported, above n_g
+        with pytest.raises(abi.BispecError) as e:
+            grid(512, 1500.0, 1.0, 100, n_est=bad)
+        assert e.value.status == abi.BISPEC_EINVAL

@@ -26,7 +26,9 @@ def _cmp(g_gpu, g_ref, tol=TOL):
 
 
 @pytest.mark.parametrize("n_g,box,dk,n_s,beta", [(16, 100.0, 1.0, 4, 0.0), (16, 100.0, 1.0, 4, 0.5),
-                                                 (32, 300.0, 1.0, 10, 0.0), (48, 200.0, 1.5, 9, 1.0)])
+                                                 (32, 300.0, 1.0, 10, 0.0), (48, 200.0, 1.5, 9, 1.0),
+                                                 (64, 300.0, 1.0, 8, 0.5),     # estimator grid 32
+                                                 (48, 200.0, 1.0, 5, 0.0)])    # estimator grid 16
 def test_vjp_matches_oracle(n_g, box, dk, n_s, beta):
     import torch
     import paper_2107_14564_amd as P

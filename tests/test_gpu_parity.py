@@ -22,19 +22,19 @@ def _field(n_g, box, seed, index=-1.0, f_ng=1.0):
     return quadratic_ng_field(gaussian_field(n_g, box, PowerLaw(index), seed), f_ng)
 
 
-def _check(n_g, box, dk, n_s, beta, seed, precision, tri_kw=None, tol=TOL):
+def _check(n_g, box, dk, n_s, beta, seed, precision, tri_kw=None, tol=TOL, n_est=0):
     import paper_2107_14564_amd as P
     tri_kw = tri_kw or {}
-    say("case n_g=%d box=%g dk=%g n_s=%d beta=%g seed=%d prec=%d %s" % (n_g, box, dk, n_s, beta, seed, precision,
-                                                                        tri_kw))
+    say("case n_g=%d box=%g dk=%g n_s=%d beta=%g seed=%d prec=%d n_est=%d %s" % (
+        n_g, box, dk, n_s, beta, seed, precision, n_est, tri_kw))
     delta_gpu, delta64 = to_gpu(_field(n_g, box, seed))
-    plan = P.Plan(n_g, box, dk, n_s, rsd_beta=beta, precision=precision, **tri_kw)
+    plan = P.Plan(n_g, box, dk, n_s, rsd_beta=beta, precision=precision, n_est=n_est, **tri_kw)
     B = plan.run(delta_gpu).cpu().numpy()
     tri = plan.triangles.numpy()
     ref = fbe.estimate(delta64, box, dk, tri, rsd_beta=beta, with_abs=True)
     assert np.array_equal(plan.ntri.numpy(), ref["ntri"]), "N_tri differs"
     m = metrics(B, ref["B"], ref["S"])
-    say("  n_tri=%d %s" % (len(tri), m))
+    say("  n_tri=%d G=%d %s" % (len(tri), plan.n_est, m))
     assert m["e_cond"] <= tol and m["e_norm"] <= tol, m
     plan.close()
     return m
@@ -49,6 +49,9 @@ def _check(n_g, box, dk, n_s, beta, seed, precision, tri_kw=None, tol=TOL):
     (64, 500.0, 2.0, 10, 0.0),
     (48, 200.0, 1.5, 9, 1.0),      # mixed radix 3 (48 = 8*2*3, 24 = 8*3)
     (40, 200.0, 1.0, 12, 0.0),     # mixed radix 5 (40 = 8*5, 20 = 4*5)
+    (64, 300.0, 1.0, 8, 0.5),      # estimator grid 32 < n_g
+    (96, 300.0, 1.0, 10, 0.0),     # estimator grid 32 < n_g (input grid radix 3)
+    (80, 200.0, 1.0, 12, 0.0),     # estimator grid 40 < n_g
 ])
 def test_all_triangles(n_g, box, dk, n_s, beta, precision):
     _check(n_g, box, dk, n_s, beta, 100 + n_g, precision)
@@ -68,19 +71,28 @@ def test_single_triangle_and_single_shell(precision):
     _check(16, 100.0, 1.0, 1, 0.0, 8, precision)
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+def test_estimator_grid_choice(precision):
+    """The same B for every admissible estimator grid G (3 max|m_i| < G <= n_g)."""
+    for n_est in (0, 40, 48, 64):
+        _check(64, 300.0, 1.0, 8, 0.5, 77, precision, n_est=n_est)
+
+
 def test_fields_match_oracle():
-    """Steps a and b alone: the data shell fields D_n against float64 FFTs."""
+    """Steps a and b alone: the data shell fields D_n against float64 FFTs, on
+    the estimator grid (the input grid itself, or a coarser one)."""
     import paper_2107_14564_amd as P
-    for n_g, box, dk, n_s, beta in [(32, 300.0, 1.0, 10, 0.5), (128, 600.0, 2.0, 20, 0.0)]:
-        say("fields n_g=%d n_s=%d" % (n_g, n_s))
+    for n_g, box, dk, n_s, beta in [(32, 300.0, 1.0, 10, 0.5), (128, 600.0, 2.0, 20, 0.0),
+                                    (64, 300.0, 1.0, 8, 0.5), (96, 400.0, 1.0, 20, 0.0)]:
         delta_gpu, delta64 = to_gpu(_field(n_g, box, 11))
         plan = P.Plan(n_g, box, dk, n_s, rsd_beta=beta, precision=1)
+        say("fields n_g=%d n_s=%d G=%d" % (n_g, n_s, plan.n_est))
         plan.run(delta_gpu)
         spec = fbe.spectrum(delta64, box, beta)
         masks = fbe.shell_masks(n_g, dk, list(range(1, n_s + 1)))
         scale = (box / n_g) ** 3 * n_g ** 1.5
         for n in (1, n_s // 2, n_s):
-            ref = fbe.shell_field(spec, masks[n]) / scale
+            ref = fbe.shell_field_at(spec, masks[n], plan.n_est) / scale
             got = plan.field(n).cpu().numpy().astype(np.float64)
             err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
             say("  shell %d max err / max %.3g" % (n, err))

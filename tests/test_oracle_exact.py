@@ -161,3 +161,53 @@ def test_cutoff_enforced():
     d = np.zeros((24, 24, 24))
     with pytest.raises(ValueError):
         fbe.estimate(d, 50.0, 1.0, np.array([[8, 8, 8]]))
+
+
+def test_field_on_another_grid_is_the_mode_sum():
+    """shell_field_at evaluates D_n(x) = sum_{k in n} Delta(k) e^{ik.x} at the points
+    of a coarser grid: against the explicit complex sum over the full spectrum at
+    a few points, and equal to shell_field on the input grid itself."""
+    n_g, L = 16, L16
+    d = _field(n_g, 21)
+    spec = fbe.spectrum(d, L, 0.5)
+    masks = fbe.shell_masks(n_g, 1.0, [2, 3])
+    full = np.fft.fftn(d) * (L / n_g) ** 3
+    m = np.fft.fftfreq(n_g, d=1.0 / n_g)
+    mx, my, mz = np.meshgrid(m, m, m, indexing="ij")
+    m2 = mx ** 2 + my ** 2 + mz ** 2
+    with np.errstate(invalid="ignore", divide="ignore"):
+        z = np.where(m2 > 0, 1 + 0.5 * mz ** 2 / np.where(m2 > 0, m2, 1), 1.0)
+    shell_full = geometry.shell_of_m2(m2.astype(np.int64), 1.0, 3)
+    for n in (2, 3):
+        np.testing.assert_allclose(fbe.shell_field_at(spec, masks[n], n_g), fbe.shell_field(spec, masks[n]),
+                                   rtol=0, atol=1e-12 * np.abs(fbe.shell_field(spec, masks[n])).max())
+        g = 12                                   # modes |m_i| <= 3 < 6
+        coarse = fbe.shell_field_at(spec, masks[n], g)
+        sel = shell_full == n
+        for j in [(0, 0, 0), (1, 5, 11), (7, 3, 2), (11, 11, 6)]:
+            phase = 2j * np.pi * (mx[sel] * j[0] + my[sel] * j[1] + mz[sel] * j[2]) / g
+            ref = np.sum(z[sel] * full[sel] * np.exp(phase))
+            assert abs(ref.imag) < 1e-9 * abs(ref.real) + 1e-12
+            assert abs(coarse[j] - ref.real) <= 1e-10 * np.abs(coarse).max()
+    with pytest.raises(ValueError):
+        fbe.shell_field_at(spec, masks[3], 6)
+
+
+def test_triple_sum_on_a_coarser_grid():
+    """Section 2.2's aliasing argument on an evaluation grid G: the G^3-point sum of
+    D_a1 D_a2 D_a3, scaled by (N/G)^3, equals the N^3-point sum when G > 3 max|m_i|
+    (and counts extra triangles when G is smaller)."""
+    n_g, L, n_s = 24, 50.0, 4        # shells 1-4, max component 4
+    d = _field(n_g, 33)
+    spec = fbe.spectrum(d, L)
+    tri = geometry.all_triangles(n_s)
+    masks = fbe.shell_masks(n_g, 1.0, list(range(1, n_s + 1)))
+    ref = fbe.triple_sums({n: fbe.shell_field(spec, masks[n]) for n in masks}, tri)
+    for g in (13, 16, 20):
+        fields = {n: fbe.shell_field_at(spec, masks[n], g) for n in masks}
+        got = fbe.triple_sums(fields, tri) * (n_g / g) ** 3
+        np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+    ones = {n: fbe.shell_field_at(masks[n].astype(np.complex128), masks[n], 12) for n in masks}
+    n12 = fbe.triple_sums(ones, tri) / 12 ** 3
+    exact = fbe.estimate(np.zeros((n_g,) * 3), L, 1.0, tri)["ntri"]
+    assert np.any(np.rint(n12) > exact)       # G = 12 = 3 * 4 aliases
