@@ -59,13 +59,12 @@ template <typename T> hipError_t upload(DevBuf& b, const std::vector<T>& v, hipS
   return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
 }
 
-// voxel ranges of the MFMA kernel: about 1024 work groups overall, a multiple
-// of 8 (all work groups of a range on one XCD)
-int n_krange_mfma_for(long long groups, long long n_vox) {
-  long long k = (1024 + groups - 1) / groups;
-  k = ((k + 7) / 8) * 8;
-  const long long cap = std::max(8LL, (n_vox / 64) / 8 * 8);
-  return (int)std::min(std::max(k, 8LL), cap);
+// voxel ranges of the MFMA kernel: 256 (a multiple of 8, so all work groups of
+// a range share an XCD; groups * 256 work groups fill whole rounds of the 256
+// CUs at one work group per CU), fewer for small grids (>= 4 chunks per range)
+int n_krange_mfma_for(long long n_vox) {
+  const long long cap = std::max(8LL, (n_vox / (64 * 4)) / 8 * 8);
+  return (int)std::min(256LL, cap);
 }
 
 int n_krange_for(long long groups, long long n_vox) {
@@ -81,7 +80,7 @@ struct Sizes {
   long long n_vox = 0, n_tri = 0;
   size_t spec = 0, fields32 = 0, a1_32 = 0, a2_32 = 0, fields64 = 0, a1_64 = 0, a2_64 = 0, grad = 0;
   size_t tables = 0, partial_run = 0, partial_plan = 0;
-  size_t run_total() const { return spec + 2 * fields32 + a1_32 + a2_32 + grad + tables + partial_run; }
+  size_t run_total() const { return spec + fields32 + a1_32 + a2_32 + grad + tables + partial_run; }
   size_t plan_peak() const {
     size_t p1 = fields64 + a1_64 + a2_64 + tables + partial_plan;
     return std::max(p1, run_total());
@@ -108,7 +107,6 @@ struct bispec_plan_s {
   DevBuf spec, F, a1, a2, partial, partial_mfma, norm, tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols,
       mfma_wgrows, mfma_slot, shells, x_tiles,
       y_off, z_off, tw32, tw32e;
-  DevBuf Fh, Fl;   // bf16 hi/lo planes of F (column operands of the split-bf16 contraction)
   // gradient workspace (BISPEC_FLAG_GRAD)
   DevBuf G, g_terms, g_term_off, g_w, ball_shells, ball_x, ball_y, ball_z;
   long long n_terms = 0;
@@ -166,7 +164,7 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 + (size_t)3 * s.n_tri * (sizeof(int4) + sizeof(float)) : 0;
   const long long ntasks = (long long)p.tiles.task_off.size() - 1;
   p.n_krange_vec = n_krange_for(ntasks, s.n_vox);
-  p.n_krange_mfma = n_krange_mfma_for(p.mfma.n_wg, s.n_vox);
+  p.n_krange_mfma = n_krange_mfma_for(s.n_vox);
   s.partial_run = (size_t)p.n_krange_vec * s.n_tri * sizeof(double) +
                   (size_t)p.n_krange_mfma * p.mfma.n_wg * kTilesPerWg * 1024 * sizeof(double);
   s.partial_plan = (size_t)p.n_krange_vec * s.n_tri * sizeof(double);
@@ -187,8 +185,7 @@ WsArgs ws_args(bispec_plan_s& p) {
   a.wg_rows = p.mfma_wgrows.as<WgRows>();
   a.n_wg = p.mfma.n_wg;
   a.n_s = p.geo.n_s;
-  a.max_f = p.mfma.max_f;
-  a.max_b = p.mfma.max_b;
+  a.max_s = p.mfma.max_s;
   a.n_vox = p.sz.n_vox;
   a.n_krange = p.n_krange_mfma;
   a.partial = p.partial_mfma.as<double>();
@@ -429,8 +426,6 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
   PLAN_HIP(dalloc(p->a1, p->sz.a1_32));
   PLAN_HIP(dalloc(p->a2, p->sz.a2_32));
   PLAN_HIP(dalloc(p->F, p->sz.fields32));
-  PLAN_HIP(dalloc(p->Fh, p->sz.fields32 / 2));
-  PLAN_HIP(dalloc(p->Fl, p->sz.fields32 / 2));
   if (p->cfg.flags & BISPEC_FLAG_GRAD) {
     PLAN_HIP(dalloc(p->G, p->sz.fields32));
     // terms (t, j, l) of every shell n: d(F_a1 F_a2 F_a3)/dF_n
@@ -504,10 +499,8 @@ int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream)
   HIP_TRY(launch_forward(delta, p->spec.as<float2>(), n, (float)p->geo.beta, p->tw32.as<float2>(), s));
   if (timing) HIP_TRY(hipEventRecord(p->ev[1], s));
   ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s, n);
-  const bool split = p->precision == BISPEC_PREC_SPLITBF16;
   HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), p->F.as<float>(), L,
-                             p->geo.n_est, p->tw32e.as<float2>(), split ? p->Fh.as<__bf16>() : nullptr,
-                             split ? p->Fl.as<__bf16>() : nullptr, s));
+                             p->geo.n_est, p->tw32e.as<float2>(), s));
   if (timing) HIP_TRY(hipEventRecord(p->ev[2], s));
   if (p->precision == BISPEC_PREC_FP32) {
     HIP_TRY(launch_contract_fp32(p->F.as<float>(), contract_args(*p, p->n_krange_vec), s));
@@ -515,7 +508,7 @@ int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream)
     HIP_TRY(launch_reduce(p->partial.as<double>(), p->n_krange_vec, p->sz.n_tri, p->sz.n_tri, nullptr,
                           p->norm.as<double>(), B, s));
   } else {
-    HIP_TRY(launch_contract_bf16x3(p->F.as<float>(), p->Fh.as<__bf16>(), p->Fl.as<__bf16>(), ws_args(*p), s));
+    HIP_TRY(launch_contract_bf16x3(p->F.as<float>(), ws_args(*p), s));
     if (timing) HIP_TRY(hipEventRecord(p->ev[3], s));
     HIP_TRY(launch_reduce(p->partial_mfma.as<double>(), p->n_krange_mfma,
                           (long long)p->mfma.n_wg * kTilesPerWg * 1024, p->sz.n_tri, p->mfma_slot.as<int32_t>(),
@@ -544,7 +537,7 @@ int bispec_grad(bispec_plan_t p, const double* gB, float* gdelta, void* hip_stre
   // gdelta = unnormalised inverse transform of S on the n_g grid (one pseudo-shell: natural layout)
   ShellLaunch B = shell_launch(p->pass_ball, p->ball_shells, p->ball_x, p->ball_y, p->ball_z, 1, n);
   HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), gdelta, B, n,
-                             p->tw32.as<float2>(), nullptr, nullptr, s));
+                             p->tw32.as<float2>(), s));
   return BISPEC_OK;
 }
 

@@ -147,53 +147,56 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 // Split-BF16 MFMA form (step c).  Each fp32 operand v is written as
 // v = hi + lo with hi = bf16(v), lo = bf16(v - hi); a product of two operands
 // is accumulated as hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-16 relative, is
-// dropped) by three v_mfma_f32_32x32x16_bf16 per 16 voxels.  The row operand
-// is the pair product F_i F_j formed in fp32 and then split; the column
-// operand comes pre-split as bf16 planes written by the C2R pass.
+// dropped) by three v_mfma_f32_32x32x16_bf16 per 16 voxels.
 //
-// Work group = 8 wavefronts (512 threads), two per SIMD:
-//   consumers (waves 0-3): slot w = kRbPerSlot row blocks of one span and
-//     their <= kMaxColTiles column tiles; per 16 voxels it reads the row fragments of its
-//     row blocks and each column fragment once (shared by both row blocks) and
-//     issues 3 MFMAs per (row block, tile);
-//   producers (waves 4-7): copy the work group's F rows (chunk c+2) and column
-//     plane rows (chunk c+1) from registers loaded two chunks earlier, and
-//     form + split the pair products of chunk c+1 for all kRbPerWg row blocks.
-// Only the shell rows the work group needs are staged (WgRows).  LDS holds two
-// buffers of everything (one barrier per chunk of kC2 = 32 voxels):
-//   F32 [2][max_f + 1][kC2 + 4] fp32, Bh/Bl [2][max_b + 1][kC2 + 8] bf16,
-//   Ah/Al [2][kRbPerWg][32][kC2 + 8] bf16      (the extra row is all zero).
+// GEMM view per voxel range: C[(i,j), l] = sum_x A[(i,j), x] B[x, l] with the
+// row operand A = F_i F_j (a pair product) and the column operand B = F_l.
+// Work group = kSlotsPerWg wavefronts (two per SIMD); wave w owns slot w:
+// kRbPerSlot row blocks of 32 pairs and their <= kMaxColTiles column tiles of
+// 32 shells (accumulators 4 x 2 x 16 fp32 per lane).
+//
+// Per chunk of 32 voxels (one voxel block) every thread loads <= 2 float4 of
+// the work group's shell rows s_lo .. s_lo + s_n - 1 (contiguous in the
+// voxel-blocked layout) one chunk ahead, and stores them into the other LDS
+// buffer as fp32 (row operands) and as bf16 hi/lo (column operands, split
+// once per value).  Per 16 voxels a lane then
+//   - reads its column fragments (hi, lo: 8 voxels of shell l each),
+//   - for each row block reads 8 voxels of F_i and F_j, forms the 8 pair
+//     products in registers, splits them (the MFMA row-operand layout: lane
+//     = row + 32 * (voxel octet)), and issues 3 MFMAs per column tile.
+// There is no LDS round trip for the products and one barrier per chunk.
+//
+// LDS (two buffers): F32 [2][s + 1][36] fp32, Bh/Bl [2][s + 1][40] bf16 with
+// s = the largest s_n and the extra row all zero (padding rows and columns
+// point there).  Row strides of 36 and 20 dwords keep 8 consecutive rows on
+// distinct banks for the 16-byte fragment reads.
 // Accumulation: fp32 MFMA chains of kFlushChunks chunks, added in float64 into
 // partial[range][tile][element] (tile-major, coalesced); the reduction maps
 // elements to triangles.
 // ============================================================================
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kC2 = 32;              // voxels per chunk (= one voxel block)
 constexpr int kF32S = kC2 + 4;       // fp32 row stride (floats)
 constexpr int kBS = kC2 + 8;         // bf16 row stride (elements)
 constexpr int kFlushChunks = 256;    // 8192 voxels per float32 accumulation chain
-constexpr int kWsThreads = 512;
-constexpr int kProd = 256;           // producer threads
-constexpr int kNV = 4;               // float4 / uint4 staging slots per producer thread
+constexpr int kWsThreads = kSlotsPerWg * 64;
+constexpr int kPf = 2;               // float4 loads per thread per chunk
 static_assert(kC2 == kVoxBlock, "chunks are voxel blocks");
 
 struct WsLds {
-  float* f32;      // [2][nf1][kF32S]
-  __bf16* bh;      // [2][nb1][kBS]
+  float* f32;      // [2][ns1][kF32S]
+  __bf16* bh;      // [2][ns1][kBS]
   __bf16* bl;
-  __bf16* ah;      // [2][kRbPerWg][32][kBS]
-  __bf16* al;
-  int nf1, nb1;    // rows per buffer including the zero row
-  __device__ float* F(int buf, int r) const { return f32 + (buf * nf1 + r) * kF32S; }
-  __device__ __bf16* Bh(int buf, int r) const { return bh + (buf * nb1 + r) * kBS; }
-  __device__ __bf16* Bl(int buf, int r) const { return bl + (buf * nb1 + r) * kBS; }
-  __device__ __bf16* Ah(int buf, int rb, int r) const { return ah + ((buf * kRbPerWg + rb) * 32 + r) * kBS; }
-  __device__ __bf16* Al(int buf, int rb, int r) const { return al + ((buf * kRbPerWg + rb) * 32 + r) * kBS; }
+  int ns1;         // rows per buffer including the zero row
+  __device__ float* F(int buf, int r) const { return f32 + (buf * ns1 + r) * kF32S; }
+  __device__ __bf16* Bh(int buf, int r) const { return bh + (buf * ns1 + r) * kBS; }
+  __device__ __bf16* Bl(int buf, int r) const { return bl + (buf * ns1 + r) * kBS; }
 };
 
-__device__ __forceinline__ void split8(const float* p, bf16x8& hi, bf16x8& lo) {
+__device__ __forceinline__ void split8(const float (&p)[8], bf16x8& hi, bf16x8& lo) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const __bf16 h = (__bf16)p[e];
@@ -202,262 +205,166 @@ __device__ __forceinline__ void split8(const float* p, bf16x8& hi, bf16x8& lo) {
   }
 }
 
-struct WsRange {
-  long long k_lo, k_hi;
-  int n_chunks;
-};
-
-// ---- producers ---------------------------------------------------------------
-struct WsPf {
-  float4 f[kNV];
-  uint4 b[kNV];    // slots [0, 4 b_n) hi plane rows, [4 b_n, 8 b_n) lo plane rows
-};
-
-__device__ __forceinline__ void ws_load_f(const float* __restrict__ F, const WsArgs& a, const WgRows& wr,
-                                          const WsRange& R, int c, WsPf& pf, int tid) {
-  if (c >= R.n_chunks) return;
-  const float4* base = reinterpret_cast<const float4*>(F + ((R.k_lo / kC2) + c) * (long long)a.n_s * kC2 +
-                                                       (long long)wr.f_lo * kC2);
-  const int n4 = wr.f_n * (kC2 / 4);
+// chunk c of the range: rows s_lo .. s_lo + s_n - 1, 8 float4 per row
+__device__ __forceinline__ void ws_load(const float* __restrict__ F, int n_s, long long blk0, const WgRows& wr,
+                                        int c, float4 (&pf)[kPf], int tid) {
+  const float4* base =
+      reinterpret_cast<const float4*>(F + (blk0 + c) * (long long)n_s * kC2 + (long long)wr.s_lo * kC2);
 #pragma unroll
-  for (int u = 0; u < kNV; ++u) {
-    const int idx = tid + u * kProd;
-    if (idx < n4) pf.f[u] = base[idx];
+  for (int u = 0; u < kPf; ++u) {
+    const int idx = tid + u * kWsThreads;
+    if (idx < wr.s_n * (kC2 / 4)) pf[u] = base[idx];
   }
 }
 
-__device__ __forceinline__ void ws_load_b(const __bf16* __restrict__ fh, const __bf16* __restrict__ fl,
-                                          const WsArgs& a, const WgRows& wr, const WsRange& R, int c, WsPf& pf,
-                                          int tid) {
-  if (c >= R.n_chunks) return;
-  const long long off = ((R.k_lo / kC2) + c) * (long long)a.n_s * kC2 + (long long)wr.b_lo * kC2;
-  const uint4* bh = reinterpret_cast<const uint4*>(fh + off);
-  const uint4* bl = reinterpret_cast<const uint4*>(fl + off);
-  const int per_plane = wr.b_n * (kC2 / 8);
+__device__ __forceinline__ void ws_store(const WsLds& L, const WgRows& wr, int buf, const float4 (&pf)[kPf],
+                                         int tid) {
 #pragma unroll
-  for (int u = 0; u < kNV; ++u) {
-    const int idx = tid + u * kProd;
-    if (idx < per_plane)
-      pf.b[u] = bh[idx];
-    else if (idx < 2 * per_plane)
-      pf.b[u] = bl[idx - per_plane];
-  }
-}
-
-__device__ __forceinline__ void ws_store_f(const WsLds& L, const WgRows& wr, int buf, const WsPf& pf, int tid) {
+  for (int u = 0; u < kPf; ++u) {
+    const int idx = tid + u * kWsThreads;
+    if (idx < wr.s_n * (kC2 / 4)) {
+      const int r = idx >> 3, x = 4 * (idx & 7);
+      *reinterpret_cast<float4*>(L.F(buf, r) + x) = pf[u];
+      const float v[4] = {pf[u].x, pf[u].y, pf[u].z, pf[u].w};
+      bf16x4 h, l;
 #pragma unroll
-  for (int u = 0; u < kNV; ++u) {
-    const int idx = tid + u * kProd;
-    if (idx < wr.f_n * (kC2 / 4)) *reinterpret_cast<float4*>(L.F(buf, idx >> 3) + 4 * (idx & 7)) = pf.f[u];
-  }
-}
-
-__device__ __forceinline__ void ws_store_b(const WsLds& L, const WgRows& wr, int buf, const WsPf& pf, int tid) {
-  const int per_plane = wr.b_n * (kC2 / 8);
-#pragma unroll
-  for (int u = 0; u < kNV; ++u) {
-    const int idx = tid + u * kProd;
-    if (idx < 2 * per_plane) {
-      const int plane = idx >= per_plane;
-      const int k = idx - plane * per_plane;
-      __bf16* dst = (plane ? L.Bl(buf, k >> 2) : L.Bh(buf, k >> 2)) + 8 * (k & 3);
-      *reinterpret_cast<uint4*>(dst) = pf.b[u];
+      for (int e = 0; e < 4; ++e) {
+        h[e] = (__bf16)v[e];
+        l[e] = (__bf16)(v[e] - (float)h[e]);
+      }
+      *reinterpret_cast<bf16x4*>(L.Bh(buf, r) + x) = h;
+      *reinterpret_cast<bf16x4*>(L.Bl(buf, r) + x) = l;
     }
   }
 }
 
-// pair products of the chunk in F32 buffer buf, split into A[buf]:
-// kRbPerWg * 32 pairs x 4 groups of 8 voxels, 4 groups per thread
-__device__ __forceinline__ void ws_products(const WsLds& L, int buf, const int (&pi)[4], const int (&pj)[4],
-                                            int tid) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    // two groups in flight at a time (bounds the producer's register use)
-    if (u == 2) asm volatile("" ::: "memory");
-    const int g = tid + u * kProd;
-    const int rbr = g >> 2, xg = (g & 3) * 8;  // rbr = rb * 32 + row
-    const float* fi = L.F(buf, pi[u]) + xg;
-    const float* fj = L.F(buf, pj[u]) + xg;
-    const float4 i0 = *reinterpret_cast<const float4*>(fi), i1 = *reinterpret_cast<const float4*>(fi + 4);
-    const float4 j0 = *reinterpret_cast<const float4*>(fj), j1 = *reinterpret_cast<const float4*>(fj + 4);
-    const float p[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
-                        i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
-    bf16x8 hi, lo;
-    split8(p, hi, lo);
-    *reinterpret_cast<bf16x8*>(L.Ah(buf, rbr >> 5, rbr & 31) + xg) = hi;
-    *reinterpret_cast<bf16x8*>(L.Al(buf, rbr >> 5, rbr & 31) + xg) = lo;
-  }
-}
-
-// Iteration c: products of chunk c+1 (F32[(c+1)%2] -> A[(c+1)%2]); F32[c%2] <- F rows
-// of chunk c+2 and B[(c+1)%2] <- plane rows of chunk c+1 from registers loaded two
-// iterations earlier; then the loads of chunks c+4 (F) and c+3 (planes) are issued.
-__device__ __forceinline__ void ws_producer(const float* __restrict__ F, const __bf16* __restrict__ fh,
-                                            const __bf16* __restrict__ fl, const WsArgs& a, const WsLds& L,
-                                            const WsRange& R, int wg, int tid) {
-  const WgRows wr = a.wg_rows[wg];
-  int pi[4], pj[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int g = tid + u * kProd;
-    const int rb = wg * kRbPerWg + ((g >> 2) >> 5), r = (g >> 2) & 31;
-    const int i = a.rows[rb].i[r], j = a.rows[rb].j[r];
-    pi[u] = j > 0 ? i - 1 - wr.f_lo : wr.f_n;  // row f_n of the buffer is zero
-    pj[u] = j > 0 ? j - 1 - wr.f_lo : wr.f_n;
-  }
-  WsPf p0, p1;
-  ws_load_f(F, a, wr, R, 0, p0, tid);
-  ws_load_f(F, a, wr, R, 1, p1, tid);
-  ws_load_b(fh, fl, a, wr, R, 0, p0, tid);
-  ws_store_f(L, wr, 0, p0, tid);
-  ws_store_f(L, wr, 1, p1, tid);
-  ws_store_b(L, wr, 0, p0, tid);
-  ws_load_f(F, a, wr, R, 2, p0, tid);
-  ws_load_f(F, a, wr, R, 3, p1, tid);
-  ws_load_b(fh, fl, a, wr, R, 1, p0, tid);
-  ws_load_b(fh, fl, a, wr, R, 2, p1, tid);
-  __syncthreads();                 // barrier P1
-  ws_products(L, 0, pi, pj, tid);  // chunk 0 -> A[0]
-  __syncthreads();                 // barrier P2
-  for (int c = 0; c < R.n_chunks; c += 2) {
-    if (c + 1 < R.n_chunks) ws_products(L, 1, pi, pj, tid);
-    ws_store_f(L, wr, 0, p0, tid);   // F of chunk c+2
-    ws_store_b(L, wr, 1, p0, tid);   // planes of chunk c+1
-    ws_load_f(F, a, wr, R, c + 4, p0, tid);
-    ws_load_b(fh, fl, a, wr, R, c + 3, p0, tid);
-    __syncthreads();
-    if (c + 1 >= R.n_chunks) break;
-    if (c + 2 < R.n_chunks) ws_products(L, 0, pi, pj, tid);
-    ws_store_f(L, wr, 1, p1, tid);   // F of chunk c+3
-    ws_store_b(L, wr, 0, p1, tid);   // planes of chunk c+2
-    ws_load_f(F, a, wr, R, c + 5, p1, tid);
-    ws_load_b(fh, fl, a, wr, R, c + 4, p1, tid);
-    __syncthreads();
-  }
-}
-
-// ---- consumers ---------------------------------------------------------------
-// NT = column tiles of this slot (constant over the run).
+// 32 voxels of buffer buf for a slot with NT column tiles
 template <int NT>
-__device__ __forceinline__ void ws_consumer_nt(const WsArgs& a, const WsLds& L, const WsRange& R, int wg, int w,
-                                               const SlotCols& sc, const WgRows& wr, int lane, int kr) {
-  const int kg = lane >> 5;
-  int cs[NT];
+__device__ __forceinline__ void ws_compute(const WsLds& L, int buf, const int (&ri)[kRbPerSlot],
+                                           const int (&rj)[kRbPerSlot], const int (&cs)[kMaxColTiles], int kg,
+                                           f32x16 (&acc)[kRbPerSlot][kMaxColTiles]) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int l = sc.col0[t] + (lane & 31);  // 1-based column shell
-    cs[t] = (l <= a.n_s) ? l - 1 - wr.b_lo : wr.b_n;  // row b_n of the buffer is zero
+  for (int ks = 0; ks < kC2 / 16; ++ks) {
+    const int off = ks * 16 + kg * 8;
+    bf16x8 bhi[NT], blo[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      bhi[t] = *reinterpret_cast<const bf16x8*>(L.Bh(buf, cs[t]) + off);
+      blo[t] = *reinterpret_cast<const bf16x8*>(L.Bl(buf, cs[t]) + off);
+    }
+#pragma unroll
+    for (int q = 0; q < kRbPerSlot; ++q) {
+      const float* fi = L.F(buf, ri[q]) + off;
+      const float* fj = L.F(buf, rj[q]) + off;
+      const float4 i0 = *reinterpret_cast<const float4*>(fi), i1 = *reinterpret_cast<const float4*>(fi + 4);
+      const float4 j0 = *reinterpret_cast<const float4*>(fj), j1 = *reinterpret_cast<const float4*>(fj + 4);
+      const float p[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
+                          i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
+      bf16x8 ahi, alo;
+      split8(p, ahi, alo);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[t], acc[q][t], 0, 0, 0);
+        acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[t], acc[q][t], 0, 0, 0);
+        acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[t], acc[q][t], 0, 0, 0);
+      }
+    }
   }
-  f32x16 acc[kRbPerSlot][NT];
+}
+
+// float64 flush of the slot's accumulators (first: write, else add), then reset.
+// The base pointer passes through an empty asm so the 8 x 16 element addresses
+// are formed here, not hoisted out of the main loop into live registers.
+template <int NT>
+__device__ __forceinline__ void ws_flush(double* out, bool first, f32x16 (&acc)[kRbPerSlot][kMaxColTiles]) {
+  asm volatile("" : "+v"(out));
 #pragma unroll
   for (int q = 0; q < kRbPerSlot; ++q)
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t) {
+      double* o = out + (long long)(q * kMaxColTiles + t) * 1024;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[q][t][v] = 0.f;
-  // partial[kr][tile][element] with tile = wg*kTilesPerWg + (slot rows)*kMaxColTiles + t
-  double* out = a.partial + ((long long)kr * a.n_wg * kTilesPerWg + (long long)wg * kTilesPerWg) * 1024 + lane;
-  bool first = true;
-  __syncthreads();  // matches producer barrier P1
-  __syncthreads();  // matches producer barrier P2
-  int chain = 0;
-  for (int c = 0; c < R.n_chunks; ++c) {
-    const int buf = c & 1;
-#pragma unroll
-    for (int ks = 0; ks < kC2 / 16; ++ks) {
-      const int off = ks * 16 + kg * 8;
-      bf16x8 ahi[kRbPerSlot], alo[kRbPerSlot];
-#pragma unroll
-      for (int q = 0; q < kRbPerSlot; ++q) {
-        ahi[q] = *reinterpret_cast<const bf16x8*>(L.Ah(buf, w * kRbPerSlot + q, lane & 31) + off);
-        alo[q] = *reinterpret_cast<const bf16x8*>(L.Al(buf, w * kRbPerSlot + q, lane & 31) + off);
-      }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(L.Bh(buf, cs[t]) + off);
-        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(L.Bl(buf, cs[t]) + off);
-#pragma unroll
-        for (int q = 0; q < kRbPerSlot; ++q) {
-          acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[q], bhi, acc[q][t], 0, 0, 0);
-          acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[q], blo, acc[q][t], 0, 0, 0);
-          acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[q], bhi, acc[q][t], 0, 0, 0);
-        }
+      for (int v = 0; v < 16; ++v) {
+        o[v * 64] = first ? (double)acc[q][t][v] : o[v * 64] + (double)acc[q][t][v];
+        acc[q][t][v] = 0.f;
       }
     }
-    if (++chain == kFlushChunks || c + 1 == R.n_chunks) {
-      chain = 0;
-#pragma unroll
-      for (int q = 0; q < kRbPerSlot; ++q)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          double* o = out + (long long)((w * kRbPerSlot + q) * kMaxColTiles + t) * 1024;
-          // one tile at a time: keeps the float64 read-modify-write of the
-          // partials from being hoisted across tiles (register pressure)
-          asm volatile("" ::: "memory");
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            o[v * 64] = first ? (double)acc[q][t][v] : o[v * 64] + (double)acc[q][t][v];
-            acc[q][t][v] = 0.f;
-          }
-        }
-      first = false;
-    }
-    __syncthreads();  // matches the producer's per-chunk barrier
-  }
-  if (R.n_chunks == 0) {  // empty range: its partials are zero
-#pragma unroll
-    for (int q = 0; q < kRbPerSlot; ++q)
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) out[(long long)((w * kRbPerSlot + q) * kMaxColTiles + t) * 1024 + v * 64] = 0.0;
-  }
 }
 
-__device__ __forceinline__ void ws_consumer(const WsArgs& a, const WsLds& L, const WsRange& R, int wg, int w,
-                                            int lane, int kr) {
-  const SlotCols sc = a.cols[wg * kSlotsPerWg + w];
-  const WgRows wr = a.wg_rows[wg];
-  switch (sc.n) {
-    case 1: ws_consumer_nt<1>(a, L, R, wg, w, sc, wr, lane, kr); break;
-    case 2: ws_consumer_nt<2>(a, L, R, wg, w, sc, wr, lane, kr); break;
-    default:  // idle slot: keep the barrier count of the work group
-      for (int c = 0; c < R.n_chunks + 2; ++c) __syncthreads();
-      break;
-  }
-}
-
-__global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __restrict__ F,
-                                                                const __bf16* __restrict__ fh,
-                                                                const __bf16* __restrict__ fl, WsArgs a) {
+__global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __restrict__ F, WsArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   WsLds L;
-  L.nf1 = a.max_f + 1;
-  L.nb1 = a.max_b + 1;
+  L.ns1 = a.max_s + 1;
   L.f32 = reinterpret_cast<float*>(smem_raw);
-  L.bh = reinterpret_cast<__bf16*>(L.f32 + 2 * L.nf1 * kF32S);
-  L.bl = L.bh + 2 * L.nb1 * kBS;
-  L.ah = L.bl + 2 * L.nb1 * kBS;
-  L.al = L.ah + 2 * kRbPerWg * 32 * kBS;
+  L.bh = reinterpret_cast<__bf16*>(L.f32 + 2 * L.ns1 * kF32S);
+  L.bl = L.bh + 2 * L.ns1 * kBS;
   int wg, kr;
   xcd_map(a.n_wg, wg, kr);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, kg = lane >> 5;
   const WgRows wr = a.wg_rows[wg];
-  // zero rows (index f_n / b_n of each buffer), never overwritten afterwards
-  for (int e = threadIdx.x; e < 2 * kF32S; e += kWsThreads) L.F(e / kF32S, wr.f_n)[e % kF32S] = 0.f;
-  for (int e = threadIdx.x; e < 2 * kBS; e += kWsThreads) {
-    L.Bh(e / kBS, wr.b_n)[e % kBS] = (__bf16)0.f;
-    L.Bl(e / kBS, wr.b_n)[e % kBS] = (__bf16)0.f;
+  // zero row (index s_n of each buffer), never overwritten afterwards
+  for (int e = tid; e < 2 * kF32S; e += kWsThreads) L.F(e / kF32S, wr.s_n)[e % kF32S] = 0.f;
+  for (int e = tid; e < 2 * kBS; e += kWsThreads) {
+    L.Bh(e / kBS, wr.s_n)[e % kBS] = (__bf16)0.f;
+    L.Bl(e / kBS, wr.s_n)[e % kBS] = (__bf16)0.f;
+  }
+  // this lane's rows (pair shells) and columns, as LDS row indices
+  const SlotCols sc = a.cols[wg * kSlotsPerWg + w];
+  int ri[kRbPerSlot], rj[kRbPerSlot], cs[kMaxColTiles];
+#pragma unroll
+  for (int q = 0; q < kRbPerSlot; ++q) {
+    const RowBlock& rb = a.rows[wg * kRbPerWg + w * kRbPerSlot + q];
+    const int i = rb.i[lane & 31], j = rb.j[lane & 31];
+    ri[q] = j > 0 ? i - 1 - wr.s_lo : wr.s_n;
+    rj[q] = j > 0 ? j - 1 - wr.s_lo : wr.s_n;
+  }
+#pragma unroll
+  for (int t = 0; t < kMaxColTiles; ++t) {
+    const int l = t < sc.n ? sc.col0[t] + (lane & 31) : 0;  // 1-based column shell
+    cs[t] = (l >= 1 && l <= a.n_s) ? l - 1 - wr.s_lo : wr.s_n;
+  }
+  f32x16 acc[kRbPerSlot][kMaxColTiles];
+#pragma unroll
+  for (int q = 0; q < kRbPerSlot; ++q)
+#pragma unroll
+    for (int t = 0; t < kMaxColTiles; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[q][t][v] = 0.f;
+  // partial[kr][tile][element] with tile = wg*kTilesPerWg + (w*kRbPerSlot + q)*kMaxColTiles + t
+  double* out = a.partial +
+                ((long long)kr * a.n_wg * kTilesPerWg + (long long)wg * kTilesPerWg +
+                 (long long)w * kRbPerSlot * kMaxColTiles) * 1024 + lane;
+  const long long k_lo = range_lo(a.n_vox, a.n_krange, kr), k_hi = range_lo(a.n_vox, a.n_krange, kr + 1);
+  const int n_chunks = (int)((k_hi - k_lo) / kC2);
+  const long long blk0 = k_lo / kC2;
+  float4 pf[kPf];
+  if (n_chunks > 0) {
+    ws_load(F, a.n_s, blk0, wr, 0, pf, tid);
+    ws_store(L, wr, 0, pf, tid);
   }
   __syncthreads();
-  WsRange R;
-  R.k_lo = range_lo(a.n_vox, a.n_krange, kr);
-  R.k_hi = range_lo(a.n_vox, a.n_krange, kr + 1);
-  R.n_chunks = (int)((R.k_hi - R.k_lo + kC2 - 1) / kC2);
-  const int wave = threadIdx.x >> 6;
-  if (wave < kSlotsPerWg)
-    ws_consumer(a, L, R, wg, wave, threadIdx.x & 63, kr);
-  else
-    ws_producer(F, fh, fl, a, L, R, wg, threadIdx.x - 256);
+  bool first = true;
+  int chain = 0;
+  for (int c = 0; c < n_chunks; ++c) {
+    const bool more = c + 1 < n_chunks;
+    if (more) ws_load(F, a.n_s, blk0, wr, c + 1, pf, tid);
+    if (sc.n == 2)
+      ws_compute<2>(L, c & 1, ri, rj, cs, kg, acc);
+    else if (sc.n == 1)
+      ws_compute<1>(L, c & 1, ri, rj, cs, kg, acc);
+    if (more) ws_store(L, wr, (c + 1) & 1, pf, tid);
+    if (++chain == kFlushChunks || !more) {
+      chain = 0;
+      if (sc.n == 2)
+        ws_flush<2>(out, first, acc);
+      else if (sc.n == 1)
+        ws_flush<1>(out, first, acc);
+      first = false;
+    }
+    __syncthreads();
+  }
+  if (n_chunks == 0)  // empty range: its partials are zero
+    for (int e = 0; e < kRbPerSlot * kMaxColTiles * 16; ++e) out[(long long)(e >> 4) * 1024 + (e & 15) * 64] = 0.0;
 }
 
 // ============================================================================
@@ -529,23 +436,22 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
 
 }  // namespace
 
-size_t bf16x3_lds_bytes(int max_f, int max_b) {
-  return 2 * (size_t)(max_f + 1) * kF32S * sizeof(float) + 4 * (size_t)(max_b + 1) * kBS * sizeof(__bf16) +
-         4 * (size_t)kRbPerWg * 32 * kBS * sizeof(__bf16);
+size_t bf16x3_lds_bytes(int max_s) {
+  return 2 * (size_t)(max_s + 1) * kF32S * sizeof(float) + 4 * (size_t)(max_s + 1) * kBS * sizeof(__bf16);
 }
 
 hipError_t launch_contract_fp32(const float* F, const ContractArgs& a, hipStream_t st) { return launch_vec<float>(F, a, st); }
 hipError_t launch_contract_fp64(const double* F, const ContractArgs& a, hipStream_t st) { return launch_vec<double>(F, a, st); }
 
-hipError_t launch_contract_bf16x3(const float* F, const __bf16* f_hi, const __bf16* f_lo, const WsArgs& a,
-                                  hipStream_t st) {
-  if (a.max_f * (kC2 / 4) > kProd * kNV || 2 * a.max_b * (kC2 / 8) > kProd * kNV) return hipErrorInvalidValue;
-  const size_t lds = bf16x3_lds_bytes(a.max_f, a.max_b);
+hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t st) {
+  // every staged row fits the per-thread loads; ranges are whole voxel blocks
+  if (a.max_s * (kC2 / 4) > kWsThreads * kPf || a.max_s > a.n_s || a.n_vox % 64 != 0) return hipErrorInvalidValue;
+  const size_t lds = bf16x3_lds_bytes(a.max_s);
   hipError_t e = hipFuncSetAttribute((const void*)k_contract_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)a.n_wg * (unsigned)a.n_krange;
-  hipLaunchKernelGGL(k_contract_bf16x3, dim3(blocks), dim3(kWsThreads), lds, st, F, f_hi, f_lo, a);
+  hipLaunchKernelGGL(k_contract_bf16x3, dim3(blocks), dim3(kWsThreads), lds, st, F, a);
   return hipGetLastError();
 }
 

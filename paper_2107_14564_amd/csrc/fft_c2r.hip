@@ -5,16 +5,15 @@ namespace bispec {
 
 using namespace fftk;
 
-template <typename T, typename OutT, bool SPLIT>
-static hipError_t c2r(const V2<T>* a2, OutT* out, __bf16* hi, __bf16* lo, const ShellLaunch& L, int n,
-                      const V2<T>* tw, hipStream_t st) {
+template <typename T, typename OutT>
+static hipError_t c2r(const V2<T>* a2, OutT* out, const ShellLaunch& L, int n, const V2<T>* tw, hipStream_t st) {
   if (L.n_z_blocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)L.n_z_blocks);
   switch (n) {
 #define BISPEC_CASE(NN)                                                                                        \
   case NN:                                                                                                     \
-    hipLaunchKernelGGL((k_c2r_z<T, OutT, SPLIT, NN>), grid, dim3(kThrZ), 0, st, a2, out, L.z_off, L.n_shells, \
-                       L.shells, tw, hi, lo);                                                                  \
+    hipLaunchKernelGGL((k_c2r_z<T, OutT, NN>), grid, dim3(kThrZ), 0, st, a2, out, L.z_off, L.n_shells, \
+                       L.shells, tw);                                                                     \
     break;
     BISPEC_FOR_EACH_N(BISPEC_CASE)
 #undef BISPEC_CASE
@@ -23,15 +22,14 @@ static hipError_t c2r(const V2<T>* a2, OutT* out, __bf16* hi, __bf16* lo, const 
   return hipGetLastError();
 }
 
-hipError_t launch_c2r_f32(const float2* a2, float* F, __bf16* f_hi, __bf16* f_lo, const ShellLaunch& L, int n,
-                          const float2* tw, hipStream_t st) {
-  if (f_hi && f_lo) return c2r<float, float, true>(a2, F, f_hi, f_lo, L, n, tw, st);
-  return c2r<float, float, false>(a2, F, nullptr, nullptr, L, n, tw, st);
+hipError_t launch_c2r_f32(const float2* a2, float* F, const ShellLaunch& L, int n, const float2* tw,
+                          hipStream_t st) {
+  return c2r<float, float>(a2, F, L, n, tw, st);
 }
 
 hipError_t launch_c2r_f64(const double2* a2, double* I, const ShellLaunch& L, int n, const double2* tw,
                           hipStream_t st) {
-  return c2r<double, double, false>(a2, I, nullptr, nullptr, L, n, tw, st);
+  return c2r<double, double>(a2, I, L, n, tw, st);
 }
 
 }  // namespace bispec

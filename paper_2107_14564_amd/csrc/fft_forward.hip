@@ -77,10 +77,10 @@ void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p
 }
 
 hipError_t launch_data_shells(const float2* spec, float2* a1, float2* a2, float* F, const ShellLaunch& L, int n,
-                              const float2* tw, __bf16* f_hi, __bf16* f_lo, hipStream_t st) {
+                              const float2* tw, hipStream_t st) {
   hipError_t e = launch_inv_x_f32(spec, a1, L, n, tw, st);
   if (e == hipSuccess) e = launch_inv_y_f32(a1, a2, L, n, tw, st);
-  if (e == hipSuccess) e = launch_c2r_f32(a2, F, f_hi, f_lo, L, n, tw, st);
+  if (e == hipSuccess) e = launch_c2r_f32(a2, F, L, n, tw, st);
   return e;
 }
 

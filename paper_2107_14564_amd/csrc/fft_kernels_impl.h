@@ -194,12 +194,11 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1
 // Per (x, y) line: X_k (k = 0..M, zero beyond R), Z'_k = (X_k + X*_{M-k})
 // + i W_N^{-k} (X_k - X*_{M-k}) for k < M, M-point inverse FFT; the
 // unnormalised real line is (Re z_m, Im z_m) at (2m, 2m+1), written
-// voxel-blocked; with SPLIT also as bf16 planes hi = bf16(v), lo = bf16(v - hi).
-template <typename T, typename OutT, bool SPLIT, int N>
+// voxel-blocked.
+template <typename T, typename OutT, int N>
 __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, OutT* __restrict__ out,
                                                  const long long* __restrict__ blk_off, int n_shells,
-                                                 const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw,
-                                                 __bf16* __restrict__ out_hi, __bf16* __restrict__ out_lo) {
+                                                 const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw) {
   constexpr int M = N / 2;
   constexpr int NL = fft_z_lines(M, sizeof(T) == 8);
   constexpr int LS = M + 1;
@@ -246,16 +245,6 @@ __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, O
     const OutT x0 = (OutT)z.x, x1 = (OutT)z.y;
     const long long at = vox_index((line0 + c) * N + 2 * q, sn, n_shells);  // even: pair stays in one block
     *reinterpret_cast<V2<OutT>*>(out + at) = mk<OutT>(x0, x1);
-    if constexpr (SPLIT) {
-      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-      bf16x2 h, l;
-      h[0] = (__bf16)x0;
-      h[1] = (__bf16)x1;
-      l[0] = (__bf16)(x0 - (float)h[0]);
-      l[1] = (__bf16)(x1 - (float)h[1]);
-      *reinterpret_cast<bf16x2*>(out_hi + at) = h;
-      *reinterpret_cast<bf16x2*>(out_lo + at) = l;
-    }
   }
 }
 

@@ -331,17 +331,17 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
   mt.cols.assign((size_t)mt.n_wg * kSlotsPerWg, SlotCols{});
   mt.wg_rows.assign(mt.n_wg, WgRows{});
   mt.tiles = 0;
-  mt.max_f = mt.max_b = 0;
+  mt.max_s = 0;
   std::map<std::tuple<int, int, int>, int32_t> where;
   for (int w = 0; w < mt.n_wg; ++w) {
-    int f_lo = 1 << 30, f_hi = -1, b_lo = 1 << 30, b_hi = -1;
+    int s_lo = 1 << 30, s_hi = -1;
     for (int sidx = 0; sidx < kSlotsPerWg; ++sidx) {
       const Slot& sl = slots[(size_t)w * kSlotsPerWg + sidx];
       mt.cols[(size_t)w * kSlotsPerWg + sidx] = sl.sc;
       mt.tiles += (int64_t)sl.sc.n * kRbPerSlot;
       for (int t = 0; t < sl.sc.n; ++t) {
-        b_lo = std::min(b_lo, sl.sc.col0[t] - 1);
-        b_hi = std::max(b_hi, std::min(sl.sc.col0[t] - 1 + kCols - 1, n_shells - 1));
+        s_lo = std::min(s_lo, sl.sc.col0[t] - 1);
+        s_hi = std::max(s_hi, std::min(sl.sc.col0[t] - 1 + kCols - 1, n_shells - 1));
       }
       for (int q = 0; q < kRbPerSlot; ++q) {
         const int rbi = sidx * kRbPerSlot + q;  // row block within the work group
@@ -349,8 +349,8 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
         for (int r = 0; r < kRows; ++r) {
           const int i = sl.rb[q].i[r], j = sl.rb[q].j[r];
           if (!j) continue;
-          f_lo = std::min(f_lo, std::min(i, j) - 1);
-          f_hi = std::max(f_hi, std::max(i, j) - 1);
+          s_lo = std::min(s_lo, std::min(i, j) - 1);
+          s_hi = std::max(s_hi, std::max(i, j) - 1);
           // element of the 32x32 accumulator: row r, column c -> (v, lane)
           for (int t = 0; t < sl.sc.n; ++t)
             for (int l : pl[{i, j}]) {
@@ -364,14 +364,10 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
       }
     }
     WgRows& wr = mt.wg_rows[w];
-    if (f_hi < 0) { f_lo = 0; f_hi = -1; }
-    if (b_hi < 0) { b_lo = 0; b_hi = -1; }
-    wr.f_lo = f_lo;
-    wr.f_n = f_hi - f_lo + 1;
-    wr.b_lo = b_lo;
-    wr.b_n = b_hi - b_lo + 1;
-    mt.max_f = std::max(mt.max_f, wr.f_n);
-    mt.max_b = std::max(mt.max_b, wr.b_n);
+    if (s_hi < 0) { s_lo = 0; s_hi = -1; }
+    wr.s_lo = s_lo;
+    wr.s_n = s_hi - s_lo + 1;
+    mt.max_s = std::max(mt.max_s, wr.s_n);
   }
   mt.slot_of.resize(s.tri.size());
   for (size_t t = 0; t < s.tri.size(); ++t) mt.slot_of[t] = where.at({s.tri[t].a1, s.tri[t].a2, s.tri[t].a3});

@@ -84,12 +84,13 @@ void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp);
 // are taken in windows of kMaxColTiles blocks; within a window, pairs are
 // grouped by the span of column blocks their selected l fall in, so each row
 // block of kRows pairs meets the column blocks of one span as whole rectangles
-// of at most kMaxColTiles tiles.  A consumer slot holds kRbPerSlot row blocks
-// of one span (they share the column operands); a work group has kSlotsPerWg
-// slots.  A pair whose l reach several windows appears once per window.
+// of at most kMaxColTiles tiles.  A slot (one wavefront of the kernel) holds
+// kRbPerSlot row blocks of one span, which share the column operands; a work
+// group has kSlotsPerWg slots.  A pair whose l reach several windows appears
+// once per window.
 constexpr int kMaxColTiles = 2;
-constexpr int kRbPerSlot = 2;
-constexpr int kSlotsPerWg = 4;
+constexpr int kRbPerSlot = 4;
+constexpr int kSlotsPerWg = 8;
 constexpr int kRbPerWg = kRbPerSlot * kSlotsPerWg;
 constexpr int kTilesPerWg = kRbPerWg * kMaxColTiles;
 
@@ -99,8 +100,7 @@ struct SlotCols {
 };
 
 struct WgRows {
-  int32_t f_lo, f_n;   // F (fp32) rows staged: shells f_lo .. f_lo + f_n - 1 (0-based)
-  int32_t b_lo, b_n;   // column-plane rows staged
+  int32_t s_lo, s_n;   // shells staged by the work group: s_lo .. s_lo + s_n - 1 (0-based)
 };
 
 struct MfmaTiling {
@@ -110,8 +110,8 @@ struct MfmaTiling {
   // triangle t sits in partial slot slot_of[t] = tile * kRows*kCols + element
   std::vector<int32_t> slot_of;
   int32_t n_wg = 0;
-  int64_t tiles = 0;              // non-empty tiles
-  int32_t max_f = 0, max_b = 0;   // largest staged row counts (LDS sizing)
+  int64_t tiles = 0;              // non-empty (row block, column tile) products
+  int32_t max_s = 0;              // largest s_n
 };
 
 void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt);

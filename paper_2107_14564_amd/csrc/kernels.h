@@ -78,15 +78,14 @@ hipError_t launch_inv_y_f32(const float2* a1, float2* a2, const ShellLaunch& L, 
                             hipStream_t st);
 hipError_t launch_inv_y_f64(const double2* a1, double2* a2, const ShellLaunch& L, int n, const double2* tw,
                             hipStream_t st);
-hipError_t launch_c2r_f32(const float2* a2, float* F, __bf16* f_hi, __bf16* f_lo, const ShellLaunch& L, int n,
-                          const float2* tw, hipStream_t st);
+hipError_t launch_c2r_f32(const float2* a2, float* F, const ShellLaunch& L, int n, const float2* tw,
+                          hipStream_t st);
 hipError_t launch_c2r_f64(const double2* a2, double* I, const ShellLaunch& L, int n, const double2* tw,
                           hipStream_t st);
 // n: the grid of the passes (the estimator grid); the spectrum grid is L.spec_n.
-// F_hi/F_lo (optional, both or neither): bf16 planes hi = bf16(F), lo = bf16(F - hi)
 // Fields are written voxel-blocked (vox_index).
 hipError_t launch_data_shells(const float2* spec, float2* a1, float2* a2, float* F, const ShellLaunch& L, int n,
-                              const float2* tw, __bf16* f_hi, __bf16* f_lo, hipStream_t st);
+                              const float2* tw, hipStream_t st);
 hipError_t launch_unit_shells(double2* a1, double2* a2, double* I, const ShellLaunch& L, int n, const double2* tw,
                               hipStream_t st);
 // dst[v] = F[vox_index(v, shell, n_s)] for v < n_vox (float32)
@@ -115,14 +114,13 @@ struct WsArgs {
   const WgRows* wg_rows = nullptr;    // device [n_wg]
   int n_wg = 0;                       // work groups per voxel range
   int n_s = 0;
-  int max_f = 0, max_b = 0;           // staged rows (LDS sizing)
+  int max_s = 0;                      // most shells staged by one work group (LDS sizing)
   long long n_vox = 0;
   int n_krange = 0;                   // multiple of 8
   double* partial = nullptr;          // device [n_krange][n_wg * kTilesPerWg][1024]
 };
-size_t bf16x3_lds_bytes(int max_f, int max_b);
-hipError_t launch_contract_bf16x3(const float* F, const __bf16* f_hi, const __bf16* f_lo, const WsArgs& a,
-                                  hipStream_t st);
+size_t bf16x3_lds_bytes(int max_s);
+hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t st);
 // Gradient: w_k = gB[t_k] norm[t_k]; G_n = sum_{terms (t, j, l) of n} w F_j F_l
 // (terms: int4 (t, j, l, 0) with 0-based shells, grouped by n via term_off[n_s + 1])
 hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, const int4* terms, long long n_terms,

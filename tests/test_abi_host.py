@@ -105,13 +105,13 @@ def test_known_counts():
 
 def test_workspace_bytes():
     run, peak = abi.bispec_workspace_bytes(abi.make_config(512, 1500.0, 1.0, 100, rsd_beta=0.5)[0])
-    # shells live on the 320^3 estimator grid: float32 fields 100 * 320^3 * 4 B and
-    # their bf16 hi/lo planes as much again; float64 unit shells 100 * 320^3 * 8 B
-    assert run > 2 * 100 * 320 ** 3 * 4 and peak > 100 * 320 ** 3 * 8
-    assert run < 40e9 and peak < 40e9
+    # shells live on the 320^3 estimator grid: float32 fields 100 * 320^3 * 4 B;
+    # float64 unit shells of the planning phase 100 * 320^3 * 8 B
+    assert run > 100 * 320 ** 3 * 4 and peak > 100 * 320 ** 3 * 8
+    assert run < 25e9 and peak < 45e9
     run512, peak512 = abi.bispec_workspace_bytes(abi.make_config(512, 1500.0, 1.0, 100, rsd_beta=0.5, n_est=512)[0])
-    assert run512 > 2 * 100 * 512 ** 3 * 4 and peak512 > 100 * 512 ** 3 * 8
-    assert run512 < 130e9 and peak512 < 150e9
+    assert run512 > 100 * 512 ** 3 * 4 and peak512 > 100 * 512 ** 3 * 8
+    assert run512 < 80e9 and peak512 < 150e9
 
 
 def test_estimator_grid():
