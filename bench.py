@@ -12,12 +12,20 @@ Prints one JSON line (rank 0): metric/value/unit, the per-stage times, the
 roofline of the dominant kernel (the contraction) measured with HIP events
 recorded by the library on the run stream, the plain-fp32 contraction time of
 the same plan, and the float64 CPU oracle timed on a bounded sample.
+
+The roofline's `traffic` (HBM bytes per launch of the contraction) comes from
+the rocprofv3 FETCH_SIZE / WRITE_SIZE summary committed under profiles/; it is
+reported only while the contraction sources hash to the value recorded there
+(else null).  --copy-calibration adds a plain 1 GiB device copy after the timed
+region: its counter readings give the bytes-per-count scale of those runs.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,6 +44,43 @@ WORKLOADS = {
 
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense bf16 MFMA
 PEAK_HBM_GBS = 8000.0
+
+# sources that determine the contraction kernel and its launch (tiling, ranges)
+TRAFFIC_SOURCES = ["paper_2107_14564_amd/csrc/contract_kernels.hip", "paper_2107_14564_amd/csrc/geometry.cpp",
+                   "paper_2107_14564_amd/csrc/geometry.h", "paper_2107_14564_amd/csrc/kernels.h",
+                   "paper_2107_14564_amd/csrc/api.cpp"]
+
+
+def contraction_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the split-bf16 contraction from the committed
+    counter summary, or None if absent or taken from other sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_contract_bf16x3_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_sha = re.search(r"^source_sha256:\s*([0-9a-f]{64})\s*$", txt, re.M)
+    m_b = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)\s*$", txt, re.M)
+    if not (m_sha and m_b) or m_sha.group(1) != contraction_source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def copy_calibration(torch, dev, n_bytes: int = 1 << 30, reps: int = 3):
+    """A plain streaming copy (read n_bytes, write n_bytes) for counter scaling."""
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    return {"bytes_read": n_bytes, "bytes_written": n_bytes, "launches": reps, "kernel": "torch.neg (elementwise)"}
 
 
 def cpu_baseline(delta32, w: dict, budget_s: float = 30.0) -> dict:
@@ -67,6 +112,7 @@ def main():
     ap.add_argument("--precision", default="splitbf16", choices=["splitbf16", "fp32"])
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the estimator would shard "
@@ -143,7 +189,8 @@ def main():
         "stages_ms": {"forward_fft": stages[0], "shell_ffts": stages[1], "contraction": stages[2],
                       "normalise": stages[3]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_BF16_TFLOPS,
+                     "traffic": measured_traffic(args.workload) if prec == P.PREC_SPLITBF16 else None,
                      "kernel": "k_contract_bf16x3" if prec == P.PREC_SPLITBF16 else "k_contract_vec<float>",
                      "algorithmic_flop": flop},
         "fft_hbm": {"algorithmic_bytes": (8.0 * n ** 3 + 4.0 * n_vox * w["n_shells"]),
@@ -166,6 +213,8 @@ def main():
         result["fp32_contraction_ms"] = float(np.mean(f32))
         result["speedup_vs_fp32_contraction"] = float(np.mean(f32)) / contract_ms
         result["splitbf16_vs_fp32_norm_diff"] = float(np.linalg.norm(b_host - b32) / np.linalg.norm(b32))
+    if args.copy_calibration:
+        result["copy_calibration"] = copy_calibration(torch, dev)
     if not args.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(delta32, w)
