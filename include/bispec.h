@@ -54,6 +54,7 @@ extern "C" {
 #endif
 
 typedef struct bispec_plan_s* bispec_plan_t;
+typedef struct bispec_many_s* bispec_many_t;
 
 enum bispec_status {
   BISPEC_OK = 0,
@@ -86,7 +87,9 @@ enum bispec_precision {
 
 enum bispec_flags {
   BISPEC_FLAG_GRAD = 1u,         /* allocate the workspace for bispec_grad            */
-  BISPEC_FLAG_STAGE_TIMING = 2u  /* record HIP events around each stage of run       */
+  BISPEC_FLAG_STAGE_TIMING = 2u, /* record HIP events around each stage of run       */
+  BISPEC_FLAG_AUTOTUNE = 4u      /* time the split-bf16 contraction at plan time for  */
+                                 /* 64..512 voxel ranges and keep the fastest         */
 };
 
 typedef struct bispec_config {
@@ -171,7 +174,35 @@ int bispec_stage_times(bispec_plan_t plan, float* ms, int32_t n);
  * (device float32 [G^3], G from bispec_estimator_grid). */
 int bispec_copy_field(bispec_plan_t plan, int32_t shell, float* dst, void* hip_stream);
 
+/* Release a plan (not one obtained from bispec_many_plan: EINVAL). */
 int bispec_destroy(bispec_plan_t plan);
+
+/* ---- batched form: many realisations / configurations ---------------------- */
+/* The same estimator over n configurations (any mix of n_g, shells, selection,
+ * precision; no BISPEC_FLAG_GRAD), e.g. an ensemble of realisations as in the
+ * validation of Section 3.  One shared run workspace sized for the largest
+ * member; tables and N_tri per member.  hip_stream as for bispec_plan.
+ * Errors: as bispec_plan, plus EINVAL for n < 1 or a GRAD flag. */
+int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bispec_many_t* out);
+
+/* Packed layout: member i reads delta[delta_off[i] .. delta_off[i+1]) (its
+ * N_g^3 field, C order) and writes B[b_off[i] .. b_off[i+1]) (its n_tri
+ * results, ordered as bispec_triangles of that member).  delta_off and b_off
+ * are host int64 [n + 1]; n (host) receives the member count.  Any may be null. */
+int bispec_many_layout(bispec_many_t batch, int32_t* n, int64_t* delta_off, int64_t* b_off);
+
+/* Member i as a plan handle for bispec_num_triangles / bispec_triangles /
+ * bispec_stage_times queries (owned by the batch: never bispec_destroy it). */
+int bispec_many_plan(bispec_many_t batch, int32_t i, bispec_plan_t* plan);
+
+/* All members, back to back, asynchronously on hip_stream.  delta: device
+ * float32 packed fields; B: device float64 packed results (caller-owned).
+ * use_graph != 0: the launches of all members are captured once into a HIP
+ * graph (on a private stream; recaptured when delta or B change) and replayed
+ * with one hipGraphLaunch on hip_stream; 0: launched directly. */
+int bispec_run_many(bispec_many_t batch, const float* delta, double* B, int32_t use_graph, void* hip_stream);
+
+int bispec_destroy_many(bispec_many_t batch);
 
 /* Last error message of the calling thread ("" if none). */
 const char* bispec_last_error(void);

@@ -16,7 +16,7 @@ BISPEC_EHIP, BISPEC_ESTATE, BISPEC_EPREC = -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECUTOFF", -3: "ENOMEM", -4: "EHIP", -5: "ESTATE", -6: "EPREC"}
 TRI_ALL, TRI_K1SET, TRI_MUT_GRID, TRI_LIST = 0, 1, 2, 3
 PREC_SPLITBF16, PREC_FP32 = 0, 1
-FLAG_GRAD, FLAG_STAGE_TIMING = 1, 2
+FLAG_GRAD, FLAG_STAGE_TIMING, FLAG_AUTOTUNE = 1, 2, 4
 
 
 class BispecError(RuntimeError):
@@ -62,6 +62,11 @@ def lib() -> C.CDLL:
             "bispec_stage_times": [P, C.POINTER(C.c_float), I32],
             "bispec_copy_field": [P, I32, P, P],
             "bispec_destroy": [P],
+            "bispec_plan_many": [cfgp, I32, P, C.POINTER(P)],
+            "bispec_many_layout": [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64)],
+            "bispec_many_plan": [P, I32, C.POINTER(P)],
+            "bispec_run_many": [P, P, P, I32, P],
+            "bispec_destroy_many": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -181,6 +186,38 @@ def bispec_copy_field(plan: int, shell: int, dst_ptr: int, stream: int = 0):
 
 def bispec_destroy(plan: int):
     _check(lib().bispec_destroy(C.c_void_p(plan)), "bispec_destroy")
+
+
+def bispec_plan_many(cfgs, stream: int = 0) -> int:
+    """cfgs: a list of bispec_config structures (copied into one array)."""
+    arr = (bispec_config * len(cfgs))(*cfgs)
+    h = C.c_void_p()
+    _check(lib().bispec_plan_many(arr, len(cfgs), C.c_void_p(stream), C.byref(h)), "bispec_plan_many")
+    return h.value
+
+
+def bispec_many_layout(batch: int):
+    n = C.c_int32(0)
+    _check(lib().bispec_many_layout(C.c_void_p(batch), C.byref(n), None, None), "bispec_many_layout")
+    d = (C.c_int64 * (n.value + 1))()
+    b = (C.c_int64 * (n.value + 1))()
+    _check(lib().bispec_many_layout(C.c_void_p(batch), None, d, b), "bispec_many_layout")
+    return list(d), list(b)
+
+
+def bispec_many_plan(batch: int, i: int) -> int:
+    h = C.c_void_p()
+    _check(lib().bispec_many_plan(C.c_void_p(batch), int(i), C.byref(h)), "bispec_many_plan")
+    return h.value
+
+
+def bispec_run_many(batch: int, delta_ptr: int, b_ptr: int, use_graph: bool = True, stream: int = 0):
+    _check(lib().bispec_run_many(C.c_void_p(batch), C.c_void_p(delta_ptr), C.c_void_p(b_ptr), int(bool(use_graph)),
+                                 C.c_void_p(stream)), "bispec_run_many")
+
+
+def bispec_destroy_many(batch: int):
+    _check(lib().bispec_destroy_many(C.c_void_p(batch)), "bispec_destroy_many")
 
 
 def bispec_last_error() -> str:

@@ -35,11 +35,22 @@ int set_err(int code, const std::string& msg) {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = true;   // false: a view of memory owned elsewhere (a batch's shared workspace)
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
+  }
+  void view(const DevBuf& o) {
+    release();
+    p = o.p;
+    bytes = o.bytes;
+    owned = false;
   }
   template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
 };
@@ -76,18 +87,36 @@ int n_krange_for(long long groups, long long n_vox) {
   return (int)k;
 }
 
+// candidate voxel-range counts of the autotuner (multiples of 8)
+constexpr int kTuneRanges[] = {64, 128, 256, 512};
+
 struct Sizes {
   long long n_vox = 0, n_tri = 0;
   size_t spec = 0, fields32 = 0, a1_32 = 0, a2_32 = 0, fields64 = 0, a1_64 = 0, a2_64 = 0, grad = 0;
-  size_t tables = 0, partial_run = 0, partial_plan = 0;
-  size_t run_total() const { return spec + fields32 + a1_32 + a2_32 + grad + tables + partial_run; }
-  size_t plan_peak() const {
-    size_t p1 = fields64 + a1_64 + a2_64 + tables + partial_plan;
-    return std::max(p1, run_total());
-  }
+  size_t tables = 0, partial_vec = 0, partial_mfma = 0;
+  size_t workspace() const { return spec + fields32 + a1_32 + a2_32 + partial_vec + partial_mfma; }
+  size_t run_total() const { return workspace() + grad + tables; }
+  // planning: the float64 unit shells and their pass buffers exist before the run workspace
+  size_t plan_temp() const { return fields64 + a1_64 + a2_64 + n_tri * sizeof(double); }
+  size_t plan_peak() const { return std::max(plan_temp() + tables + partial_vec + partial_mfma, run_total()); }
 };
 
 }  // namespace
+
+struct bispec_plan_s;
+
+// A batch: heterogeneous plans run back to back on one shared workspace,
+// optionally replayed from a captured HIP graph.
+struct bispec_many_s {
+  std::vector<bispec_plan_s*> plans;
+  std::vector<int64_t> d_off, b_off;   // prefix sums of N_g^3 and n_tri
+  hipStream_t cap_stream = nullptr;    // private stream the graph is captured on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const float* g_delta = nullptr;      // pointers baked into the graph
+  double* g_B = nullptr;
+  ~bispec_many_s();
+};
 
 struct bispec_plan_s {
   bispec_config cfg{};
@@ -101,7 +130,9 @@ struct bispec_plan_s {
   std::vector<int64_t> ntri;
   int precision = BISPEC_PREC_SPLITBF16;
   int n_krange_vec = 8, n_krange_mfma = 8;
+  int n_krange_mfma_cap = 8;   // the partial buffer holds this many ranges
   bool ran = false;
+  bool in_batch = false;       // owned by a bispec_many_t (workspace shared)
   int device = 0;
   // device memory
   DevBuf spec, F, a1, a2, partial, partial_mfma, norm, tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols,
@@ -128,7 +159,7 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   int st = build_shells(*cfg, p.geo, err);
   if (st) return set_err(st, err);
   if (p.geo.n_s > 256) return set_err(BISPEC_EINVAL, "n_shells > 256 is not supported by the contraction kernels");
-  if (cfg->precision == BISPEC_PREC_SPLITBF16 && p.geo.n_s > 128)
+  if (cfg->precision == BISPEC_PREC_SPLITBF16 && p.geo.n_s > kMaxSplitShells)
     return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 128");
   st = select_triangles(*cfg, p.geo, p.sel, err);
   if (st) return set_err(st, err);
@@ -165,9 +196,12 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   const long long ntasks = (long long)p.tiles.task_off.size() - 1;
   p.n_krange_vec = n_krange_for(ntasks, s.n_vox);
   p.n_krange_mfma = n_krange_mfma_for(s.n_vox);
-  s.partial_run = (size_t)p.n_krange_vec * s.n_tri * sizeof(double) +
-                  (size_t)p.n_krange_mfma * p.mfma.n_wg * kTilesPerWg * 1024 * sizeof(double);
-  s.partial_plan = (size_t)p.n_krange_vec * s.n_tri * sizeof(double);
+  p.n_krange_mfma_cap = p.n_krange_mfma;
+  if (cfg->flags & BISPEC_FLAG_AUTOTUNE)
+    for (int k : kTuneRanges)
+      if (k <= std::max(8LL, (s.n_vox / (64 * 4)) / 8 * 8)) p.n_krange_mfma_cap = std::max(p.n_krange_mfma_cap, k);
+  s.partial_vec = (size_t)p.n_krange_vec * s.n_tri * sizeof(double);
+  s.partial_mfma = (size_t)p.n_krange_mfma_cap * p.mfma.n_wg * kTilesPerWg * 1024 * sizeof(double);
   s.tables = (size_t)p.geo.n_s * p.geo.n_s * p.geo.n_s * sizeof(int32_t) + p.tiles.rows.size() * sizeof(RowBlock) +
              p.tiles.tiles.size() * sizeof(Tile) + p.mfma.rows.size() * sizeof(RowBlock) +
              p.mfma.cols.size() * sizeof(SlotCols) + p.mfma.wg_rows.size() * sizeof(WgRows) +
@@ -279,6 +313,214 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
   return BISPEC_OK;
 }
 
+
+int check_memory(size_t need) {
+  size_t free_b = 0, total_b = 0;
+  hipError_t e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) return set_err(BISPEC_EHIP, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+  const size_t cap = max_bytes_env();
+  if (need > free_b || (cap && need > cap)) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "plan needs %.3f GB of device memory; %.3f GB free%s", need / 1e9, free_b / 1e9,
+                  cap ? " (or above BISPEC_MAX_BYTES)" : "");
+    return set_err(BISPEC_ENOMEM, buf);
+  }
+  return BISPEC_OK;
+}
+
+// The run workspace of a plan: its own buffers, or views of a batch's shared ones.
+struct Workspace {
+  DevBuf spec, F, a1, a2, partial, partial_mfma;
+};
+
+hipError_t take_workspace(bispec_plan_s& p, const Workspace* shared, bool fields) {
+  if (shared) {
+    if (!fields) {
+      p.partial.view(shared->partial);
+      p.partial_mfma.view(shared->partial_mfma);
+    } else {
+      p.spec.view(shared->spec);
+      p.F.view(shared->F);
+      p.a1.view(shared->a1);
+      p.a2.view(shared->a2);
+    }
+    return hipSuccess;
+  }
+  hipError_t e = hipSuccess;
+  if (!fields) {
+    e = dalloc(p.partial_mfma, p.sz.partial_mfma);
+    if (e == hipSuccess) e = dalloc(p.partial, p.sz.partial_vec);
+  } else {
+    e = dalloc(p.spec, p.sz.spec);
+    if (e == hipSuccess) e = dalloc(p.a1, p.sz.a1_32);
+    if (e == hipSuccess) e = dalloc(p.a2, p.sz.a2_32);
+    if (e == hipSuccess) e = dalloc(p.F, p.sz.fields32);
+  }
+  return e;
+}
+
+// The four stages of one pass; events only when timing (never under capture).
+int run_core(bispec_plan_s& p, const float* delta, double* B, hipStream_t s, bool timing) {
+  const int n = p.geo.n_g;
+  if (timing) HIP_TRY(hipEventRecord(p.ev[0], s));
+  HIP_TRY(launch_forward(delta, p.spec.as<float2>(), n, (float)p.geo.beta, p.tw32.as<float2>(), s));
+  if (timing) HIP_TRY(hipEventRecord(p.ev[1], s));
+  ShellLaunch L = shell_launch(p.pass32, p.shells, p.x_tiles, p.y_off, p.z_off, p.geo.n_s, n);
+  HIP_TRY(launch_data_shells(p.spec.as<float2>(), p.a1.as<float2>(), p.a2.as<float2>(), p.F.as<float>(), L,
+                             p.geo.n_est, p.tw32e.as<float2>(), s));
+  if (timing) HIP_TRY(hipEventRecord(p.ev[2], s));
+  if (p.precision == BISPEC_PREC_FP32) {
+    HIP_TRY(launch_contract_fp32(p.F.as<float>(), contract_args(p, p.n_krange_vec), s));
+    if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
+    HIP_TRY(launch_reduce(p.partial.as<double>(), p.n_krange_vec, p.sz.n_tri, p.sz.n_tri, nullptr,
+                          p.norm.as<double>(), B, s));
+  } else {
+    HIP_TRY(launch_contract_bf16x3(p.F.as<float>(), ws_args(p), s));
+    if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
+    HIP_TRY(launch_reduce(p.partial_mfma.as<double>(), p.n_krange_mfma,
+                          (long long)p.mfma.n_wg * kTilesPerWg * 1024, p.sz.n_tri, p.mfma_slot.as<int32_t>(),
+                          p.norm.as<double>(), B, s));
+  }
+  if (timing) HIP_TRY(hipEventRecord(p.ev[4], s));
+  p.ran = true;
+  return BISPEC_OK;
+}
+
+// Autotuner: the voxel-range count of the split-bf16 contraction, timed on the
+// plan's own field buffer (zero-filled; MFMA timing does not depend on values).
+int autotune_mfma(bispec_plan_s& p, hipStream_t s) {
+  if (p.precision != BISPEC_PREC_SPLITBF16) return BISPEC_OK;
+  HIP_TRY(hipMemsetAsync(p.F.p, 0, p.sz.fields32, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_k = p.n_krange_mfma;
+  int st = BISPEC_OK;
+  for (int k : kTuneRanges) {
+    if (k > p.n_krange_mfma_cap) continue;
+    p.n_krange_mfma = k;
+    const WsArgs a = ws_args(p);
+    hipError_t e = launch_contract_bf16x3(p.F.as<float>(), a, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_contract_bf16x3(p.F.as<float>(), a, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+      break;
+    }
+    if (ms < best) {
+      best = ms;
+      best_k = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p.n_krange_mfma = best_k;
+  return st;
+}
+
+// Device side of a plan: tables, N_tri (float64 unit shells), normalisation,
+// run workspace (own or shared), gradient tables, events, autotuning.
+int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
+  bispec_plan_s* p = &pr;
+  {
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) return set_err(BISPEC_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  }
+  const int ns = p->geo.n_s;
+#define PLAN_HIP(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return set_err(BISPEC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  // triangle index table (i-1, j-1, l-1) -> t
+  {
+    std::vector<int32_t> idx((size_t)ns * ns * ns, -1);
+    for (size_t t = 0; t < p->sel.tri.size(); ++t) {
+      const Tri& q = p->sel.tri[t];
+      idx[((size_t)(q.a1 - 1) * ns + (q.a2 - 1)) * ns + (q.a3 - 1)] = (int32_t)t;
+    }
+    PLAN_HIP(upload(p->tri_index, idx, s));
+  }
+  PLAN_HIP(upload(p->rows, p->tiles.rows, s));
+  PLAN_HIP(upload(p->tile_list, p->tiles.tiles, s));
+  PLAN_HIP(upload(p->task_off, p->tiles.task_off, s));
+  PLAN_HIP(upload(p->mfma_rows, p->mfma.rows, s));
+  PLAN_HIP(upload(p->mfma_cols, p->mfma.cols, s));
+  PLAN_HIP(upload(p->mfma_wgrows, p->mfma.wg_rows, s));
+  PLAN_HIP(upload(p->mfma_slot, p->mfma.slot_of, s));
+  PLAN_HIP(take_workspace(*p, shared, false));
+  // N_tri first (largest memory phase), then the run workspace
+  int st = compute_ntri(*p, s);
+  if (st) return st;
+  PLAN_HIP(upload(p->shells, p->pass32.shells, s));
+  PLAN_HIP(upload(p->x_tiles, p->pass32.x_tiles, s));
+  PLAN_HIP(upload(p->y_off, p->pass32.y_off, s));
+  PLAN_HIP(upload(p->z_off, p->pass32.z_off, s));
+  {
+    const int n = p->geo.n_g, ne = p->geo.n_est;
+    auto twiddles = [](int m) {
+      std::vector<float2> t(m);
+      for (int k = 0; k < m; ++k) {
+        const double ang = 2.0 * M_PI * (double)k / (double)m;
+        t[k] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+      }
+      return t;
+    };
+    PLAN_HIP(upload(p->tw32, twiddles(n), s));
+    PLAN_HIP(upload(p->tw32e, twiddles(ne), s));
+    // The fields are F_s = D / (dV N^{3/2}) on G^3 points (forward transform
+    // scaled by N^{-3/2}); eq. bsfin with the sum over the G grid:
+    //   B = (dV N^{3/2})^3 sum_y F_s F_s F_s / (V N_tri G^3)
+    const double V = p->geo.box_l * p->geo.box_l * p->geo.box_l;
+    const double dV = V / ((double)n * n * n);
+    const double c = dV * dV * dV * std::pow((double)n, 4.5) / (V * (double)ne * ne * ne);
+    std::vector<double> norm(p->sz.n_tri);
+    for (long long t = 0; t < p->sz.n_tri; ++t) norm[t] = p->ntri[t] > 0 ? c / (double)p->ntri[t] : NAN;
+    PLAN_HIP(upload(p->norm, norm, s));
+  }
+  PLAN_HIP(take_workspace(*p, shared, true));
+  if (p->cfg.flags & BISPEC_FLAG_GRAD) {
+    PLAN_HIP(dalloc(p->G, p->sz.fields32));
+    // terms (t, j, l) of every shell n: d(F_a1 F_a2 F_a3)/dF_n
+    std::vector<std::vector<int4>> per(ns);
+    for (size_t t = 0; t < p->sel.tri.size(); ++t) {
+      const Tri& q = p->sel.tri[t];
+      per[q.a1 - 1].push_back(make_int4((int)t, q.a2 - 1, q.a3 - 1, 0));
+      per[q.a2 - 1].push_back(make_int4((int)t, q.a1 - 1, q.a3 - 1, 0));
+      per[q.a3 - 1].push_back(make_int4((int)t, q.a1 - 1, q.a2 - 1, 0));
+    }
+    std::vector<int4> terms;
+    std::vector<int32_t> off(1, 0);
+    for (int n = 0; n < ns; ++n) {
+      terms.insert(terms.end(), per[n].begin(), per[n].end());
+      off.push_back((int32_t)terms.size());
+    }
+    p->n_terms = (long long)terms.size();
+    PLAN_HIP(upload(p->g_terms, terms, s));
+    PLAN_HIP(upload(p->g_term_off, off, s));
+    PLAN_HIP(dalloc(p->g_w, terms.size() * sizeof(float)));
+    PLAN_HIP(upload(p->ball_shells, p->pass_ball.shells, s));
+    PLAN_HIP(upload(p->ball_x, p->pass_ball.x_tiles, s));
+    PLAN_HIP(upload(p->ball_y, p->pass_ball.y_off, s));
+    PLAN_HIP(upload(p->ball_z, p->pass_ball.z_off, s));
+  }
+  if (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING)
+    for (auto& e : p->ev) PLAN_HIP(hipEventCreate(&e));
+  PLAN_HIP(prepare_contract_bf16x3());
+  if (p->cfg.flags & BISPEC_FLAG_AUTOTUNE) {
+    st = autotune_mfma(*p, s);
+    if (st) return st;
+  }
+  PLAN_HIP(hipStreamSynchronize(s));
+#undef PLAN_HIP
+  return BISPEC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -346,115 +588,13 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
   *out = nullptr;
   bispec_plan_s* p = new (std::nothrow) bispec_plan_s();
   if (!p) return set_err(BISPEC_ENOMEM, "host allocation failed");
-  auto fail = [&](int code) {
-    delete p;
-    return code;
-  };
   int st = build_host(cfg, *p);
-  if (st) return fail(st);
-  hipStream_t s = (hipStream_t)hip_stream;
-  {
-    hipError_t e = hipGetDevice(&p->device);
-    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e)));
-    size_t free_b = 0, total_b = 0;
-    e = hipMemGetInfo(&free_b, &total_b);
-    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("hipMemGetInfo: ") + hipGetErrorString(e)));
-    const size_t need = p->sz.plan_peak();
-    const size_t cap = max_bytes_env();
-    if (need > free_b || (cap && need > cap)) {
-      char buf[256];
-      std::snprintf(buf, sizeof buf, "plan needs %.3f GB of device memory; %.3f GB free%s", need / 1e9, free_b / 1e9,
-                    cap ? " (or above BISPEC_MAX_BYTES)" : "");
-      return fail(set_err(BISPEC_ENOMEM, buf));
-    }
+  if (st == BISPEC_OK) st = check_memory(p->sz.plan_peak());
+  if (st == BISPEC_OK) st = plan_build(*p, (hipStream_t)hip_stream, nullptr);
+  if (st != BISPEC_OK) {
+    delete p;
+    return st;
   }
-  const int ns = p->geo.n_s;
-  // triangle index table (i-1, j-1, l-1) -> t
-  {
-    std::vector<int32_t> idx((size_t)ns * ns * ns, -1);
-    for (size_t t = 0; t < p->sel.tri.size(); ++t) {
-      const Tri& q = p->sel.tri[t];
-      idx[((size_t)(q.a1 - 1) * ns + (q.a2 - 1)) * ns + (q.a3 - 1)] = (int32_t)t;
-    }
-    hipError_t e = upload(p->tri_index, idx, s);
-    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, hipGetErrorString(e)));
-  }
-#define PLAN_HIP(expr)                                                                                     \
-  do {                                                                                                     \
-    hipError_t e_ = (expr);                                                                                \
-    if (e_ != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_))); \
-  } while (0)
-  PLAN_HIP(upload(p->rows, p->tiles.rows, s));
-  PLAN_HIP(upload(p->tile_list, p->tiles.tiles, s));
-  PLAN_HIP(upload(p->task_off, p->tiles.task_off, s));
-  PLAN_HIP(upload(p->mfma_rows, p->mfma.rows, s));
-  PLAN_HIP(upload(p->mfma_cols, p->mfma.cols, s));
-  PLAN_HIP(upload(p->mfma_wgrows, p->mfma.wg_rows, s));
-  PLAN_HIP(upload(p->mfma_slot, p->mfma.slot_of, s));
-  PLAN_HIP(dalloc(p->partial_mfma, (size_t)p->n_krange_mfma * p->mfma.n_wg * kTilesPerWg * 1024 * sizeof(double)));
-  PLAN_HIP(dalloc(p->partial, (size_t)p->n_krange_vec * p->sz.n_tri * sizeof(double)));
-  // N_tri first (largest memory phase), then the run workspace
-  st = compute_ntri(*p, s);
-  if (st) return fail(st);
-  PLAN_HIP(upload(p->shells, p->pass32.shells, s));
-  PLAN_HIP(upload(p->x_tiles, p->pass32.x_tiles, s));
-  PLAN_HIP(upload(p->y_off, p->pass32.y_off, s));
-  PLAN_HIP(upload(p->z_off, p->pass32.z_off, s));
-  {
-    const int n = p->geo.n_g, ne = p->geo.n_est;
-    auto twiddles = [](int m) {
-      std::vector<float2> t(m);
-      for (int k = 0; k < m; ++k) {
-        const double ang = 2.0 * M_PI * (double)k / (double)m;
-        t[k] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
-      }
-      return t;
-    };
-    PLAN_HIP(upload(p->tw32, twiddles(n), s));
-    PLAN_HIP(upload(p->tw32e, twiddles(ne), s));
-    // The fields are F_s = D / (dV N^{3/2}) on G^3 points (forward transform
-    // scaled by N^{-3/2}); eq. bsfin with the sum over the G grid:
-    //   B = (dV N^{3/2})^3 sum_y F_s F_s F_s / (V N_tri G^3)
-    const double V = p->geo.box_l * p->geo.box_l * p->geo.box_l;
-    const double dV = V / ((double)n * n * n);
-    const double c = dV * dV * dV * std::pow((double)n, 4.5) / (V * (double)ne * ne * ne);
-    std::vector<double> norm(p->sz.n_tri);
-    for (long long t = 0; t < p->sz.n_tri; ++t) norm[t] = p->ntri[t] > 0 ? c / (double)p->ntri[t] : NAN;
-    PLAN_HIP(upload(p->norm, norm, s));
-  }
-  PLAN_HIP(dalloc(p->spec, p->sz.spec));
-  PLAN_HIP(dalloc(p->a1, p->sz.a1_32));
-  PLAN_HIP(dalloc(p->a2, p->sz.a2_32));
-  PLAN_HIP(dalloc(p->F, p->sz.fields32));
-  if (p->cfg.flags & BISPEC_FLAG_GRAD) {
-    PLAN_HIP(dalloc(p->G, p->sz.fields32));
-    // terms (t, j, l) of every shell n: d(F_a1 F_a2 F_a3)/dF_n
-    std::vector<std::vector<int4>> per(ns);
-    for (size_t t = 0; t < p->sel.tri.size(); ++t) {
-      const Tri& q = p->sel.tri[t];
-      per[q.a1 - 1].push_back(make_int4((int)t, q.a2 - 1, q.a3 - 1, 0));
-      per[q.a2 - 1].push_back(make_int4((int)t, q.a1 - 1, q.a3 - 1, 0));
-      per[q.a3 - 1].push_back(make_int4((int)t, q.a1 - 1, q.a2 - 1, 0));
-    }
-    std::vector<int4> terms;
-    std::vector<int32_t> off(1, 0);
-    for (int n = 0; n < ns; ++n) {
-      terms.insert(terms.end(), per[n].begin(), per[n].end());
-      off.push_back((int32_t)terms.size());
-    }
-    p->n_terms = (long long)terms.size();
-    PLAN_HIP(upload(p->g_terms, terms, s));
-    PLAN_HIP(upload(p->g_term_off, off, s));
-    PLAN_HIP(dalloc(p->g_w, terms.size() * sizeof(float)));
-    PLAN_HIP(upload(p->ball_shells, p->pass_ball.shells, s));
-    PLAN_HIP(upload(p->ball_x, p->pass_ball.x_tiles, s));
-    PLAN_HIP(upload(p->ball_y, p->pass_ball.y_off, s));
-    PLAN_HIP(upload(p->ball_z, p->pass_ball.z_off, s));
-  }
-  if (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING)
-    for (auto& e : p->ev) PLAN_HIP(hipEventCreate(&e));
-  PLAN_HIP(hipStreamSynchronize(s));
-#undef PLAN_HIP
   *out = p;
   return BISPEC_OK;
 }
@@ -484,7 +624,7 @@ int bispec_set_precision(bispec_plan_t p, int32_t precision) {
   if (!p) return set_err(BISPEC_EINVAL, "null plan");
   if (precision != BISPEC_PREC_SPLITBF16 && precision != BISPEC_PREC_FP32)
     return set_err(BISPEC_EINVAL, "unknown precision");
-  if (precision == BISPEC_PREC_SPLITBF16 && p->geo.n_s > 128)
+  if (precision == BISPEC_PREC_SPLITBF16 && p->geo.n_s > kMaxSplitShells)
     return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 128");
   p->precision = precision;
   return BISPEC_OK;
@@ -492,31 +632,7 @@ int bispec_set_precision(bispec_plan_t p, int32_t precision) {
 
 int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream) {
   if (!p || !delta || !B) return set_err(BISPEC_EINVAL, "null argument");
-  hipStream_t s = (hipStream_t)hip_stream;
-  const bool timing = (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING) != 0;
-  const int n = p->geo.n_g;
-  if (timing) HIP_TRY(hipEventRecord(p->ev[0], s));
-  HIP_TRY(launch_forward(delta, p->spec.as<float2>(), n, (float)p->geo.beta, p->tw32.as<float2>(), s));
-  if (timing) HIP_TRY(hipEventRecord(p->ev[1], s));
-  ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s, n);
-  HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), p->F.as<float>(), L,
-                             p->geo.n_est, p->tw32e.as<float2>(), s));
-  if (timing) HIP_TRY(hipEventRecord(p->ev[2], s));
-  if (p->precision == BISPEC_PREC_FP32) {
-    HIP_TRY(launch_contract_fp32(p->F.as<float>(), contract_args(*p, p->n_krange_vec), s));
-    if (timing) HIP_TRY(hipEventRecord(p->ev[3], s));
-    HIP_TRY(launch_reduce(p->partial.as<double>(), p->n_krange_vec, p->sz.n_tri, p->sz.n_tri, nullptr,
-                          p->norm.as<double>(), B, s));
-  } else {
-    HIP_TRY(launch_contract_bf16x3(p->F.as<float>(), ws_args(*p), s));
-    if (timing) HIP_TRY(hipEventRecord(p->ev[3], s));
-    HIP_TRY(launch_reduce(p->partial_mfma.as<double>(), p->n_krange_mfma,
-                          (long long)p->mfma.n_wg * kTilesPerWg * 1024, p->sz.n_tri, p->mfma_slot.as<int32_t>(),
-                          p->norm.as<double>(), B, s));
-  }
-  if (timing) HIP_TRY(hipEventRecord(p->ev[4], s));
-  p->ran = true;
-  return BISPEC_OK;
+  return run_core(*p, delta, B, (hipStream_t)hip_stream, (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING) != 0);
 }
 
 int bispec_grad(bispec_plan_t p, const double* gB, float* gdelta, void* hip_stream) {
@@ -558,8 +674,130 @@ int bispec_copy_field(bispec_plan_t p, int32_t shell, float* dst, void* hip_stre
 }
 
 int bispec_destroy(bispec_plan_t p) {
+  if (p && p->in_batch) return set_err(BISPEC_EINVAL, "this plan belongs to a batch (bispec_destroy_many)");
   delete p;
   return BISPEC_OK;
 }
 
+int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bispec_many_t* out) {
+  if (!out || !cfgs || n < 1) return set_err(BISPEC_EINVAL, "bad argument");
+  *out = nullptr;
+  bispec_many_s* m = new (std::nothrow) bispec_many_s();
+  if (!m) return set_err(BISPEC_ENOMEM, "host allocation failed");
+  auto fail = [&](int code) {
+    delete m;
+    return code;
+  };
+  hipStream_t s = (hipStream_t)hip_stream;
+  m->d_off.assign(1, 0);
+  m->b_off.assign(1, 0);
+  size_t ws_spec = 0, ws_F = 0, ws_a1 = 0, ws_a2 = 0, ws_pv = 0, ws_pm = 0, tables = 0, temp = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (cfgs[i].flags & BISPEC_FLAG_GRAD) return fail(set_err(BISPEC_EINVAL, "batched plans do not take BISPEC_FLAG_GRAD"));
+    bispec_plan_s* p = new (std::nothrow) bispec_plan_s();
+    if (!p) return fail(set_err(BISPEC_ENOMEM, "host allocation failed"));
+    p->in_batch = true;
+    m->plans.push_back(p);
+    int st = build_host(&cfgs[i], *p);
+    if (st) return fail(st);
+    const Sizes& z = p->sz;
+    ws_spec = std::max(ws_spec, z.spec);
+    ws_F = std::max(ws_F, z.fields32);
+    ws_a1 = std::max(ws_a1, z.a1_32);
+    ws_a2 = std::max(ws_a2, z.a2_32);
+    ws_pv = std::max(ws_pv, z.partial_vec);
+    ws_pm = std::max(ws_pm, z.partial_mfma);
+    tables += z.tables;
+    temp = std::max(temp, z.plan_temp());
+    m->d_off.push_back(m->d_off.back() + (int64_t)p->geo.n_g * p->geo.n_g * p->geo.n_g);
+    m->b_off.push_back(m->b_off.back() + (int64_t)z.n_tri);
+  }
+  int st = check_memory(ws_spec + ws_F + ws_a1 + ws_a2 + ws_pv + ws_pm + tables + temp);
+  if (st) return fail(st);
+  Workspace ws;
+  hipError_t e = dalloc(ws.spec, ws_spec);
+  if (e == hipSuccess) e = dalloc(ws.F, ws_F);
+  if (e == hipSuccess) e = dalloc(ws.a1, ws_a1);
+  if (e == hipSuccess) e = dalloc(ws.a2, ws_a2);
+  if (e == hipSuccess) e = dalloc(ws.partial, ws_pv);
+  if (e == hipSuccess) e = dalloc(ws.partial_mfma, ws_pm);
+  if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("workspace: ") + hipGetErrorString(e)));
+  // the plans take views; ownership of the shared buffers passes to plan 0
+  for (bispec_plan_s* p : m->plans) {
+    st = plan_build(*p, s, &ws);
+    if (st) return fail(st);
+  }
+  for (DevBuf* b : {&m->plans[0]->spec, &m->plans[0]->F, &m->plans[0]->a1, &m->plans[0]->a2,
+                    &m->plans[0]->partial, &m->plans[0]->partial_mfma})
+    b->owned = true;
+  for (DevBuf* b : {&ws.spec, &ws.F, &ws.a1, &ws.a2, &ws.partial, &ws.partial_mfma}) b->owned = false;
+  *out = m;
+  return BISPEC_OK;
+}
+
+int bispec_many_layout(bispec_many_t m, int32_t* n, int64_t* delta_off, int64_t* b_off) {
+  if (!m) return set_err(BISPEC_EINVAL, "null batch");
+  if (n) *n = (int32_t)m->plans.size();
+  for (size_t i = 0; i < m->d_off.size(); ++i) {
+    if (delta_off) delta_off[i] = m->d_off[i];
+    if (b_off) b_off[i] = m->b_off[i];
+  }
+  return BISPEC_OK;
+}
+
+int bispec_many_plan(bispec_many_t m, int32_t i, bispec_plan_t* plan) {
+  if (!m || !plan || i < 0 || i >= (int32_t)m->plans.size()) return set_err(BISPEC_EINVAL, "bad argument");
+  *plan = m->plans[i];
+  return BISPEC_OK;
+}
+
+int bispec_run_many(bispec_many_t m, const float* delta, double* B, int32_t use_graph, void* hip_stream) {
+  if (!m || !delta || !B) return set_err(BISPEC_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (!use_graph) {
+    for (size_t i = 0; i < m->plans.size(); ++i) {
+      int st = run_core(*m->plans[i], delta + m->d_off[i], B + m->b_off[i], s, false);
+      if (st) return st;
+    }
+    return BISPEC_OK;
+  }
+  if (!m->exec || m->g_delta != delta || m->g_B != B) {
+    if (m->exec) (void)hipGraphExecDestroy(m->exec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    m->exec = nullptr;
+    m->graph = nullptr;
+    if (!m->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+    int st = BISPEC_OK;
+    for (size_t i = 0; i < m->plans.size() && st == BISPEC_OK; ++i)
+      st = run_core(*m->plans[i], delta + m->d_off[i], B + m->b_off[i], m->cap_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(m->cap_stream, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return set_err(BISPEC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    m->graph = g;
+    HIP_TRY(hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
+    m->g_delta = delta;
+    m->g_B = B;
+  }
+  HIP_TRY(hipGraphLaunch(m->exec, s));
+  return BISPEC_OK;
+}
+
+int bispec_destroy_many(bispec_many_t m) {
+  delete m;
+  return BISPEC_OK;
+}
+
 }  // extern "C"
+
+bispec_many_s::~bispec_many_s() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  // plan 0 owns the shared workspace: release the other plans first
+  for (size_t i = plans.size(); i-- > 0;) delete plans[i];
+}

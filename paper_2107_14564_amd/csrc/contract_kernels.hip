@@ -152,8 +152,9 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 // GEMM view per voxel range: C[(i,j), l] = sum_x A[(i,j), x] B[x, l] with the
 // row operand A = F_i F_j (a pair product) and the column operand B = F_l.
 // Work group = kSlotsPerWg wavefronts (two per SIMD); wave w owns slot w:
-// kRbPerSlot row blocks of 32 pairs and their <= kMaxColTiles column tiles of
-// 32 shells (accumulators 4 x 2 x 16 fp32 per lane).
+// kRbPerSlot row blocks of 32 pairs and the <= kMaxColTiles column tiles of 32
+// shells they meet (accumulators kRbPerSlot x kMaxColTiles x 16 fp32 per lane;
+// the tile count of a slot is uniform over the wave, so the code path is too).
 //
 // Per chunk of 32 voxels (one voxel block) every thread loads <= 2 float4 of
 // the work group's shell rows s_lo .. s_lo + s_n - 1 (contiguous in the
@@ -169,40 +170,58 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 // LDS (two buffers): F32 [2][s + 1][36] fp32, Bh/Bl [2][s + 1][40] bf16 with
 // s = the largest s_n and the extra row all zero (padding rows and columns
 // point there).  Row strides of 36 and 20 dwords keep 8 consecutive rows on
-// distinct banks for the 16-byte fragment reads.
+// distinct banks for the 16-byte fragment reads; LDS addresses are 32-bit
+// byte offsets from the shared array.
 // Accumulation: fp32 MFMA chains of kFlushChunks chunks, added in float64 into
 // partial[range][tile][element] (tile-major, coalesced); the reduction maps
 // elements to triangles.
 // ============================================================================
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kC2 = 32;              // voxels per chunk (= one voxel block)
-constexpr int kF32S = kC2 + 4;       // fp32 row stride (floats)
-constexpr int kBS = kC2 + 8;         // bf16 row stride (elements)
+constexpr int kF32S = kC2 + 4;       // fp32 row stride (floats): 36 dwords
+constexpr int kBS = kC2 + 8;         // bf16 row stride (elements): 20 dwords
 constexpr int kFlushChunks = 256;    // 8192 voxels per float32 accumulation chain
 constexpr int kWsThreads = kSlotsPerWg * 64;
 constexpr int kPf = 2;               // float4 loads per thread per chunk
 static_assert(kC2 == kVoxBlock, "chunks are voxel blocks");
 
-struct WsLds {
-  float* f32;      // [2][ns1][kF32S]
-  __bf16* bh;      // [2][ns1][kBS]
-  __bf16* bl;
-  int ns1;         // rows per buffer including the zero row
-  __device__ float* F(int buf, int r) const { return f32 + (buf * ns1 + r) * kF32S; }
-  __device__ __bf16* Bh(int buf, int r) const { return bh + (buf * ns1 + r) * kBS; }
-  __device__ __bf16* Bl(int buf, int r) const { return bl + (buf * ns1 + r) * kBS; }
+// LDS byte layout for ns1 rows per buffer (row ns1 - 1 is all zero):
+//   F32 [2][ns1][kF32S] fp32 | Bh [2][ns1][kBS] bf16 | Bl [2][ns1][kBS] bf16
+struct WsLayout {
+  unsigned f_buf, b_buf;   // bytes per buffer of F32 and of one bf16 plane
+  unsigned bh0, bl0;       // byte offsets of the Bh and Bl regions
 };
 
-__device__ __forceinline__ void split8(const float (&p)[8], bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 h = (__bf16)p[e];
-    hi[e] = h;
-    lo[e] = (__bf16)(p[e] - (float)h);
-  }
+__device__ __forceinline__ WsLayout ws_layout(int ns1) {
+  WsLayout y;
+  y.f_buf = (unsigned)ns1 * kF32S * 4;
+  y.b_buf = (unsigned)ns1 * kBS * 2;
+  y.bh0 = 2 * y.f_buf;
+  y.bl0 = y.bh0 + 2 * y.b_buf;
+  return y;
+}
+
+// hi = bf16(v) (round to nearest even) for two values, and the exact fp32 of each hi
+__device__ __forceinline__ unsigned bf16_pair(float v0, float v1, float& h0, float& h1) {
+  bf16x2 h;
+  h[0] = (__bf16)v0;
+  h[1] = (__bf16)v1;
+  const unsigned u = __builtin_bit_cast(unsigned, h);
+  h0 = __builtin_bit_cast(float, u << 16);
+  h1 = __builtin_bit_cast(float, u & 0xffff0000u);
+  return u;
+}
+
+__device__ __forceinline__ unsigned bf16_pack(float v0, float v1) {
+  bf16x2 h;
+  h[0] = (__bf16)v0;
+  h[1] = (__bf16)v1;
+  return __builtin_bit_cast(unsigned, h);
 }
 
 // chunk c of the range: rows s_lo .. s_lo + s_n - 1, 8 float4 per row
@@ -217,51 +236,68 @@ __device__ __forceinline__ void ws_load(const float* __restrict__ F, int n_s, lo
   }
 }
 
-__device__ __forceinline__ void ws_store(const WsLds& L, const WgRows& wr, int buf, const float4 (&pf)[kPf],
-                                         int tid) {
+// fp32 rows, and the bf16 split hi = bf16(v), lo = bf16(v - hi) of every value
+__device__ __forceinline__ void ws_store(unsigned char* lds, const WsLayout& y, int s_n, int buf,
+                                         const float4 (&pf)[kPf], int tid) {
 #pragma unroll
   for (int u = 0; u < kPf; ++u) {
     const int idx = tid + u * kWsThreads;
-    if (idx < wr.s_n * (kC2 / 4)) {
-      const int r = idx >> 3, x = 4 * (idx & 7);
-      *reinterpret_cast<float4*>(L.F(buf, r) + x) = pf[u];
-      const float v[4] = {pf[u].x, pf[u].y, pf[u].z, pf[u].w};
-      bf16x4 h, l;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        h[e] = (__bf16)v[e];
-        l[e] = (__bf16)(v[e] - (float)h[e]);
-      }
-      *reinterpret_cast<bf16x4*>(L.Bh(buf, r) + x) = h;
-      *reinterpret_cast<bf16x4*>(L.Bl(buf, r) + x) = l;
+    if (idx < s_n * (kC2 / 4)) {
+      const unsigned r = idx >> 3, x = 4 * (idx & 7);
+      *reinterpret_cast<float4*>(lds + buf * y.f_buf + (r * kF32S + x) * 4) = pf[u];
+      float h0, h1, h2, h3;
+      u32x2 hi, lo;
+      hi[0] = bf16_pair(pf[u].x, pf[u].y, h0, h1);
+      hi[1] = bf16_pair(pf[u].z, pf[u].w, h2, h3);
+      lo[0] = bf16_pack(pf[u].x - h0, pf[u].y - h1);
+      lo[1] = bf16_pack(pf[u].z - h2, pf[u].w - h3);
+      const unsigned o = buf * y.b_buf + (r * kBS + x) * 2;
+      *reinterpret_cast<u32x2*>(lds + y.bh0 + o) = hi;
+      *reinterpret_cast<u32x2*>(lds + y.bl0 + o) = lo;
     }
   }
 }
 
-// 32 voxels of buffer buf for a slot with NT column tiles
+// Row operand of one row block for 8 voxels: products p = F_i F_j, split
+// into hi = bf16(p) and lo = bf16(F_i F_j - hi) (the fma keeps lo exact).
+__device__ __forceinline__ void ws_row_operand(const unsigned char* lds, unsigned oi, unsigned oj, bf16x8& ahi,
+                                               bf16x8& alo) {
+  const float4 i0 = *reinterpret_cast<const float4*>(lds + oi), i1 = *reinterpret_cast<const float4*>(lds + oi + 16);
+  const float4 j0 = *reinterpret_cast<const float4*>(lds + oj), j1 = *reinterpret_cast<const float4*>(lds + oj + 16);
+  const float a[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
+  const float b[8] = {j0.x, j0.y, j0.z, j0.w, j1.x, j1.y, j1.z, j1.w};
+  u32x4 h, l;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float h0, h1;
+    h[e] = bf16_pair(a[2 * e] * b[2 * e], a[2 * e + 1] * b[2 * e + 1], h0, h1);
+    l[e] = bf16_pack(__builtin_fmaf(a[2 * e], b[2 * e], -h0), __builtin_fmaf(a[2 * e + 1], b[2 * e + 1], -h1));
+  }
+  ahi = __builtin_bit_cast(bf16x8, h);
+  alo = __builtin_bit_cast(bf16x8, l);
+}
+
+// 32 voxels of buffer buf for a slot with NT column tiles.  fo[q], go[q]:
+// byte offsets of this lane's F_i and F_j rows (+ its voxel octet) in buffer 0;
+// co[t]: of its column row in plane Bh buffer 0.
 template <int NT>
-__device__ __forceinline__ void ws_compute(const WsLds& L, int buf, const int (&ri)[kRbPerSlot],
-                                           const int (&rj)[kRbPerSlot], const int (&cs)[kMaxColTiles], int kg,
+__device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLayout& y, int buf,
+                                           const unsigned (&fo)[kRbPerSlot], const unsigned (&go)[kRbPerSlot],
+                                           const unsigned (&co)[kMaxColTiles],
                                            f32x16 (&acc)[kRbPerSlot][kMaxColTiles]) {
+  const unsigned fb = buf * y.f_buf, bb = y.bh0 + buf * y.b_buf, lb = y.bl0 + buf * y.b_buf;
 #pragma unroll
   for (int ks = 0; ks < kC2 / 16; ++ks) {
-    const int off = ks * 16 + kg * 8;
     bf16x8 bhi[NT], blo[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      bhi[t] = *reinterpret_cast<const bf16x8*>(L.Bh(buf, cs[t]) + off);
-      blo[t] = *reinterpret_cast<const bf16x8*>(L.Bl(buf, cs[t]) + off);
+      bhi[t] = *reinterpret_cast<const bf16x8*>(lds + bb + co[t] + ks * 32);
+      blo[t] = *reinterpret_cast<const bf16x8*>(lds + lb + co[t] + ks * 32);
     }
 #pragma unroll
     for (int q = 0; q < kRbPerSlot; ++q) {
-      const float* fi = L.F(buf, ri[q]) + off;
-      const float* fj = L.F(buf, rj[q]) + off;
-      const float4 i0 = *reinterpret_cast<const float4*>(fi), i1 = *reinterpret_cast<const float4*>(fi + 4);
-      const float4 j0 = *reinterpret_cast<const float4*>(fj), j1 = *reinterpret_cast<const float4*>(fj + 4);
-      const float p[8] = {i0.x * j0.x, i0.y * j0.y, i0.z * j0.z, i0.w * j0.w,
-                          i1.x * j1.x, i1.y * j1.y, i1.z * j1.z, i1.w * j1.w};
       bf16x8 ahi, alo;
-      split8(p, ahi, alo);
+      ws_row_operand(lds, fb + fo[q] + ks * 64, fb + go[q] + ks * 64, ahi, alo);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[t], acc[q][t], 0, 0, 0);
@@ -273,8 +309,8 @@ __device__ __forceinline__ void ws_compute(const WsLds& L, int buf, const int (&
 }
 
 // float64 flush of the slot's accumulators (first: write, else add), then reset.
-// The base pointer passes through an empty asm so the 8 x 16 element addresses
-// are formed here, not hoisted out of the main loop into live registers.
+// The base pointer passes through an empty asm so the element addresses are
+// formed here, not hoisted out of the main loop into live registers.
 template <int NT>
 __device__ __forceinline__ void ws_flush(double* out, bool first, f32x16 (&acc)[kRbPerSlot][kMaxColTiles]) {
   asm volatile("" : "+v"(out));
@@ -291,37 +327,48 @@ __device__ __forceinline__ void ws_flush(double* out, bool first, f32x16 (&acc)[
     }
 }
 
+template <int NT>
+__device__ __forceinline__ void ws_step(const unsigned char* lds, const WsLayout& y, int buf, bool flush,
+                                        bool first, double* out, const unsigned (&fo)[kRbPerSlot],
+                                        const unsigned (&go)[kRbPerSlot], const unsigned (&co)[kMaxColTiles],
+                                        f32x16 (&acc)[kRbPerSlot][kMaxColTiles]) {
+  ws_compute<NT>(lds, y, buf, fo, go, co, acc);
+  if (flush) ws_flush<NT>(out, first, acc);
+}
+
 __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __restrict__ F, WsArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  WsLds L;
-  L.ns1 = a.max_s + 1;
-  L.f32 = reinterpret_cast<float*>(smem_raw);
-  L.bh = reinterpret_cast<__bf16*>(L.f32 + 2 * L.ns1 * kF32S);
-  L.bl = L.bh + 2 * L.ns1 * kBS;
+  const int ns1 = a.max_s + 1;
+  const WsLayout y = ws_layout(ns1);
   int wg, kr;
   xcd_map(a.n_wg, wg, kr);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, kg = lane >> 5;
   const WgRows wr = a.wg_rows[wg];
-  // zero row (index s_n of each buffer), never overwritten afterwards
-  for (int e = tid; e < 2 * kF32S; e += kWsThreads) L.F(e / kF32S, wr.s_n)[e % kF32S] = 0.f;
+  const int zr = wr.s_n;  // the zero row
+  // zero row of each buffer, never overwritten afterwards
+  for (int e = tid; e < 2 * kF32S; e += kWsThreads)
+    *reinterpret_cast<float*>(smem_raw + (e / kF32S) * y.f_buf + (zr * kF32S + e % kF32S) * 4) = 0.f;
   for (int e = tid; e < 2 * kBS; e += kWsThreads) {
-    L.Bh(e / kBS, wr.s_n)[e % kBS] = (__bf16)0.f;
-    L.Bl(e / kBS, wr.s_n)[e % kBS] = (__bf16)0.f;
+    const unsigned o = (e / kBS) * y.b_buf + (zr * kBS + e % kBS) * 2;
+    *reinterpret_cast<__bf16*>(smem_raw + y.bh0 + o) = (__bf16)0.f;
+    *reinterpret_cast<__bf16*>(smem_raw + y.bl0 + o) = (__bf16)0.f;
   }
-  // this lane's rows (pair shells) and columns, as LDS row indices
+  // this lane's rows (pair shells) and columns as byte offsets in buffer 0
   const SlotCols sc = a.cols[wg * kSlotsPerWg + w];
-  int ri[kRbPerSlot], rj[kRbPerSlot], cs[kMaxColTiles];
+  unsigned fo[kRbPerSlot], go[kRbPerSlot], co[kMaxColTiles];
 #pragma unroll
   for (int q = 0; q < kRbPerSlot; ++q) {
     const RowBlock& rb = a.rows[wg * kRbPerWg + w * kRbPerSlot + q];
     const int i = rb.i[lane & 31], j = rb.j[lane & 31];
-    ri[q] = j > 0 ? i - 1 - wr.s_lo : wr.s_n;
-    rj[q] = j > 0 ? j - 1 - wr.s_lo : wr.s_n;
+    const int ri = j > 0 ? i - 1 - wr.s_lo : zr, rj = j > 0 ? j - 1 - wr.s_lo : zr;
+    fo[q] = (unsigned)(ri * kF32S + kg * 8) * 4;
+    go[q] = (unsigned)(rj * kF32S + kg * 8) * 4;
   }
 #pragma unroll
   for (int t = 0; t < kMaxColTiles; ++t) {
     const int l = t < sc.n ? sc.col0[t] + (lane & 31) : 0;  // 1-based column shell
-    cs[t] = (l >= 1 && l <= a.n_s) ? l - 1 - wr.s_lo : wr.s_n;
+    const int rc = (l >= 1 && l <= a.n_s) ? l - 1 - wr.s_lo : zr;
+    co[t] = (unsigned)(rc * kBS + kg * 8) * 2;
   }
   f32x16 acc[kRbPerSlot][kMaxColTiles];
 #pragma unroll
@@ -340,7 +387,7 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
   float4 pf[kPf];
   if (n_chunks > 0) {
     ws_load(F, a.n_s, blk0, wr, 0, pf, tid);
-    ws_store(L, wr, 0, pf, tid);
+    ws_store(smem_raw, y, wr.s_n, 0, pf, tid);
   }
   __syncthreads();
   bool first = true;
@@ -348,19 +395,19 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
   for (int c = 0; c < n_chunks; ++c) {
     const bool more = c + 1 < n_chunks;
     if (more) ws_load(F, a.n_s, blk0, wr, c + 1, pf, tid);
-    if (sc.n == 2)
-      ws_compute<2>(L, c & 1, ri, rj, cs, kg, acc);
-    else if (sc.n == 1)
-      ws_compute<1>(L, c & 1, ri, rj, cs, kg, acc);
-    if (more) ws_store(L, wr, (c + 1) & 1, pf, tid);
-    if (++chain == kFlushChunks || !more) {
+    const bool flush = ++chain == kFlushChunks || !more;
+    switch (sc.n) {  // uniform per wave
+      case 4: ws_step<4>(smem_raw, y, c & 1, flush, first, out, fo, go, co, acc); break;
+      case 3: ws_step<3>(smem_raw, y, c & 1, flush, first, out, fo, go, co, acc); break;
+      case 2: ws_step<2>(smem_raw, y, c & 1, flush, first, out, fo, go, co, acc); break;
+      case 1: ws_step<1>(smem_raw, y, c & 1, flush, first, out, fo, go, co, acc); break;
+      default: break;
+    }
+    if (flush) {
       chain = 0;
-      if (sc.n == 2)
-        ws_flush<2>(out, first, acc);
-      else if (sc.n == 1)
-        ws_flush<1>(out, first, acc);
       first = false;
     }
+    if (more) ws_store(smem_raw, y, wr.s_n, (c + 1) & 1, pf, tid);
     __syncthreads();
   }
   if (n_chunks == 0)  // empty range: its partials are zero
@@ -443,13 +490,19 @@ size_t bf16x3_lds_bytes(int max_s) {
 hipError_t launch_contract_fp32(const float* F, const ContractArgs& a, hipStream_t st) { return launch_vec<float>(F, a, st); }
 hipError_t launch_contract_fp64(const double* F, const ContractArgs& a, hipStream_t st) { return launch_vec<double>(F, a, st); }
 
+// Raises the kernel's dynamic LDS limit to what 128 staged shells need (the
+// split-bf16 maximum); done at plan time so launches stay capture-safe.
+hipError_t prepare_contract_bf16x3() {
+  return hipFuncSetAttribute((const void*)k_contract_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bf16x3_lds_bytes(kMaxSplitShells));
+}
+
 hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t st) {
   // every staged row fits the per-thread loads; ranges are whole voxel blocks
-  if (a.max_s * (kC2 / 4) > kWsThreads * kPf || a.max_s > a.n_s || a.n_vox % 64 != 0) return hipErrorInvalidValue;
+  if (a.max_s * (kC2 / 4) > kWsThreads * kPf || a.max_s > a.n_s || a.max_s > kMaxSplitShells ||
+      a.n_vox % 64 != 0)
+    return hipErrorInvalidValue;
   const size_t lds = bf16x3_lds_bytes(a.max_s);
-  hipError_t e = hipFuncSetAttribute((const void*)k_contract_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)a.n_wg * (unsigned)a.n_krange;
   hipLaunchKernelGGL(k_contract_bf16x3, dim3(blocks), dim3(kWsThreads), lds, st, F, a);
   return hipGetLastError();

@@ -62,7 +62,7 @@ int validate(const bispec_config& c, std::string& err) {
       break;
     default: return fail(err, BISPEC_EINVAL, "unknown tri_mode");
   }
-  if (c.flags & ~(uint32_t)(BISPEC_FLAG_GRAD | BISPEC_FLAG_STAGE_TIMING))
+  if (c.flags & ~(uint32_t)(BISPEC_FLAG_GRAD | BISPEC_FLAG_STAGE_TIMING | BISPEC_FLAG_AUTOTUNE))
     return fail(err, BISPEC_EINVAL, "unknown flag bits");
   return BISPEC_OK;
 }
@@ -326,6 +326,19 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
     }
   }
   while (slots.size() % kSlotsPerWg) slots.push_back(Slot{});
+  // Balance: slots by column-tile count, largest first; a work group takes 8
+  // consecutive slots and pairs its largest with its smallest on each SIMD
+  // (wave q runs on SIMD q % 4, so waves q and q + 4 share one).
+  std::stable_sort(slots.begin(), slots.end(), [](const Slot& a, const Slot& b) { return a.sc.n > b.sc.n; });
+  static_assert(kSlotsPerWg == 8, "the SIMD pairing below assumes 8 slots per work group");
+  for (size_t w0 = 0; w0 < slots.size(); w0 += kSlotsPerWg) {
+    Slot tmp[kSlotsPerWg];
+    for (int q = 0; q < kSlotsPerWg; ++q) tmp[q] = slots[w0 + q];
+    for (int q = 0; q < 4; ++q) {
+      slots[w0 + q] = tmp[q];
+      slots[w0 + 4 + q] = tmp[kSlotsPerWg - 1 - q];
+    }
+  }
   mt.n_wg = (int32_t)(slots.size() / kSlotsPerWg);
   mt.rows.assign((size_t)mt.n_wg * kRbPerWg, RowBlock{});
   mt.cols.assign((size_t)mt.n_wg * kSlotsPerWg, SlotCols{});

@@ -88,8 +88,8 @@ void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp);
 // kRbPerSlot row blocks of one span, which share the column operands; a work
 // group has kSlotsPerWg slots.  A pair whose l reach several windows appears
 // once per window.
-constexpr int kMaxColTiles = 2;
-constexpr int kRbPerSlot = 4;
+constexpr int kMaxColTiles = 4;
+constexpr int kRbPerSlot = 2;
 constexpr int kSlotsPerWg = 8;
 constexpr int kRbPerWg = kRbPerSlot * kSlotsPerWg;
 constexpr int kTilesPerWg = kRbPerWg * kMaxColTiles;

@@ -119,7 +119,9 @@ struct WsArgs {
   int n_krange = 0;                   // multiple of 8
   double* partial = nullptr;          // device [n_krange][n_wg * kTilesPerWg][1024]
 };
+constexpr int kMaxSplitShells = 128;   // most shells of a split-bf16 plan
 size_t bf16x3_lds_bytes(int max_s);
+hipError_t prepare_contract_bf16x3();   // once per plan, before any launch (and before graph capture)
 hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t st);
 // Gradient: w_k = gB[t_k] norm[t_k]; G_n = sum_{terms (t, j, l) of n} w F_j F_l
 // (terms: int4 (t, j, l, 0) with 0-based shells, grouped by n via term_off[n_s + 1])

@@ -90,6 +90,74 @@ class _BispecFn(torch.autograd.Function):
         return ctx.plan.grad(g_b), None
 
 
+class BatchPlan:
+    """Many configurations run back to back on one shared workspace (the batched
+    form).  configs: a list of dicts with the Plan keyword arguments (n_g, box_l,
+    dk, n_shells, rsd_beta, tri_mode, k1_shells, n_mu, n_t, triangles,
+    precision, flags, n_est)."""
+
+    def __init__(self, configs):
+        if not torch.cuda.is_available():
+            raise RuntimeError("BatchPlan needs a HIP device")
+        self._keep = []
+        cfgs = []
+        for c in configs:
+            c = dict(c)
+            cfg, keep = _abi.make_config(c.pop("n_g"), c.pop("box_l"), c.pop("dk"), c.pop("n_shells"), **c)
+            cfgs.append(cfg)
+            self._keep.append(keep)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.handle = _abi.bispec_plan_many(cfgs, _stream())
+        self.delta_off, self.b_off = _abi.bispec_many_layout(self.handle)
+        self.n = len(cfgs)
+        self.n_g = [int(round((self.delta_off[i + 1] - self.delta_off[i]) ** (1 / 3))) for i in range(self.n)]
+        self.triangles, self.ntri = [], []
+        for i in range(self.n):
+            abc, _, ntri = _abi.bispec_triangles(_abi.bispec_many_plan(self.handle, i))
+            self.triangles.append(torch.tensor(abc, dtype=torch.int32))
+            self.ntri.append(torch.tensor(ntri, dtype=torch.int64))
+        self.n_tri = self.b_off[-1]
+
+    def pack(self, deltas) -> torch.Tensor:
+        """One contiguous float32 device buffer of the members' fields."""
+        if len(deltas) != self.n:
+            raise ValueError("one field per member")
+        for d, n in zip(deltas, self.n_g):
+            if tuple(d.shape) != (n,) * 3 or d.dtype != torch.float32:
+                raise ValueError("member fields must be float32 (n_g, n_g, n_g)")
+        return torch.cat([d.reshape(-1).to(self.device) for d in deltas])
+
+    def run(self, packed: torch.Tensor, use_graph: bool = True) -> torch.Tensor:
+        """Packed B (float64 [total n_tri]); split with self.split()."""
+        if packed.dtype != torch.float32 or not packed.is_cuda or not packed.is_contiguous() \
+                or packed.numel() != self.delta_off[-1]:
+            raise ValueError("packed fields must be a contiguous float32 CUDA tensor of the batch's total size")
+        out = torch.empty(self.n_tri, dtype=torch.float64, device=packed.device)
+        _abi.bispec_run_many(self.handle, packed.data_ptr(), out.data_ptr(), use_graph, _stream())
+        return out
+
+    def run_into(self, packed: torch.Tensor, out: torch.Tensor, use_graph: bool = True) -> torch.Tensor:
+        """As run, into a caller-kept output (a stable pointer keeps the captured graph)."""
+        if out.dtype != torch.float64 or out.numel() != self.n_tri or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of the batch's total n_tri")
+        _abi.bispec_run_many(self.handle, packed.data_ptr(), out.data_ptr(), use_graph, _stream())
+        return out
+
+    def split(self, b: torch.Tensor):
+        return [b[self.b_off[i]:self.b_off[i + 1]] for i in range(self.n)]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _abi.bispec_destroy_many(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def bispectrum(delta: torch.Tensor, plan: Plan) -> torch.Tensor:
     """B (float64 [n_tri]) of delta; differentiable when the plan has FLAG_GRAD."""
     return _BispecFn.apply(delta, plan)

@@ -108,3 +108,26 @@ def workload_field(name: str, n_g: int | None = None, seed: int | None = None) -
         w["seed"] = seed
     dg = gaussian_field(w["n_g"], w["box_l"], w["power"], w["seed"])
     return quadratic_ng_field(dg, w["f_ng"])
+
+
+def batch_members(n: int = 64, seed: int = 4999, grids=(96, 128, 160), n_s_range=(16, 48),
+                  box_l: float = 1000.0) -> list:
+    """An ensemble of heterogeneous realisations (the batched form): per member
+    N_g ~ U(grids), n_shells ~ U{n_s_range} clipped to the largest count below
+    the aliasing cutoff at that N_g (shell width one k_f), f_NG ~ U(0.5, 2),
+    P = k^-1, seed 4000 + i; the draws come from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        n_g = int(rng.choice(grids))
+        n_s = int(rng.integers(n_s_range[0], n_s_range[1] + 1))
+        n_s = min(n_s, int(np.floor(n_g / 3.0 - 0.5)))
+        f_ng = float(rng.uniform(0.5, 2.0))
+        out.append(dict(n_g=n_g, n_shells=n_s, f_ng=f_ng, seed=4000 + i, box_l=box_l))
+    return out
+
+
+def batch_field(member: dict) -> np.ndarray:
+    """The non-Gaussian field of one batch member (float64)."""
+    dg = gaussian_field(member["n_g"], member["box_l"], PowerLaw(-1.0), member["seed"])
+    return quadratic_ng_field(dg, member["f_ng"])
