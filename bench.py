@@ -42,6 +42,9 @@ WORKLOADS = {
                                sel=dict(tri_mode=2, k1_shells=list(range(5, 11)), n_mu=10, n_t=10)),
 }
 
+# batched form: 64 heterogeneous realisations (N_g in {96, 128, 160}, 16-48 shells)
+BATCH_WORKLOADS = {"batch64_ng96_160": dict(n=64, seed=4999)}
+
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense bf16 MFMA
 PEAK_HBM_GBS = 8000.0
 
@@ -108,7 +111,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="ng512_100shells_rsd", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ng512_100shells_rsd", choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
+    ap.add_argument("--autotune", action="store_true", help="plan with FLAG_AUTOTUNE")
     ap.add_argument("--precision", default="splitbf16", choices=["splitbf16", "fp32"])
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -125,6 +129,8 @@ def main():
     import paper_2107_14564_amd as P
     from synth import workload_field
 
+    if args.workload in BATCH_WORKLOADS:
+        return bench_batch(args, np, torch, P)
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -136,7 +142,7 @@ def main():
     prec = P.PREC_SPLITBF16 if args.precision == "splitbf16" else P.PREC_FP32
     t0 = time.perf_counter()
     plan = P.Plan(w["n_g"], w["box_l"], w["dk"], w["n_shells"], rsd_beta=w["rsd_beta"], precision=prec,
-                  flags=P.FLAG_STAGE_TIMING, **w["sel"])
+                  flags=P.FLAG_STAGE_TIMING | (P.FLAG_AUTOTUNE if args.autotune else 0), **w["sel"])
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     print("plan ready (%.1f s), %d triangles" % (plan_s, plan.n_tri), file=sys.stderr, flush=True)
@@ -220,6 +226,80 @@ def main():
         result["cpu_baseline"] = cpu_baseline(delta32, w)
     plan.close()
     print(json.dumps(result), flush=True)
+
+
+def bench_batch(args, np, torch, P):
+    """The batched form: every member of the ensemble in one replay of a captured
+    HIP graph; one step = one pass over all members."""
+    from synth import batch_field, batch_members
+    bw = BATCH_WORKLOADS[args.workload]
+    members = batch_members(bw["n"], bw["seed"])
+    prec = P.PREC_SPLITBF16 if args.precision == "splitbf16" else P.PREC_FP32
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    fields = [torch.from_numpy(np.ascontiguousarray(batch_field(m), dtype=np.float32)) for m in members]
+    print("fields ready (%.1f s)" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    configs = [dict(n_g=m["n_g"], box_l=m["box_l"], dk=1.0, n_shells=m["n_shells"], precision=prec,
+                    flags=P.FLAG_AUTOTUNE if args.autotune else 0) for m in members]
+    t0 = time.perf_counter()
+    bp = P.BatchPlan(configs)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    print("batch plan ready (%.1f s), %d triangles" % (plan_s, bp.n_tri), file=sys.stderr, flush=True)
+    packed = bp.pack(fields)
+    out = torch.empty(bp.n_tri, dtype=torch.float64, device=dev)
+    for _ in range(max(1, args.warmup)):
+        bp.run_into(packed, out, use_graph=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    step_ms = []
+    for k in range(args.steps):
+        start.record(stream)
+        bp.run_into(packed, out, use_graph=True)
+        stop.record(stream)
+        stop.synchronize()
+        step_ms.append(start.elapsed_time(stop))
+        print("step %d: %.3f ms" % (k, step_ms[-1]), file=sys.stderr, flush=True)
+    ms = float(np.mean(step_ms))
+    assert np.all(np.isfinite(out.cpu().numpy())), "non-finite B"
+    # direct launches of the same batch, for the graph's gain
+    bp.run(packed, use_graph=False)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(max(1, min(3, args.steps))):
+        bp.run(packed, use_graph=False)
+    stop.record(stream)
+    stop.synchronize()
+    eager_ms = start.elapsed_time(stop) / max(1, min(3, args.steps))
+    flop = 0.0
+    for i in range(bp.n):
+        tri = bp.triangles[i].numpy()
+        g = P.bispec_estimator_grid(bp_cfg(P, configs[i]))
+        n_pairs = len({(int(a), int(b)) for a, b, _ in tri})
+        flop += float(g) ** 3 * (2.0 * len(tri) + n_pairs)
+    achieved = flop / (ms * 1e-3) / 1e12
+    result = {
+        "metric": "triangles/s", "value": bp.n_tri / (ms * 1e-3), "unit": "triangles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x3-fp32acc" if prec == P.PREC_SPLITBF16 else "fp32", "data": "synthetic",
+        "config": {"workload": args.workload, "members": bp.n, "grids": sorted({m["n_g"] for m in members}),
+                   "n_shells_range": [min(m["n_shells"] for m in members), max(m["n_shells"] for m in members)],
+                   "n_tri": bp.n_tri, "precision": args.precision, "autotune": bool(args.autotune)},
+        "eager_ms_per_step": eager_ms,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None, "kernel": "whole step (all kernels)",
+                     "algorithmic_flop": flop},
+        "plan_s": plan_s,
+    }
+    bp.close()
+    print(json.dumps(result), flush=True)
+
+
+def bp_cfg(P, c):
+    c = dict(c)
+    return P.make_config(c.pop("n_g"), c.pop("box_l"), c.pop("dk"), c.pop("n_shells"), **c)[0]
 
 
 if __name__ == "__main__":

@@ -151,16 +151,18 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 //
 // GEMM view per voxel range: C[(i,j), l] = sum_x A[(i,j), x] B[x, l] with the
 // row operand A = F_i F_j (a pair product) and the column operand B = F_l.
-// Work group = kSlotsPerWg wavefronts (two per SIMD); wave w owns slot w:
-// kRbPerSlot row blocks of 32 pairs and the <= kMaxColTiles column tiles of 32
-// shells they meet (accumulators kRbPerSlot x kMaxColTiles x 16 fp32 per lane;
-// the tile count of a slot is uniform over the wave, so the code path is too).
+// Work group = kSlotsPerWg = 12 wavefronts (three per SIMD, which the
+// register budget of <= 170 VGPRs allows); wave w owns slot w: NT <=
+// kMaxColTiles column tiles of 32 shells and n_rb <= slot_row_blocks(NT) row
+// blocks of 32 pairs that meet them (at most kSlotTiles = 4 accumulator tiles
+// of 16 fp32 per lane; NT is uniform over the wave, so the code path is too).
 //
-// Per chunk of 32 voxels (one voxel block) every thread loads <= 2 float4 of
-// the work group's shell rows s_lo .. s_lo + s_n - 1 (contiguous in the
+// Voxel range kr is the set of voxel blocks kr + m n_krange (interleaved over
+// the box).  Per chunk of 32 voxels (one block) every thread loads <= 2 float4
+// of the work group's shell rows s_lo .. s_lo + s_n - 1 (contiguous in the
 // voxel-blocked layout) one chunk ahead, and stores them into the other LDS
-// buffer as fp32 (row operands) and as bf16 hi/lo (column operands, split
-// once per value).  Per 16 voxels a lane then
+// buffer as fp32 (row operands) and as bf16 hi/lo (column operands, split once
+// per value).  Per 16 voxels a lane then
 //   - reads its column fragments (hi, lo: 8 voxels of shell l each),
 //   - for each row block reads 8 voxels of F_i and F_j, forms the 8 pair
 //     products in registers, splits them (the MFMA row-operand layout: lane
@@ -224,11 +226,10 @@ __device__ __forceinline__ unsigned bf16_pack(float v0, float v1) {
   return __builtin_bit_cast(unsigned, h);
 }
 
-// chunk c of the range: rows s_lo .. s_lo + s_n - 1, 8 float4 per row
-__device__ __forceinline__ void ws_load(const float* __restrict__ F, int n_s, long long blk0, const WgRows& wr,
-                                        int c, float4 (&pf)[kPf], int tid) {
-  const float4* base =
-      reinterpret_cast<const float4*>(F + (blk0 + c) * (long long)n_s * kC2 + (long long)wr.s_lo * kC2);
+// voxel block blk: rows s_lo .. s_lo + s_n - 1, 8 float4 per row
+__device__ __forceinline__ void ws_load(const float* __restrict__ F, int n_s, long long blk, const WgRows& wr,
+                                        float4 (&pf)[kPf], int tid) {
+  const float4* base = reinterpret_cast<const float4*>(F + blk * (long long)n_s * kC2 + (long long)wr.s_lo * kC2);
 #pragma unroll
   for (int u = 0; u < kPf; ++u) {
     const int idx = tid + u * kWsThreads;
@@ -258,14 +259,27 @@ __device__ __forceinline__ void ws_store(unsigned char* lds, const WsLayout& y, 
   }
 }
 
-// Row operand of one row block for 8 voxels: products p = F_i F_j, split
-// into hi = bf16(p) and lo = bf16(F_i F_j - hi) (the fma keeps lo exact).
-__device__ __forceinline__ void ws_row_operand(const unsigned char* lds, unsigned oi, unsigned oj, bf16x8& ahi,
-                                               bf16x8& alo) {
-  const float4 i0 = *reinterpret_cast<const float4*>(lds + oi), i1 = *reinterpret_cast<const float4*>(lds + oi + 16);
-  const float4 j0 = *reinterpret_cast<const float4*>(lds + oj), j1 = *reinterpret_cast<const float4*>(lds + oj + 16);
-  const float a[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
-  const float b[8] = {j0.x, j0.y, j0.z, j0.w, j1.x, j1.y, j1.z, j1.w};
+// Row operand of one row block for 8 voxels: F_i and F_j (8 floats each) are
+// read into registers first (ws_row_read), and the products p = F_i F_j are
+// split later (ws_row_split) into hi = bf16(p) and lo = bf16(F_i F_j - hi)
+// (the fma keeps lo exact), so the reads of one block can be issued before
+// the previous block's products and MFMAs.
+struct RowIn {
+  float4 i0, i1, j0, j1;
+};
+
+__device__ __forceinline__ RowIn ws_row_read(const unsigned char* lds, unsigned oi, unsigned oj) {
+  RowIn r;
+  r.i0 = *reinterpret_cast<const float4*>(lds + oi);
+  r.i1 = *reinterpret_cast<const float4*>(lds + oi + 16);
+  r.j0 = *reinterpret_cast<const float4*>(lds + oj);
+  r.j1 = *reinterpret_cast<const float4*>(lds + oj + 16);
+  return r;
+}
+
+__device__ __forceinline__ void ws_row_split(const RowIn& r, bf16x8& ahi, bf16x8& alo) {
+  const float a[8] = {r.i0.x, r.i0.y, r.i0.z, r.i0.w, r.i1.x, r.i1.y, r.i1.z, r.i1.w};
+  const float b[8] = {r.j0.x, r.j0.y, r.j0.z, r.j0.w, r.j1.x, r.j1.y, r.j1.z, r.j1.w};
   u32x4 h, l;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -277,15 +291,19 @@ __device__ __forceinline__ void ws_row_operand(const unsigned char* lds, unsigne
   alo = __builtin_bit_cast(bf16x8, l);
 }
 
-// 32 voxels of buffer buf for a slot with NT column tiles.  fo[q], go[q]:
+// 32 voxels of buffer buf for a slot with NT column tiles and n_rb row blocks
+// (n_rb <= slot_row_blocks(NT); accumulator tile q * NT + t).  fo[q], go[q]:
 // byte offsets of this lane's F_i and F_j rows (+ its voxel octet) in buffer 0;
 // co[t]: of its column row in plane Bh buffer 0.
-template <int NT>
-__device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLayout& y, int buf,
-                                           const unsigned (&fo)[kRbPerSlot], const unsigned (&go)[kRbPerSlot],
-                                           const unsigned (&co)[kMaxColTiles],
-                                           f32x16 (&acc)[kRbPerSlot][kMaxColTiles]) {
+// FULL: n_rb == slot_row_blocks(NT), no per-block branch (lets the compiler
+// overlap one block's LDS reads and products with the previous block's MFMAs).
+template <int NT, bool FULL>
+__device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLayout& y, int buf, int n_rb,
+                                           const unsigned (&fo)[kMaxRbPerSlot], const unsigned (&go)[kMaxRbPerSlot],
+                                           const unsigned (&co)[kMaxColTiles], f32x16 (&acc)[kSlotTiles]) {
+  constexpr int RBM = slot_row_blocks(NT);
   const unsigned fb = buf * y.f_buf, bb = y.bh0 + buf * y.b_buf, lb = y.bl0 + buf * y.b_buf;
+  const int nq = FULL ? RBM : n_rb;
 #pragma unroll
   for (int ks = 0; ks < kC2 / 16; ++ks) {
     bf16x8 bhi[NT], blo[NT];
@@ -294,16 +312,26 @@ __device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLay
       bhi[t] = *reinterpret_cast<const bf16x8*>(lds + bb + co[t] + ks * 32);
       blo[t] = *reinterpret_cast<const bf16x8*>(lds + lb + co[t] + ks * 32);
     }
+    // software pipeline over the row blocks: reads of block q + 1 are in
+    // flight while block q is split and multiplied
+    RowIn cur = ws_row_read(lds, fb + fo[0] + ks * 64, fb + go[0] + ks * 64);
 #pragma unroll
-    for (int q = 0; q < kRbPerSlot; ++q) {
+    for (int q = 0; q < RBM; ++q) {
+      if (!FULL && q >= nq) break;  // uniform over the wave
+      RowIn nxt = cur;
+      if (q + 1 < RBM && (FULL || q + 1 < nq))
+        nxt = ws_row_read(lds, fb + fo[q + 1] + ks * 64, fb + go[q + 1] + ks * 64);
+      __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this block's work
       bf16x8 ahi, alo;
-      ws_row_operand(lds, fb + fo[q] + ks * 64, fb + go[q] + ks * 64, ahi, alo);
+      ws_row_split(cur, ahi, alo);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[t], acc[q][t], 0, 0, 0);
-        acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[t], acc[q][t], 0, 0, 0);
-        acc[q][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[t], acc[q][t], 0, 0, 0);
+        f32x16& c = acc[q * NT + t];
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[t], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[t], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[t], c, 0, 0, 0);
       }
+      cur = nxt;
     }
   }
 }
@@ -312,28 +340,28 @@ __device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLay
 // The base pointer passes through an empty asm so the element addresses are
 // formed here, not hoisted out of the main loop into live registers.
 template <int NT>
-__device__ __forceinline__ void ws_flush(double* out, bool first, f32x16 (&acc)[kRbPerSlot][kMaxColTiles]) {
+__device__ __forceinline__ void ws_flush(double* out, bool first, int n_rb, f32x16 (&acc)[kSlotTiles]) {
+  constexpr int RBM = slot_row_blocks(NT);
   asm volatile("" : "+v"(out));
 #pragma unroll
-  for (int q = 0; q < kRbPerSlot; ++q)
+  for (int k = 0; k < RBM * NT; ++k) {
+    if (k >= n_rb * NT) break;
+    double* o = out + (long long)k * 1024;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      double* o = out + (long long)(q * kMaxColTiles + t) * 1024;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        o[v * 64] = first ? (double)acc[q][t][v] : o[v * 64] + (double)acc[q][t][v];
-        acc[q][t][v] = 0.f;
-      }
+    for (int v = 0; v < 16; ++v) {
+      o[v * 64] = first ? (double)acc[k][v] : o[v * 64] + (double)acc[k][v];
+      acc[k][v] = 0.f;
     }
+  }
 }
 
-template <int NT>
+template <int NT, bool FULL>
 __device__ __forceinline__ void ws_step(const unsigned char* lds, const WsLayout& y, int buf, bool flush,
-                                        bool first, double* out, const unsigned (&fo)[kRbPerSlot],
-                                        const unsigned (&go)[kRbPerSlot], const unsigned (&co)[kMaxColTiles],
-                                        f32x16 (&acc)[kRbPerSlot][kMaxColTiles]) {
-  ws_compute<NT>(lds, y, buf, fo, go, co, acc);
-  if (flush) ws_flush<NT>(out, first, acc);
+                                        bool first, double* out, int n_rb, const unsigned (&fo)[kMaxRbPerSlot],
+                                        const unsigned (&go)[kMaxRbPerSlot], const unsigned (&co)[kMaxColTiles],
+                                        f32x16 (&acc)[kSlotTiles]) {
+  ws_compute<NT, FULL>(lds, y, buf, n_rb, fo, go, co, acc);
+  if (flush) ws_flush<NT>(out, first, n_rb, acc);
 }
 
 __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __restrict__ F, WsArgs a) {
@@ -355,10 +383,10 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
   }
   // this lane's rows (pair shells) and columns as byte offsets in buffer 0
   const SlotCols sc = a.cols[wg * kSlotsPerWg + w];
-  unsigned fo[kRbPerSlot], go[kRbPerSlot], co[kMaxColTiles];
+  unsigned fo[kMaxRbPerSlot], go[kMaxRbPerSlot], co[kMaxColTiles];
 #pragma unroll
-  for (int q = 0; q < kRbPerSlot; ++q) {
-    const RowBlock& rb = a.rows[wg * kRbPerWg + w * kRbPerSlot + q];
+  for (int q = 0; q < kMaxRbPerSlot; ++q) {
+    const RowBlock& rb = a.rows[wg * kRbPerWg + w * kMaxRbPerSlot + q];
     const int i = rb.i[lane & 31], j = rb.j[lane & 31];
     const int ri = j > 0 ? i - 1 - wr.s_lo : zr, rj = j > 0 ? j - 1 - wr.s_lo : zr;
     fo[q] = (unsigned)(ri * kF32S + kg * 8) * 4;
@@ -370,48 +398,56 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
     const int rc = (l >= 1 && l <= a.n_s) ? l - 1 - wr.s_lo : zr;
     co[t] = (unsigned)(rc * kBS + kg * 8) * 2;
   }
-  f32x16 acc[kRbPerSlot][kMaxColTiles];
+  f32x16 acc[kSlotTiles];
 #pragma unroll
-  for (int q = 0; q < kRbPerSlot; ++q)
+  for (int k = 0; k < kSlotTiles; ++k)
 #pragma unroll
-    for (int t = 0; t < kMaxColTiles; ++t)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[q][t][v] = 0.f;
-  // partial[kr][tile][element] with tile = wg*kTilesPerWg + (w*kRbPerSlot + q)*kMaxColTiles + t
+    for (int v = 0; v < 16; ++v) acc[k][v] = 0.f;
+  // partial[kr][tile][element] with tile = wg*kTilesPerWg + w*kSlotTiles + (q*NT + t)
   double* out = a.partial +
-                ((long long)kr * a.n_wg * kTilesPerWg + (long long)wg * kTilesPerWg +
-                 (long long)w * kRbPerSlot * kMaxColTiles) * 1024 + lane;
-  const long long k_lo = range_lo(a.n_vox, a.n_krange, kr), k_hi = range_lo(a.n_vox, a.n_krange, kr + 1);
-  const int n_chunks = (int)((k_hi - k_lo) / kC2);
-  const long long blk0 = k_lo / kC2;
+                ((long long)kr * a.n_wg * kTilesPerWg + (long long)wg * kTilesPerWg + (long long)w * kSlotTiles) * 1024 +
+                lane;
+  const int n_rb = sc.n_rb;
+  // Range kr takes the voxel blocks kr, kr + n_krange, kr + 2 n_krange, ...:
+  // every float32 chain samples the whole box, so its partial sums cancel like
+  // the total instead of growing with a slab's coherent sum.
+  const long long n_blocks = a.n_vox / kC2;
+  const int n_chunks = kr < n_blocks ? (int)((n_blocks - kr + a.n_krange - 1) / a.n_krange) : 0;
+  const long long kstep = a.n_krange;
   float4 pf[kPf];
   if (n_chunks > 0) {
-    ws_load(F, a.n_s, blk0, wr, 0, pf, tid);
+    ws_load(F, a.n_s, kr, wr, pf, tid);
     ws_store(smem_raw, y, wr.s_n, 0, pf, tid);
   }
   __syncthreads();
+  const int variant = sc.n * 2 + (n_rb == slot_row_blocks(sc.n) ? 1 : 0);  // uniform per wave
   bool first = true;
   int chain = 0;
   for (int c = 0; c < n_chunks; ++c) {
     const bool more = c + 1 < n_chunks;
-    if (more) ws_load(F, a.n_s, blk0, wr, c + 1, pf, tid);
+    if (more) ws_load(F, a.n_s, kr + (c + 1) * kstep, wr, pf, tid);
     const bool flush = ++chain == kFlushChunks || !more;
-    switch (sc.n) {  // uniform per wave
-      case 4: ws_step<4>(smem_raw, y, c & 1, flush, first, out, fo, go, co, acc); break;
-      case 3: ws_step<3>(smem_raw, y, c & 1, flush, first, out, fo, go, co, acc); break;
-      case 2: ws_step<2>(smem_raw, y, c & 1, flush, first, out, fo, go, co, acc); break;
-      case 1: ws_step<1>(smem_raw, y, c & 1, flush, first, out, fo, go, co, acc); break;
+    const int buf = c & 1;
+    switch (variant) {
+      case 9: ws_step<4, true>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
+      case 8: ws_step<4, false>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
+      case 7: ws_step<3, true>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
+      case 6: ws_step<3, false>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
+      case 5: ws_step<2, true>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
+      case 4: ws_step<2, false>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
+      case 3: ws_step<1, true>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
+      case 2: ws_step<1, false>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
       default: break;
     }
     if (flush) {
       chain = 0;
       first = false;
     }
-    if (more) ws_store(smem_raw, y, wr.s_n, (c + 1) & 1, pf, tid);
+    if (more) ws_store(smem_raw, y, wr.s_n, buf ^ 1, pf, tid);
     __syncthreads();
   }
   if (n_chunks == 0)  // empty range: its partials are zero
-    for (int e = 0; e < kRbPerSlot * kMaxColTiles * 16; ++e) out[(long long)(e >> 4) * 1024 + (e & 15) * 64] = 0.0;
+    for (int e = 0; e < kSlotTiles * 16; ++e) out[(long long)(e >> 4) * 1024 + (e & 15) * 64] = 0.0;
 }
 
 // ============================================================================
@@ -500,7 +536,7 @@ hipError_t prepare_contract_bf16x3() {
 hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t st) {
   // every staged row fits the per-thread loads; ranges are whole voxel blocks
   if (a.max_s * (kC2 / 4) > kWsThreads * kPf || a.max_s > a.n_s || a.max_s > kMaxSplitShells ||
-      a.n_vox % 64 != 0)
+      a.n_vox % kC2 != 0)
     return hipErrorInvalidValue;
   const size_t lds = bf16x3_lds_bytes(a.max_s);
   const unsigned blocks = (unsigned)a.n_wg * (unsigned)a.n_krange;

@@ -290,8 +290,16 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
   }
   std::map<std::pair<int, int>, std::vector<P>> spans;  // (first, last column block) -> pairs
   for (auto& g : groups) spans[{std::get<1>(g.first), std::get<2>(g.first)}] = g.second;
-  // slots: kRbPerSlot row blocks of one span + that span's non-empty column tiles
-  struct Slot { RowBlock rb[kRbPerSlot]; SlotCols sc; };
+  // slots: row blocks of one span + the non-empty column tiles they meet
+  struct Slot { RowBlock rb[kMaxRbPerSlot]; SlotCols sc; };
+  auto col_used = [&](const RowBlock& rb, int col0) {
+    for (int r = 0; r < kRows; ++r) {
+      if (!rb.j[r]) continue;
+      for (int l : pl[{rb.i[r], rb.j[r]}])
+        if (l >= col0 && l < col0 + kCols) return true;
+    }
+    return false;
+  };
   std::vector<Slot> slots;
   for (auto& sp : spans) {
     auto& ps = sp.second;
@@ -301,44 +309,28 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
       if (a.i != b.i) return a.i < b.i;
       return a.j < b.j;
     });
-    const size_t per_slot = (size_t)kRows * kRbPerSlot;
-    for (size_t p0 = 0; p0 < ps.size(); p0 += per_slot) {
+    std::vector<RowBlock> rbs((ps.size() + kRows - 1) / kRows, RowBlock{});
+    for (size_t k = 0; k < ps.size(); ++k) {
+      rbs[k / kRows].i[k % kRows] = (int16_t)ps[k].i;
+      rbs[k / kRows].j[k % kRows] = (int16_t)ps[k].j;
+    }
+    const int n_blocks = sp.first.second - sp.first.first + 1;
+    const int per_slot = slot_row_blocks(n_blocks);
+    for (size_t b0 = 0; b0 < rbs.size(); b0 += per_slot) {
       Slot sl{};
-      for (int q = 0; q < kRbPerSlot; ++q)
-        for (int r = 0; r < kRows; ++r) {
-          const size_t k = p0 + (size_t)q * kRows + r;
-          sl.rb[q].i[r] = k < ps.size() ? (int16_t)ps[k].i : 0;
-          sl.rb[q].j[r] = k < ps.size() ? (int16_t)ps[k].j : 0;
-        }
+      sl.sc.n_rb = (int32_t)std::min<size_t>(per_slot, rbs.size() - b0);
+      for (int q = 0; q < sl.sc.n_rb; ++q) sl.rb[q] = rbs[b0 + q];
       sl.sc.n = 0;
       for (int c = sp.first.first; c <= sp.first.second; ++c) {
         const int col0 = c * kCols + 1;
         bool any = false;
-        for (int q = 0; q < kRbPerSlot && !any; ++q)
-          for (int r = 0; r < kRows && !any; ++r) {
-            if (!sl.rb[q].j[r]) continue;
-            for (int l : pl[{sl.rb[q].i[r], sl.rb[q].j[r]}])
-              if (l >= col0 && l < col0 + kCols) { any = true; break; }
-          }
+        for (int q = 0; q < sl.sc.n_rb && !any; ++q) any = col_used(sl.rb[q], col0);
         if (any) sl.sc.col0[sl.sc.n++] = col0;
       }
       slots.push_back(sl);
     }
   }
   while (slots.size() % kSlotsPerWg) slots.push_back(Slot{});
-  // Balance: slots by column-tile count, largest first; a work group takes 8
-  // consecutive slots and pairs its largest with its smallest on each SIMD
-  // (wave q runs on SIMD q % 4, so waves q and q + 4 share one).
-  std::stable_sort(slots.begin(), slots.end(), [](const Slot& a, const Slot& b) { return a.sc.n > b.sc.n; });
-  static_assert(kSlotsPerWg == 8, "the SIMD pairing below assumes 8 slots per work group");
-  for (size_t w0 = 0; w0 < slots.size(); w0 += kSlotsPerWg) {
-    Slot tmp[kSlotsPerWg];
-    for (int q = 0; q < kSlotsPerWg; ++q) tmp[q] = slots[w0 + q];
-    for (int q = 0; q < 4; ++q) {
-      slots[w0 + q] = tmp[q];
-      slots[w0 + 4 + q] = tmp[kSlotsPerWg - 1 - q];
-    }
-  }
   mt.n_wg = (int32_t)(slots.size() / kSlotsPerWg);
   mt.rows.assign((size_t)mt.n_wg * kRbPerWg, RowBlock{});
   mt.cols.assign((size_t)mt.n_wg * kSlotsPerWg, SlotCols{});
@@ -351,14 +343,13 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
     for (int sidx = 0; sidx < kSlotsPerWg; ++sidx) {
       const Slot& sl = slots[(size_t)w * kSlotsPerWg + sidx];
       mt.cols[(size_t)w * kSlotsPerWg + sidx] = sl.sc;
-      mt.tiles += (int64_t)sl.sc.n * kRbPerSlot;
+      mt.tiles += (int64_t)sl.sc.n * sl.sc.n_rb;
       for (int t = 0; t < sl.sc.n; ++t) {
         s_lo = std::min(s_lo, sl.sc.col0[t] - 1);
         s_hi = std::max(s_hi, std::min(sl.sc.col0[t] - 1 + kCols - 1, n_shells - 1));
       }
-      for (int q = 0; q < kRbPerSlot; ++q) {
-        const int rbi = sidx * kRbPerSlot + q;  // row block within the work group
-        mt.rows[(size_t)w * kRbPerWg + rbi] = sl.rb[q];
+      for (int q = 0; q < sl.sc.n_rb; ++q) {
+        mt.rows[(size_t)w * kRbPerWg + sidx * kMaxRbPerSlot + q] = sl.rb[q];
         for (int r = 0; r < kRows; ++r) {
           const int i = sl.rb[q].i[r], j = sl.rb[q].j[r];
           if (!j) continue;
@@ -370,7 +361,7 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
               const int c = l - sl.sc.col0[t];
               if (c < 0 || c >= kCols) continue;
               const int lane = c + 32 * ((r >> 2) & 1), v = 4 * (r >> 3) + (r & 3);
-              const int tile = w * kTilesPerWg + rbi * kMaxColTiles + t;
+              const int tile = w * kTilesPerWg + sidx * kSlotTiles + q * sl.sc.n + t;
               where[{i, j, l}] = tile * (kRows * kCols) + v * 64 + lane;
             }
         }

@@ -85,17 +85,21 @@ void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp);
 // grouped by the span of column blocks their selected l fall in, so each row
 // block of kRows pairs meets the column blocks of one span as whole rectangles
 // of at most kMaxColTiles tiles.  A slot (one wavefront of the kernel) holds
-// kRbPerSlot row blocks of one span, which share the column operands; a work
-// group has kSlotsPerWg slots.  A pair whose l reach several windows appears
-// once per window.
+// n_rb row blocks of one span and the n <= kMaxColTiles column tiles they
+// meet, with n_rb <= slot_row_blocks(n) so that n * n_rb <= kSlotTiles
+// accumulator tiles; a work group has kSlotsPerWg slots.  A pair whose l reach
+// several windows appears once per window (never for <= 128 shells).
 constexpr int kMaxColTiles = 4;
-constexpr int kRbPerSlot = 2;
-constexpr int kSlotsPerWg = 8;
-constexpr int kRbPerWg = kRbPerSlot * kSlotsPerWg;
-constexpr int kTilesPerWg = kRbPerWg * kMaxColTiles;
+constexpr int kSlotTiles = 4;
+constexpr int kMaxRbPerSlot = 4;
+constexpr int kSlotsPerWg = 12;
+constexpr int kRbPerWg = kMaxRbPerSlot * kSlotsPerWg;
+constexpr int kTilesPerWg = kSlotTiles * kSlotsPerWg;
+inline constexpr int slot_row_blocks(int n_cols) { return n_cols <= 1 ? 4 : n_cols == 2 ? 2 : 1; }
 
 struct SlotCols {
   int32_t n;                      // column tiles of this slot (0 = idle slot)
+  int32_t n_rb;                   // row blocks of this slot
   int32_t col0[kMaxColTiles];     // first shell (1-based) of each column tile
 };
 
@@ -104,7 +108,7 @@ struct WgRows {
 };
 
 struct MfmaTiling {
-  std::vector<RowBlock> rows;     // kRbPerWg per work group
+  std::vector<RowBlock> rows;     // kRbPerWg per work group (kMaxRbPerSlot per slot)
   std::vector<SlotCols> cols;     // kSlotsPerWg per work group
   std::vector<WgRows> wg_rows;    // one per work group
   // triangle t sits in partial slot slot_of[t] = tile * kRows*kCols + element
