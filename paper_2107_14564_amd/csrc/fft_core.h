@@ -177,6 +177,25 @@ __device__ __forceinline__ void ct_passes(V2<T>* buf, const V2<T>* __restrict__ 
   }
 }
 
+// Block-wide copy of COUNT elements (thread t handles e = t + it * NT) in two
+// phases: all of a thread's loads first (held in registers), then its stores,
+// so every load of the thread is in flight at once.
+template <int COUNT, int NT, typename T, typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(Load&& load, Store&& store) {
+  constexpr int IT = (COUNT + NT - 1) / NT;
+  T v[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * NT;
+    if (COUNT % NT == 0 || e < COUNT) v[it] = load(e);
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * NT;
+    if (COUNT % NT == 0 || e < COUNT) store(e, v[it]);
+  }
+}
+
 // Full FFT (sign -1 forward, +1 inverse, unnormalised) of NL lines of length N
 // in LDS; starts and ends with the block synchronised.
 template <typename T, int N, int NL, int NT, bool INTERLEAVED, int LSX, int TWS>

@@ -35,6 +35,12 @@ constexpr int kThrZ = 256;     // threads of a contiguous-pass block
 
 __device__ __forceinline__ int freq(int q, int n) { return q < n / 2 ? q : q - n; }
 
+// the N-entry twiddle table into LDS (twiddle reads of every pass then stay on chip)
+template <int N, int NT, typename T>
+__device__ __forceinline__ void stage_twiddles(V2<T>* twl, const V2<T>* __restrict__ tw) {
+  staged_copy<N, NT, V2<T>>([&](int e) { return tw[e]; }, [&](int e, V2<T> v) { twl[e] = v; });
+}
+
 // ---- (a) forward: real z lines -> half spectrum ------------------------------
 // Two real samples per complex slot: z_m = x_{2m} + i x_{2m+1}, M-point FFT,
 // then X_k = (Z_k + Z*_{M-k})/2 + W_N^k (Z_k - Z*_{M-k})/(2i), k = 0..M.
@@ -45,16 +51,17 @@ __global__ void __launch_bounds__(kThrZ) k_r2c_z(const float* __restrict__ in, f
   constexpr int NL = fft_z_lines(M, false);
   constexpr int LS = M + 1;
   __shared__ float2 buf[NL * LS];
+  __shared__ float2 twl[N];
   const long long n_lines = (long long)N * N;
   const long long line0 = (long long)blockIdx.x * NL;
   const int lines = (int)min((long long)NL, n_lines - line0);
   const float2* src = reinterpret_cast<const float2*>(in) + line0 * M;
-  for (int e = threadIdx.x; e < NL * M; e += kThrZ) {
-    const int c = e / M, q = e % M;
-    if (c < lines) buf[c * LS + q] = src[(long long)c * M + q];
-  }
+  staged_copy<NL * M, kThrZ, float2>(
+      [&](int e) { return e / M < lines ? src[(long long)e] : mk<float>(0.f, 0.f); },
+      [&](int e, float2 v) { buf[(e / M) * LS + e % M] = v; });
+  stage_twiddles<N, kThrZ, float>(twl, tw);
   __syncthreads();
-  ct_fft<float, M, NL, kThrZ, false, LS, 2>(buf, tw, -1.0f);
+  ct_fft<float, M, NL, kThrZ, false, LS, 2>(buf, twl, -1.0f);
   float2* dst = out + line0 * (M + 1);
   for (int e = threadIdx.x; e < NL * (M + 1); e += kThrZ) {
     const int c = e / (M + 1), k = e % (M + 1);
@@ -63,7 +70,7 @@ __global__ void __launch_bounds__(kThrZ) k_r2c_z(const float* __restrict__ in, f
     const float2 zc = conjv<float>(buf[c * LS + (k == 0 ? 0 : M - k)]);
     const float2 a = scl<float>(add<float>(zk, zc), 0.5f);
     const float2 d = scl<float>(sub<float>(zk, zc), 0.5f);  // (Z_k - Z*_{M-k}) / 2
-    const float2 w = tw[k];
+    const float2 w = twl[k];
     const float2 bi = mk<float>(d.y, -d.x);                 // d / i
     dst[(long long)c * (M + 1) + k] = scl<float>(add<float>(a, mul<float>(w, bi)), scale);
   }
@@ -79,17 +86,18 @@ __global__ void __launch_bounds__(kThrAxis) k_fft_axis(float2* __restrict__ data
                                                        float sign, float scale, int rsd_pass, float beta) {
   constexpr int TW = fft_tile_cols(N, false);
   __shared__ float2 buf[N * TW];
+  __shared__ float2 twl[N];
   const int n_ct = (n_cols + TW - 1) / TW;
   const int o = blockIdx.x / n_ct;
   const int c0 = (blockIdx.x % n_ct) * TW;
   const int cols = min(TW, n_cols - c0);
   float2* base = data + (long long)o * outer_stride + c0;
-  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
-    const int q = e / TW, c = e % TW;
-    buf[e] = c < cols ? base[(long long)q * stride + c] : mk<float>(0.f, 0.f);
-  }
+  staged_copy<N * TW, kThrAxis, float2>(
+      [&](int e) { return e % TW < cols ? base[(long long)(e / TW) * stride + e % TW] : mk<float>(0.f, 0.f); },
+      [&](int e, float2 v) { buf[e] = v; });
+  stage_twiddles<N, kThrAxis, float>(twl, tw);
   __syncthreads();
-  ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, tw, sign);
+  ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, twl, sign);
   for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
     const int q = e / TW, c = e % TW;
     if (c >= cols) continue;
@@ -113,6 +121,7 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ s
                                                     const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw) {
   constexpr int TW = fft_tile_cols(N, sizeof(T) == 8);
   __shared__ V2<T> buf[N * TW];
+  __shared__ V2<T> twl[N];
   const int4 td = tiles[blockIdx.x];
   const int sn = td.x, ky = td.y, kz0 = td.z;
   const ShellDev d = sh[sn];
@@ -120,26 +129,29 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ s
   const int cols = min(TW, R + 1 - kz0);
   const int yrow = ky < 0 ? ky + spec_n : ky;
   const long long ky2 = (long long)ky * ky;
-  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
-    const int q = e / TW, c = e % TW;
-    V2<T> v = mk<T>((T)0, (T)0);
-    if (c < cols) {
-      const long long mx = freq(q, N), kz = kz0 + c;
-      const long long m2 = mx * mx + ky2 + kz * kz;
-      if (m2 >= d.lo2 && m2 < d.hi2) {
-        if (UNIT) {
-          v = mk<T>((T)1, (T)0);
-        } else {
-          const long long xrow = mx < 0 ? mx + spec_n : mx;
-          const float2 x = spec[(xrow * spec_n + yrow) * (spec_n / 2 + 1) + kz];
-          v = mk<T>((T)x.x, (T)x.y);
+  staged_copy<N * TW, kThrAxis, V2<T>>(
+      [&](int e) {
+        const int q = e / TW, c = e % TW;
+        V2<T> v = mk<T>((T)0, (T)0);
+        if (c < cols) {
+          const long long mx = freq(q, N), kz = kz0 + c;
+          const long long m2 = mx * mx + ky2 + kz * kz;
+          if (m2 >= d.lo2 && m2 < d.hi2) {
+            if (UNIT) {
+              v = mk<T>((T)1, (T)0);
+            } else {
+              const long long xrow = mx < 0 ? mx + spec_n : mx;
+              const float2 x = spec[(xrow * spec_n + yrow) * (spec_n / 2 + 1) + kz];
+              v = mk<T>((T)x.x, (T)x.y);
+            }
+          }
         }
-      }
-    }
-    buf[e] = v;
-  }
+        return v;
+      },
+      [&](int e, V2<T> v) { buf[e] = v; });
+  stage_twiddles<N, kThrAxis, T>(twl, tw);
   __syncthreads();
-  ct_fft<T, N, TW, kThrAxis, true, 1, 1>(buf, tw, (T)1);
+  ct_fft<T, N, TW, kThrAxis, true, 1, 1>(buf, twl, (T)1);
   V2<T>* dst = a1 + d.a1_off;
   const int wy = 2 * R + 1, wz = R + 1;
   for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
@@ -156,6 +168,7 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1
                                                     const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw) {
   constexpr int TW = fft_tile_cols(N, sizeof(T) == 8);
   __shared__ V2<T> buf[N * TW];
+  __shared__ V2<T> twl[N];
   const long long b = blockIdx.x;
   int lo = 0, hi = n_shells;  // sn with tile_off[sn] <= b < tile_off[sn+1]
   while (hi - lo > 1) {
@@ -172,17 +185,20 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1
   const int cols = min(TW, R + 1 - kz0);
   const int wy = 2 * R + 1, wz = R + 1;
   const V2<T>* src = a1 + d.a1_off + (long long)x * wy * wz;
-  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
-    const int q = e / TW, c = e % TW;
-    V2<T> v = mk<T>((T)0, (T)0);
-    if (c < cols) {
-      const long long my = freq(q, N), kz = kz0 + c;
-      if (my >= -R && my <= R && my * my + kz * kz < d.hi2) v = src[(my + R) * wz + kz];
-    }
-    buf[e] = v;
-  }
+  staged_copy<N * TW, kThrAxis, V2<T>>(
+      [&](int e) {
+        const int q = e / TW, c = e % TW;
+        V2<T> v = mk<T>((T)0, (T)0);
+        if (c < cols) {
+          const long long my = freq(q, N), kz = kz0 + c;
+          if (my >= -R && my <= R && my * my + kz * kz < d.hi2) v = src[(my + R) * wz + kz];
+        }
+        return v;
+      },
+      [&](int e, V2<T> v) { buf[e] = v; });
+  stage_twiddles<N, kThrAxis, T>(twl, tw);
   __syncthreads();
-  ct_fft<T, N, TW, kThrAxis, true, 1, 1>(buf, tw, (T)1);
+  ct_fft<T, N, TW, kThrAxis, true, 1, 1>(buf, twl, (T)1);
   V2<T>* dst = a2 + d.a2_off + (long long)x * N * wz;
   for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
     const int q = e / TW, c = e % TW;
@@ -203,6 +219,7 @@ __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, O
   constexpr int NL = fft_z_lines(M, sizeof(T) == 8);
   constexpr int LS = M + 1;
   __shared__ V2<T> buf[NL * LS];
+  __shared__ V2<T> twl[N];
   const long long b = blockIdx.x;
   int lo = 0, hi = n_shells;
   while (hi - lo > 1) {
@@ -216,10 +233,13 @@ __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, O
   const long long line0 = (b - blk_off[sn]) * NL;
   const int lines = (int)min((long long)NL, n_lines - line0);
   const V2<T>* src = a2 + d.a2_off + line0 * wz;
-  for (int e = threadIdx.x; e < NL * LS; e += kThrZ) {
-    const int c = e / LS, k = e % LS;
-    buf[e] = (c < lines && k < wz) ? src[(long long)c * wz + k] : mk<T>((T)0, (T)0);
-  }
+  staged_copy<NL * LS, kThrZ, V2<T>>(
+      [&](int e) {
+        const int c = e / LS, k = e % LS;
+        return (c < lines && k < wz) ? src[(long long)c * wz + k] : mk<T>((T)0, (T)0);
+      },
+      [&](int e, V2<T> v) { buf[e] = v; });
+  stage_twiddles<N, kThrZ, T>(twl, tw);
   __syncthreads();
   // pairs (k, M-k), k = 0..M/2, one thread each, in place
   constexpr int HALF = M / 2 + 1;
@@ -228,16 +248,16 @@ __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, O
     V2<T>* L = buf + c * LS;
     const V2<T> xk = L[k], xmk = L[M - k];
     const V2<T> sp = add<T>(xk, conjv<T>(xmk));
-    const V2<T> t = mul<T>(conjv<T>(tw[k]), sub<T>(xk, conjv<T>(xmk)));
+    const V2<T> t = mul<T>(conjv<T>(twl[k]), sub<T>(xk, conjv<T>(xmk)));
     if (k > 0 && k < M - k) {
       const V2<T> sp2 = add<T>(xmk, conjv<T>(xk));
-      const V2<T> t2 = mul<T>(conjv<T>(tw[M - k]), sub<T>(xmk, conjv<T>(xk)));
+      const V2<T> t2 = mul<T>(conjv<T>(twl[M - k]), sub<T>(xmk, conjv<T>(xk)));
       L[M - k] = mk<T>(sp2.x - t2.y, sp2.y + t2.x);
     }
     if (k < M) L[k] = mk<T>(sp.x - t.y, sp.y + t.x);
   }
   __syncthreads();
-  ct_fft<T, M, NL, kThrZ, false, LS, 2>(buf, tw, (T)1);
+  ct_fft<T, M, NL, kThrZ, false, LS, 2>(buf, twl, (T)1);
   for (int e = threadIdx.x; e < NL * M; e += kThrZ) {
     const int c = e / M, q = e % M;
     if (c >= lines) continue;
@@ -274,6 +294,7 @@ __global__ void __launch_bounds__(kThrZ) k_g_r2c_z(const float* __restrict__ G, 
   constexpr int NL = fft_z_lines(M, false);
   constexpr int LS = M + 1;
   __shared__ float2 buf[NL * LS];
+  __shared__ float2 twl[N];
   const long long b = blockIdx.x;
   int lo = 0, hi = n_shells;
   while (hi - lo > 1) {
@@ -286,15 +307,17 @@ __global__ void __launch_bounds__(kThrZ) k_g_r2c_z(const float* __restrict__ G, 
   const long long n_lines = (long long)N * N;
   const long long line0 = (b - blk_off[sn]) * NL;
   const int lines = (int)min((long long)NL, n_lines - line0);
-  for (int e = threadIdx.x; e < NL * M; e += kThrZ) {
-    const int c = e / M, q = e % M;
-    if (c < lines) {
-      const long long at = vox_index((line0 + c) * N + 2 * q, sn, n_shells);
-      buf[c * LS + q] = *reinterpret_cast<const float2*>(G + at);
-    }
-  }
+  staged_copy<NL * M, kThrZ, float2>(
+      [&](int e) {
+        const int c = e / M, q = e % M;
+        if (c >= lines) return mk<float>(0.f, 0.f);
+        const long long at = vox_index((line0 + c) * N + 2 * q, sn, n_shells);
+        return *reinterpret_cast<const float2*>(G + at);
+      },
+      [&](int e, float2 v) { buf[(e / M) * LS + e % M] = v; });
+  stage_twiddles<N, kThrZ, float>(twl, tw);
   __syncthreads();
-  ct_fft<float, M, NL, kThrZ, false, LS, 2>(buf, tw, -1.0f);
+  ct_fft<float, M, NL, kThrZ, false, LS, 2>(buf, twl, -1.0f);
   float2* dst = a2 + d.a2_off + line0 * wz;
   for (int e = threadIdx.x; e < NL * wz; e += kThrZ) {
     const int c = e / wz, k = e % wz;
@@ -304,7 +327,7 @@ __global__ void __launch_bounds__(kThrZ) k_g_r2c_z(const float* __restrict__ G, 
     const float2 a = scl<float>(add<float>(zk, zc), 0.5f);
     const float2 dd = scl<float>(sub<float>(zk, zc), 0.5f);
     const float2 bi = mk<float>(dd.y, -dd.x);
-    dst[(long long)c * wz + k] = add<float>(a, mul<float>(tw[k], bi));
+    dst[(long long)c * wz + k] = add<float>(a, mul<float>(twl[k], bi));
   }
 }
 
@@ -316,6 +339,7 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_y(const float2* __restrict__
                                                       const float2* __restrict__ tw) {
   constexpr int TW = fft_tile_cols(N, false);
   __shared__ float2 buf[N * TW];
+  __shared__ float2 twl[N];
   const long long b = blockIdx.x;
   int lo = 0, hi = n_shells;
   while (hi - lo > 1) {
@@ -332,12 +356,12 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_y(const float2* __restrict__
   const int cols = min(TW, R + 1 - kz0);
   const int wy = 2 * R + 1, wz = R + 1;
   const float2* src = a2 + d.a2_off + (long long)x * N * wz;
-  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
-    const int q = e / TW, c = e % TW;
-    buf[e] = c < cols ? src[(long long)q * wz + kz0 + c] : mk<float>(0.f, 0.f);
-  }
+  staged_copy<N * TW, kThrAxis, float2>(
+      [&](int e) { return e % TW < cols ? src[(long long)(e / TW) * wz + kz0 + e % TW] : mk<float>(0.f, 0.f); },
+      [&](int e, float2 v) { buf[e] = v; });
+  stage_twiddles<N, kThrAxis, float>(twl, tw);
   __syncthreads();
-  ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, tw, -1.0f);
+  ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, twl, -1.0f);
   float2* dst = a1 + d.a1_off + (long long)x * wy * wz;
   for (int e = threadIdx.x; e < wy * TW; e += kThrAxis) {
     const int ky = e / TW - R, c = e % TW;
@@ -355,6 +379,7 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__
                                                       const float2* __restrict__ tw, float scale, float beta) {
   constexpr int TW = fft_tile_cols(N, false);
   __shared__ float2 buf[N * TW];
+  __shared__ float2 twl[N];
   const int4 td = tiles[blockIdx.x];
   const int sn = td.x, ky = td.y, kz0 = td.z;
   const ShellDev d = sh[sn];
@@ -362,12 +387,14 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__
   const int cols = min(TW, R + 1 - kz0);
   const int wy = 2 * R + 1, wz = R + 1;
   const float2* src = a1 + d.a1_off;
-  for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
-    const int q = e / TW, c = e % TW;
-    buf[e] = c < cols ? src[((long long)q * wy + (ky + R)) * wz + kz0 + c] : mk<float>(0.f, 0.f);
-  }
+  staged_copy<N * TW, kThrAxis, float2>(
+      [&](int e) {
+        return e % TW < cols ? src[((long long)(e / TW) * wy + (ky + R)) * wz + kz0 + e % TW] : mk<float>(0.f, 0.f);
+      },
+      [&](int e, float2 v) { buf[e] = v; });
+  stage_twiddles<N, kThrAxis, float>(twl, tw);
   __syncthreads();
-  ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, tw, -1.0f);
+  ct_fft<float, N, TW, kThrAxis, true, 1, 1>(buf, twl, -1.0f);
   const int yrow = ky < 0 ? ky + spec_n : ky;
   const long long ky2 = (long long)ky * ky;
   for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {

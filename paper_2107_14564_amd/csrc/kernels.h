@@ -11,9 +11,10 @@
 namespace bispec {
 
 // Tile shapes of the FFT passes (shared by kernels and host planning).
-// Strided passes: TW columns x N rows per block (<= 64 KB of LDS).
+// Strided passes: TW columns x N rows per block plus the N-entry twiddle table
+// (<= 64 KB of LDS together).
 __host__ __device__ constexpr int fft_tile_cols(int n, bool f64) {
-  return ((f64 ? 4096 : 8192) / n) < 64 ? ((f64 ? 4096 : 8192) / n) : 64;
+  return (((f64 ? 4096 : 8192) - n) / n) < 64 ? (((f64 ? 4096 : 8192) - n) / n) : 64;
 }
 // Contiguous passes over lines of length len (LDS stride len + 1): lines per block.
 __host__ __device__ constexpr int fft_z_lines(int len, bool f64) { return (f64 ? 2048 : 2048) / (len + 1); }
