@@ -330,7 +330,45 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
       slots.push_back(sl);
     }
   }
-  while (slots.size() % kSlotsPerWg) slots.push_back(Slot{});
+  // Cost-balanced placement: per chunk a slot costs about 3 NT n_rb MFMAs
+  // (32 cycles each) and n_rb row-operand formations (~64 VALU instructions of
+  // 4 cycles).  Work groups get equal totals (longest first, to the least
+  // loaded group), so the groups that share a voxel range advance together
+  // and re-read each chunk from L2; within a group, waves q, q + 4, q + 8 share
+  // SIMD q % 4, which gets equal totals the same way.
+  {
+    auto cost = [](const Slot& sl) { return sl.sc.n_rb * (96 * sl.sc.n + 256); };
+    std::vector<Slot> real;
+    for (const Slot& sl : slots)
+      if (sl.sc.n) real.push_back(sl);
+    std::stable_sort(real.begin(), real.end(), [&](const Slot& a, const Slot& b) { return cost(a) > cost(b); });
+    const int n_wg = std::max<int>(1, (int)((real.size() + kSlotsPerWg - 1) / kSlotsPerWg));
+    std::vector<std::vector<Slot>> wg(n_wg);
+    std::vector<long> load(n_wg, 0);
+    for (const Slot& sl : real) {
+      int best = -1;
+      for (int w = 0; w < n_wg; ++w)
+        if ((int)wg[w].size() < kSlotsPerWg && (best < 0 || load[w] < load[best])) best = w;
+      wg[best].push_back(sl);
+      load[best] += cost(sl);
+    }
+    constexpr int kSimds = 4, kPerSimd = kSlotsPerWg / kSimds;
+    static_assert(kSlotsPerWg % kSimds == 0, "slots per work group must fill the SIMDs evenly");
+    slots.assign((size_t)n_wg * kSlotsPerWg, Slot{});
+    for (int w = 0; w < n_wg; ++w) {
+      std::vector<std::vector<Slot>> simd(kSimds);
+      std::vector<long> sl_load(kSimds, 0);
+      for (const Slot& sl : wg[w]) {  // already in decreasing cost
+        int best = -1;
+        for (int q = 0; q < kSimds; ++q)
+          if ((int)simd[q].size() < kPerSimd && (best < 0 || sl_load[q] < sl_load[best])) best = q;
+        simd[best].push_back(sl);
+        sl_load[best] += cost(sl);
+      }
+      for (int q = 0; q < kSimds; ++q)
+        for (size_t k = 0; k < simd[q].size(); ++k) slots[(size_t)w * kSlotsPerWg + q + kSimds * k] = simd[q][k];
+    }
+  }
   mt.n_wg = (int32_t)(slots.size() / kSlotsPerWg);
   mt.rows.assign((size_t)mt.n_wg * kRbPerWg, RowBlock{});
   mt.cols.assign((size_t)mt.n_wg * kSlotsPerWg, SlotCols{});
