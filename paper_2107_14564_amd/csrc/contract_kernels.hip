@@ -158,11 +158,11 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 // of 16 fp32 per lane; NT is uniform over the wave, so the code path is too).
 //
 // Voxel range kr is the set of voxel blocks kr + m n_krange (interleaved over
-// the box).  Per chunk of 32 voxels (one block) every thread loads <= 2 float4
-// of the work group's shell rows s_lo .. s_lo + s_n - 1 (contiguous in the
-// voxel-blocked layout) one chunk ahead, and stores them into the other LDS
-// buffer as fp32 (row operands) and as bf16 hi/lo (column operands, split once
-// per value).  Per 16 voxels a lane then
+// the box).  Per chunk of 32 voxels (one block) each thread loads one 8-voxel
+// segment (2 float4) of the work group's shell rows s_lo .. s_lo + s_n - 1
+// (contiguous in the voxel-blocked layout) one chunk ahead, and stores it into
+// the other LDS buffer as fp32 (row operands) and as bf16 hi/lo (column
+// operands, split once per value) with four 16-byte stores.  Per 16 voxels a lane then
 //   - reads its column fragments (hi, lo: 8 voxels of shell l each),
 //   - for each row block reads 8 voxels of F_i and F_j, forms the 8 pair
 //     products in registers, splits them (the MFMA row-operand layout: lane
@@ -189,7 +189,7 @@ constexpr int kF32S = kC2 + 4;       // fp32 row stride (floats): 36 dwords
 constexpr int kBS = kC2 + 8;         // bf16 row stride (elements): 20 dwords
 constexpr int kFlushChunks = 256;    // 8192 voxels per float32 accumulation chain
 constexpr int kWsThreads = kSlotsPerWg * 64;
-constexpr int kPf = 2;               // float4 loads per thread per chunk
+constexpr int kPf = 1;               // 8-voxel row segments per thread per chunk (2 float4 each)
 static_assert(kC2 == kVoxBlock, "chunks are voxel blocks");
 
 // LDS byte layout for ns1 rows per buffer (row ns1 - 1 is all zero):
@@ -226,35 +226,48 @@ __device__ __forceinline__ unsigned bf16_pack(float v0, float v1) {
   return __builtin_bit_cast(unsigned, h);
 }
 
-// voxel block blk: rows s_lo .. s_lo + s_n - 1, 8 float4 per row
+// voxel block blk: rows s_lo .. s_lo + s_n - 1; thread t stages the 8 voxels
+// 8 (t % 4) .. + 7 of row t / 4 (two float4, contiguous in global memory)
+struct Seg {
+  float4 a, b;
+};
+
 __device__ __forceinline__ void ws_load(const float* __restrict__ F, int n_s, long long blk, const WgRows& wr,
-                                        float4 (&pf)[kPf], int tid) {
+                                        Seg (&pf)[kPf], int tid) {
   const float4* base = reinterpret_cast<const float4*>(F + blk * (long long)n_s * kC2 + (long long)wr.s_lo * kC2);
 #pragma unroll
   for (int u = 0; u < kPf; ++u) {
     const int idx = tid + u * kWsThreads;
-    if (idx < wr.s_n * (kC2 / 4)) pf[u] = base[idx];
+    if (idx < wr.s_n * (kC2 / 8)) {
+      pf[u].a = base[2 * idx];
+      pf[u].b = base[2 * idx + 1];
+    }
   }
 }
 
-// fp32 rows, and the bf16 split hi = bf16(v), lo = bf16(v - hi) of every value
+// fp32 row segment, and the bf16 split hi = bf16(v), lo = bf16(v - hi) of
+// every value: four 16-byte stores per thread
 __device__ __forceinline__ void ws_store(unsigned char* lds, const WsLayout& y, int s_n, int buf,
-                                         const float4 (&pf)[kPf], int tid) {
+                                         const Seg (&pf)[kPf], int tid) {
 #pragma unroll
   for (int u = 0; u < kPf; ++u) {
     const int idx = tid + u * kWsThreads;
-    if (idx < s_n * (kC2 / 4)) {
-      const unsigned r = idx >> 3, x = 4 * (idx & 7);
-      *reinterpret_cast<float4*>(lds + buf * y.f_buf + (r * kF32S + x) * 4) = pf[u];
-      float h0, h1, h2, h3;
-      u32x2 hi, lo;
-      hi[0] = bf16_pair(pf[u].x, pf[u].y, h0, h1);
-      hi[1] = bf16_pair(pf[u].z, pf[u].w, h2, h3);
-      lo[0] = bf16_pack(pf[u].x - h0, pf[u].y - h1);
-      lo[1] = bf16_pack(pf[u].z - h2, pf[u].w - h3);
+    if (idx < s_n * (kC2 / 8)) {
+      const unsigned r = idx >> 2, x = 8 * (idx & 3);
+      unsigned char* f = lds + buf * y.f_buf + (r * kF32S + x) * 4;
+      *reinterpret_cast<float4*>(f) = pf[u].a;
+      *reinterpret_cast<float4*>(f + 16) = pf[u].b;
+      const float v[8] = {pf[u].a.x, pf[u].a.y, pf[u].a.z, pf[u].a.w, pf[u].b.x, pf[u].b.y, pf[u].b.z, pf[u].b.w};
+      u32x4 hi, lo;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float h0, h1;
+        hi[e] = bf16_pair(v[2 * e], v[2 * e + 1], h0, h1);
+        lo[e] = bf16_pack(v[2 * e] - h0, v[2 * e + 1] - h1);
+      }
       const unsigned o = buf * y.b_buf + (r * kBS + x) * 2;
-      *reinterpret_cast<u32x2*>(lds + y.bh0 + o) = hi;
-      *reinterpret_cast<u32x2*>(lds + y.bl0 + o) = lo;
+      *reinterpret_cast<u32x4*>(lds + y.bh0 + o) = hi;
+      *reinterpret_cast<u32x4*>(lds + y.bl0 + o) = lo;
     }
   }
 }
@@ -414,7 +427,7 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
   const long long n_blocks = a.n_vox / kC2;
   const int n_chunks = kr < n_blocks ? (int)((n_blocks - kr + a.n_krange - 1) / a.n_krange) : 0;
   const long long kstep = a.n_krange;
-  float4 pf[kPf];
+  Seg pf[kPf];
   if (n_chunks > 0) {
     ws_load(F, a.n_s, kr, wr, pf, tid);
     ws_store(smem_raw, y, wr.s_n, 0, pf, tid);
@@ -535,7 +548,7 @@ hipError_t prepare_contract_bf16x3() {
 
 hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t st) {
   // every staged row fits the per-thread loads; ranges are whole voxel blocks
-  if (a.max_s * (kC2 / 4) > kWsThreads * kPf || a.max_s > a.n_s || a.max_s > kMaxSplitShells ||
+  if (a.max_s * (kC2 / 8) > kWsThreads * kPf || a.max_s > a.n_s || a.max_s > kMaxSplitShells ||
       a.n_vox % kC2 != 0)
     return hipErrorInvalidValue;
   const size_t lds = bf16x3_lds_bytes(a.max_s);

@@ -370,6 +370,60 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
     }
   }
   mt.n_wg = (int32_t)(slots.size() / kSlotsPerWg);
+  // LDS bank groups: a 16-byte fragment read serves 8 lanes per cycle, and the
+  // fp32 rows (stride 36 dwords) of shells s and s' share a bank group when
+  // s = s' (mod 8).  Within each row block, order the pairs so that every
+  // aligned group of 8 lanes reads F_i rows, and F_j rows, that are equal or
+  // distinct mod 8 (a local search over swaps; the order of rows is free).
+  for (int w = 0; w < mt.n_wg; ++w) {
+    int s_lo = 1 << 30;
+    for (int sidx = 0; sidx < kSlotsPerWg; ++sidx) {
+      const Slot& sl = slots[(size_t)w * kSlotsPerWg + sidx];
+      for (int t = 0; t < sl.sc.n; ++t) s_lo = std::min(s_lo, sl.sc.col0[t] - 1);
+      for (int q = 0; q < sl.sc.n_rb; ++q)
+        for (int r = 0; r < kRows; ++r)
+          if (sl.rb[q].j[r]) s_lo = std::min(s_lo, std::min<int>(sl.rb[q].i[r], sl.rb[q].j[r]) - 1);
+    }
+    for (int sidx = 0; sidx < kSlotsPerWg; ++sidx) {
+      Slot& sl = slots[(size_t)w * kSlotsPerWg + sidx];
+      for (int q = 0; q < sl.sc.n_rb; ++q) {
+        RowBlock& rb = sl.rb[q];
+        // a padding row (j = 0) reads the zero row: give it a key no real row has
+        auto key = [&](int r, bool first) { return rb.j[r] ? (first ? rb.i[r] : rb.j[r]) - 1 - s_lo : -1; };
+        auto clash = [&](int a, int b) {
+          int c = 0;
+          for (int f = 0; f < 2; ++f) {
+            const int ka = key(a, f == 0), kb = key(b, f == 0);
+            if (ka != kb && ka >= 0 && kb >= 0 && (ka & 7) == (kb & 7)) ++c;
+          }
+          return c;
+        };
+        auto group_cost = [&](int g) {
+          int c = 0;
+          for (int a = 8 * g; a < 8 * g + 8; ++a)
+            for (int b = a + 1; b < 8 * g + 8; ++b) c += clash(a, b);
+          return c;
+        };
+        for (int pass = 0; pass < 4; ++pass) {
+          bool improved = false;
+          for (int a = 0; a < kRows; ++a)
+            for (int b = a + 1; b < kRows; ++b) {
+              if (a / 8 == b / 8) continue;
+              const int before = group_cost(a / 8) + group_cost(b / 8);
+              std::swap(rb.i[a], rb.i[b]);
+              std::swap(rb.j[a], rb.j[b]);
+              if (group_cost(a / 8) + group_cost(b / 8) < before) {
+                improved = true;
+              } else {
+                std::swap(rb.i[a], rb.i[b]);
+                std::swap(rb.j[a], rb.j[b]);
+              }
+            }
+          if (!improved) break;
+        }
+      }
+    }
+  }
   mt.rows.assign((size_t)mt.n_wg * kRbPerWg, RowBlock{});
   mt.cols.assign((size_t)mt.n_wg * kSlotsPerWg, SlotCols{});
   mt.wg_rows.assign(mt.n_wg, WgRows{});
