@@ -40,6 +40,9 @@ WORKLOADS = {
                                 sel=dict(tri_mode=2, k1_shells=list(range(2, 41, 2)), n_mu=20, n_t=20)),
     "ng32_10shells_grid": dict(field="ng32", n_g=32, box_l=300.0, dk=1.0, n_shells=10, rsd_beta=0.0,
                                sel=dict(tri_mode=2, k1_shells=list(range(5, 11)), n_mu=10, n_t=10)),
+    # differentiation workload: 30 shells, a1 in {29, 30} (494 triangles); --grad times bispec_grad too
+    "ng256_30shells_grad": dict(field="ng256_grad", n_g=256, box_l=1000.0, dk=1.0, n_shells=30, rsd_beta=0.0,
+                                sel=dict(tri_mode=1, k1_shells=[29, 30])),
 }
 
 # batched form: 64 heterogeneous realisations (N_g in {96, 128, 160}, 16-48 shells)
@@ -113,6 +116,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ng512_100shells_rsd", choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
     ap.add_argument("--autotune", action="store_true", help="plan with FLAG_AUTOTUNE")
+    ap.add_argument("--grad", action="store_true", help="also time the vector-Jacobian product (bispec_grad)")
     ap.add_argument("--precision", default="splitbf16", choices=["splitbf16", "fp32"])
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,7 +146,8 @@ def main():
     prec = P.PREC_SPLITBF16 if args.precision == "splitbf16" else P.PREC_FP32
     t0 = time.perf_counter()
     plan = P.Plan(w["n_g"], w["box_l"], w["dk"], w["n_shells"], rsd_beta=w["rsd_beta"], precision=prec,
-                  flags=P.FLAG_STAGE_TIMING | (P.FLAG_AUTOTUNE if args.autotune else 0), **w["sel"])
+                  flags=P.FLAG_STAGE_TIMING | (P.FLAG_AUTOTUNE if args.autotune else 0) |
+                  (P.FLAG_GRAD if args.grad else 0), **w["sel"])
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     print("plan ready (%.1f s), %d triangles" % (plan_s, plan.n_tri), file=sys.stderr, flush=True)
@@ -219,6 +224,27 @@ def main():
         result["fp32_contraction_ms"] = float(np.mean(f32))
         result["speedup_vs_fp32_contraction"] = float(np.mean(f32)) / contract_ms
         result["splitbf16_vs_fp32_norm_diff"] = float(np.linalg.norm(b_host - b32) / np.linalg.norm(b32))
+    if args.grad:
+        # vector-Jacobian product of the last run: adjoint field build, pruned
+        # forward transforms of every adjoint shell, one inverse at n_g
+        g_b = torch.ones(plan.n_tri, dtype=torch.float64, device=dev)
+        plan.grad(g_b)
+        torch.cuda.synchronize()
+        gms = []
+        for _ in range(max(2, min(5, args.steps))):
+            start.record(stream)
+            plan.grad(g_b)
+            stop.record(stream)
+            stop.synchronize()
+            gms.append(start.elapsed_time(stop))
+        result["grad_ms"] = float(np.mean(gms))
+        # algorithmic bytes of the adjoint: read every shell field once (G build,
+        # 4 G^3 B per shell), write G (4 G^3 per shell), the forward transforms
+        # read G (4 G^3 per shell), the last inverse writes gdelta (4 N^3)
+        g3 = float(plan.n_est) ** 3
+        gbytes = 12.0 * g3 * w["n_shells"] + 4.0 * float(n) ** 3
+        result["grad_hbm"] = {"algorithmic_bytes": gbytes, "achieved_GBs": gbytes / (result["grad_ms"] * 1e-3) / 1e9,
+                              "peak_GBs": PEAK_HBM_GBS}
     if args.copy_calibration:
         result["copy_calibration"] = copy_calibration(torch, dev)
     if not args.no_cpu_baseline:
