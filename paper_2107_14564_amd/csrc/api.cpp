@@ -105,11 +105,18 @@ struct Sizes {
 
 struct bispec_plan_s;
 
-// A batch: heterogeneous plans run back to back on one shared workspace,
-// optionally replayed from a captured HIP graph.
+struct ManyLane;
+
+// A batch: heterogeneous plans on up to kMaxLanes concurrent lanes (a private
+// stream and a run workspace each; a lane runs its members back to back),
+// forked from and joined back into the caller's stream, optionally replayed
+// from a captured HIP graph.
 struct bispec_many_s {
   std::vector<bispec_plan_s*> plans;
   std::vector<int64_t> d_off, b_off;   // prefix sums of N_g^3 and n_tri
+  std::vector<int> lane_of;            // member -> lane
+  std::vector<ManyLane*> lanes;
+  hipEvent_t ev_fork = nullptr;
   hipStream_t cap_stream = nullptr;    // private stream the graph is captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -333,6 +340,24 @@ struct Workspace {
   DevBuf spec, F, a1, a2, partial, partial_mfma;
 };
 
+}  // namespace
+
+struct ManyLane {
+  Workspace ws;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_join = nullptr;
+  ~ManyLane() {
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+constexpr int kMaxLanes = 4;
+
+
+
 hipError_t take_workspace(bispec_plan_s& p, const Workspace* shared, bool fields) {
   if (shared) {
     if (!fields) {
@@ -383,6 +408,22 @@ int run_core(bispec_plan_s& p, const float* delta, double* B, hipStream_t s, boo
   }
   if (timing) HIP_TRY(hipEventRecord(p.ev[4], s));
   p.ran = true;
+  return BISPEC_OK;
+}
+
+// Enqueue every member of the batch on its lane, forked from and joined back
+// into stream s (which may be capturing).
+int many_enqueue(bispec_many_s& m, const float* delta, double* B, hipStream_t s) {
+  HIP_TRY(hipEventRecord(m.ev_fork, s));
+  for (ManyLane* l : m.lanes) HIP_TRY(hipStreamWaitEvent(l->stream, m.ev_fork, 0));
+  for (size_t i = 0; i < m.plans.size(); ++i) {
+    int st = run_core(*m.plans[i], delta + m.d_off[i], B + m.b_off[i], m.lanes[m.lane_of[i]]->stream, false);
+    if (st) return st;
+  }
+  for (ManyLane* l : m.lanes) {
+    HIP_TRY(hipEventRecord(l->ev_join, l->stream));
+    HIP_TRY(hipStreamWaitEvent(s, l->ev_join, 0));
+  }
   return BISPEC_OK;
 }
 
@@ -692,6 +733,7 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
   m->d_off.assign(1, 0);
   m->b_off.assign(1, 0);
   size_t ws_spec = 0, ws_F = 0, ws_a1 = 0, ws_a2 = 0, ws_pv = 0, ws_pm = 0, tables = 0, temp = 0;
+  std::vector<double> cost(n);
   for (int32_t i = 0; i < n; ++i) {
     if (cfgs[i].flags & BISPEC_FLAG_GRAD) return fail(set_err(BISPEC_EINVAL, "batched plans do not take BISPEC_FLAG_GRAD"));
     bispec_plan_s* p = new (std::nothrow) bispec_plan_s();
@@ -711,26 +753,58 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
     temp = std::max(temp, z.plan_temp());
     m->d_off.push_back(m->d_off.back() + (int64_t)p->geo.n_g * p->geo.n_g * p->geo.n_g);
     m->b_off.push_back(m->b_off.back() + (int64_t)z.n_tri);
+    // run-time estimate: shell fields written plus contraction tiles, per voxel
+    cost[i] = (double)z.n_vox * (p->geo.n_s + 8.0 * (double)p->mfma.tiles);
   }
-  int st = check_memory(ws_spec + ws_F + ws_a1 + ws_a2 + ws_pv + ws_pm + tables + temp);
+  // lanes: as many concurrent workspaces as members, kMaxLanes and memory allow
+  const size_t lane_bytes = ws_spec + ws_F + ws_a1 + ws_a2 + ws_pv + ws_pm;
+  size_t free_b = 0, total_b = 0;
+  {
+    hipError_t e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("hipMemGetInfo: ") + hipGetErrorString(e)));
+  }
+  const size_t cap = max_bytes_env();
+  const size_t avail = cap ? std::min(free_b, cap) : free_b;
+  int n_lanes = std::min<int>(kMaxLanes, n);
+  while (n_lanes > 1 && (size_t)n_lanes * lane_bytes + tables + temp > avail) --n_lanes;
+  int st = check_memory((size_t)n_lanes * lane_bytes + tables + temp);
   if (st) return fail(st);
-  Workspace ws;
-  hipError_t e = dalloc(ws.spec, ws_spec);
-  if (e == hipSuccess) e = dalloc(ws.F, ws_F);
-  if (e == hipSuccess) e = dalloc(ws.a1, ws_a1);
-  if (e == hipSuccess) e = dalloc(ws.a2, ws_a2);
-  if (e == hipSuccess) e = dalloc(ws.partial, ws_pv);
-  if (e == hipSuccess) e = dalloc(ws.partial_mfma, ws_pm);
-  if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("workspace: ") + hipGetErrorString(e)));
-  // the plans take views; ownership of the shared buffers passes to plan 0
-  for (bispec_plan_s* p : m->plans) {
-    st = plan_build(*p, s, &ws);
+  // members to lanes: longest first onto the least-loaded lane
+  {
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<double> load(n_lanes, 0.0);
+    m->lane_of.assign(n, 0);
+    for (int i : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      m->lane_of[i] = k;
+      load[k] += cost[i];
+    }
+  }
+  for (int k = 0; k < n_lanes; ++k) {
+    ManyLane* l = new (std::nothrow) ManyLane();
+    if (!l) return fail(set_err(BISPEC_ENOMEM, "host allocation failed"));
+    m->lanes.push_back(l);
+    hipError_t e = dalloc(l->ws.spec, ws_spec);
+    if (e == hipSuccess) e = dalloc(l->ws.F, ws_F);
+    if (e == hipSuccess) e = dalloc(l->ws.a1, ws_a1);
+    if (e == hipSuccess) e = dalloc(l->ws.a2, ws_a2);
+    if (e == hipSuccess) e = dalloc(l->ws.partial, ws_pv);
+    if (e == hipSuccess) e = dalloc(l->ws.partial_mfma, ws_pm);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&l->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("batch lane: ") + hipGetErrorString(e)));
+  }
+  {
+    hipError_t e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e)));
+  }
+  // the plans take views of their lane's workspace (owned by the lane)
+  for (int32_t i = 0; i < n; ++i) {
+    st = plan_build(*m->plans[i], s, &m->lanes[m->lane_of[i]]->ws);
     if (st) return fail(st);
   }
-  for (DevBuf* b : {&m->plans[0]->spec, &m->plans[0]->F, &m->plans[0]->a1, &m->plans[0]->a2,
-                    &m->plans[0]->partial, &m->plans[0]->partial_mfma})
-    b->owned = true;
-  for (DevBuf* b : {&ws.spec, &ws.F, &ws.a1, &ws.a2, &ws.partial, &ws.partial_mfma}) b->owned = false;
   *out = m;
   return BISPEC_OK;
 }
@@ -754,13 +828,7 @@ int bispec_many_plan(bispec_many_t m, int32_t i, bispec_plan_t* plan) {
 int bispec_run_many(bispec_many_t m, const float* delta, double* B, int32_t use_graph, void* hip_stream) {
   if (!m || !delta || !B) return set_err(BISPEC_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)hip_stream;
-  if (!use_graph) {
-    for (size_t i = 0; i < m->plans.size(); ++i) {
-      int st = run_core(*m->plans[i], delta + m->d_off[i], B + m->b_off[i], s, false);
-      if (st) return st;
-    }
-    return BISPEC_OK;
-  }
+  if (!use_graph) return many_enqueue(*m, delta, B, s);
   if (!m->exec || m->g_delta != delta || m->g_B != B) {
     if (m->exec) (void)hipGraphExecDestroy(m->exec);
     if (m->graph) (void)hipGraphDestroy(m->graph);
@@ -768,9 +836,7 @@ int bispec_run_many(bispec_many_t m, const float* delta, double* B, int32_t use_
     m->graph = nullptr;
     if (!m->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
-    int st = BISPEC_OK;
-    for (size_t i = 0; i < m->plans.size() && st == BISPEC_OK; ++i)
-      st = run_core(*m->plans[i], delta + m->d_off[i], B + m->b_off[i], m->cap_stream, false);
+    const int st = many_enqueue(*m, delta, B, m->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(m->cap_stream, &g);
     if (st) {
@@ -798,6 +864,7 @@ bispec_many_s::~bispec_many_s() {
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  // plan 0 owns the shared workspace: release the other plans first
-  for (size_t i = plans.size(); i-- > 0;) delete plans[i];
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  for (bispec_plan_s* p : plans) delete p;  // views of the lanes' workspaces
+  for (ManyLane* l : lanes) delete l;
 }
