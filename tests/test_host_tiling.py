@@ -1,0 +1,41 @@
+"""The contraction's work decomposition on the host: a small C++ checker is
+built against geometry.cpp and run for several configurations (every selected
+triangle maps to exactly one accumulator element that decodes back to it, its
+shells are staged by its work group, and the vector-kernel tiles cover it)."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2107_14564_amd", "csrc")
+
+CASES = [
+    ("512", "100", "1500", "1", "0"),        # all closable triangles of 100 shells
+    ("256", "40", "1000", "2", "2", *[str(k) for k in range(2, 41, 2)]),   # (mu, t) grid selection
+    ("256", "30", "1000", "1", "1", "29", "30"),
+    ("32", "10", "300", "1", "0"),
+    ("64", "20", "100", "1", "0"),
+    ("48", "9", "200", "1.5", "0"),
+    ("16", "1", "100", "1", "0"),            # one shell, one triangle
+    ("1024", "128", "1000", "1", "1", "128", "100", "64"),   # the split-bf16 maximum of 128 shells
+]
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("tiling") / "tiling_check")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                    os.path.join(ROOT, "tests", "host", "tiling_check.cpp"), os.path.join(CSRC, "geometry.cpp"),
+                    "-o", exe], check=True, capture_output=True)
+    return exe
+
+
+@pytest.mark.parametrize("args", CASES, ids=lambda a: "_".join(a[:5]))
+def test_tiling_covers_every_triangle_once(checker, args):
+    r = subprocess.run([checker, *args], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout + r.stderr
