@@ -330,14 +330,16 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
       slots.push_back(sl);
     }
   }
-  // Cost-balanced placement: per chunk a slot costs about 3 NT n_rb MFMAs
-  // (32 cycles each) and n_rb row-operand formations (~64 VALU instructions of
-  // 4 cycles).  Work groups get equal totals (longest first, to the least
-  // loaded group), so the groups that share a voxel range advance together
-  // and re-read each chunk from L2; within a group, waves q, q + 4, q + 8 share
-  // SIMD q % 4, which gets equal totals the same way.
+  // Cost-balanced placement: per 32 voxels a slot costs 6 NT n_rb MFMAs (32
+  // cycles each) and 2 n_rb row-operand formations (~32 VALU instructions of
+  // 4 cycles each); the matrix unit and the vector ALU of a SIMD do not
+  // overlap measurably, so a SIMD's time is the sum over its waves.  Work
+  // groups get equal totals (longest first, to the least loaded group), so
+  // the groups that share a voxel range advance together and re-read each
+  // chunk from L2; within a group, waves q, q + 4, q + 8 share SIMD q % 4,
+  // which gets equal totals the same way.
   {
-    auto cost = [](const Slot& sl) { return sl.sc.n_rb * (96 * sl.sc.n + 256); };
+    auto cost = [](const Slot& sl) { return sl.sc.n_rb * (192 * sl.sc.n + 256); };
     std::vector<Slot> real;
     for (const Slot& sl : slots)
       if (sl.sc.n) real.push_back(sl);
