@@ -208,9 +208,9 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
     for (int k : kTuneRanges)
       if (k <= std::max(8LL, (s.n_vox / (64 * 4)) / 8 * 8)) p.n_krange_mfma_cap = std::max(p.n_krange_mfma_cap, k);
   s.partial_vec = (size_t)p.n_krange_vec * s.n_tri * sizeof(double);
-  s.partial_mfma = (size_t)p.n_krange_mfma_cap * p.mfma.n_wg * kTilesPerWg * 1024 * sizeof(double);
+  s.partial_mfma = (size_t)p.n_krange_mfma_cap * p.mfma.n_wg * kTilesPerWg * kMTileElems * sizeof(double);
   s.tables = (size_t)p.geo.n_s * p.geo.n_s * p.geo.n_s * sizeof(int32_t) + p.tiles.rows.size() * sizeof(RowBlock) +
-             p.tiles.tiles.size() * sizeof(Tile) + p.mfma.rows.size() * sizeof(RowBlock) +
+             p.tiles.tiles.size() * sizeof(Tile) + p.mfma.rows.size() * sizeof(MRowBlock) +
              p.mfma.cols.size() * sizeof(SlotCols) + p.mfma.wg_rows.size() * sizeof(WgRows) +
              p.mfma.slot_of.size() * sizeof(int32_t) +
              p.pass32.x_tiles.size() * sizeof(int4) + (size_t)s.n_tri * 8 +
@@ -221,7 +221,7 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
 
 WsArgs ws_args(bispec_plan_s& p) {
   WsArgs a;
-  a.rows = p.mfma_rows.as<RowBlock>();
+  a.rows = p.mfma_rows.as<MRowBlock>();
   a.cols = p.mfma_cols.as<SlotCols>();
   a.wg_rows = p.mfma_wgrows.as<WgRows>();
   a.n_wg = p.mfma.n_wg;
@@ -403,7 +403,7 @@ int run_core(bispec_plan_s& p, const float* delta, double* B, hipStream_t s, boo
     HIP_TRY(launch_contract_bf16x3(p.F.as<float>(), ws_args(p), s));
     if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
     HIP_TRY(launch_reduce(p.partial_mfma.as<double>(), p.n_krange_mfma,
-                          (long long)p.mfma.n_wg * kTilesPerWg * 1024, p.sz.n_tri, p.mfma_slot.as<int32_t>(),
+                          (long long)p.mfma.n_wg * kTilesPerWg * kMTileElems, p.sz.n_tri, p.mfma_slot.as<int32_t>(),
                           p.norm.as<double>(), B, s));
   }
   if (timing) HIP_TRY(hipEventRecord(p.ev[4], s));
@@ -754,7 +754,7 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
     m->d_off.push_back(m->d_off.back() + (int64_t)p->geo.n_g * p->geo.n_g * p->geo.n_g);
     m->b_off.push_back(m->b_off.back() + (int64_t)z.n_tri);
     // run-time estimate: shell fields written plus contraction tiles, per voxel
-    cost[i] = (double)z.n_vox * (p->geo.n_s + 8.0 * (double)p->mfma.tiles);
+    cost[i] = (double)z.n_vox * (p->geo.n_s + 2.0 * (double)p->mfma.tiles);
   }
   // lanes: as many concurrent workspaces as members, kMaxLanes and memory allow
   const size_t lane_bytes = ws_spec + ws_F + ws_a1 + ws_a2 + ws_pv + ws_pm;

@@ -3,7 +3,8 @@
 // the numerator of eq. bsfin (data shells) and of eq. Ntri2 (unit shells).
 //
 // Work decomposition (geometry.h): rows are shell pairs (i, j), columns single
-// shells l, a tile is 32 pairs x 32 consecutive shells, a task <= 8 tiles.
+// shells l; a tile is 32 pairs x 32 consecutive shells in the vector kernels
+// (a task <= 8 tiles), 16 x 16 in the split-bf16 MFMA kernel.
 // Every kernel walks a voxel range [k_lo, k_hi) in chunks staged in LDS (all
 // shells of the chunk, so one HBM read serves every tile of the work group),
 // keeps its tiles' sums in registers over the whole range and writes one
@@ -147,61 +148,76 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 // Split-BF16 MFMA form (step c).  Each fp32 operand v is written as
 // v = hi + lo with hi = bf16(v), lo = bf16(v - hi); a product of two operands
 // is accumulated as hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-16 relative, is
-// dropped) by three v_mfma_f32_32x32x16_bf16 per 16 voxels.
+// dropped) by three v_mfma_f32_16x16x32_bf16 per 32 voxels.
 //
 // GEMM view per voxel range: C[(i,j), l] = sum_x A[(i,j), x] B[x, l] with the
 // row operand A = F_i F_j (a pair product) and the column operand B = F_l.
-// Work group = kSlotsPerWg = 12 wavefronts (three per SIMD, which the
-// register budget of <= 170 VGPRs allows); wave w owns slot w: NT <=
-// kMaxColTiles column tiles of 32 shells and n_rb <= slot_row_blocks(NT) row
-// blocks of 32 pairs that meet them (at most kSlotTiles = 4 accumulator tiles
-// of 16 fp32 per lane; NT is uniform over the wave, so the code path is too).
+// Tiles are 16 pairs x 16 shells: finer than 32 x 32 tiles, they waste less
+// of the triangle wedge l <= j, j + l >= i (68 % of the tile entries are
+// triangles at 100 shells, against 54 % for 32 x 32).
+// Work group = kSlotsPerWg = 12 wavefronts (three per SIMD); wave w owns slot
+// w: NT <= kMaxColTiles column tiles and n_rb <= slot_row_blocks(NT) row
+// blocks that meet them (at most kSlotTiles = 16 accumulator tiles of 4 fp32
+// per lane; NT is uniform over the wave, so the code path is too).  The
+// matrix unit and the vector ALU of a SIMD do not overlap measurably on this
+// chip, so the slot placement balances MFMA plus VALU cycles per SIMD.
 //
 // Voxel range kr is the set of voxel blocks kr + m n_krange (interleaved over
 // the box).  Per chunk of 32 voxels (one block) each thread loads one 8-voxel
 // segment (2 float4) of the work group's shell rows s_lo .. s_lo + s_n - 1
 // (contiguous in the voxel-blocked layout) one chunk ahead, and stores it into
 // the other LDS buffer as fp32 (row operands) and as bf16 hi/lo (column
-// operands, split once per value) with four 16-byte stores.  Per 16 voxels a lane then
+// operands, split once per value) with four 16-byte stores.  Per chunk a lane
+// (row or column lane % 16, voxel octet lane / 16) then
 //   - reads its column fragments (hi, lo: 8 voxels of shell l each),
 //   - for each row block reads 8 voxels of F_i and F_j, forms the 8 pair
-//     products in registers, splits them (the MFMA row-operand layout: lane
-//     = row + 32 * (voxel octet)), and issues 3 MFMAs per column tile.
+//     products in registers, splits them (the MFMA row-operand layout), and
+//     issues 3 MFMAs per column tile.
 // There is no LDS round trip for the products and one barrier per chunk.
 //
-// LDS (two buffers): F32 [2][s + 1][36] fp32, Bh/Bl [2][s + 1][40] bf16 with
-// s = the largest s_n and the extra row all zero (padding rows and columns
-// point there).  Row strides of 36 and 20 dwords keep 8 consecutive rows on
-// distinct banks for the 16-byte fragment reads; LDS addresses are 32-bit
-// byte offsets from the shared array.
+// LDS (two buffers): F32 [2][4][s + 1][8] fp32 (one plane per voxel octet),
+// Bh/Bl [2][s + 1][48] bf16, with s = the largest s_n and the extra row all
+// zero (padding rows and columns point there).  LDS has 128 banks of 4 bytes
+// and serves a 16-byte read for lanes 0-31, then 32-63, i.e. 16 rows at two
+// voxel octets: the bf16 row stride of 24 dwords puts 16 consecutive column
+// shells at both octets on distinct banks, and the octet planes (16 bytes
+// longer than their rows, an odd number of bank groups) put distinct pair
+// shells of a block on distinct banks unless they differ by a multiple of 16.
+// LDS addresses are 32-bit byte offsets from the shared array.
 // Accumulation: fp32 MFMA chains of kFlushChunks chunks, added in float64 into
 // partial[range][tile][element] (tile-major, coalesced); the reduction maps
-// elements to triangles.
+// elements to triangles.  Output element (v, lane) of a tile is row
+// 4 (lane / 16) + v, column lane % 16.
 // ============================================================================
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kC2 = 32;              // voxels per chunk (= one voxel block)
-constexpr int kF32S = kC2 + 4;       // fp32 row stride (floats): 36 dwords
-constexpr int kBS = kC2 + 8;         // bf16 row stride (elements): 20 dwords
+constexpr int kOct = kC2 / 8;        // voxel octets per chunk (one per 16 lanes of a wave)
+constexpr int kBS = kC2 + 16;        // bf16 row stride (elements): 24 dwords
 constexpr int kFlushChunks = 256;    // 8192 voxels per float32 accumulation chain
 constexpr int kWsThreads = kSlotsPerWg * 64;
 constexpr int kPf = 1;               // 8-voxel row segments per thread per chunk (2 float4 each)
 static_assert(kC2 == kVoxBlock, "chunks are voxel blocks");
 
 // LDS byte layout for ns1 rows per buffer (row ns1 - 1 is all zero):
-//   F32 [2][ns1][kF32S] fp32 | Bh [2][ns1][kBS] bf16 | Bl [2][ns1][kBS] bf16
+//   F32 [2][kOct][ns1 * 8 + 4] fp32 | Bh [2][ns1][kBS] bf16 | Bl [2][ns1][kBS] bf16
+// The fp32 rows are split by voxel octet: plane k holds octet k of every row
+// (32 bytes per row) and the planes are 16 bytes longer than their rows, an
+// odd number of 16-byte bank groups.
 struct WsLayout {
-  unsigned f_buf, b_buf;   // bytes per buffer of F32 and of one bf16 plane
+  unsigned f_plane, f_buf; // bytes per fp32 octet plane and per fp32 buffer
+  unsigned b_buf;          // bytes per buffer of one bf16 plane
   unsigned bh0, bl0;       // byte offsets of the Bh and Bl regions
 };
 
 __device__ __forceinline__ WsLayout ws_layout(int ns1) {
   WsLayout y;
-  y.f_buf = (unsigned)ns1 * kF32S * 4;
+  y.f_plane = (unsigned)ns1 * 32 + 16;
+  y.f_buf = kOct * y.f_plane;
   y.b_buf = (unsigned)ns1 * kBS * 2;
   y.bh0 = 2 * y.f_buf;
   y.bl0 = y.bh0 + 2 * y.b_buf;
@@ -226,21 +242,29 @@ __device__ __forceinline__ unsigned bf16_pack(float v0, float v1) {
   return __builtin_bit_cast(unsigned, h);
 }
 
-// voxel block blk: rows s_lo .. s_lo + s_n - 1; thread t stages the 8 voxels
-// 8 (t % 4) .. + 7 of row t / 4 (two float4, contiguous in global memory)
+// voxel block blk: rows s_lo .. s_lo + s_n - 1, each 4 octets of 8 voxels
+// (two float4, contiguous in global memory).  Staging index idx takes row
+// 16 (idx / 64) + idx % 16, octet (idx / 16) % 4: lanes 0-31 of a wave, which
+// LDS serves together, store 16 rows at two octets, on distinct banks in
+// both layouts; a wave still covers 16 whole rows (2 KiB contiguous) of
+// global memory.
 struct Seg {
   float4 a, b;
 };
+
+__device__ __forceinline__ int seg_row(int idx) { return 16 * (idx >> 6) + (idx & 15); }
+__device__ __forceinline__ int seg_oct(int idx) { return (idx >> 4) & 3; }
 
 __device__ __forceinline__ void ws_load(const float* __restrict__ F, int n_s, long long blk, const WgRows& wr,
                                         Seg (&pf)[kPf], int tid) {
   const float4* base = reinterpret_cast<const float4*>(F + blk * (long long)n_s * kC2 + (long long)wr.s_lo * kC2);
 #pragma unroll
   for (int u = 0; u < kPf; ++u) {
-    const int idx = tid + u * kWsThreads;
-    if (idx < wr.s_n * (kC2 / 8)) {
-      pf[u].a = base[2 * idx];
-      pf[u].b = base[2 * idx + 1];
+    const int idx = tid + u * kWsThreads, r = seg_row(idx);
+    if (r < wr.s_n) {
+      const int o = 2 * (kOct * r + seg_oct(idx));
+      pf[u].a = base[o];
+      pf[u].b = base[o + 1];
     }
   }
 }
@@ -252,9 +276,9 @@ __device__ __forceinline__ void ws_store(unsigned char* lds, const WsLayout& y, 
 #pragma unroll
   for (int u = 0; u < kPf; ++u) {
     const int idx = tid + u * kWsThreads;
-    if (idx < s_n * (kC2 / 8)) {
-      const unsigned r = idx >> 2, x = 8 * (idx & 3);
-      unsigned char* f = lds + buf * y.f_buf + (r * kF32S + x) * 4;
+    if (seg_row(idx) < s_n) {
+      const unsigned r = seg_row(idx), k = seg_oct(idx), x = 8 * k;
+      unsigned char* f = lds + buf * y.f_buf + k * y.f_plane + r * 32;
       *reinterpret_cast<float4*>(f) = pf[u].a;
       *reinterpret_cast<float4*>(f + 16) = pf[u].b;
       const float v[8] = {pf[u].a.x, pf[u].a.y, pf[u].a.z, pf[u].a.w, pf[u].b.x, pf[u].b.y, pf[u].b.z, pf[u].b.w};
@@ -304,47 +328,75 @@ __device__ __forceinline__ void ws_row_split(const RowIn& r, bf16x8& ahi, bf16x8
   alo = __builtin_bit_cast(bf16x8, l);
 }
 
-// 32 voxels of buffer buf for a slot with NT column tiles and n_rb row blocks
-// (n_rb <= slot_row_blocks(NT); accumulator tile q * NT + t).  fo[q], go[q]:
-// byte offsets of this lane's F_i and F_j rows (+ its voxel octet) in buffer 0;
-// co[t]: of its column row in plane Bh buffer 0.
-// FULL: n_rb == slot_row_blocks(NT), no per-block branch (lets the compiler
-// overlap one block's LDS reads and products with the previous block's MFMAs).
+// 3 MFMAs per tile: hi*hi + hi*lo + lo*hi (16 x 16 output, K = 32 voxels)
+__device__ __forceinline__ void ws_mfma3(const bf16x8& ahi, const bf16x8& alo, const bf16x8& bhi, const bf16x8& blo,
+                                         f32x4& c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, c, 0, 0, 0);
+}
+
+// One chunk (32 voxels of buffer buf) for a slot with NT column tiles and
+// n_rb row blocks (accumulator tile q * NT + t).  fo[q], go[q]: byte offsets
+// of this lane's F_i and F_j rows (+ its voxel octet) in buffer 0; co[t]: of
+// its column row in plane Bh, buffer 0.
+// NT <= 4 ("tall"): the column fragments of all tiles stay in registers and
+// the row blocks stream through, the reads of block q + 1 issued before block
+// q is split and multiplied.  NT >= 5 ("wide", n_rb <= 3): the row operands
+// of all blocks stay in registers and the column fragments stream through.
+// FULL: n_rb == slot_row_blocks(NT), no per-block branch.
 template <int NT, bool FULL>
 __device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLayout& y, int buf, int n_rb,
-                                           const unsigned (&fo)[kMaxRbPerSlot], const unsigned (&go)[kMaxRbPerSlot],
-                                           const unsigned (&co)[kMaxColTiles], f32x16 (&acc)[kSlotTiles]) {
+                                           const unsigned* fo, const unsigned* go, const unsigned* co, f32x4* acc) {
   constexpr int RBM = slot_row_blocks(NT);
   const unsigned fb = buf * y.f_buf, bb = y.bh0 + buf * y.b_buf, lb = y.bl0 + buf * y.b_buf;
   const int nq = FULL ? RBM : n_rb;
-#pragma unroll
-  for (int ks = 0; ks < kC2 / 16; ++ks) {
+  if constexpr (NT <= 4) {
     bf16x8 bhi[NT], blo[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      bhi[t] = *reinterpret_cast<const bf16x8*>(lds + bb + co[t] + ks * 32);
-      blo[t] = *reinterpret_cast<const bf16x8*>(lds + lb + co[t] + ks * 32);
+      bhi[t] = *reinterpret_cast<const bf16x8*>(lds + bb + co[t]);
+      blo[t] = *reinterpret_cast<const bf16x8*>(lds + lb + co[t]);
     }
-    // software pipeline over the row blocks: reads of block q + 1 are in
-    // flight while block q is split and multiplied
-    RowIn cur = ws_row_read(lds, fb + fo[0] + ks * 64, fb + go[0] + ks * 64);
+    RowIn cur = ws_row_read(lds, fb + fo[0], fb + go[0]);
+    // (guards instead of early exits keep every index a constant, so the
+    // accumulators stay in registers; the partial NT = 4 form reads each
+    // block when it needs it, the prefetch registers would not fit)
+    constexpr bool kPrefetch = FULL || NT < 4;
 #pragma unroll
     for (int q = 0; q < RBM; ++q) {
-      if (!FULL && q >= nq) break;  // uniform over the wave
-      RowIn nxt = cur;
-      if (q + 1 < RBM && (FULL || q + 1 < nq))
-        nxt = ws_row_read(lds, fb + fo[q + 1] + ks * 64, fb + go[q + 1] + ks * 64);
-      __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this block's work
-      bf16x8 ahi, alo;
-      ws_row_split(cur, ahi, alo);
+      if (FULL || q < nq) {  // uniform over the wave
+        if (!kPrefetch && q > 0) cur = ws_row_read(lds, fb + fo[q], fb + go[q]);
+        RowIn nxt = cur;
+        if (kPrefetch && q + 1 < RBM && (FULL || q + 1 < nq))
+          nxt = ws_row_read(lds, fb + fo[q + 1], fb + go[q + 1]);
+        __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this block's work
+        bf16x8 ahi, alo;
+        ws_row_split(cur, ahi, alo);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        f32x16& c = acc[q * NT + t];
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[t], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[t], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[t], c, 0, 0, 0);
+        for (int t = 0; t < NT; ++t) ws_mfma3(ahi, alo, bhi[t], blo[t], acc[q * NT + t]);
+        cur = nxt;
       }
-      cur = nxt;
+    }
+  } else {
+    bf16x8 ahi[RBM], alo[RBM];
+#pragma unroll
+    for (int q = 0; q < RBM; ++q)
+      if (FULL || q < nq) ws_row_split(ws_row_read(lds, fb + fo[q], fb + go[q]), ahi[q], alo[q]);
+    bf16x8 bhi = *reinterpret_cast<const bf16x8*>(lds + bb + co[0]);
+    bf16x8 blo = *reinterpret_cast<const bf16x8*>(lds + lb + co[0]);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      bf16x8 nhi = bhi, nlo = blo;
+      if (t + 1 < NT) {
+        nhi = *reinterpret_cast<const bf16x8*>(lds + bb + co[t + 1]);
+        nlo = *reinterpret_cast<const bf16x8*>(lds + lb + co[t + 1]);
+      }
+#pragma unroll
+      for (int q = 0; q < RBM; ++q)
+        if (FULL || q < nq) ws_mfma3(ahi[q], alo[q], bhi, blo, acc[q * NT + t]);
+      bhi = nhi;
+      blo = nlo;
     }
   }
 }
@@ -353,28 +405,93 @@ __device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLay
 // The base pointer passes through an empty asm so the element addresses are
 // formed here, not hoisted out of the main loop into live registers.
 template <int NT>
-__device__ __forceinline__ void ws_flush(double* out, bool first, int n_rb, f32x16 (&acc)[kSlotTiles]) {
+__device__ __forceinline__ void ws_flush(double* out, bool first, int n_rb, f32x4* acc) {
   constexpr int RBM = slot_row_blocks(NT);
   asm volatile("" : "+v"(out));
 #pragma unroll
   for (int k = 0; k < RBM * NT; ++k) {
-    if (k >= n_rb * NT) break;
-    double* o = out + (long long)k * 1024;
+    if (k < n_rb * NT) {
+      double* o = out + (long long)k * kMTileElems;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      o[v * 64] = first ? (double)acc[k][v] : o[v * 64] + (double)acc[k][v];
-      acc[k][v] = 0.f;
+      for (int v = 0; v < 4; ++v) {
+        o[v * 64] = first ? (double)acc[k][v] : o[v * 64] + (double)acc[k][v];
+        acc[k][v] = 0.f;
+      }
     }
   }
 }
 
+// The whole voxel range of one wave.  Range kr takes the voxel blocks kr,
+// kr + n_krange, kr + 2 n_krange, ...: every float32 chain samples the whole
+// box, so its partial sums cancel like the total instead of growing with a
+// slab's coherent sum.
 template <int NT, bool FULL>
-__device__ __forceinline__ void ws_step(const unsigned char* lds, const WsLayout& y, int buf, bool flush,
-                                        bool first, double* out, int n_rb, const unsigned (&fo)[kMaxRbPerSlot],
-                                        const unsigned (&go)[kMaxRbPerSlot], const unsigned (&co)[kMaxColTiles],
-                                        f32x16 (&acc)[kSlotTiles]) {
-  ws_compute<NT, FULL>(lds, y, buf, n_rb, fo, go, co, acc);
-  if (flush) ws_flush<NT>(out, first, n_rb, acc);
+__device__ __forceinline__ void ws_run(const float* __restrict__ F, const WsArgs& a, unsigned char* lds,
+                                       const WsLayout& y, const WgRows& wr, int kr, int n_chunks, int tid,
+                                       const SlotCols& sc, const MRowBlock* rows, double* out) {
+  constexpr int RBM = slot_row_blocks(NT);
+  const int lane = tid & 63, kg = lane >> 4, zr = wr.s_n, n_rb = sc.n_rb;
+  // this lane's rows (pair shells) and columns as byte offsets in buffer 0
+  unsigned fo[RBM], go[RBM], co[NT];
+#pragma unroll
+  for (int q = 0; q < RBM; ++q) {
+    const MRowBlock& rb = rows[q < n_rb ? q : 0];
+    const int i = rb.i[lane & 15], j = rb.j[lane & 15];
+    const int ri = j > 0 ? i - 1 - wr.s_lo : zr, rj = j > 0 ? j - 1 - wr.s_lo : zr;
+    fo[q] = kg * y.f_plane + ri * 32;
+    go[q] = kg * y.f_plane + rj * 32;
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int l = sc.col0[t] + (lane & 15);  // 1-based column shell
+    const int rc = (l >= 1 && l <= a.n_s) ? l - 1 - wr.s_lo : zr;
+    co[t] = (unsigned)(rc * kBS + kg * 8) * 2;
+  }
+  f32x4 acc[RBM * NT];
+#pragma unroll
+  for (int k = 0; k < RBM * NT; ++k)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[k][v] = 0.f;
+  const long long kstep = a.n_krange;
+  Seg pf[kPf];
+  if (n_chunks > 0) {
+    ws_load(F, a.n_s, kr, wr, pf, tid);
+    ws_store(lds, y, wr.s_n, 0, pf, tid);
+  }
+  __syncthreads();
+  bool first = true;
+  int chain = 0;
+  for (int c = 0; c < n_chunks; ++c) {
+    const bool more = c + 1 < n_chunks;
+    if (more) ws_load(F, a.n_s, kr + (c + 1) * kstep, wr, pf, tid);
+    ws_compute<NT, FULL>(lds, y, c & 1, n_rb, fo, go, co, acc);
+    if (++chain == kFlushChunks || !more) {
+      ws_flush<NT>(out, first, n_rb, acc);
+      chain = 0;
+      first = false;
+    }
+    if (more) ws_store(lds, y, wr.s_n, (c & 1) ^ 1, pf, tid);
+    __syncthreads();
+  }
+}
+
+// A wave without a slot only stages its share of every chunk.
+__device__ __forceinline__ void ws_idle(const float* __restrict__ F, const WsArgs& a, unsigned char* lds,
+                                        const WsLayout& y, const WgRows& wr, int kr, int n_chunks, int tid) {
+  Seg pf[kPf];
+  if (n_chunks > 0) {
+    ws_load(F, a.n_s, kr, wr, pf, tid);
+    ws_store(lds, y, wr.s_n, 0, pf, tid);
+  }
+  __syncthreads();
+  for (int c = 0; c < n_chunks; ++c) {
+    // buffer (c + 1) & 1 was last read in chunk c - 1, before the previous barrier
+    if (c + 1 < n_chunks) {
+      ws_load(F, a.n_s, kr + (c + 1) * (long long)a.n_krange, wr, pf, tid);
+      ws_store(lds, y, wr.s_n, (c + 1) & 1, pf, tid);
+    }
+    __syncthreads();
+  }
 }
 
 __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __restrict__ F, WsArgs a) {
@@ -383,84 +500,40 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
   const WsLayout y = ws_layout(ns1);
   int wg, kr;
   xcd_map(a.n_wg, wg, kr);
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, kg = lane >> 5;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const WgRows wr = a.wg_rows[wg];
   const int zr = wr.s_n;  // the zero row
   // zero row of each buffer, never overwritten afterwards
-  for (int e = tid; e < 2 * kF32S; e += kWsThreads)
-    *reinterpret_cast<float*>(smem_raw + (e / kF32S) * y.f_buf + (zr * kF32S + e % kF32S) * 4) = 0.f;
+  for (int e = tid; e < 2 * kOct * 8; e += kWsThreads)
+    *reinterpret_cast<float*>(smem_raw + (e / 8) * y.f_plane + zr * 32 + (e % 8) * 4) = 0.f;
   for (int e = tid; e < 2 * kBS; e += kWsThreads) {
     const unsigned o = (e / kBS) * y.b_buf + (zr * kBS + e % kBS) * 2;
     *reinterpret_cast<__bf16*>(smem_raw + y.bh0 + o) = (__bf16)0.f;
     *reinterpret_cast<__bf16*>(smem_raw + y.bl0 + o) = (__bf16)0.f;
   }
-  // this lane's rows (pair shells) and columns as byte offsets in buffer 0
   const SlotCols sc = a.cols[wg * kSlotsPerWg + w];
-  unsigned fo[kMaxRbPerSlot], go[kMaxRbPerSlot], co[kMaxColTiles];
-#pragma unroll
-  for (int q = 0; q < kMaxRbPerSlot; ++q) {
-    const RowBlock& rb = a.rows[wg * kRbPerWg + w * kMaxRbPerSlot + q];
-    const int i = rb.i[lane & 31], j = rb.j[lane & 31];
-    const int ri = j > 0 ? i - 1 - wr.s_lo : zr, rj = j > 0 ? j - 1 - wr.s_lo : zr;
-    fo[q] = (unsigned)(ri * kF32S + kg * 8) * 4;
-    go[q] = (unsigned)(rj * kF32S + kg * 8) * 4;
-  }
-#pragma unroll
-  for (int t = 0; t < kMaxColTiles; ++t) {
-    const int l = t < sc.n ? sc.col0[t] + (lane & 31) : 0;  // 1-based column shell
-    const int rc = (l >= 1 && l <= a.n_s) ? l - 1 - wr.s_lo : zr;
-    co[t] = (unsigned)(rc * kBS + kg * 8) * 2;
-  }
-  f32x16 acc[kSlotTiles];
-#pragma unroll
-  for (int k = 0; k < kSlotTiles; ++k)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[k][v] = 0.f;
+  const MRowBlock* rows = a.rows + wg * kRbPerWg + w * kMaxRbPerSlot;
   // partial[kr][tile][element] with tile = wg*kTilesPerWg + w*kSlotTiles + (q*NT + t)
   double* out = a.partial +
-                ((long long)kr * a.n_wg * kTilesPerWg + (long long)wg * kTilesPerWg + (long long)w * kSlotTiles) * 1024 +
+                ((long long)kr * a.n_wg * kTilesPerWg + (long long)wg * kTilesPerWg + (long long)w * kSlotTiles) *
+                    kMTileElems +
                 lane;
-  const int n_rb = sc.n_rb;
-  // Range kr takes the voxel blocks kr, kr + n_krange, kr + 2 n_krange, ...:
-  // every float32 chain samples the whole box, so its partial sums cancel like
-  // the total instead of growing with a slab's coherent sum.
   const long long n_blocks = a.n_vox / kC2;
   const int n_chunks = kr < n_blocks ? (int)((n_blocks - kr + a.n_krange - 1) / a.n_krange) : 0;
-  const long long kstep = a.n_krange;
-  Seg pf[kPf];
-  if (n_chunks > 0) {
-    ws_load(F, a.n_s, kr, wr, pf, tid);
-    ws_store(smem_raw, y, wr.s_n, 0, pf, tid);
-  }
-  __syncthreads();
-  const int variant = sc.n * 2 + (n_rb == slot_row_blocks(sc.n) ? 1 : 0);  // uniform per wave
-  bool first = true;
-  int chain = 0;
-  for (int c = 0; c < n_chunks; ++c) {
-    const bool more = c + 1 < n_chunks;
-    if (more) ws_load(F, a.n_s, kr + (c + 1) * kstep, wr, pf, tid);
-    const bool flush = ++chain == kFlushChunks || !more;
-    const int buf = c & 1;
-    switch (variant) {
-      case 9: ws_step<4, true>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
-      case 8: ws_step<4, false>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
-      case 7: ws_step<3, true>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
-      case 6: ws_step<3, false>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
-      case 5: ws_step<2, true>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
-      case 4: ws_step<2, false>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
-      case 3: ws_step<1, true>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
-      case 2: ws_step<1, false>(smem_raw, y, buf, flush, first, out, n_rb, fo, go, co, acc); break;
-      default: break;
-    }
-    if (flush) {
-      chain = 0;
-      first = false;
-    }
-    if (more) ws_store(smem_raw, y, wr.s_n, buf ^ 1, pf, tid);
-    __syncthreads();
-  }
   if (n_chunks == 0)  // empty range: its partials are zero
-    for (int e = 0; e < kSlotTiles * 16; ++e) out[(long long)(e >> 4) * 1024 + (e & 15) * 64] = 0.0;
+    for (int e = 0; e < kSlotTiles * 4; ++e) out[(long long)(e >> 2) * kMTileElems + (e & 3) * 64] = 0.0;
+  // every wave passes the same barriers whatever its variant (uniform per wave)
+  const bool full = sc.n_rb == slot_row_blocks(sc.n);
+  switch (sc.n) {
+#define WS_CASE(N)                                                                              \
+  case N:                                                                                       \
+    if (full) ws_run<N, true>(F, a, smem_raw, y, wr, kr, n_chunks, tid, sc, rows, out);         \
+    else ws_run<N, false>(F, a, smem_raw, y, wr, kr, n_chunks, tid, sc, rows, out);             \
+    break;
+    WS_CASE(1) WS_CASE(2) WS_CASE(3) WS_CASE(4) WS_CASE(5) WS_CASE(6) WS_CASE(7) WS_CASE(8)
+#undef WS_CASE
+    default: ws_idle(F, a, smem_raw, y, wr, kr, n_chunks, tid); break;
+  }
 }
 
 // ============================================================================
@@ -533,7 +606,7 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
 }  // namespace
 
 size_t bf16x3_lds_bytes(int max_s) {
-  return 2 * (size_t)(max_s + 1) * kF32S * sizeof(float) + 4 * (size_t)(max_s + 1) * kBS * sizeof(__bf16);
+  return 2 * (size_t)kOct * ((size_t)(max_s + 1) * 32 + 16) + 4 * (size_t)(max_s + 1) * kBS * sizeof(__bf16);
 }
 
 hipError_t launch_contract_fp32(const float* F, const ContractArgs& a, hipStream_t st) { return launch_vec<float>(F, a, st); }

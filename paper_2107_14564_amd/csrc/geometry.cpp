@@ -278,25 +278,25 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
   for (auto& kv : pl) {
     std::map<int, std::pair<int, int>> per_window;  // window -> (min l, max l)
     for (int l : kv.second) {
-      const int wdw = ((l - 1) / kCols) / kMaxColTiles;
+      const int wdw = ((l - 1) / kMCols) / kMaxColTiles;
       auto it = per_window.find(wdw);
       if (it == per_window.end()) per_window[wdw] = {l, l};
       else it->second = {std::min(it->second.first, l), std::max(it->second.second, l)};
     }
     for (auto& pw : per_window) {
       const int lo = pw.second.first, hi = pw.second.second;
-      groups[{pw.first, (lo - 1) / kCols, (hi - 1) / kCols}].push_back({kv.first.first, kv.first.second, lo, hi});
+      groups[{pw.first, (lo - 1) / kMCols, (hi - 1) / kMCols}].push_back({kv.first.first, kv.first.second, lo, hi});
     }
   }
   std::map<std::pair<int, int>, std::vector<P>> spans;  // (first, last column block) -> pairs
   for (auto& g : groups) spans[{std::get<1>(g.first), std::get<2>(g.first)}] = g.second;
   // slots: row blocks of one span + the non-empty column tiles they meet
-  struct Slot { RowBlock rb[kMaxRbPerSlot]; SlotCols sc; };
-  auto col_used = [&](const RowBlock& rb, int col0) {
-    for (int r = 0; r < kRows; ++r) {
+  struct Slot { MRowBlock rb[kMaxRbPerSlot]; SlotCols sc; };
+  auto col_used = [&](const MRowBlock& rb, int col0) {
+    for (int r = 0; r < kMRows; ++r) {
       if (!rb.j[r]) continue;
       for (int l : pl[{rb.i[r], rb.j[r]}])
-        if (l >= col0 && l < col0 + kCols) return true;
+        if (l >= col0 && l < col0 + kMCols) return true;
     }
     return false;
   };
@@ -309,10 +309,10 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
       if (a.i != b.i) return a.i < b.i;
       return a.j < b.j;
     });
-    std::vector<RowBlock> rbs((ps.size() + kRows - 1) / kRows, RowBlock{});
+    std::vector<MRowBlock> rbs((ps.size() + kMRows - 1) / kMRows, MRowBlock{});
     for (size_t k = 0; k < ps.size(); ++k) {
-      rbs[k / kRows].i[k % kRows] = (int16_t)ps[k].i;
-      rbs[k / kRows].j[k % kRows] = (int16_t)ps[k].j;
+      rbs[k / kMRows].i[k % kMRows] = (int16_t)ps[k].i;
+      rbs[k / kMRows].j[k % kMRows] = (int16_t)ps[k].j;
     }
     const int n_blocks = sp.first.second - sp.first.first + 1;
     const int per_slot = slot_row_blocks(n_blocks);
@@ -322,7 +322,7 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
       for (int q = 0; q < sl.sc.n_rb; ++q) sl.rb[q] = rbs[b0 + q];
       sl.sc.n = 0;
       for (int c = sp.first.first; c <= sp.first.second; ++c) {
-        const int col0 = c * kCols + 1;
+        const int col0 = c * kMCols + 1;
         bool any = false;
         for (int q = 0; q < sl.sc.n_rb && !any; ++q) any = col_used(sl.rb[q], col0);
         if (any) sl.sc.col0[sl.sc.n++] = col0;
@@ -330,103 +330,126 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
       slots.push_back(sl);
     }
   }
-  // Cost-balanced placement: per 32 voxels a slot costs 6 NT n_rb MFMAs (32
-  // cycles each) and 2 n_rb row-operand formations (~32 VALU instructions of
-  // 4 cycles each); the matrix unit and the vector ALU of a SIMD do not
-  // overlap measurably, so a SIMD's time is the sum over its waves.  Work
-  // groups get equal totals (longest first, to the least loaded group), so
-  // the groups that share a voxel range advance together and re-read each
-  // chunk from L2; within a group, waves q, q + 4, q + 8 share SIMD q % 4,
-  // which gets equal totals the same way.
+  // LDS bank conflicts of the row reads: LDS has 128 banks of 4 bytes and
+  // serves a 16-byte read for lanes 0-31, then 32-63; lanes 0-31 hold the 16
+  // pairs of one row block at two voxel octets.  The kernel keeps each octet
+  // of the fp32 rows in a plane of its own (32 bytes per row, planes an odd
+  // number of 16-byte bank groups apart), so two distinct shells of a block
+  // collide when they differ by a multiple of 16; equal shells share the
+  // read.  Within each slot, swap pairs between its row blocks while that
+  // lowers the summed worst collision count of the blocks (the slot's column
+  // tiles do not change).
   {
-    auto cost = [](const Slot& sl) { return sl.sc.n_rb * (192 * sl.sc.n + 256); };
+    auto block_cost = [](const MRowBlock& rb) {
+      int c = 0;
+      for (int f = 0; f < 2; ++f) {
+        int mult[16] = {0};
+        int seen[kMRows], n_seen = 0;
+        for (int r = 0; r < kMRows; ++r) {
+          if (!rb.j[r]) continue;
+          const int sh = f ? rb.j[r] : rb.i[r];
+          bool dup = false;
+          for (int k = 0; k < n_seen; ++k) dup = dup || seen[k] == sh;
+          if (dup) continue;
+          seen[n_seen++] = sh;
+          ++mult[sh & 15];
+        }
+        int m = 0;
+        for (int b = 0; b < 16; ++b) m = std::max(m, mult[b]);
+        c += std::max(0, m - 1);
+      }
+      return c;
+    };
+    for (Slot& sl : slots) {
+      if (sl.sc.n_rb < 2) continue;
+      for (int pass = 0; pass < 6; ++pass) {
+        bool improved = false;
+        for (int q0 = 0; q0 < sl.sc.n_rb; ++q0)
+          for (int q1 = q0 + 1; q1 < sl.sc.n_rb; ++q1)
+            for (int a = 0; a < kMRows; ++a)
+              for (int b = 0; b < kMRows; ++b) {
+                MRowBlock &x = sl.rb[q0], &y = sl.rb[q1];
+                const int before = block_cost(x) + block_cost(y);
+                std::swap(x.i[a], y.i[b]);
+                std::swap(x.j[a], y.j[b]);
+                if (block_cost(x) + block_cost(y) < before) {
+                  improved = true;
+                } else {
+                  std::swap(x.i[a], y.i[b]);
+                  std::swap(x.j[a], y.j[b]);
+                }
+              }
+        if (!improved) break;
+      }
+    }
+  }
+  // Cost-balanced placement: per 32 voxels a slot costs 3 NT n_rb MFMAs (16
+  // cycles each) and n_rb row-operand formations (~32 VALU instructions of 4
+  // cycles each); the matrix unit and the vector ALU of a SIMD do not overlap
+  // measurably, so a SIMD's time is the sum over its waves, and a work
+  // group's time that of its busiest SIMD.  Waves q, q + 4, q + 8 of a group
+  // share SIMD q % 4: slots go longest first to the least-loaded (group,
+  // SIMD) bin with room, which evens out the SIMDs of every group and so the
+  // groups too (groups that share a voxel range then advance together and
+  // re-read each chunk from L2).
+  {
+    auto cost = [](const Slot& sl) { return sl.sc.n_rb * (48 * sl.sc.n + 128); };
     std::vector<Slot> real;
     for (const Slot& sl : slots)
       if (sl.sc.n) real.push_back(sl);
     std::stable_sort(real.begin(), real.end(), [&](const Slot& a, const Slot& b) { return cost(a) > cost(b); });
-    const int n_wg = std::max<int>(1, (int)((real.size() + kSlotsPerWg - 1) / kSlotsPerWg));
-    std::vector<std::vector<Slot>> wg(n_wg);
-    std::vector<long> load(n_wg, 0);
-    for (const Slot& sl : real) {
-      int best = -1;
-      for (int w = 0; w < n_wg; ++w)
-        if ((int)wg[w].size() < kSlotsPerWg && (best < 0 || load[w] < load[best])) best = w;
-      wg[best].push_back(sl);
-      load[best] += cost(sl);
-    }
     constexpr int kSimds = 4, kPerSimd = kSlotsPerWg / kSimds;
     static_assert(kSlotsPerWg % kSimds == 0, "slots per work group must fill the SIMDs evenly");
+    const int n_wg = std::max<int>(1, (int)((real.size() + kSlotsPerWg - 1) / kSlotsPerWg));
+    const int n_bins = n_wg * kSimds;
+    std::vector<std::vector<Slot>> bin(n_bins);
+    std::vector<long> load(n_bins, 0);
+    for (const Slot& sl : real) {
+      int best = -1;
+      for (int b = 0; b < n_bins; ++b)
+        if ((int)bin[b].size() < kPerSimd && (best < 0 || load[b] < load[best])) best = b;
+      bin[best].push_back(sl);
+      load[best] += cost(sl);
+    }
+    // then swaps of slots between bins while they lower the sum over groups
+    // of the busiest SIMD's load (the time the groups of one range take)
+    for (auto& bv : bin) bv.resize(kPerSimd, Slot{});  // idle slots pad the bins
+    auto bin_load = [&](int b) {
+      long t = 0;
+      for (const Slot& sl : bin[b]) t += sl.sc.n ? cost(sl) : 0;
+      return t;
+    };
+    auto wg_time = [&](int w) {
+      long m = 0;
+      for (int q = 0; q < kSimds; ++q) m = std::max(m, bin_load(w * kSimds + q));
+      return m;
+    };
+    for (int pass = 0; pass < 8; ++pass) {
+      bool improved = false;
+      for (int b0 = 0; b0 < n_bins; ++b0)
+        for (int b1 = b0 + 1; b1 < n_bins; ++b1)
+          for (int k0 = 0; k0 < kPerSimd; ++k0)
+            for (int k1 = 0; k1 < kPerSimd; ++k1) {
+              const int w0 = b0 / kSimds, w1 = b1 / kSimds;
+              const long before = wg_time(w0) + (w1 != w0 ? wg_time(w1) : 0);
+              std::swap(bin[b0][k0], bin[b1][k1]);
+              const long after = wg_time(w0) + (w1 != w0 ? wg_time(w1) : 0);
+              if (after < before) improved = true;
+              else std::swap(bin[b0][k0], bin[b1][k1]);
+            }
+      if (!improved) break;
+    }
     slots.assign((size_t)n_wg * kSlotsPerWg, Slot{});
-    for (int w = 0; w < n_wg; ++w) {
-      std::vector<std::vector<Slot>> simd(kSimds);
-      std::vector<long> sl_load(kSimds, 0);
-      for (const Slot& sl : wg[w]) {  // already in decreasing cost
-        int best = -1;
-        for (int q = 0; q < kSimds; ++q)
-          if ((int)simd[q].size() < kPerSimd && (best < 0 || sl_load[q] < sl_load[best])) best = q;
-        simd[best].push_back(sl);
-        sl_load[best] += cost(sl);
-      }
-      for (int q = 0; q < kSimds; ++q)
-        for (size_t k = 0; k < simd[q].size(); ++k) slots[(size_t)w * kSlotsPerWg + q + kSimds * k] = simd[q][k];
+    for (int b = 0; b < n_bins; ++b) {
+      const int w = b / kSimds, q = b % kSimds;
+      for (size_t k = 0; k < bin[b].size(); ++k) slots[(size_t)w * kSlotsPerWg + q + kSimds * k] = bin[b][k];
     }
   }
   mt.n_wg = (int32_t)(slots.size() / kSlotsPerWg);
-  // LDS bank groups: a 16-byte fragment read serves 8 lanes per cycle, and the
-  // fp32 rows (stride 36 dwords) of shells s and s' share a bank group when
-  // s = s' (mod 8).  Within each row block, order the pairs so that every
-  // aligned group of 8 lanes reads F_i rows, and F_j rows, that are equal or
-  // distinct mod 8 (a local search over swaps; the order of rows is free).
-  for (int w = 0; w < mt.n_wg; ++w) {
-    int s_lo = 1 << 30;
-    for (int sidx = 0; sidx < kSlotsPerWg; ++sidx) {
-      const Slot& sl = slots[(size_t)w * kSlotsPerWg + sidx];
-      for (int t = 0; t < sl.sc.n; ++t) s_lo = std::min(s_lo, sl.sc.col0[t] - 1);
-      for (int q = 0; q < sl.sc.n_rb; ++q)
-        for (int r = 0; r < kRows; ++r)
-          if (sl.rb[q].j[r]) s_lo = std::min(s_lo, std::min<int>(sl.rb[q].i[r], sl.rb[q].j[r]) - 1);
-    }
-    for (int sidx = 0; sidx < kSlotsPerWg; ++sidx) {
-      Slot& sl = slots[(size_t)w * kSlotsPerWg + sidx];
-      for (int q = 0; q < sl.sc.n_rb; ++q) {
-        RowBlock& rb = sl.rb[q];
-        // a padding row (j = 0) reads the zero row: give it a key no real row has
-        auto key = [&](int r, bool first) { return rb.j[r] ? (first ? rb.i[r] : rb.j[r]) - 1 - s_lo : -1; };
-        auto clash = [&](int a, int b) {
-          int c = 0;
-          for (int f = 0; f < 2; ++f) {
-            const int ka = key(a, f == 0), kb = key(b, f == 0);
-            if (ka != kb && ka >= 0 && kb >= 0 && (ka & 7) == (kb & 7)) ++c;
-          }
-          return c;
-        };
-        auto group_cost = [&](int g) {
-          int c = 0;
-          for (int a = 8 * g; a < 8 * g + 8; ++a)
-            for (int b = a + 1; b < 8 * g + 8; ++b) c += clash(a, b);
-          return c;
-        };
-        for (int pass = 0; pass < 4; ++pass) {
-          bool improved = false;
-          for (int a = 0; a < kRows; ++a)
-            for (int b = a + 1; b < kRows; ++b) {
-              if (a / 8 == b / 8) continue;
-              const int before = group_cost(a / 8) + group_cost(b / 8);
-              std::swap(rb.i[a], rb.i[b]);
-              std::swap(rb.j[a], rb.j[b]);
-              if (group_cost(a / 8) + group_cost(b / 8) < before) {
-                improved = true;
-              } else {
-                std::swap(rb.i[a], rb.i[b]);
-                std::swap(rb.j[a], rb.j[b]);
-              }
-            }
-          if (!improved) break;
-        }
-      }
-    }
-  }
-  mt.rows.assign((size_t)mt.n_wg * kRbPerWg, RowBlock{});
+  // LDS bank conflicts of the row reads: the 16 lanes served together are
+  // the 16 rows of one block (same voxel octet), so the order of the pairs
+  // within a block does not matter and is left as built.
+  mt.rows.assign((size_t)mt.n_wg * kRbPerWg, MRowBlock{});
   mt.cols.assign((size_t)mt.n_wg * kSlotsPerWg, SlotCols{});
   mt.wg_rows.assign(mt.n_wg, WgRows{});
   mt.tiles = 0;
@@ -440,23 +463,23 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
       mt.tiles += (int64_t)sl.sc.n * sl.sc.n_rb;
       for (int t = 0; t < sl.sc.n; ++t) {
         s_lo = std::min(s_lo, sl.sc.col0[t] - 1);
-        s_hi = std::max(s_hi, std::min(sl.sc.col0[t] - 1 + kCols - 1, n_shells - 1));
+        s_hi = std::max(s_hi, std::min(sl.sc.col0[t] - 1 + kMCols - 1, n_shells - 1));
       }
       for (int q = 0; q < sl.sc.n_rb; ++q) {
         mt.rows[(size_t)w * kRbPerWg + sidx * kMaxRbPerSlot + q] = sl.rb[q];
-        for (int r = 0; r < kRows; ++r) {
+        for (int r = 0; r < kMRows; ++r) {
           const int i = sl.rb[q].i[r], j = sl.rb[q].j[r];
           if (!j) continue;
           s_lo = std::min(s_lo, std::min(i, j) - 1);
           s_hi = std::max(s_hi, std::max(i, j) - 1);
-          // element of the 32x32 accumulator: row r, column c -> (v, lane)
+          // element of the 16x16 accumulator: row r, column c -> (v, lane)
           for (int t = 0; t < sl.sc.n; ++t)
             for (int l : pl[{i, j}]) {
               const int c = l - sl.sc.col0[t];
-              if (c < 0 || c >= kCols) continue;
-              const int lane = c + 32 * ((r >> 2) & 1), v = 4 * (r >> 3) + (r & 3);
+              if (c < 0 || c >= kMCols) continue;
+              const int lane = c + 16 * (r >> 2), v = r & 3;
               const int tile = w * kTilesPerWg + sidx * kSlotTiles + q * sl.sc.n + t;
-              where[{i, j, l}] = tile * (kRows * kCols) + v * 64 + lane;
+              where[{i, j, l}] = tile * kMTileElems + v * 64 + lane;
             }
         }
       }

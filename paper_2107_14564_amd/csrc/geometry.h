@@ -80,22 +80,32 @@ struct TilePlan {
 
 void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp);
 
-// Tiling of the MFMA kernel.  Column blocks (aligned blocks of kCols shells)
-// are taken in windows of kMaxColTiles blocks; within a window, pairs are
-// grouped by the span of column blocks their selected l fall in, so each row
-// block of kRows pairs meets the column blocks of one span as whole rectangles
-// of at most kMaxColTiles tiles.  A slot (one wavefront of the kernel) holds
-// n_rb row blocks of one span and the n <= kMaxColTiles column tiles they
-// meet, with n_rb <= slot_row_blocks(n) so that n * n_rb <= kSlotTiles
-// accumulator tiles; a work group has kSlotsPerWg slots.  A pair whose l reach
-// several windows appears once per window (never for <= 128 shells).
-constexpr int kMaxColTiles = 4;
-constexpr int kSlotTiles = 4;
-constexpr int kMaxRbPerSlot = 4;
+// Tiling of the MFMA kernel (v_mfma_f32_16x16x32_bf16): a row block holds
+// kMRows shell pairs, a column tile kMCols consecutive shells.  Column tiles
+// are taken in windows of kMaxColTiles; within a window, pairs are grouped by
+// the span of column tiles their selected l fall in, so each row block meets
+// the column tiles of one span as whole rectangles.  A slot (one wavefront of
+// the kernel) holds n_rb row blocks of one span and the n <= kMaxColTiles
+// column tiles they meet, with n_rb <= slot_row_blocks(n) so that
+// n * n_rb <= kSlotTiles accumulator tiles; a work group has kSlotsPerWg
+// slots.  A pair whose l reach several windows appears once per window
+// (never for <= 128 shells).
+constexpr int kMRows = 16;
+constexpr int kMCols = 16;
+constexpr int kMTileElems = kMRows * kMCols;  // partial sums per tile
+struct MRowBlock {
+  int16_t i[kMRows];
+  int16_t j[kMRows];   // 0 = padding row
+};
+constexpr int kMaxColTiles = 8;
+constexpr int kSlotTiles = 16;
+constexpr int kMaxRbPerSlot = 8;
 constexpr int kSlotsPerWg = 12;
 constexpr int kRbPerWg = kMaxRbPerSlot * kSlotsPerWg;
 constexpr int kTilesPerWg = kSlotTiles * kSlotsPerWg;
-inline constexpr int slot_row_blocks(int n_cols) { return n_cols <= 1 ? 4 : n_cols == 2 ? 2 : 1; }
+inline constexpr int slot_row_blocks(int n_cols) {
+  return n_cols <= 2 ? 8 : n_cols == 3 ? 5 : n_cols == 4 ? 4 : n_cols == 5 ? 3 : 2;
+}
 
 struct SlotCols {
   int32_t n;                      // column tiles of this slot (0 = idle slot)
@@ -108,10 +118,10 @@ struct WgRows {
 };
 
 struct MfmaTiling {
-  std::vector<RowBlock> rows;     // kRbPerWg per work group (kMaxRbPerSlot per slot)
+  std::vector<MRowBlock> rows;    // kRbPerWg per work group (kMaxRbPerSlot per slot)
   std::vector<SlotCols> cols;     // kSlotsPerWg per work group
   std::vector<WgRows> wg_rows;    // one per work group
-  // triangle t sits in partial slot slot_of[t] = tile * kRows*kCols + element
+  // triangle t sits in partial slot slot_of[t] = tile * kMTileElems + element
   std::vector<int32_t> slot_of;
   int32_t n_wg = 0;
   int64_t tiles = 0;              // non-empty (row block, column tile) products

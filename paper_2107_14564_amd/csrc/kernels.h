@@ -110,7 +110,7 @@ hipError_t launch_contract_fp32(const float* F, const ContractArgs& a, hipStream
 hipError_t launch_contract_fp64(const double* F, const ContractArgs& a, hipStream_t st);
 
 struct WsArgs {
-  const RowBlock* rows = nullptr;     // device [n_wg * kRbPerWg]
+  const MRowBlock* rows = nullptr;    // device [n_wg * kRbPerWg]
   const SlotCols* cols = nullptr;     // device [n_wg * kSlotsPerWg]
   const WgRows* wg_rows = nullptr;    // device [n_wg]
   int n_wg = 0;                       // work groups per voxel range
@@ -118,7 +118,7 @@ struct WsArgs {
   int max_s = 0;                      // most shells staged by one work group (LDS sizing)
   long long n_vox = 0;
   int n_krange = 0;                   // multiple of 8
-  double* partial = nullptr;          // device [n_krange][n_wg * kTilesPerWg][1024]
+  double* partial = nullptr;          // device [n_krange][n_wg * kTilesPerWg][kMTileElems]
 };
 constexpr int kMaxSplitShells = 128;   // most shells of a split-bf16 plan
 size_t bf16x3_lds_bytes(int max_s);

@@ -39,13 +39,13 @@ int main(int argc, char** argv) {
   }
   MfmaTiling mt;
   build_mfma_tiles(s, c.n_shells, mt);
-  const long long cap = (long long)mt.n_wg * kTilesPerWg * kRows * kCols;
+  const long long cap = (long long)mt.n_wg * kTilesPerWg * kMTileElems;
   std::set<int> seen;
   for (size_t t = 0; t < s.tri.size(); ++t) {
     const int v = mt.slot_of[t];
     if (v < 0 || v >= cap) { std::printf("triangle %zu: element %d out of range\n", t, v); return 1; }
     if (!seen.insert(v).second) { std::printf("triangle %zu: element %d used twice\n", t, v); return 1; }
-    const int tile = v / (kRows * kCols), el = v % (kRows * kCols);
+    const int tile = v / kMTileElems, el = v % kMTileElems;
     const int w = tile / kTilesPerWg, loc = tile % kTilesPerWg;
     const int slot = loc / kSlotTiles, k = loc % kSlotTiles;
     const SlotCols& sc = mt.cols[(size_t)w * kSlotsPerWg + slot];
@@ -55,10 +55,10 @@ int main(int argc, char** argv) {
     }
     const int q = k / sc.n, ct = k % sc.n;
     if (q >= sc.n_rb) { std::printf("triangle %zu: row block beyond the slot\n", t); return 1; }
-    // accumulator element -> (row, column) of the 32 x 32 tile (MFMA output layout)
+    // accumulator element -> (row, column) of the 16 x 16 tile (MFMA output layout)
     const int lane = el % 64, vv = el / 64;
-    const int row = 8 * (vv >> 2) + 4 * (lane >> 5) + (vv & 3), col = lane % 32;
-    const RowBlock& rb = mt.rows[(size_t)w * kRbPerWg + slot * kMaxRbPerSlot + q];
+    const int row = 4 * (lane >> 4) + vv, col = lane % 16;
+    const MRowBlock& rb = mt.rows[(size_t)w * kRbPerWg + slot * kMaxRbPerSlot + q];
     const int i = rb.i[row], j = rb.j[row], l = sc.col0[ct] + col;
     if (i != s.tri[t].a1 || j != s.tri[t].a2 || l != s.tri[t].a3) {
       std::printf("triangle %zu (%d,%d,%d) decodes to (%d,%d,%d)\n", t, s.tri[t].a1, s.tri[t].a2, s.tri[t].a3, i, j, l);
