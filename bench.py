@@ -36,6 +36,9 @@ if ROOT not in sys.path:
 WORKLOADS = {
     # name: (synth workload key, n_g, box_l, dk, n_shells, rsd_beta, selection)
     "ng512_100shells_rsd": dict(field="ng512", n_g=512, box_l=1500.0, dk=1.0, n_shells=100, rsd_beta=0.5, sel={}),
+    # the same estimator on a 1024^3 grid (the paper's largest timing point is N_g = 1000)
+    "ng1024_100shells_rsd": dict(field="ng1024", n_g=1024, box_l=3000.0, dk=1.0, n_shells=100, rsd_beta=0.5,
+                                 sel={}),
     "ng256_40shells_grid": dict(field="ng256", n_g=256, box_l=1000.0, dk=2.0, n_shells=40, rsd_beta=0.0,
                                 sel=dict(tri_mode=2, k1_shells=list(range(2, 41, 2)), n_mu=20, n_t=20)),
     "ng32_10shells_grid": dict(field="ng32", n_g=32, box_l=300.0, dk=1.0, n_shells=10, rsd_beta=0.0,
@@ -98,7 +101,7 @@ def cpu_baseline(delta32, w: dict, budget_s: float = 30.0) -> dict:
     from oracle import fbe, geometry
     cores = os.cpu_count() or 1
     d64 = delta32.astype(np.float64)
-    s_shells = 4
+    s_shells = 4 if delta32.shape[0] <= 512 else 2   # 8 (4) float64 fields of N^3 on the host
     tri = geometry.all_triangles(s_shells)
     t0 = time.perf_counter()
     fbe.estimate(d64, w["box_l"], w["dk"], tri, rsd_beta=w["rsd_beta"])

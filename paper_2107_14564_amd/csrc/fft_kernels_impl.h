@@ -33,6 +33,18 @@ namespace fftk {
 constexpr int kThrAxis = 512;  // threads of a strided-pass block
 constexpr int kThrZ = 256;     // threads of a contiguous-pass block
 
+// Shell of block b from the per-shell block prefix sums off[0 .. n_shells]:
+// every thread tests a few entries (one coalesced read instead of a chain of
+// dependent reads in a binary search).  Uniform over the block; contains a
+// barrier, so every thread of the block must call it.
+__device__ __forceinline__ int block_shell(const long long* __restrict__ off, int n_shells, long long b) {
+  __shared__ int s_shell;
+  for (int t = threadIdx.x; t < n_shells; t += blockDim.x)
+    if (off[t] <= b && b < off[t + 1]) s_shell = t;
+  __syncthreads();
+  return s_shell;
+}
+
 __device__ __forceinline__ int freq(int q, int n) { return q < n / 2 ? q : q - n; }
 
 // the N-entry twiddle table into LDS (twiddle reads of every pass then stay on chip)
@@ -170,12 +182,7 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1
   __shared__ V2<T> buf[N * TW];
   __shared__ V2<T> twl[N];
   const long long b = blockIdx.x;
-  int lo = 0, hi = n_shells;  // sn with tile_off[sn] <= b < tile_off[sn+1]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (tile_off[mid] <= b) lo = mid; else hi = mid;
-  }
-  const int sn = lo;
+  const int sn = block_shell(tile_off, n_shells, b);  // tile_off[sn] <= b < tile_off[sn + 1]
   const ShellDev d = sh[sn];
   const int R = d.rad;
   const int n_ct = (R + 1 + TW - 1) / TW;
@@ -210,7 +217,8 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1
 // Per (x, y) line: X_k (k = 0..M, zero beyond R), Z'_k = (X_k + X*_{M-k})
 // + i W_N^{-k} (X_k - X*_{M-k}) for k < M, M-point inverse FFT; the
 // unnormalised real line is (Re z_m, Im z_m) at (2m, 2m+1), written
-// voxel-blocked.
+// voxel-blocked.  Every shell has N^2 lines, hence the same number of blocks
+// (blk_off[sn] = sn * blocks per shell; the table is not read).
 template <typename T, typename OutT, int N>
 __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, OutT* __restrict__ out,
                                                  const long long* __restrict__ blk_off, int n_shells,
@@ -220,17 +228,16 @@ __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, O
   constexpr int LS = M + 1;
   __shared__ V2<T> buf[NL * LS];
   __shared__ V2<T> twl[N];
+  // every shell has the same N^2 lines, so the same number of blocks; the
+  // shell runs fastest, so blocks in flight together write neighbouring
+  // 128-byte pieces of the same voxel blocks (DRAM pages) instead of one
+  // piece per 12.8 KB of the field
+  const long long n_lines = (long long)N * N;
   const long long b = blockIdx.x;
-  int lo = 0, hi = n_shells;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (blk_off[mid] <= b) lo = mid; else hi = mid;
-  }
-  const int sn = lo;
+  const int sn = (int)(b % n_shells);
   const ShellDev d = sh[sn];
   const int wz = d.rad + 1;
-  const long long n_lines = (long long)N * N;
-  const long long line0 = (b - blk_off[sn]) * NL;
+  const long long line0 = (b / n_shells) * NL;
   const int lines = (int)min((long long)NL, n_lines - line0);
   const V2<T>* src = a2 + d.a2_off + line0 * wz;
   staged_copy<NL * LS, kThrZ, V2<T>>(
@@ -295,17 +302,14 @@ __global__ void __launch_bounds__(kThrZ) k_g_r2c_z(const float* __restrict__ G, 
   constexpr int LS = M + 1;
   __shared__ float2 buf[NL * LS];
   __shared__ float2 twl[N];
+  // every shell has the same N^2 lines, so the same number of blocks
+  const long long n_lines = (long long)N * N;
+  constexpr long long kBps = ((long long)N * N + NL - 1) / NL;
   const long long b = blockIdx.x;
-  int lo = 0, hi = n_shells;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (blk_off[mid] <= b) lo = mid; else hi = mid;
-  }
-  const int sn = lo;
+  const int sn = (int)(b / kBps);
   const ShellDev d = sh[sn];
   const int wz = d.rad + 1;
-  const long long n_lines = (long long)N * N;
-  const long long line0 = (b - blk_off[sn]) * NL;
+  const long long line0 = (b - sn * kBps) * NL;
   const int lines = (int)min((long long)NL, n_lines - line0);
   staged_copy<NL * M, kThrZ, float2>(
       [&](int e) {
@@ -341,12 +345,7 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_y(const float2* __restrict__
   __shared__ float2 buf[N * TW];
   __shared__ float2 twl[N];
   const long long b = blockIdx.x;
-  int lo = 0, hi = n_shells;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (tile_off[mid] <= b) lo = mid; else hi = mid;
-  }
-  const int sn = lo;
+  const int sn = block_shell(tile_off, n_shells, b);  // tile_off[sn] <= b < tile_off[sn + 1]
   const ShellDev d = sh[sn];
   const int R = d.rad;
   const int n_ct = (R + 1 + TW - 1) / TW;

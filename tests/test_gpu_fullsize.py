@@ -53,3 +53,34 @@ def test_fullsize_sampled_parity():
                                                                       cond[k]))
         assert m["e_cond"] <= 1e-5 and m["e_norm"] <= 1e-5, (name, m)
     plan.close()
+
+
+@pytest.mark.timeout(1100)
+def test_ng1024_sampled_parity():
+    """The same estimator on a 1024^3 grid (L = 3000 Mpc, the same cell size;
+    the estimator grid stays G = 320): all closable triangles of shells 1 and
+    100 -- the lowest and highest shell, (1,1,1), (100,100,1), (100,100,100) --
+    against the float64 oracle on the full 1024^3 grid (about 80 GB of host
+    memory for its fields)."""
+    import paper_2107_14564_amd as P
+    n_g, box, dk, n_s, beta = 1024, 3000.0, 1.0, 100, 0.5
+    t0 = time.time()
+    delta_gpu, delta64 = to_gpu(workload_field("ng1024"))
+    say("field %.1fs" % (time.time() - t0))
+    plan = P.Plan(n_g, box, dk, n_s, rsd_beta=beta, precision=P.PREC_SPLITBF16)
+    assert plan.n_tri == 89625 and plan.n_est == 320
+    b_split = plan.run(delta_gpu).cpu().numpy()
+    tri_all = plan.triangles.numpy()
+    ntri_all = plan.ntri.numpy()
+    plan.close()
+    del delta_gpu
+    index = {tuple(r): t for t, r in enumerate(tri_all.tolist())}
+    sample = [r for r in geometry.all_triangles(n_s).tolist() if set(r) <= {1, 100}]
+    assert len(sample) == 3
+    idx = np.array([index[tuple(r)] for r in sample])
+    ref = fbe.estimate(delta64, box, dk, np.array(sample), rsd_beta=beta, with_abs=True)
+    say("oracle %.1fs on %d triangles" % (time.time() - t0, len(sample)))
+    assert np.array_equal(ntri_all[idx], ref["ntri"])
+    m = metrics(b_split[idx], ref["B"], ref["S"])
+    say("split-bf16", m)
+    assert m["e_cond"] <= 1e-5 and m["e_norm"] <= 1e-5, m
