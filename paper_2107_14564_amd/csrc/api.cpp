@@ -553,6 +553,7 @@ int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
   if (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING)
     for (auto& e : p->ev) PLAN_HIP(hipEventCreate(&e));
   PLAN_HIP(prepare_contract_bf16x3());
+  PLAN_HIP(prepare_forward());
   if (p->cfg.flags & BISPEC_FLAG_AUTOTUNE) {
     st = autotune_mfma(*p, s);
     if (st) return st;

@@ -33,6 +33,13 @@ namespace fftk {
 constexpr int kThrAxis = 512;  // threads of a strided-pass block
 constexpr int kThrZ = 256;     // threads of a contiguous-pass block
 
+// Forward strided passes (k_fft_axis): columns per block, and the dynamic LDS
+// bytes of the sizes whose tile does not fit the 64 KB of static LDS.
+__host__ __device__ constexpr int fwd_tile_cols(int n) { return n >= 1024 ? 16 : fft_tile_cols(n, false); }
+__host__ __device__ constexpr unsigned fwd_dyn_lds(int n) {
+  return n >= 1024 ? (unsigned)(n * fwd_tile_cols(n) + n) * 8u : 0u;
+}
+
 // Shell of block b from the per-shell block prefix sums off[0 .. n_shells]:
 // every thread tests a few entries (one coalesced read instead of a chain of
 // dependent reads in a binary search).  Uniform over the block; contains a
@@ -92,13 +99,20 @@ __global__ void __launch_bounds__(kThrZ) k_r2c_z(const float* __restrict__ in, f
 // Lines along an axis of length N with element stride `stride`; n_cols
 // consecutive columns; planes at outer_stride.  rsd_pass (the final x pass):
 // multiply by 1 + beta kz^2/|m|^2.
+// The tile takes fwd_tile_cols(N) columns; at N = 1024 that is 16 (128-byte
+// row pieces) in dynamic LDS (fwd_dyn_lds(N) bytes, above the 64 KB of static
+// LDS), where the static limit would allow 7.
 template <int N>
 __global__ void __launch_bounds__(kThrAxis) k_fft_axis(float2* __restrict__ data, long long stride, int n_cols,
                                                        long long outer_stride, const float2* __restrict__ tw,
                                                        float sign, float scale, int rsd_pass, float beta) {
-  constexpr int TW = fft_tile_cols(N, false);
-  __shared__ float2 buf[N * TW];
-  __shared__ float2 twl[N];
+  constexpr int TW = fwd_tile_cols(N);
+  constexpr bool kDyn = fwd_dyn_lds(N) > 0;
+  __shared__ float2 sbuf[kDyn ? 1 : N * TW];
+  __shared__ float2 stwl[kDyn ? 1 : N];
+  extern __shared__ float2 dlds[];
+  float2* buf = kDyn ? dlds : sbuf;
+  float2* twl = kDyn ? dlds + N * TW : stwl;
   const int n_ct = (n_cols + TW - 1) / TW;
   const int o = blockIdx.x / n_ct;
   const int c0 = (blockIdx.x % n_ct) * TW;

@@ -70,6 +70,7 @@ struct ShellPassPlan {
 // passes of every shell of g on a grid of n points per side
 void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p);
 
+hipError_t prepare_forward();   // once per plan, before any launch (and before graph capture)
 hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, const float2* tw, hipStream_t st);
 // the three inverse passes of every shell (fft_inv_x.hip, fft_inv_y.hip, fft_c2r.hip)
 hipError_t launch_inv_x_f32(const float2* spec, float2* a1, const ShellLaunch& L, int n, const float2* tw,
