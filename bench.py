@@ -49,7 +49,10 @@ WORKLOADS = {
 }
 
 # batched form: 64 heterogeneous realisations (N_g in {96, 128, 160}, 16-48 shells)
-BATCH_WORKLOADS = {"batch64_ng96_160": dict(n=64, seed=4999)}
+BATCH_WORKLOADS = {"batch64_ng96_160": dict(n=64, seed=4999),
+                   # the validation ensemble: 32 realisations of one configuration per replay
+                   "ensemble32_ng64": dict(n=32, ensemble=dict(n_g=64, box_l=600.0, n_shells=20, k1_shells=[16, 17, 18, 19, 20],
+                                                          seed=11000))}
 
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense bf16 MFMA
 PEAK_HBM_GBS = 8000.0
@@ -262,15 +265,21 @@ def bench_batch(args, np, torch, P):
     HIP graph; one step = one pass over all members."""
     from synth import batch_field, batch_members
     bw = BATCH_WORKLOADS[args.workload]
-    members = batch_members(bw["n"], bw["seed"])
+    ens = bw.get("ensemble")
+    if ens:  # identical configurations, seeded realisations of the quadratic field (f_NG = 1)
+        members = [dict(n_g=ens["n_g"], box_l=ens["box_l"], n_shells=ens["n_shells"], f_ng=1.0,
+                        seed=ens["seed"] + i) for i in range(bw["n"])]
+    else:
+        members = batch_members(bw["n"], bw["seed"])
     prec = P.PREC_SPLITBF16 if args.precision == "splitbf16" else P.PREC_FP32
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
     fields = [torch.from_numpy(np.ascontiguousarray(batch_field(m), dtype=np.float32)) for m in members]
     print("fields ready (%.1f s)" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    sel = dict(tri_mode=P.TRI_K1SET, k1_shells=ens["k1_shells"]) if ens else {}
     configs = [dict(n_g=m["n_g"], box_l=m["box_l"], dk=1.0, n_shells=m["n_shells"], precision=prec,
-                    flags=P.FLAG_AUTOTUNE if args.autotune else 0) for m in members]
+                    flags=P.FLAG_AUTOTUNE if args.autotune else 0, **sel) for m in members]
     t0 = time.perf_counter()
     bp = P.BatchPlan(configs)
     torch.cuda.synchronize()
@@ -317,6 +326,7 @@ def bench_batch(args, np, torch, P):
                    "n_shells_range": [min(m["n_shells"] for m in members), max(m["n_shells"] for m in members)],
                    "n_tri": bp.n_tri, "precision": args.precision, "autotune": bool(args.autotune)},
         "eager_ms_per_step": eager_ms,
+        "realisations_per_s": bp.n / (ms * 1e-3),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None, "kernel": "whole step (all kernels)",
                      "algorithmic_flop": flop},

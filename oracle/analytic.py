@@ -95,3 +95,29 @@ def rsd_monopole_factor_mc(k1, k2, k3, beta: float, n_dirs: int, seed: int = 0):
         mu = zrow @ v / np.linalg.norm(v)
         prod *= 1.0 + beta * mu * mu
     return float(prod.mean()), float(prod.std() / np.sqrt(n_dirs))
+
+
+def gaussian_variance_binavg(n_g: int, box_l: float, w: float, triangles, power) -> np.ndarray:
+    """Variance of the estimated B of a Gaussian field (B = 0) in bins of three
+    distinct shells: the Gaussian term of eq. cv, V P1 P2 P3 / N_tri, with the
+    product averaged over the closed triangles of the bin (only the pairing of
+    each triangle with its mirror image survives when the shells differ):
+        Var B = V N^-3 sum_x I^P_a1 I^P_a2 I^P_a3 / N_tri^2,
+    I^P the P-weighted unit fields.  Bins with repeated shells have extra
+    pairings (eq. cv carries no symmetry factor) and are rejected."""
+    tri = np.asarray(triangles, dtype=np.int64).reshape(-1, 3)
+    if np.any((tri[:, 0] == tri[:, 1]) | (tri[:, 1] == tri[:, 2])):
+        raise ValueError("bins with repeated shells have extra pairings")
+    shells = sorted(set(int(v) for v in tri.ravel()))
+    masks = fbe.shell_masks(n_g, w, shells)
+    kf = 2.0 * np.pi / box_l
+    pk = power(kf * np.sqrt(fbe.half_grid_m2(n_g).astype(np.float64)))
+    IP = {n: _weighted_unit_field(pk, masks[n]) for n in shells}
+    I1 = {n: fbe.unit_field(masks[n]) for n in shells}
+    vol = box_l ** 3
+    out = np.zeros(len(tri))
+    for t, (a1, a2, a3) in enumerate(tri):
+        a1, a2, a3 = int(a1), int(a2), int(a3)
+        ntri = np.rint(np.sum(I1[a1] * I1[a2] * I1[a3]) / float(n_g) ** 3)
+        out[t] = vol * np.sum(IP[a1] * IP[a2] * IP[a3]) / float(n_g) ** 3 / ntri ** 2
+    return out

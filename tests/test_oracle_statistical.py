@@ -54,3 +54,24 @@ def test_bin_average_approaches_label_value_for_thin_bins():
     rel = np.abs(pred / at_labels - 1)
     assert rel[0] < 0.05 and rel[1] < 0.05
     assert rel[2] > rel[0]
+
+
+def test_gaussian_variance_matches_eq_cv():
+    """The scatter of the estimated B of Gaussian fields against the Gaussian
+    term of eq. cv, V <P1 P2 P3> / N_tri, bin-averaged, in bins of three
+    distinct shells.  A variance estimate from n realisations has a relative
+    spread of sqrt(2 / (n - 1)) per bin; averaged over the bins the ratio must
+    be 1 within 12 %, and a formula off by a factor 2 (e.g. without the mirror
+    pairing) is rejected."""
+    tri = np.array([t for t in geometry.all_triangles(N_S, k1_set=[8, 9, 10]).tolist() if len(set(t)) == 3])
+    n_real = 96
+    bs = np.array([fbe.estimate(gaussian_field(N_G, BOX, POWER, seed=9100 + r), BOX, W, tri)["B"]
+                   for r in range(n_real)])
+    var_sim = bs.var(0, ddof=1)
+    var_cv = analytic.gaussian_variance_binavg(N_G, BOX, W, tri, POWER)
+    ratio = var_sim / var_cv
+    assert abs(float(np.mean(ratio)) - 1.0) < 0.12, float(np.mean(ratio))
+    assert float(np.median(ratio)) > 0.75 and float(np.median(ratio)) < 1.3
+    assert abs(float(np.mean(var_sim / (2.0 * var_cv))) - 1.0) > 0.3
+    with pytest.raises(ValueError):
+        analytic.gaussian_variance_binavg(N_G, BOX, W, [[10, 10, 5]], POWER)
