@@ -337,20 +337,19 @@ __device__ __forceinline__ void ws_mfma3(const bf16x8& ahi, const bf16x8& alo, c
 }
 
 // One chunk (32 voxels of buffer buf) for a slot with NT column tiles and
-// n_rb row blocks (accumulator tile q * NT + t).  fo[q], go[q]: byte offsets
-// of this lane's F_i and F_j rows (+ its voxel octet) in buffer 0; co[t]: of
-// its column row in plane Bh, buffer 0.
+// NRB row blocks (accumulator tile q * NT + t); both are template parameters,
+// so every slot shape runs straight-line code with constant indices (the
+// accumulators stay in registers).  fo[q], go[q]: byte offsets of this lane's
+// F_i and F_j rows (+ its voxel octet) in buffer 0; co[t]: of its column row
+// in plane Bh, buffer 0.
 // NT <= 4 ("tall"): the column fragments of all tiles stay in registers and
 // the row blocks stream through, the reads of block q + 1 issued before block
-// q is split and multiplied.  NT >= 5 ("wide", n_rb <= 3): the row operands
-// of all blocks stay in registers and the column fragments stream through.
-// FULL: n_rb == slot_row_blocks(NT), no per-block branch.
-template <int NT, bool FULL>
-__device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLayout& y, int buf, int n_rb,
+// q is split and multiplied.  NT >= 5 ("wide", NRB <= 3): the row operands of
+// all blocks stay in registers and the column fragments stream through.
+template <int NT, int NRB>
+__device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLayout& y, int buf,
                                            const unsigned* fo, const unsigned* go, const unsigned* co, f32x4* acc) {
-  constexpr int RBM = slot_row_blocks(NT);
   const unsigned fb = buf * y.f_buf, bb = y.bh0 + buf * y.b_buf, lb = y.bl0 + buf * y.b_buf;
-  const int nq = FULL ? RBM : n_rb;
   if constexpr (NT <= 4) {
     bf16x8 bhi[NT], blo[NT];
 #pragma unroll
@@ -359,30 +358,21 @@ __device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLay
       blo[t] = *reinterpret_cast<const bf16x8*>(lds + lb + co[t]);
     }
     RowIn cur = ws_row_read(lds, fb + fo[0], fb + go[0]);
-    // (guards instead of early exits keep every index a constant, so the
-    // accumulators stay in registers; the partial NT = 4 form reads each
-    // block when it needs it, the prefetch registers would not fit)
-    constexpr bool kPrefetch = FULL || NT < 4;
 #pragma unroll
-    for (int q = 0; q < RBM; ++q) {
-      if (FULL || q < nq) {  // uniform over the wave
-        if (!kPrefetch && q > 0) cur = ws_row_read(lds, fb + fo[q], fb + go[q]);
-        RowIn nxt = cur;
-        if (kPrefetch && q + 1 < RBM && (FULL || q + 1 < nq))
-          nxt = ws_row_read(lds, fb + fo[q + 1], fb + go[q + 1]);
-        __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this block's work
-        bf16x8 ahi, alo;
-        ws_row_split(cur, ahi, alo);
+    for (int q = 0; q < NRB; ++q) {
+      RowIn nxt = cur;
+      if (q + 1 < NRB) nxt = ws_row_read(lds, fb + fo[q + 1], fb + go[q + 1]);
+      __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this block's work
+      bf16x8 ahi, alo;
+      ws_row_split(cur, ahi, alo);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) ws_mfma3(ahi, alo, bhi[t], blo[t], acc[q * NT + t]);
-        cur = nxt;
-      }
+      for (int t = 0; t < NT; ++t) ws_mfma3(ahi, alo, bhi[t], blo[t], acc[q * NT + t]);
+      cur = nxt;
     }
   } else {
-    bf16x8 ahi[RBM], alo[RBM];
+    bf16x8 ahi[NRB], alo[NRB];
 #pragma unroll
-    for (int q = 0; q < RBM; ++q)
-      if (FULL || q < nq) ws_row_split(ws_row_read(lds, fb + fo[q], fb + go[q]), ahi[q], alo[q]);
+    for (int q = 0; q < NRB; ++q) ws_row_split(ws_row_read(lds, fb + fo[q], fb + go[q]), ahi[q], alo[q]);
     bf16x8 bhi = *reinterpret_cast<const bf16x8*>(lds + bb + co[0]);
     bf16x8 blo = *reinterpret_cast<const bf16x8*>(lds + lb + co[0]);
 #pragma unroll
@@ -393,8 +383,7 @@ __device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLay
         nlo = *reinterpret_cast<const bf16x8*>(lds + lb + co[t + 1]);
       }
 #pragma unroll
-      for (int q = 0; q < RBM; ++q)
-        if (FULL || q < nq) ws_mfma3(ahi[q], alo[q], bhi, blo, acc[q * NT + t]);
+      for (int q = 0; q < NRB; ++q) ws_mfma3(ahi[q], alo[q], bhi, blo, acc[q * NT + t]);
       bhi = nhi;
       blo = nlo;
     }
@@ -404,19 +393,16 @@ __device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLay
 // float64 flush of the slot's accumulators (first: write, else add), then reset.
 // The base pointer passes through an empty asm so the element addresses are
 // formed here, not hoisted out of the main loop into live registers.
-template <int NT>
-__device__ __forceinline__ void ws_flush(double* out, bool first, int n_rb, f32x4* acc) {
-  constexpr int RBM = slot_row_blocks(NT);
+template <int NT, int NRB>
+__device__ __forceinline__ void ws_flush(double* out, bool first, f32x4* acc) {
   asm volatile("" : "+v"(out));
 #pragma unroll
-  for (int k = 0; k < RBM * NT; ++k) {
-    if (k < n_rb * NT) {
-      double* o = out + (long long)k * kMTileElems;
+  for (int k = 0; k < NRB * NT; ++k) {
+    double* o = out + (long long)k * kMTileElems;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        o[v * 64] = first ? (double)acc[k][v] : o[v * 64] + (double)acc[k][v];
-        acc[k][v] = 0.f;
-      }
+    for (int v = 0; v < 4; ++v) {
+      o[v * 64] = first ? (double)acc[k][v] : o[v * 64] + (double)acc[k][v];
+      acc[k][v] = 0.f;
     }
   }
 }
@@ -425,17 +411,16 @@ __device__ __forceinline__ void ws_flush(double* out, bool first, int n_rb, f32x
 // kr + n_krange, kr + 2 n_krange, ...: every float32 chain samples the whole
 // box, so its partial sums cancel like the total instead of growing with a
 // slab's coherent sum.
-template <int NT, bool FULL>
+template <int NT, int NRB>
 __device__ __forceinline__ void ws_run(const float* __restrict__ F, const WsArgs& a, unsigned char* lds,
                                        const WsLayout& y, const WgRows& wr, int kr, int n_chunks, int tid,
                                        const SlotCols& sc, const MRowBlock* rows, double* out) {
-  constexpr int RBM = slot_row_blocks(NT);
-  const int lane = tid & 63, kg = lane >> 4, zr = wr.s_n, n_rb = sc.n_rb;
+  const int lane = tid & 63, kg = lane >> 4, zr = wr.s_n;
   // this lane's rows (pair shells) and columns as byte offsets in buffer 0
-  unsigned fo[RBM], go[RBM], co[NT];
+  unsigned fo[NRB], go[NRB], co[NT];
 #pragma unroll
-  for (int q = 0; q < RBM; ++q) {
-    const MRowBlock& rb = rows[q < n_rb ? q : 0];
+  for (int q = 0; q < NRB; ++q) {
+    const MRowBlock& rb = rows[q];
     const int i = rb.i[lane & 15], j = rb.j[lane & 15];
     const int ri = j > 0 ? i - 1 - wr.s_lo : zr, rj = j > 0 ? j - 1 - wr.s_lo : zr;
     fo[q] = kg * y.f_plane + ri * 32;
@@ -447,9 +432,9 @@ __device__ __forceinline__ void ws_run(const float* __restrict__ F, const WsArgs
     const int rc = (l >= 1 && l <= a.n_s) ? l - 1 - wr.s_lo : zr;
     co[t] = (unsigned)(rc * kBS + kg * 8) * 2;
   }
-  f32x4 acc[RBM * NT];
+  f32x4 acc[NRB * NT];
 #pragma unroll
-  for (int k = 0; k < RBM * NT; ++k)
+  for (int k = 0; k < NRB * NT; ++k)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[k][v] = 0.f;
   const long long kstep = a.n_krange;
@@ -464,9 +449,9 @@ __device__ __forceinline__ void ws_run(const float* __restrict__ F, const WsArgs
   for (int c = 0; c < n_chunks; ++c) {
     const bool more = c + 1 < n_chunks;
     if (more) ws_load(F, a.n_s, kr + (c + 1) * kstep, wr, pf, tid);
-    ws_compute<NT, FULL>(lds, y, c & 1, n_rb, fo, go, co, acc);
+    ws_compute<NT, NRB>(lds, y, c & 1, fo, go, co, acc);
     if (++chain == kFlushChunks || !more) {
-      ws_flush<NT>(out, first, n_rb, acc);
+      ws_flush<NT, NRB>(out, first, acc);
       chain = 0;
       first = false;
     }
@@ -523,14 +508,15 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
   if (n_chunks == 0)  // empty range: its partials are zero
     for (int e = 0; e < kSlotTiles * 4; ++e) out[(long long)(e >> 2) * kMTileElems + (e & 3) * 64] = 0.0;
   // every wave passes the same barriers whatever its variant (uniform per wave)
-  const bool full = sc.n_rb == slot_row_blocks(sc.n);
-  switch (sc.n) {
-#define WS_CASE(N)                                                                              \
-  case N:                                                                                       \
-    if (full) ws_run<N, true>(F, a, smem_raw, y, wr, kr, n_chunks, tid, sc, rows, out);         \
-    else ws_run<N, false>(F, a, smem_raw, y, wr, kr, n_chunks, tid, sc, rows, out);             \
-    break;
-    WS_CASE(1) WS_CASE(2) WS_CASE(3) WS_CASE(4) WS_CASE(5) WS_CASE(6) WS_CASE(7) WS_CASE(8)
+  switch (sc.n * 16 + sc.n_rb) {
+#define WS_CASE(N, R) \
+  case N * 16 + R: ws_run<N, R>(F, a, smem_raw, y, wr, kr, n_chunks, tid, sc, rows, out); break;
+    WS_CASE(1, 1) WS_CASE(1, 2) WS_CASE(1, 3) WS_CASE(1, 4) WS_CASE(1, 5) WS_CASE(1, 6) WS_CASE(1, 7) WS_CASE(1, 8)
+    WS_CASE(2, 1) WS_CASE(2, 2) WS_CASE(2, 3) WS_CASE(2, 4) WS_CASE(2, 5) WS_CASE(2, 6) WS_CASE(2, 7) WS_CASE(2, 8)
+    WS_CASE(3, 1) WS_CASE(3, 2) WS_CASE(3, 3) WS_CASE(3, 4) WS_CASE(3, 5)
+    WS_CASE(4, 1) WS_CASE(4, 2) WS_CASE(4, 3) WS_CASE(4, 4)
+    WS_CASE(5, 1) WS_CASE(5, 2) WS_CASE(5, 3)
+    WS_CASE(6, 1) WS_CASE(6, 2) WS_CASE(7, 1) WS_CASE(7, 2) WS_CASE(8, 1) WS_CASE(8, 2)
 #undef WS_CASE
     default: ws_idle(F, a, smem_raw, y, wr, kr, n_chunks, tid); break;
   }
