@@ -343,9 +343,10 @@ __device__ __forceinline__ void ws_mfma3(const bf16x8& ahi, const bf16x8& alo, c
 // F_i and F_j rows (+ its voxel octet) in buffer 0; co[t]: of its column row
 // in plane Bh, buffer 0.
 // NT <= 4 ("tall"): the column fragments of all tiles stay in registers and
-// the row blocks stream through, the reads of block q + 1 issued before block
-// q is split and multiplied.  NT >= 5 ("wide", NRB <= 3): the row operands of
-// all blocks stay in registers and the column fragments stream through.
+// the row blocks stream through, one block ahead: block q + 1 is split while
+// block q's MFMAs run, and block q + 2's rows are read.  NT >= 5 ("wide",
+// NRB <= 3): the row operands of all blocks stay in registers and the column
+// fragments stream through.
 template <int NT, int NRB>
 __device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLayout& y, int buf,
                                            const unsigned* fo, const unsigned* go, const unsigned* co, f32x4* acc) {
@@ -357,17 +358,20 @@ __device__ __forceinline__ void ws_compute(const unsigned char* lds, const WsLay
       bhi[t] = *reinterpret_cast<const bf16x8*>(lds + bb + co[t]);
       blo[t] = *reinterpret_cast<const bf16x8*>(lds + lb + co[t]);
     }
-    RowIn cur = ws_row_read(lds, fb + fo[0], fb + go[0]);
+    // two register sets for the row operand, used alternately: block q's
+    // MFMAs read set q & 1 while block q + 1 is split into the other set (so
+    // the split never overwrites an operand an MFMA in flight still reads)
+    // and block q + 2's rows are read from LDS
+    bf16x8 ahi[2], alo[2];
+    RowIn r = ws_row_read(lds, fb + fo[0], fb + go[0]);
+    ws_row_split(r, ahi[0], alo[0]);
+    if (NRB > 1) r = ws_row_read(lds, fb + fo[1 % NRB], fb + go[1 % NRB]);
 #pragma unroll
     for (int q = 0; q < NRB; ++q) {
-      RowIn nxt = cur;
-      if (q + 1 < NRB) nxt = ws_row_read(lds, fb + fo[q + 1], fb + go[q + 1]);
-      __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this block's work
-      bf16x8 ahi, alo;
-      ws_row_split(cur, ahi, alo);
+      if (q + 1 < NRB) ws_row_split(r, ahi[(q + 1) & 1], alo[(q + 1) & 1]);
+      if (q + 2 < NRB) r = ws_row_read(lds, fb + fo[(q + 2) % NRB], fb + go[(q + 2) % NRB]);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) ws_mfma3(ahi, alo, bhi[t], blo[t], acc[q * NT + t]);
-      cur = nxt;
+      for (int t = 0; t < NT; ++t) ws_mfma3(ahi[q & 1], alo[q & 1], bhi[t], blo[t], acc[q * NT + t]);
     }
   } else {
     bf16x8 ahi[NRB], alo[NRB];
