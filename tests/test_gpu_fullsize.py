@@ -84,3 +84,37 @@ def test_ng1024_sampled_parity():
     m = metrics(b_split[idx], ref["B"], ref["S"])
     say("split-bf16", m)
     assert m["e_cond"] <= 1e-5 and m["e_norm"] <= 1e-5, m
+
+
+@pytest.mark.timeout(900)
+def test_max_shells_sampled_parity():
+    """The largest split-bf16 plan: 128 shells of one k_f, which needs the
+    estimator grid G = 512 (> 3 x 128), on the 512^3 benchmark field; the
+    contraction's widest row sets (128 shells staged per work group).  All
+    closable triangles among shells {1, 2, 64, 65, 127, 128} against the
+    float64 oracle, N_tri exact and the 1e-5 gate for both precisions."""
+    import paper_2107_14564_amd as P
+    n_g, box, dk, n_s, beta = 512, 1500.0, 1.0, 128, 0.5
+    t0 = time.time()
+    delta_gpu, delta64 = to_gpu(workload_field("ng512"))
+    plan = P.Plan(n_g, box, dk, n_s, rsd_beta=beta, precision=P.PREC_SPLITBF16)
+    say("plan %.1fs: G=%d n_tri=%d" % (time.time() - t0, plan.n_est, plan.n_tri))
+    assert plan.n_est == 512
+    b_split = plan.run(delta_gpu).cpu().numpy()
+    plan.set_precision(P.PREC_FP32)
+    b_fp32 = plan.run(delta_gpu).cpu().numpy()
+    tri_all = plan.triangles.numpy()
+    ntri_all = plan.ntri.numpy()
+    plan.close()
+    del delta_gpu
+    index = {tuple(r): t for t, r in enumerate(tri_all.tolist())}
+    sset = {1, 2, 64, 65, 127, 128}
+    sample = [r for r in geometry.all_triangles(n_s).tolist() if set(r) <= sset]
+    idx = np.array([index[tuple(r)] for r in sample])
+    ref = fbe.estimate(delta64, box, dk, np.array(sample), rsd_beta=beta, with_abs=True)
+    say("oracle %.1fs on %d triangles" % (time.time() - t0, len(sample)))
+    assert np.array_equal(ntri_all[idx], ref["ntri"])
+    for name, b in (("fp32", b_fp32), ("split-bf16", b_split)):
+        m = metrics(b[idx], ref["B"], ref["S"])
+        say(name, m)
+        assert m["e_cond"] <= 1e-5 and m["e_norm"] <= 1e-5, (name, m)

@@ -100,6 +100,37 @@ def test_fields_match_oracle():
         plan.close()
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+def test_zero_and_constant_fields(precision):
+    """Degenerate inputs.  delta = 0 gives B = 0 exactly.  A constant delta has
+    only the k = 0 mode, which no shell holds (shell 1 starts at |m| = w/2),
+    so B vanishes up to the float32 transform's rounding in the other modes:
+    below 1e-9 of the B scale of a unit-variance field on the same plan (a mean
+    mode leaking into a shell would give B of that scale times 0.75^3).
+    N_tri does not depend on the field."""
+    import paper_2107_14564_amd as P
+    import torch
+    n_g, box = 32, 300.0
+    plan = P.Plan(n_g, box, 1.0, 10, rsd_beta=0.5, precision=precision)
+    ref_ntri = fbe.estimate(np.zeros((n_g,) * 3), box, 1.0, plan.triangles.numpy())["ntri"]
+    assert np.array_equal(plan.ntri.numpy(), ref_ntri)
+    field = _field(n_g, box, 7)
+    field = (field / field.std()).astype(np.float32)
+    scale = float(np.max(np.abs(plan.run(torch.from_numpy(field).cuda()).cpu().numpy())))
+    assert scale > 0.0
+    for value in (0.0, 0.75):
+        d = torch.full((n_g,) * 3, value, dtype=torch.float32, device="cuda")
+        b = plan.run(d).cpu().numpy()
+        say("constant field %g prec=%d max|B| %.3g (field scale %.3g)" % (value, precision,
+                                                                     float(np.max(np.abs(b))), scale))
+        assert b.shape == (plan.n_tri,)
+        if value == 0.0:
+            assert np.all(b == 0.0)
+        else:
+            assert float(np.max(np.abs(b))) <= 1e-9 * scale
+    plan.close()
+
+
 def test_kronecker_delta_gpu():
     """delta = 1 at one voxel gives B = dV^3 / V in every bin (both precisions):
     conditioned error <= 1e-5 against that closed form, and per bin within
