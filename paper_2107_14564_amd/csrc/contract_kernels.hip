@@ -570,15 +570,34 @@ __global__ void __launch_bounds__(kGbVox) k_gbuild(const float* __restrict__ F, 
   }
 }
 
-__global__ void k_reduce(const double* __restrict__ partial, int n_krange, long long stride, long long n_tri,
-                         const int32_t* __restrict__ slot, const double* __restrict__ norm,
-                         double* __restrict__ out) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tri) return;
-  const long long at = slot ? slot[t] : t;
+// Fixed-order float64 reduction over the voxel ranges: T_t = sum_k
+// partial[k][slot_t], times norm_t (eq. FBE normalisation) when given.  A block
+// takes kRedTri triangles, lane (tl, p): triangle tl, ranges k = p, p + kRedPart,
+// ...; the kRedPart partial sums are then added in the order p = 0, 1, ...
+// (deterministic).  Lanes run over the triangles, whose slots are mostly
+// neighbouring tile elements, so the loads of one range coalesce.
+constexpr int kRedTri = 16, kRedPart = 16;
+__global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __restrict__ partial, int n_krange,
+                                                              long long stride, long long n_tri,
+                                                              const int32_t* __restrict__ slot,
+                                                              const double* __restrict__ norm,
+                                                              double* __restrict__ out) {
+  __shared__ double part[kRedPart][kRedTri];
+  const int tl = threadIdx.x % kRedTri, p = threadIdx.x / kRedTri;
+  const long long t = (long long)blockIdx.x * kRedTri + tl;
   double s = 0.0;
-  for (int k = 0; k < n_krange; ++k) s += partial[(long long)k * stride + at];
-  out[t] = norm ? s * norm[t] : s;
+  if (t < n_tri) {
+    const long long at = slot ? slot[t] : t;
+    for (int k = p; k < n_krange; k += kRedPart) s += partial[(long long)k * stride + at];
+  }
+  part[p][tl] = s;
+  __syncthreads();
+  if (p == 0 && t < n_tri) {
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRedPart; ++q) r += part[q][tl];
+    out[t] = norm ? r * norm[t] : r;
+  }
 }
 
 template <typename T>
@@ -635,8 +654,10 @@ hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, c
 
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
                          const double* norm, double* out, hipStream_t st) {
-  const unsigned blocks = (unsigned)((n_tri + 255) / 256);
-  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(256), 0, st, partial, n_krange, stride, n_tri, slot, norm, out);
+  if (n_tri <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n_tri + kRedTri - 1) / kRedTri);
+  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(kRedTri * kRedPart), 0, st, partial, n_krange, stride, n_tri, slot,
+                     norm, out);
   return hipGetLastError();
 }
 
