@@ -129,8 +129,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the estimator would shard "
-              "voxel slabs; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the estimator would shard "
+              "voxel slabs across GPUs and add the partial triple sums).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
