@@ -159,8 +159,9 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 // w: NT <= kMaxColTiles column tiles and n_rb <= slot_row_blocks(NT) row
 // blocks that meet them (at most kSlotTiles = 16 accumulator tiles of 4 fp32
 // per lane; NT is uniform over the wave, so the code path is too).  The
-// matrix unit and the vector ALU of a SIMD do not overlap measurably on this
-// chip, so the slot placement balances MFMA plus VALU cycles per SIMD.
+// matrix unit and the vector ALU of a SIMD overlap only in part on this chip
+// (the VALU co-executes on about a third of the MFMA busy cycles), so the slot
+// placement balances MFMA plus VALU cycles per SIMD.
 //
 // Voxel range kr is the set of voxel blocks kr + m n_krange (interleaved over
 // the box).  Per chunk of 32 voxels (one block) each thread loads one 8-voxel

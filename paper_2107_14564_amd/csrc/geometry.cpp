@@ -385,8 +385,8 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
   }
   // Cost-balanced placement: per 32 voxels a slot costs 3 NT n_rb MFMAs (16
   // cycles each) and n_rb row-operand formations (~32 VALU instructions of 4
-  // cycles each); the matrix unit and the vector ALU of a SIMD do not overlap
-  // measurably, so a SIMD's time is the sum over its waves, and a work
+  // cycles each); the matrix unit and the vector ALU of a SIMD overlap only in
+  // part, so a SIMD's time is close to the sum over its waves, and a work
   // group's time that of its busiest SIMD.  Waves q, q + 4, q + 8 of a group
   // share SIMD q % 4: slots go longest first to the least-loaded (group,
   // SIMD) bin with room, which evens out the SIMDs of every group and so the
