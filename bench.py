@@ -214,6 +214,8 @@ def main():
                     "achieved_GBs": (8.0 * n ** 3 + 4.0 * n_vox * w["n_shells"]) / ((stages[0] + stages[1]) * 1e-3) / 1e9,
                     "peak_GBs": PEAK_HBM_GBS},
         "plan_s": plan_s,
+        # the paper's cost unit: mode triangles (sum of N_tri over the bins) per second
+        "mode_triangles_per_s": float(plan.ntri.numpy().astype(np.float64).sum()) / (ms * 1e-3),
     }
     result["fft_hbm"]["frac"] = result["fft_hbm"]["achieved_GBs"] / PEAK_HBM_GBS
     if not args.no_fp32_compare and prec == P.PREC_SPLITBF16:
