@@ -104,7 +104,7 @@ def cpu_baseline(delta32, w: dict, budget_s: float = 30.0) -> dict:
     from oracle import fbe, geometry
     cores = os.cpu_count() or 1
     d64 = delta32.astype(np.float64)
-    s_shells = 4 if delta32.shape[0] <= 512 else 2   # 8 (4) float64 fields of N^3 on the host
+    s_shells = 6 if delta32.shape[0] <= 512 else 2   # 12 (4) float64 fields of N^3 on the host, ~10 s
     tri = geometry.all_triangles(s_shells)
     t0 = time.perf_counter()
     fbe.estimate(d64, w["box_l"], w["dk"], tri, rsd_beta=w["rsd_beta"])
