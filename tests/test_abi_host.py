@@ -43,6 +43,14 @@ def test_errors_are_reported():
         abi.bispec_query_triangles(abi.make_config(32, 300.0, 1.0, 4, tri_mode=abi.TRI_LIST,
                                                    triangles=[(2, 1, 1), (2, 1, 1)])[0])
     assert "closable" in abi.bispec_last_error() or "duplicate" in abi.bispec_last_error()
+    # empty selections are rejected at plan time (a plan always has >= 1 triangle)
+    for kw in [dict(tri_mode=abi.TRI_LIST, triangles=[]), dict(tri_mode=abi.TRI_K1SET, k1_shells=[]),
+               dict(tri_mode=abi.TRI_MUT_GRID, k1_shells=[3], n_mu=0, n_t=5),
+               dict(tri_mode=abi.TRI_K1SET, k1_shells=[9])]:
+        with pytest.raises(abi.BispecError) as e:
+            abi.bispec_query_triangles(abi.make_config(32, 300.0, 1.0, 4, **kw)[0])
+        assert e.value.status == abi.BISPEC_EINVAL, kw
+        assert abi.bispec_last_error(), kw
 
 
 def test_cutoff_boundary():
