@@ -41,20 +41,48 @@ __device__ __forceinline__ long long range_lo(long long n_vox, int n_krange, int
 // Vector form: T = float (step c', plain fp32 FMAs) or double (step c2).
 // One work group = one task (<= 8 tiles).  Thread t: tile t/32; within the
 // tile, rows 4*((t%32)/4) .. +3 and columns 8*(t%4) .. +7 (32 sums per thread).
-// LDS chunk: [Kc][n_s + 1] (shell-contiguous per voxel, one zero shell last).
-// Sums run in T over one chunk (<= 256 voxels) and are then added into float64
-// totals: a long float32 chain would carry rounding error proportional to its
-// running partial sum, which for shells of box-scale wavelength is far larger
-// than the final (cancelling) total.
+// LDS chunk: [n_s + 1][ps] (voxel-contiguous per shell, row n_s all zero), so
+// a thread reads kVec consecutive voxels of a shell with one 16-byte load;
+// ps = kc + kVec puts consecutive shells an odd number of 16-byte bank groups
+// apart (kc a multiple of 8 kVec).  Sums run in T over one chunk (<= 256
+// voxels) and are then added into float64 totals: a long float32 chain would
+// carry rounding error proportional to its running partial sum, which for
+// shells of box-scale wavelength is far larger than the final (cancelling)
+// total.
 // ============================================================================
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__ F, ContractArgs a, int kc) {
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float2 type;
+  static constexpr int n = 2;
+};
+template <>
+struct Vec16<double> {
+  typedef double2 type;
+  static constexpr int n = 2;
+};
+template <typename T>
+__device__ __forceinline__ T vget(const typename Vec16<T>::type& v, int k);
+template <>
+__device__ __forceinline__ float vget<float>(const float2& v, int k) {
+  return k == 0 ? v.x : v.y;
+}
+template <>
+__device__ __forceinline__ double vget<double>(const double2& v, int k) {
+  return k == 0 ? v.x : v.y;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads, 3) k_contract_vec(const T* __restrict__ F, ContractArgs a, int kc) {
+  typedef typename Vec16<T>::type VT;
+  constexpr int kVec = Vec16<T>::n;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* chunk = reinterpret_cast<T*>(smem_raw);
   int task, kr;
   xcd_map(a.n_tasks, task, kr);
   const int ns = a.n_s;
-  const int ls = ns + 1;  // row stride; entry ns is the zero shell
+  const int ps = kc + kVec;  // row pitch (elements); row ns is the zero shell
   const int t0 = a.task_off[task], t1 = a.task_off[task + 1];
   const int tl = threadIdx.x >> 5;            // tile slot
   const int q = threadIdx.x & 31;
@@ -68,13 +96,13 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
   for (int u = 0; u < 4; ++u) {
     const int r = 4 * rq + u;
     const int i = active ? rb->i[r] : 0, j = active ? rb->j[r] : 0;
-    ri[u] = (j > 0) ? i - 1 : ns;
-    rj[u] = (j > 0) ? j - 1 : ns;
+    ri[u] = ((j > 0) ? i - 1 : ns) * ps;
+    rj[u] = ((j > 0) ? j - 1 : ns) * ps;
   }
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int l = tile.col0 + 8 * cq + c;
-    cl[c] = (l >= 1 && l <= ns) ? l - 1 : ns;
+    cl[c] = ((l >= 1 && l <= ns) ? l - 1 : ns) * ps;
   }
   // float32: per-chunk sums in acc, flushed into tot; float64: tot directly
   constexpr bool kF32 = sizeof(T) == 4;
@@ -86,14 +114,16 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
     for (int c = 0; c < 8; ++c) tot[u][c] = 0.0;
 
   const long long k_lo = range_lo(a.n_vox, a.n_krange, kr), k_hi = range_lo(a.n_vox, a.n_krange, kr + 1);
-  // zero shell column
-  for (int x = threadIdx.x; x < kc; x += kThreads) chunk[x * ls + ns] = (T)0;
+  // zero shell row
+  for (int x = threadIdx.x; x < kc; x += kThreads) chunk[ns * ps + x] = (T)0;
   for (long long x0 = k_lo; x0 < k_hi; x0 += kc) {
     const int len = (int)min((long long)kc, k_hi - x0);
     __syncthreads();
+    // shell s, voxels x0 .. x0 + kc - 1 (zero past the range): x runs fastest,
+    // and a shell's 32 voxels of a block are contiguous in F
     for (int e = threadIdx.x; e < ns * kc; e += kThreads) {
-      const int s = e / kc, x = e % kc;
-      chunk[x * ls + s] = x < len ? F[vox_index(x0 + x, s, ns)] : (T)0;
+      const int sh = e / kc, x = e % kc;
+      chunk[sh * ps + x] = x < len ? F[vox_index(x0 + x, sh, ns)] : (T)0;
     }
     __syncthreads();
     if (!active) continue;
@@ -103,22 +133,30 @@ __global__ void __launch_bounds__(kThreads) k_contract_vec(const T* __restrict__
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc[u][c] = (T)0;
     }
-    for (int x = 0; x < len; ++x) {
-      const T* row = chunk + x * ls;
-      T p[4], f[8];
+    for (int x = 0; x < len; x += kVec) {
+      VT vi[4], vj[4], vf[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) p[u] = row[ri[u]] * row[rj[u]];
+      for (int u = 0; u < 4; ++u) {
+        vi[u] = *reinterpret_cast<const VT*>(chunk + ri[u] + x);
+        vj[u] = *reinterpret_cast<const VT*>(chunk + rj[u] + x);
+      }
 #pragma unroll
-      for (int c = 0; c < 8; ++c) f[c] = row[cl[c]];
+      for (int c = 0; c < 8; ++c) vf[c] = *reinterpret_cast<const VT*>(chunk + cl[c] + x);
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int k = 0; k < kVec; ++k) {
+        T p[4];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          if constexpr (kF32)
-            acc[u][c] = fma(p[u], f[c], acc[u][c]);
-          else
-            tot[u][c] = fma((double)p[u], (double)f[c], tot[u][c]);
-        }
+        for (int u = 0; u < 4; ++u) p[u] = vget<T>(vi[u], k) * vget<T>(vj[u], k);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            if constexpr (kF32)
+              acc[u][c] = fma(p[u], vget<T>(vf[c], k), acc[u][c]);
+            else
+              tot[u][c] = fma(p[u], vget<T>(vf[c], k), tot[u][c]);
+          }
+      }
     }
     if constexpr (kF32) {
 #pragma unroll
@@ -603,11 +641,13 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
 
 template <typename T>
 hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
+  // chunk voxels kc: a multiple of 8 x (voxels per 16 bytes), <= 256, LDS <= 40 KB
+  constexpr int kVec = Vec16<T>::n;
   const int ls = a.n_s + 1;
-  int kc = (int)((40 * 1024) / ((size_t)ls * sizeof(T)));
-  kc = kc >= 256 ? 256 : (kc / 16) * 16;
-  if (kc < 16) return hipErrorInvalidValue;
-  const size_t lds = (size_t)kc * ls * sizeof(T);
+  int kc = (int)((40 * 1024) / ((size_t)ls * sizeof(T))) - kVec;
+  kc = kc >= 256 ? 256 : (kc / (8 * kVec)) * (8 * kVec);
+  if (kc < 8 * kVec) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(kc + kVec) * ls * sizeof(T);
   const unsigned blocks = (unsigned)a.n_tasks * (unsigned)a.n_krange;
   hipLaunchKernelGGL(k_contract_vec<T>, dim3(blocks), dim3(kThreads), lds, st, F, a, kc);
   return hipGetLastError();
