@@ -119,11 +119,29 @@ __global__ void __launch_bounds__(kThreads, 3) k_contract_vec(const T* __restric
   for (long long x0 = k_lo; x0 < k_hi; x0 += kc) {
     const int len = (int)min((long long)kc, k_hi - x0);
     __syncthreads();
-    // shell s, voxels x0 .. x0 + kc - 1 (zero past the range): x runs fastest,
-    // and a shell's 32 voxels of a block are contiguous in F
-    for (int e = threadIdx.x; e < ns * kc; e += kThreads) {
-      const int sh = e / kc, x = e % kc;
-      chunk[sh * ps + x] = x < len ? F[vox_index(x0 + x, sh, ns)] : (T)0;
+    // voxels x0 .. x0 + kc - 1 (zero past the range; x0 and kc are whole
+    // 32-voxel blocks, whose 32 voxels of a shell are contiguous in F): lane
+    // = voxel of the block, the 8 lane groups take shells g, g + 8, ...; eight
+    // loads per thread are in flight before they are stored
+    {
+      const int lane = threadIdx.x & 31, g = threadIdx.x >> 5;
+      for (int b = 0; b < kc / 32; ++b) {
+        const int x = 32 * b + lane;
+        const T* fb = F + ((x0 >> 5) + b) * (long long)ns * 32 + lane;
+        for (int s0 = g; s0 < ns; s0 += 64) {
+          T v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int sh = s0 + 8 * k;
+            v[k] = (sh < ns && x < len) ? fb[sh * 32] : (T)0;
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int sh = s0 + 8 * k;
+            if (sh < ns) chunk[sh * ps + x] = v[k];
+          }
+        }
+      }
     }
     __syncthreads();
     if (!active) continue;
@@ -641,12 +659,14 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
 
 template <typename T>
 hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
-  // chunk voxels kc: a multiple of 8 x (voxels per 16 bytes), <= 256, LDS <= 40 KB
+  // chunk voxels kc: whole 32-voxel blocks (a multiple of 8 x the voxels per
+  // load), <= 256, LDS <= 40 KB; ranges start on whole blocks
   constexpr int kVec = Vec16<T>::n;
+  static_assert(32 % (8 * kVec) == 0, "a voxel block holds whole load groups");
   const int ls = a.n_s + 1;
   int kc = (int)((40 * 1024) / ((size_t)ls * sizeof(T))) - kVec;
-  kc = kc >= 256 ? 256 : (kc / (8 * kVec)) * (8 * kVec);
-  if (kc < 8 * kVec) return hipErrorInvalidValue;
+  kc = kc >= 256 ? 256 : (kc / 32) * 32;
+  if (kc < 32 || a.n_vox % 32 != 0) return hipErrorInvalidValue;
   const size_t lds = (size_t)(kc + kVec) * ls * sizeof(T);
   const unsigned blocks = (unsigned)a.n_tasks * (unsigned)a.n_krange;
   hipLaunchKernelGGL(k_contract_vec<T>, dim3(blocks), dim3(kThreads), lds, st, F, a, kc);
