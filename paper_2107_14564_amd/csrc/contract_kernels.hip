@@ -607,11 +607,25 @@ __global__ void __launch_bounds__(kGbVox) k_gbuild(const float* __restrict__ F, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* f = reinterpret_cast<float*>(smem_raw);  // [n_s][kGbVox]
   const long long blk0 = (long long)blockIdx.x * (kGbVox / kVoxBlock);
-  // stage: kGbVox/32 voxel blocks, each n_s x 32 contiguous
-  for (int e = threadIdx.x; e < n_s * kGbVox; e += kGbVox) {
-    const int b = e / (n_s * kVoxBlock), r = e % (n_s * kVoxBlock);
-    const int sh = r / kVoxBlock, v = r % kVoxBlock;
-    f[sh * kGbVox + b * kVoxBlock + v] = F[(blk0 + b) * (long long)n_s * kVoxBlock + r];
+  // stage: kGbVox/32 consecutive voxel blocks, each n_s x 32 contiguous, so
+  // element e of the group's piece of F is at src[e]; eight loads per thread
+  // are in flight before they are stored
+  const float* src = F + blk0 * (long long)n_s * kVoxBlock;
+  const int total = n_s * kGbVox;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 8 * kGbVox) {
+    float val[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = e0 + k * kGbVox;
+      val[k] = e < total ? src[e] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = e0 + k * kGbVox;
+      if (e >= total) continue;
+      const int b = e / (n_s * kVoxBlock), r = e % (n_s * kVoxBlock);
+      f[(r / kVoxBlock) * kGbVox + b * kVoxBlock + r % kVoxBlock] = val[k];
+    }
   }
   __syncthreads();
   const int v = threadIdx.x;
