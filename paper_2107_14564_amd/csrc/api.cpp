@@ -177,7 +177,7 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   Sizes& s = p.sz;
   s.n_vox = ne * ne * ne;
   s.n_tri = (long long)p.sel.tri.size();
-  s.spec = (size_t)n * n * (n / 2 + 1) * sizeof(float2);
+  s.spec = (size_t)n * n * (size_t)spec_row(n) * sizeof(float2);
   s.fields32 = (size_t)blocked_elems(s.n_vox, p.geo.n_s) * sizeof(float);
   s.a1_32 = (size_t)p.pass32.a1_elems * sizeof(float2);
   s.a2_32 = (size_t)p.pass32.a2_elems * sizeof(float2);

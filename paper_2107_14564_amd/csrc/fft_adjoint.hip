@@ -17,7 +17,7 @@ template <int N>
 hipError_t adjoint_n(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, const float2* tw,
                      float scale, float beta, hipStream_t st) {
   const long long sn = L.spec_n;
-  const long long n_spec = sn * sn * (sn / 2 + 1);
+  const long long n_spec = sn * sn * spec_row((int)sn);
   hipLaunchKernelGGL(k_zero, dim3((unsigned)((n_spec + 255) / 256)), dim3(256), 0, st, S, n_spec);
   if (L.n_z_blocks > 0)
     hipLaunchKernelGGL(k_g_r2c_z<N>, dim3((unsigned)L.n_z_blocks), dim3(kThrZ), 0, st, G, a2, L.z_off, L.n_shells,

@@ -21,12 +21,13 @@ hipError_t forward_n(const float* delta, float2* spec, float beta, const float2*
   constexpr int TW = fwd_tile_cols(N);
   constexpr unsigned kLds = fwd_dyn_lds(N);
   const int n_ct = (M + 1 + TW - 1) / TW;
-  // y: lines [x][.][kz], stride M+1, planes x
-  hipLaunchKernelGGL(k_fft_axis<N>, dim3(N * n_ct), dim3(kThrAxis), kLds, st, spec, (long long)(M + 1), M + 1,
-                     (long long)N * (M + 1), tw, -1.0f, axis_scale, 0, 0.0f);
-  // x: lines [.][ky][kz], stride N(M+1), planes ky; RSD factor applied here
-  hipLaunchKernelGGL(k_fft_axis<N>, dim3(N * n_ct), dim3(kThrAxis), kLds, st, spec, (long long)N * (M + 1), M + 1,
-                     (long long)(M + 1), tw, -1.0f, axis_scale, beta != 0.0f ? 1 : 0, beta);
+  // y: lines [x][.][kz], stride P = spec_row(N), planes x
+  constexpr long long P = spec_row(N);
+  hipLaunchKernelGGL(k_fft_axis<N>, dim3(N * n_ct), dim3(kThrAxis), kLds, st, spec, P, M + 1, (long long)N * P, tw,
+                     -1.0f, axis_scale, 0, 0.0f);
+  // x: lines [.][ky][kz], stride N P, planes ky; RSD factor applied here
+  hipLaunchKernelGGL(k_fft_axis<N>, dim3(N * n_ct), dim3(kThrAxis), kLds, st, spec, (long long)N * P, M + 1, P, tw,
+                     -1.0f, axis_scale, beta != 0.0f ? 1 : 0, beta);
   return hipGetLastError();
 }
 
@@ -40,8 +41,18 @@ __global__ void k_unblock(const float* __restrict__ F, int shell, int n_s, long 
 // Raises the dynamic LDS limit of the forward strided pass where its tile
 // needs it (N = 1024); done at plan time so launches stay capture-safe.
 hipError_t prepare_forward() {
-  return hipFuncSetAttribute((const void*)k_fft_axis<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)fwd_dyn_lds(1024));
+  hipError_t e = hipFuncSetAttribute((const void*)k_fft_axis<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)fwd_dyn_lds(512));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_fft_axis<640>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fwd_dyn_lds(640));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_fft_axis<768>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fwd_dyn_lds(768));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_fft_axis<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fwd_dyn_lds(1024));
+  return e;
 }
 
 hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, const float2* tw, hipStream_t st) {

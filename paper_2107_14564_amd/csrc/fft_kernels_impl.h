@@ -35,9 +35,9 @@ constexpr int kThrZ = 256;     // threads of a contiguous-pass block
 
 // Forward strided passes (k_fft_axis): columns per block, and the dynamic LDS
 // bytes of the sizes whose tile does not fit the 64 KB of static LDS.
-__host__ __device__ constexpr int fwd_tile_cols(int n) { return n >= 1024 ? 16 : fft_tile_cols(n, false); }
+__host__ __device__ constexpr int fwd_tile_cols(int n) { return n >= 128 ? 16 : fft_tile_cols(n, false); }
 __host__ __device__ constexpr unsigned fwd_dyn_lds(int n) {
-  return n >= 1024 ? (unsigned)(n * fwd_tile_cols(n) + n) * 8u : 0u;
+  return n >= 512 ? (unsigned)(n * fwd_tile_cols(n) + n) * 8u : 0u;
 }
 
 // Shell of block b from the per-shell block prefix sums off[0 .. n_shells]:
@@ -81,7 +81,8 @@ __global__ void __launch_bounds__(kThrZ) k_r2c_z(const float* __restrict__ in, f
   stage_twiddles<N, kThrZ, float>(twl, tw);
   __syncthreads();
   ct_fft<float, M, NL, kThrZ, false, LS, 2>(buf, twl, -1.0f);
-  float2* dst = out + line0 * (M + 1);
+  constexpr long long P = spec_row(N);
+  float2* dst = out + line0 * P;
   for (int e = threadIdx.x; e < NL * (M + 1); e += kThrZ) {
     const int c = e / (M + 1), k = e % (M + 1);
     if (c >= lines) continue;
@@ -91,7 +92,7 @@ __global__ void __launch_bounds__(kThrZ) k_r2c_z(const float* __restrict__ in, f
     const float2 d = scl<float>(sub<float>(zk, zc), 0.5f);  // (Z_k - Z*_{M-k}) / 2
     const float2 w = twl[k];
     const float2 bi = mk<float>(d.y, -d.x);                 // d / i
-    dst[(long long)c * (M + 1) + k] = scl<float>(add<float>(a, mul<float>(w, bi)), scale);
+    dst[(long long)c * P + k] = scl<float>(add<float>(a, mul<float>(w, bi)), scale);
   }
 }
 
@@ -99,9 +100,10 @@ __global__ void __launch_bounds__(kThrZ) k_r2c_z(const float* __restrict__ in, f
 // Lines along an axis of length N with element stride `stride`; n_cols
 // consecutive columns; planes at outer_stride.  rsd_pass (the final x pass):
 // multiply by 1 + beta kz^2/|m|^2.
-// The tile takes fwd_tile_cols(N) columns; at N = 1024 that is 16 (128-byte
-// row pieces) in dynamic LDS (fwd_dyn_lds(N) bytes, above the 64 KB of static
-// LDS), where the static limit would allow 7.
+// The tile takes fwd_tile_cols(N) columns: 16 for N >= 128 (128-byte row
+// pieces; the half-spectrum rows are padded to spec_row(N), so every piece is
+// one cache line), in dynamic LDS (fwd_dyn_lds(N) bytes, above the 64 KB of
+// static LDS) for N >= 512.
 template <int N>
 __global__ void __launch_bounds__(kThrAxis) k_fft_axis(float2* __restrict__ data, long long stride, int n_cols,
                                                        long long outer_stride, const float2* __restrict__ tw,
@@ -167,7 +169,7 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ s
               v = mk<T>((T)1, (T)0);
             } else {
               const long long xrow = mx < 0 ? mx + spec_n : mx;
-              const float2 x = spec[(xrow * spec_n + yrow) * (spec_n / 2 + 1) + kz];
+              const float2 x = spec[(xrow * spec_n + yrow) * spec_row(spec_n) + kz];
               v = mk<T>((T)x.x, (T)x.y);
             }
           }
@@ -418,7 +420,7 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__
     if (m2 < d.lo2 || m2 >= d.hi2) continue;
     const float z = 1.0f + beta * (float)((double)(kz * kz) / (double)m2);
     const long long xrow = mx < 0 ? mx + spec_n : mx;
-    S[(xrow * spec_n + yrow) * (spec_n / 2 + 1) + kz] = scl<float>(buf[e], scale * z);
+    S[(xrow * spec_n + yrow) * spec_row(spec_n) + kz] = scl<float>(buf[e], scale * z);
   }
 }
 

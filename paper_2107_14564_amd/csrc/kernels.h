@@ -16,6 +16,11 @@ namespace bispec {
 __host__ __device__ constexpr int fft_tile_cols(int n, bool f64) {
   return (((f64 ? 4096 : 8192) - n) / n) < 64 ? (((f64 ? 4096 : 8192) - n) / n) : 64;
 }
+// Row length (complex entries) of the half spectrum [N][N][.]: N/2 + 1 rounded
+// up to 16 (128 bytes), so rows start on cache-line boundaries and the strided
+// forward passes' 16-column tiles read and write whole lines.  The entries past
+// N/2 are never read.
+__host__ __device__ constexpr long long spec_row(int n) { return ((long long)(n / 2 + 1) + 15) / 16 * 16; }
 // Contiguous passes over lines of length len (LDS stride len + 1): lines per block.
 __host__ __device__ constexpr int fft_z_lines(int len, bool f64) { return (f64 ? 2048 : 2048) / (len + 1); }
 
