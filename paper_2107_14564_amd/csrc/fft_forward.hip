@@ -39,7 +39,7 @@ __global__ void k_unblock(const float* __restrict__ F, int shell, int n_s, long 
 }  // namespace
 
 // Raises the dynamic LDS limit of the forward strided pass where its tile
-// needs it (N = 1024); done at plan time so launches stay capture-safe.
+// needs it (N >= 512); done at plan time so launches stay capture-safe.
 hipError_t prepare_forward() {
   hipError_t e = hipFuncSetAttribute((const void*)k_fft_axis<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)fwd_dyn_lds(512));
@@ -78,12 +78,12 @@ void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p
     d.lo2 = g.lo2[sn];
     d.hi2 = g.hi2[sn];
     d.rad = g.rad[sn];
-    d.pad = 0;
+    d.wrow = shell_row(d.rad, f64);
     const long long R = d.rad;
     d.a1_off = a1;
     d.a2_off = a2;
-    a1 += (long long)n * (2 * R + 1) * (R + 1);
-    a2 += (long long)n * n * (R + 1);
+    a1 += (long long)n * (2 * R + 1) * d.wrow;
+    a2 += (long long)n * n * d.wrow;
     for (long long ky = -R; ky <= R; ++ky)
       for (long long kz0 = 0; kz0 <= R; kz0 += twc)
         if (ky * ky + kz0 * kz0 < d.hi2) p.x_tiles.push_back(make_int4(sn, (int)ky, (int)kz0, 0));

@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ s
   __syncthreads();
   ct_fft<T, N, TW, kThrAxis, true, 1, 1>(buf, twl, (T)1);
   V2<T>* dst = a1 + d.a1_off;
-  const int wy = 2 * R + 1, wz = R + 1;
+  const int wy = 2 * R + 1, wz = d.wrow;  // row stride (padded)
   for (int e = threadIdx.x; e < N * TW; e += kThrAxis) {
     const int q = e / TW, c = e % TW;
     if (c < cols) dst[((long long)q * wy + (ky + R)) * wz + kz0 + c] = buf[e];
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1
   const int x = (int)(local / n_ct);
   const int kz0 = (int)(local % n_ct) * TW;
   const int cols = min(TW, R + 1 - kz0);
-  const int wy = 2 * R + 1, wz = R + 1;
+  const int wy = 2 * R + 1, wz = d.wrow;  // row stride (padded)
   const V2<T>* src = a1 + d.a1_off + (long long)x * wy * wz;
   staged_copy<N * TW, kThrAxis, V2<T>>(
       [&](int e) {
@@ -252,14 +252,14 @@ __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, O
   const long long b = blockIdx.x;
   const int sn = (int)(b % n_shells);
   const ShellDev d = sh[sn];
-  const int wz = d.rad + 1;
+  const int wz = d.rad + 1, ws = d.wrow;  // used kz columns, row stride
   const long long line0 = (b / n_shells) * NL;
   const int lines = (int)min((long long)NL, n_lines - line0);
-  const V2<T>* src = a2 + d.a2_off + line0 * wz;
+  const V2<T>* src = a2 + d.a2_off + line0 * ws;
   staged_copy<NL * LS, kThrZ, V2<T>>(
       [&](int e) {
         const int c = e / LS, k = e % LS;
-        return (c < lines && k < wz) ? src[(long long)c * wz + k] : mk<T>((T)0, (T)0);
+        return (c < lines && k < wz) ? src[(long long)c * ws + k] : mk<T>((T)0, (T)0);
       },
       [&](int e, V2<T> v) { buf[e] = v; });
   stage_twiddles<N, kThrZ, T>(twl, tw);
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(kThrZ) k_g_r2c_z(const float* __restrict__ G, 
   const long long b = blockIdx.x;
   const int sn = (int)(b / kBps);
   const ShellDev d = sh[sn];
-  const int wz = d.rad + 1;
+  const int wz = d.rad + 1, ws = d.wrow;  // used kz columns, row stride
   const long long line0 = (b - sn * kBps) * NL;
   const int lines = (int)min((long long)NL, n_lines - line0);
   staged_copy<NL * M, kThrZ, float2>(
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kThrZ) k_g_r2c_z(const float* __restrict__ G, 
   stage_twiddles<N, kThrZ, float>(twl, tw);
   __syncthreads();
   ct_fft<float, M, NL, kThrZ, false, LS, 2>(buf, twl, -1.0f);
-  float2* dst = a2 + d.a2_off + line0 * wz;
+  float2* dst = a2 + d.a2_off + line0 * ws;
   for (int e = threadIdx.x; e < NL * wz; e += kThrZ) {
     const int c = e / wz, k = e % wz;
     if (c >= lines) continue;
@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(kThrZ) k_g_r2c_z(const float* __restrict__ G, 
     const float2 a = scl<float>(add<float>(zk, zc), 0.5f);
     const float2 dd = scl<float>(sub<float>(zk, zc), 0.5f);
     const float2 bi = mk<float>(dd.y, -dd.x);
-    dst[(long long)c * wz + k] = add<float>(a, mul<float>(twl[k], bi));
+    dst[(long long)c * ws + k] = add<float>(a, mul<float>(twl[k], bi));
   }
 }
 
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_y(const float2* __restrict__
   const int x = (int)(local / n_ct);
   const int kz0 = (int)(local % n_ct) * TW;
   const int cols = min(TW, R + 1 - kz0);
-  const int wy = 2 * R + 1, wz = R + 1;
+  const int wy = 2 * R + 1, wz = d.wrow;  // row stride (padded)
   const float2* src = a2 + d.a2_off + (long long)x * N * wz;
   staged_copy<N * TW, kThrAxis, float2>(
       [&](int e) { return e % TW < cols ? src[(long long)(e / TW) * wz + kz0 + e % TW] : mk<float>(0.f, 0.f); },
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__
   const ShellDev d = sh[sn];
   const int R = d.rad;
   const int cols = min(TW, R + 1 - kz0);
-  const int wy = 2 * R + 1, wz = R + 1;
+  const int wy = 2 * R + 1, wz = d.wrow;  // row stride (padded)
   const float2* src = a1 + d.a1_off;
   staged_copy<N * TW, kThrAxis, float2>(
       [&](int e) {

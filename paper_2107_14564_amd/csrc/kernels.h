@@ -13,8 +13,19 @@ namespace bispec {
 // Tile shapes of the FFT passes (shared by kernels and host planning).
 // Strided passes: TW columns x N rows per block plus the N-entry twiddle table
 // (<= 64 KB of LDS together).
-__host__ __device__ constexpr int fft_tile_cols(int n, bool f64) {
+__host__ __device__ constexpr int fft_tile_cols_max(int n, bool f64) {
   return (((f64 ? 4096 : 8192) - n) / n) < 64 ? (((f64 ? 4096 : 8192) - n) / n) : 64;
+}
+// ... rounded down to whole 128-byte row pieces (16 float2, 8 double2) where at
+// least one piece fits, so tiles start on cache-line boundaries of padded rows
+__host__ __device__ constexpr int fft_tile_cols(int n, bool f64) {
+  return fft_tile_cols_max(n, f64) >= (f64 ? 8 : 16) ? fft_tile_cols_max(n, f64) / (f64 ? 8 : 16) * (f64 ? 8 : 16)
+                                                     : fft_tile_cols_max(n, f64);
+}
+// Row length (complex entries) of the per-shell intermediates A1_n, A2_n: the
+// R + 1 used kz columns rounded up to 128 bytes, so rows start on cache lines.
+__host__ __device__ constexpr int shell_row(int r, bool f64) {
+  return f64 ? (r + 1 + 7) / 8 * 8 : (r + 1 + 15) / 16 * 16;
 }
 // Row length (complex entries) of the half spectrum [N][N][.]: N/2 + 1 rounded
 // up to 16 (128 bytes), so rows start on cache-line boundaries and the strided
@@ -50,7 +61,7 @@ struct ShellDev {
   long long a1_off;     // element offset of A1_n
   long long a2_off;     // element offset of A2_n
   int rad;              // R = floor(sqrt(hi2 - 1))
-  int pad;
+  int wrow;             // row length of A1_n and A2_n: shell_row(R) >= R + 1
 };
 
 struct ShellLaunch {
