@@ -118,3 +118,32 @@ def test_max_shells_sampled_parity():
         m = metrics(b[idx], ref["B"], ref["S"])
         say(name, m)
         assert m["e_cond"] <= 1e-5 and m["e_norm"] <= 1e-5, (name, m)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("n_g", [640, 768])
+def test_large_radix3_radix5_grids(n_g):
+    """The forward transform at the large mixed-radix sizes (640 = 5 x 128,
+    768 = 3 x 256; 16-column strided tiles in dynamic LDS), with 4 shells, so
+    the shell passes and the contraction run on a small estimator grid: all
+    closable triangles against the float64 oracle on the full grid.  The
+    field is a seeded quadratic transform of white noise (non-zero B)."""
+    import paper_2107_14564_amd as P
+    box, dk, n_s = 2000.0, 1.0, 4
+    g = np.random.default_rng(640 + n_g).standard_normal((n_g,) * 3).astype(np.float32)
+    d32 = (g + np.float32(0.3) * (g * g - np.float32(1.0))).astype(np.float32)
+    del g
+    delta_gpu, delta64 = to_gpu(d32)
+    del d32
+    plan = P.Plan(n_g, box, dk, n_s, rsd_beta=0.5, precision=P.PREC_SPLITBF16)
+    b = plan.run(delta_gpu).cpu().numpy()
+    tri = plan.triangles.numpy()
+    ntri = plan.ntri.numpy()
+    say("n_g=%d G=%d n_tri=%d" % (n_g, plan.n_est, plan.n_tri))
+    plan.close()
+    del delta_gpu
+    ref = fbe.estimate(delta64, box, dk, tri, rsd_beta=0.5, with_abs=True)
+    assert np.array_equal(ntri, ref["ntri"])
+    m = metrics(b, ref["B"], ref["S"])
+    say("n_g=%d" % n_g, m)
+    assert m["e_cond"] <= 1e-5 and m["e_norm"] <= 1e-5, m
