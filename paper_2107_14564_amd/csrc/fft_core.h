@@ -114,10 +114,60 @@ template <typename T> struct Dft<T, 5> {
   }
 };
 
+// Composite radix R = R1 R2 in registers (one LDS pass instead of two):
+// with r = R2 a + b and q = c + R1 d, out[c + R1 d] = sum_b W_R2^(b d)
+// [W_R^(b c) sum_a in[R2 a + b] W_R1^(a c)]: R1-point DFTs over a for each b,
+// the twiddles W_R^(b c), then R2-point DFTs over b for each c.
+// exp(sign 2 pi i m / R) for the twiddles, as (cos, sin) with the sign applied
+template <typename T>
+__device__ __forceinline__ V2<T> rot(V2<T> x, T c, T s, T sign) {
+  return mk<T>(x.x * c - sign * s * x.y, x.y * c + sign * s * x.x);
+}
+
+template <typename T> struct Dft<T, 16> {
+  __device__ __forceinline__ static void run(V2<T>* v, T sign) {
+    const T c1 = (T)0.92387953251128675612818318939678828682;  // cos(pi/8)
+    const T s1 = (T)0.38268343236508977172845998403039886676;  // sin(pi/8)
+    const T h = (T)0.70710678118654752440084436210484903928;   // cos(pi/4)
+    V2<T> y[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      V2<T> t[4] = {v[b], v[b + 4], v[b + 8], v[b + 12]};
+      Dft<T, 4>::run(t, sign);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) y[b][c] = t[c];
+    }
+    // W_16^(b c): m = 1, 2, 3, 2, 4, 6, 3, 6, 9
+    y[1][1] = rot<T>(y[1][1], c1, s1, sign);
+    y[1][2] = rot<T>(y[1][2], h, h, sign);
+    y[1][3] = rot<T>(y[1][3], s1, c1, sign);
+    y[2][1] = rot<T>(y[2][1], h, h, sign);
+    y[2][2] = mul_i<T>(y[2][2], sign);
+    y[2][3] = rot<T>(y[2][3], -h, h, sign);
+    y[3][1] = rot<T>(y[3][1], s1, c1, sign);
+    y[3][2] = rot<T>(y[3][2], -h, h, sign);
+    y[3][3] = rot<T>(y[3][3], -c1, -s1, sign);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      V2<T> t[4] = {y[0][c], y[1][c], y[2][c], y[3][c]};
+      Dft<T, 4>::run(t, sign);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[c + 4 * d] = t[d];
+    }
+  }
+};
+
 // Radix of the next pass for a remaining length rem: 8 while it divides, then
-// 4, 2, 3, 5 (any order of the factors gives a correct Stockham FFT).
+// 4, 2, 3, 5 (any order of the factors gives a correct Stockham FFT); 16 for
+// lines of 1024 and more, where it saves a pass (1024 = 16 16 4 instead of
+// 8 8 8 2; at shorter lengths the larger in-register DFT measured no faster).
 __host__ __device__ constexpr int next_radix(int rem) {
-  return (rem % 8 == 0) ? 8 : (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3 : 5;
+  return (rem >= 1024 && rem % 16 == 0) ? 16
+         : (rem % 8 == 0)              ? 8
+         : (rem % 4 == 0)              ? 4
+         : (rem % 2 == 0)              ? 2
+         : (rem % 3 == 0)              ? 3
+                                       : 5;
 }
 
 // One radix-R pass on NL lines of length N held in LDS, all sizes known at
