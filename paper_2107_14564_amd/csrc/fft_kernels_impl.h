@@ -11,10 +11,13 @@
 //
 // Layouts (all C order, z fastest):
 //   delta  float32 [N][N][N]
-//   spec   complex [N (kx)][N (ky)][N/2+1 (kz)]              (half spectrum, in place)
-//   A1_n   complex [G (x)][2R+1 (ky + R)][R+1 (kz)]          (shell n after the x pass)
-//   A2_n   complex [G (x)][G (y)][R+1 (kz)]                  (shell n after the y pass)
+//   spec   complex [N (kx)][N (ky)][spec_row(N) (kz)]        (half spectrum, in place;
+//                                                             kz <= N/2 used)
+//   A1_n   complex [G (x)][2R+1 (ky + R)][wrow (kz)]         (shell n after the x pass)
+//   A2_n   complex [G (x)][G (y)][wrow (kz)]                 (shell n after the y pass)
 //   F_n    real, voxel-blocked (vox_index) over G^3          (shell field)
+// The kz rows are padded to 128 bytes (spec_row, shell_row = wrow >= R + 1),
+// so strided tiles of whole 128-byte pieces read and write whole cache lines.
 // R = rad[n] is the largest |m_y| of any mode of shell n, so the inverse
 // passes of shell n only touch the ball |m| <= R: the x pass runs only the
 // (ky, kz) columns inside the disc ky^2 + kz^2 < hi2[n], the y pass only the
