@@ -105,24 +105,52 @@ def unit_field(mask: np.ndarray) -> np.ndarray:
     return _irfftn(mask.astype(np.complex128), s=(n_g, n_g, n_g)) * float(n_g) ** 3
 
 
-def triple_sums(fields: dict, triangles: np.ndarray) -> np.ndarray:
+def _as_stack(fields):
+    """(stack, pos): the fields as rows of one 2-D array and shell -> row."""
+    if isinstance(fields, tuple):
+        return fields
+    keys = sorted(fields)
+    stack = np.stack([np.asarray(fields[k], dtype=np.float64).ravel() for k in keys])
+    return stack, {k: r for r, k in enumerate(keys)}
+
+
+def triple_sums(fields, triangles: np.ndarray) -> np.ndarray:
     """sum_x f_a1 f_a2 f_a3 for every row (a1, a2, a3); one product field per
-    distinct (a1, a2) and one matmul over that pair's a3 values."""
+    distinct (a1, a2) and one matmul over that pair's a3 values.  `fields` is
+    a dict shell -> field or a (stack, pos) pair of a 2-D array whose rows are
+    the fields and the shell -> row map (a pair's a3 rows are then read as a
+    view when they are consecutive rows, without a copy)."""
+    stack, pos = _as_stack(fields)
     tri = np.asarray(triangles)
     out = np.zeros(len(tri), dtype=np.float64)
     pairs = {}
     for idx, (a1, a2, a3) in enumerate(tri):
-        pairs.setdefault((int(a1), int(a2)), []).append((idx, int(a3)))
+        pairs.setdefault((int(a1), int(a2)), []).append((pos[int(a3)], idx))
+    prod = np.empty(stack.shape[1], dtype=np.float64)
     for (a1, a2), rows in pairs.items():
-        prod = (fields[a1] * fields[a2]).ravel()
-        stack = np.stack([fields[a3].ravel() for _, a3 in rows])
-        out[[i for i, _ in rows]] = stack @ prod
+        np.multiply(stack[pos[a1]], stack[pos[a2]], out=prod)
+        rows.sort()
+        r = [q for q, _ in rows]
+        if r[-1] - r[0] == len(r) - 1:
+            out[[i for _, i in rows]] = stack[r[0]:r[-1] + 1] @ prod
+        else:
+            for q, i in rows:
+                out[i] = stack[q] @ prod
     return out
 
 
-def abs_triple_sums(fields: dict, triangles: np.ndarray) -> np.ndarray:
+def abs_triple_sums(fields, triangles: np.ndarray) -> np.ndarray:
     """sum_x |f_a1 f_a2 f_a3| (the summation-condition denominator)."""
-    return triple_sums({k: np.abs(v) for k, v in fields.items()}, triangles)
+    stack, pos = _as_stack(fields)
+    return triple_sums((np.abs(stack), pos), triangles)
+
+
+def _field_stack(make, shells, n_vox):
+    """(stack, pos) with row r = make(shells[r]) flattened."""
+    stack = np.empty((len(shells), n_vox), dtype=np.float64)
+    for r, n in enumerate(shells):
+        stack[r] = make(n).ravel()
+    return stack, {n: r for r, n in enumerate(shells)}
 
 
 def estimate(delta: np.ndarray, box_l: float, w: float, triangles: np.ndarray,
@@ -139,12 +167,13 @@ def estimate(delta: np.ndarray, box_l: float, w: float, triangles: np.ndarray,
     shells = sorted(set(int(v) for v in tri.ravel()))
     masks = shell_masks(n_g, w, shells)
     spec = spectrum(delta, box_l, rsd_beta)
-    dfields = {n: shell_field(spec, masks[n]) for n in shells}
+    dfields = _field_stack(lambda n: shell_field(spec, masks[n]), shells, n_g ** 3)
     T = triple_sums(dfields, tri)
     S = abs_triple_sums(dfields, tri) if with_abs else None
     del dfields
-    ufields = {n: unit_field(masks[n]) for n in shells}
+    ufields = _field_stack(lambda n: unit_field(masks[n]), shells, n_g ** 3)
     raw = triple_sums(ufields, tri) / float(n_g) ** 3
+    del ufields
     ntri = np.rint(raw).astype(np.int64)
     resid = float(np.max(np.abs(raw - ntri))) if len(raw) else 0.0
     if resid > ntri_tol:

@@ -199,7 +199,7 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   s.fields64 = (size_t)blocked_elems(s.n_vox, p.geo.n_s) * sizeof(double);
   s.a1_64 = (size_t)p64.a1_elems * sizeof(double2);
   s.a2_64 = (size_t)p64.a2_elems * sizeof(double2);
-  s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 + (size_t)3 * s.n_tri * (sizeof(int4) + sizeof(float)) : 0;
+  s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 + (size_t)3 * s.n_tri * (sizeof(int4) + sizeof(double)) : 0;
   const long long ntasks = (long long)p.tiles.task_off.size() - 1;
   p.n_krange_vec = n_krange_for(ntasks, s.n_vox);
   p.n_krange_mfma = n_krange_mfma_for(s.n_vox);
@@ -495,6 +495,7 @@ int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
   PLAN_HIP(upload(p->mfma_wgrows, p->mfma.wg_rows, s));
   PLAN_HIP(upload(p->mfma_slot, p->mfma.slot_of, s));
   PLAN_HIP(take_workspace(*p, shared, false));
+  PLAN_HIP(prepare_contract_vec());
   // N_tri first (largest memory phase), then the run workspace
   int st = compute_ntri(*p, s);
   if (st) return st;
@@ -544,7 +545,7 @@ int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
     p->n_terms = (long long)terms.size();
     PLAN_HIP(upload(p->g_terms, terms, s));
     PLAN_HIP(upload(p->g_term_off, off, s));
-    PLAN_HIP(dalloc(p->g_w, terms.size() * sizeof(float)));
+    PLAN_HIP(dalloc(p->g_w, terms.size() * sizeof(double)));
     PLAN_HIP(upload(p->ball_shells, p->pass_ball.shells, s));
     PLAN_HIP(upload(p->ball_x, p->pass_ball.x_tiles, s));
     PLAN_HIP(upload(p->ball_y, p->pass_ball.y_off, s));
@@ -685,7 +686,7 @@ int bispec_grad(bispec_plan_t p, const double* gB, float* gdelta, void* hip_stre
   const int n = p->geo.n_g;
   // G_n = sum_t gB_t norm_t d(F_a1 F_a2 F_a3)/dF_n on the (scaled) fields of the last run
   HIP_TRY(launch_gbuild(p->F.as<float>(), gB, p->norm.as<double>(), p->g_terms.as<int4>(), p->n_terms,
-                        p->g_term_off.as<int32_t>(), p->geo.n_s, p->sz.n_vox, p->g_w.as<float>(), p->G.as<float>(),
+                        p->g_term_off.as<int32_t>(), p->geo.n_s, p->sz.n_vox, p->g_w.as<double>(), p->G.as<float>(),
                         s));
   // S = sum_n mask_n Z DFT_G(G_n) * N^{-3/2}, gathered into the n_g spectrum buffer
   ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s, n);

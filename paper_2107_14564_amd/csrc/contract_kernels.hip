@@ -591,17 +591,20 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
 // to G_a1, (t, a1, a3) to G_a2 and (t, a1, a2) to G_a3 (the three factors of
 // d(F_a1 F_a2 F_a3)), and w_t = gB_t * norm_t.  Thread = voxel; the F block
 // of kGbVox voxels x n_s shells is staged in LDS; G is written voxel-blocked.
+// The weights and each voxel's sum over its terms are float64 (the weights of
+// one shell span many orders of magnitude and a shell collects thousands of
+// terms); G itself is rounded to float32 for the adjoint transforms.
 // ============================================================================
 constexpr int kGbVox = 128;
 
 __global__ void k_gweights(const double* __restrict__ gB, const double* __restrict__ norm,
-                           const int4* __restrict__ terms, long long n_terms, float* __restrict__ w) {
+                           const int4* __restrict__ terms, long long n_terms, double* __restrict__ w) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n_terms) w[k] = (float)(gB[terms[k].x] * norm[terms[k].x]);
+  if (k < n_terms) w[k] = gB[terms[k].x] * norm[terms[k].x];
 }
 
 __global__ void __launch_bounds__(kGbVox) k_gbuild(const float* __restrict__ F, const int4* __restrict__ terms,
-                                                   const float* __restrict__ w,
+                                                   const double* __restrict__ w,
                                                    const int32_t* __restrict__ term_off, int n_s,
                                                    float* __restrict__ G) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -631,13 +634,13 @@ __global__ void __launch_bounds__(kGbVox) k_gbuild(const float* __restrict__ F, 
   const int v = threadIdx.x;
   float* g = G + (blk0 + v / kVoxBlock) * (long long)n_s * kVoxBlock + (v % kVoxBlock);
   for (int n = 0; n < n_s; ++n) {
-    float acc = 0.f;
+    double acc = 0.0;
     const int k1 = term_off[n + 1];
     for (int k = term_off[n]; k < k1; ++k) {
       const int4 tm = terms[k];
-      acc = fmaf(w[k] * f[tm.y * kGbVox + v], f[tm.z * kGbVox + v], acc);
+      acc = fma(w[k] * (double)f[tm.y * kGbVox + v], (double)f[tm.z * kGbVox + v], acc);
     }
-    g[n * kVoxBlock] = acc;
+    g[n * kVoxBlock] = (float)acc;
   }
 }
 
@@ -671,15 +674,27 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
   }
 }
 
+// chunk voxels kc of the vector kernels: whole 32-voxel blocks (a multiple of
+// 8 x the voxels per load), <= 256, LDS <= 40 KB where one block fits; plans
+// with more shells (>= 150 in float64) stage one block per chunk in up to
+// kVecLdsMax bytes (the limit is raised at plan time)
+constexpr size_t kVecLdsMax = 80 * 1024;
+template <typename T>
+int vec_chunk(int n_s) {
+  constexpr int kVec = Vec16<T>::n;
+  const int ls = n_s + 1;
+  int kc = (int)((40 * 1024) / ((size_t)ls * sizeof(T))) - kVec;
+  kc = kc >= 256 ? 256 : (kc / 32) * 32;
+  if (kc < 32 && (size_t)(32 + kVec) * ls * sizeof(T) <= kVecLdsMax) kc = 32;
+  return kc;
+}
+
 template <typename T>
 hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
-  // chunk voxels kc: whole 32-voxel blocks (a multiple of 8 x the voxels per
-  // load), <= 256, LDS <= 40 KB; ranges start on whole blocks
   constexpr int kVec = Vec16<T>::n;
   static_assert(32 % (8 * kVec) == 0, "a voxel block holds whole load groups");
   const int ls = a.n_s + 1;
-  int kc = (int)((40 * 1024) / ((size_t)ls * sizeof(T))) - kVec;
-  kc = kc >= 256 ? 256 : (kc / 32) * 32;
+  const int kc = vec_chunk<T>(a.n_s);
   if (kc < 32 || a.n_vox % 32 != 0) return hipErrorInvalidValue;
   const size_t lds = (size_t)(kc + kVec) * ls * sizeof(T);
   const unsigned blocks = (unsigned)a.n_tasks * (unsigned)a.n_krange;
@@ -695,6 +710,16 @@ size_t bf16x3_lds_bytes(int max_s) {
 
 hipError_t launch_contract_fp32(const float* F, const ContractArgs& a, hipStream_t st) { return launch_vec<float>(F, a, st); }
 hipError_t launch_contract_fp64(const double* F, const ContractArgs& a, hipStream_t st) { return launch_vec<double>(F, a, st); }
+
+// Raises the vector kernels' dynamic LDS limit to what 256 shells need; done
+// at plan time, before the first launch.
+hipError_t prepare_contract_vec() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_contract_vec<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kVecLdsMax);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_contract_vec<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kVecLdsMax);
+}
 
 // Raises the kernel's dynamic LDS limit to what 128 staged shells need (the
 // split-bf16 maximum); done at plan time so launches stay capture-safe.
@@ -715,7 +740,7 @@ hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t s
 }
 
 hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, const int4* terms, long long n_terms,
-                        const int32_t* term_off, int n_s, long long n_vox, float* w, float* G, hipStream_t st) {
+                        const int32_t* term_off, int n_s, long long n_vox, double* w, float* G, hipStream_t st) {
   if (n_vox % kGbVox) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gweights, dim3((unsigned)((n_terms + 255) / 256)), dim3(256), 0, st, gB, norm, terms, n_terms,
                      w);

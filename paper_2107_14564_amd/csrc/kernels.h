@@ -123,6 +123,7 @@ struct ContractArgs {
   long long n_tri = 0;
 };
 
+hipError_t prepare_contract_vec();   // once per plan, before the first vector-kernel launch
 hipError_t launch_contract_fp32(const float* F, const ContractArgs& a, hipStream_t st);
 hipError_t launch_contract_fp64(const double* F, const ContractArgs& a, hipStream_t st);
 
@@ -144,7 +145,7 @@ hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t s
 // Gradient: w_k = gB[t_k] norm[t_k]; G_n = sum_{terms (t, j, l) of n} w F_j F_l
 // (terms: int4 (t, j, l, 0) with 0-based shells, grouped by n via term_off[n_s + 1])
 hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, const int4* terms, long long n_terms,
-                        const int32_t* term_off, int n_s, long long n_vox, float* w, float* G, hipStream_t st);
+                        const int32_t* term_off, int n_s, long long n_vox, double* w, float* G, hipStream_t st);
 // pruned forward transforms of every G_n, scattered (times scale * Z) into the half spectrum S
 hipError_t launch_adjoint_shells(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, int n,
                                  const float2* tw, float scale, float beta, hipStream_t st);

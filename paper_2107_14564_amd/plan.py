@@ -35,11 +35,14 @@ class Plan:
         self.labels = torch.tensor(lab, dtype=torch.float64)
         self.ntri = torch.tensor(ntri, dtype=torch.int64)
         self.n_tri = len(abc)
+        # counts bispec_run calls: the plan's shell fields belong to the last run
+        self.runs = 0
 
     def run(self, delta: torch.Tensor) -> torch.Tensor:
         self._check_field(delta)
         out = torch.empty(self.n_tri, dtype=torch.float64, device=delta.device)
         _abi.bispec_run(self.handle, delta.data_ptr(), out.data_ptr(), _stream())
+        self.runs += 1
         return out
 
     def grad(self, g_b: torch.Tensor) -> torch.Tensor:
@@ -80,14 +83,27 @@ class Plan:
 
 
 class _BispecFn(torch.autograd.Function):
+    """bispec_grad differentiates the plan's last run; when the plan has run on
+    other fields since this forward, backward first runs it again on this
+    forward's input (saved, so in-place changes to it raise), which restores
+    the shell fields the vector-Jacobian product needs."""
+
     @staticmethod
     def forward(ctx, delta, plan):
+        delta = delta.contiguous()
         ctx.plan = plan
-        return plan.run(delta.contiguous())
+        out = plan.run(delta)
+        ctx.run_id = plan.runs
+        ctx.save_for_backward(delta)
+        return out
 
     @staticmethod
     def backward(ctx, g_b):
-        return ctx.plan.grad(g_b), None
+        (delta,) = ctx.saved_tensors
+        plan = ctx.plan
+        if plan.runs != ctx.run_id:
+            plan.run(delta)
+        return plan.grad(g_b), None
 
 
 class BatchPlan:

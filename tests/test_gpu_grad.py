@@ -74,6 +74,34 @@ def test_autograd_function():
     plan.close()
 
 
+def test_autograd_after_another_run():
+    """Two forward calls on one plan, then backward of the first: the gradient
+    must be that of the first field (the plan's fields belong to the second
+    run until backward runs the first field again)."""
+    import torch
+    import paper_2107_14564_amd as P
+    d1 = quadratic_ng_field(gaussian_field(32, 300.0, PowerLaw(-1.0), 43), 1.0)
+    d2 = quadratic_ng_field(gaussian_field(32, 300.0, PowerLaw(-1.0), 44), 1.0)
+    g1, _ = to_gpu(d1)
+    g2, _ = to_gpu(d2)
+    plan = P.Plan(32, 300.0, 1.0, 8, flags=P.FLAG_GRAD)
+    x1 = g1.clone().requires_grad_(True)
+    x2 = g2.clone().requires_grad_(True)
+    w = torch.linspace(-1, 1, plan.n_tri, dtype=torch.float64, device=g1.device)
+    B1 = P.bispectrum(x1, plan)
+    B2 = P.bispectrum(x2, plan)
+    (B1 * w).sum().backward()
+    plan.run(g1)
+    direct1 = plan.grad(w)
+    plan.run(g2)
+    direct2 = plan.grad(w)
+    assert torch.equal(x1.grad, direct1)
+    assert not torch.equal(direct1, direct2)
+    (B2 * w).sum().backward()
+    assert torch.equal(x2.grad, direct2)
+    plan.close()
+
+
 @pytest.mark.timeout(600)
 def test_chi2_gradient_ng256_30_shells():
     """The differentiation workload: N_g = 256, L = 1000 Mpc, P = k^-1, f_NG = 1,
@@ -118,3 +146,34 @@ def test_chi2_gradient_ng256_30_shells():
     say("  directional: fd %.8g adjoint %.8g" % (fd, an))
     assert abs(fd - an) <= 1e-4 * abs(an)
     plan.close()
+
+
+# triangles of the 100-shell headline plan spanning shells 1 .. 100: the lowest
+# and highest shells, equilateral, flattened, squeezed and generic shapes
+C3_LIST = [(1, 1, 1), (2, 1, 1), (34, 34, 34), (50, 26, 25), (51, 50, 1), (60, 41, 25), (99, 50, 50),
+           (100, 51, 50), (100, 60, 41), (100, 99, 2), (100, 100, 1), (100, 100, 100)]
+
+
+@pytest.mark.timeout(900)
+def test_vjp_headline_grid_100_shells():
+    """dL/d delta on the headline field and grid (N_g = 512, L = 1500 Mpc,
+    P = k^-1.5, f_NG = 2, RSD beta = 0.5, 100 shells of one k_f, estimator grid
+    G = 320) for a LIST of triangles spanning shells 1 .. 100, against the
+    float64 oracle adjoint on the full 512^3 grid."""
+    import time
+    import torch
+    import paper_2107_14564_amd as P
+    t0 = time.time()
+    dg, d64 = to_gpu(workload_field("ng512"))
+    plan = P.Plan(512, 1500.0, 1.0, 100, rsd_beta=0.5, tri_mode=P.TRI_LIST, triangles=C3_LIST, flags=P.FLAG_GRAD)
+    assert plan.n_tri == len(C3_LIST) and plan.n_est == 320
+    plan.run(dg)
+    v = np.random.default_rng(512).standard_normal(plan.n_tri)
+    g = plan.grad(torch.from_numpy(v).cuda()).cpu().numpy().astype(np.float64)
+    tri, ntri = plan.triangles.numpy(), plan.ntri.numpy()
+    plan.close()
+    del dg
+    say("gpu %.1fs" % (time.time() - t0))
+    ref = adjoint.gradient(d64, 1500.0, 1.0, tri, v, rsd_beta=0.5, ntri=ntri)
+    say("oracle %.1fs" % (time.time() - t0))
+    _cmp(g, ref)
