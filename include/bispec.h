@@ -88,8 +88,11 @@ enum bispec_precision {
 enum bispec_flags {
   BISPEC_FLAG_GRAD = 1u,         /* allocate the workspace for bispec_grad            */
   BISPEC_FLAG_STAGE_TIMING = 2u, /* record HIP events around each stage of run       */
-  BISPEC_FLAG_AUTOTUNE = 4u      /* time the split-bf16 contraction at plan time for  */
+  BISPEC_FLAG_AUTOTUNE = 4u,     /* time the split-bf16 contraction at plan time for  */
                                  /* 64..512 voxel ranges and keep the fastest         */
+  BISPEC_FLAG_NO_WORKSPACE = 8u  /* keep no run workspace: the plan holds its tables  */
+                                 /* and N_tri only and is run by bispec_run_noalloc   */
+                                 /* (excludes GRAD and AUTOTUNE; not in a batch)      */
 };
 
 typedef struct bispec_config {
@@ -154,6 +157,24 @@ int bispec_triangles(bispec_plan_t plan, int32_t* abc, double* k1_mu_t, int64_t*
  * delta: device float32 [N_g^3]; B: device float64 [n_tri].  Both caller-owned,
  * must not alias the plan's memory.  Asynchronous on hip_stream. */
 int bispec_run(bispec_plan_t plan, const float* delta, double* B, void* hip_stream);
+/* (ESTATE for a plan made with BISPEC_FLAG_NO_WORKSPACE.) */
+
+/* bispec_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same pass, with every run buffer (spectrum, shell-pass intermediates, shell
+ * fields, contraction partials) placed in a static per-device scratch array of
+ * 256 MiB instead of the plan's workspace.  Calls no allocating routine; the
+ * caller passes delta and B as for bispec_run.  Works with any plan whose run
+ * buffers fit (e.g. N_g <= 64 with 20 shells), including plans made with
+ * BISPEC_FLAG_NO_WORKSPACE, which hold no workspace of their own.
+ * Every call on a device shares that device's scratch and clears the part it
+ * uses first (one fill kernel on hip_stream), so calls that overlap on
+ * one device race and must be serialised by the caller.  bispec_grad and
+ * bispec_copy_field keep referring to the last bispec_run, not to this call.
+ * The plan's device must be current.
+ * Errors: EINVAL (null argument, run buffers beyond 256 MiB, plan of another
+ * device), EHIP. */
+int bispec_run_noalloc(bispec_plan_t plan, const float* delta, double* B, void* hip_stream);
 
 /* Vector-Jacobian product of the last bispec_run on this plan (needs
  * BISPEC_FLAG_GRAD): gdelta(x) = sum_t gB_t dB_t/d delta(x).

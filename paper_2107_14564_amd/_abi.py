@@ -16,7 +16,7 @@ BISPEC_EHIP, BISPEC_ESTATE, BISPEC_EPREC = -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECUTOFF", -3: "ENOMEM", -4: "EHIP", -5: "ESTATE", -6: "EPREC"}
 TRI_ALL, TRI_K1SET, TRI_MUT_GRID, TRI_LIST = 0, 1, 2, 3
 PREC_SPLITBF16, PREC_FP32 = 0, 1
-FLAG_GRAD, FLAG_STAGE_TIMING, FLAG_AUTOTUNE = 1, 2, 4
+FLAG_GRAD, FLAG_STAGE_TIMING, FLAG_AUTOTUNE, FLAG_NO_WORKSPACE = 1, 2, 4, 8
 
 
 class BispecError(RuntimeError):
@@ -57,6 +57,7 @@ def lib() -> C.CDLL:
             "bispec_num_triangles": [P, C.POINTER(I64)],
             "bispec_triangles": [P, C.POINTER(I32), C.POINTER(D), C.POINTER(I64)],
             "bispec_run": [P, P, P, P],
+            "bispec_run_noalloc": [P, P, P, P],
             "bispec_grad": [P, P, P, P],
             "bispec_set_precision": [P, I32],
             "bispec_stage_times": [P, C.POINTER(C.c_float), I32],
@@ -162,6 +163,11 @@ def bispec_triangles(plan: int):
 def bispec_run(plan: int, delta_ptr: int, b_ptr: int, stream: int = 0):
     _check(lib().bispec_run(C.c_void_p(plan), C.c_void_p(delta_ptr), C.c_void_p(b_ptr), C.c_void_p(stream)),
            "bispec_run")
+
+
+def bispec_run_noalloc(plan: int, delta_ptr: int, b_ptr: int, stream: int = 0):
+    _check(lib().bispec_run_noalloc(C.c_void_p(plan), C.c_void_p(delta_ptr), C.c_void_p(b_ptr),
+                                    C.c_void_p(stream)), "bispec_run_noalloc")
 
 
 def bispec_grad(plan: int, gb_ptr: int, gdelta_ptr: int, stream: int = 0):

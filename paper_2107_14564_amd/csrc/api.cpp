@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +16,12 @@
 #include "kernels.h"
 
 using namespace bispec;
+
+// Static run scratch of bispec_run_noalloc: one copy per device, held by every
+// GPU the library runs on until the process ends.  Host code never uses this
+// name as an address: the per-device address comes from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -94,8 +101,9 @@ struct Sizes {
   long long n_vox = 0, n_tri = 0;
   size_t spec = 0, fields32 = 0, a1_32 = 0, a2_32 = 0, fields64 = 0, a1_64 = 0, a2_64 = 0, grad = 0;
   size_t tables = 0, partial_vec = 0, partial_mfma = 0;
+  bool own_workspace = true;   // false: BISPEC_FLAG_NO_WORKSPACE (runs use the static scratch)
   size_t workspace() const { return spec + fields32 + a1_32 + a2_32 + partial_vec + partial_mfma; }
-  size_t run_total() const { return workspace() + grad + tables; }
+  size_t run_total() const { return (own_workspace ? workspace() : 0) + grad + tables; }
   // planning: the float64 unit shells and their pass buffers exist before the run workspace
   size_t plan_temp() const { return fields64 + a1_64 + a2_64 + n_tri * sizeof(double); }
   size_t plan_peak() const { return std::max(plan_temp() + tables + partial_vec + partial_mfma, run_total()); }
@@ -168,6 +176,8 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   if (p.geo.n_s > 256) return set_err(BISPEC_EINVAL, "n_shells > 256 is not supported by the contraction kernels");
   if (cfg->precision == BISPEC_PREC_SPLITBF16 && p.geo.n_s > kMaxSplitShells)
     return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 128");
+  if ((cfg->flags & BISPEC_FLAG_NO_WORKSPACE) && (cfg->flags & (BISPEC_FLAG_GRAD | BISPEC_FLAG_AUTOTUNE)))
+    return set_err(BISPEC_EINVAL, "BISPEC_FLAG_NO_WORKSPACE excludes BISPEC_FLAG_GRAD and BISPEC_FLAG_AUTOTUNE");
   st = select_triangles(*cfg, p.geo, p.sel, err);
   if (st) return set_err(st, err);
   build_tiles(p.sel, kMaxTilesPerTask, p.tiles);
@@ -215,11 +225,55 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
              p.mfma.slot_of.size() * sizeof(int32_t) +
              p.pass32.x_tiles.size() * sizeof(int4) + (size_t)s.n_tri * 8 +
              (size_t)(n + ne) * 16 + 4096 * 4;
+  s.own_workspace = !(cfg->flags & BISPEC_FLAG_NO_WORKSPACE);
   p.precision = cfg->precision;
   return BISPEC_OK;
 }
 
-WsArgs ws_args(bispec_plan_s& p) {
+// Byte offsets of one pass's buffers in the static scratch (256-byte aligned).
+struct ScratchLayout {
+  size_t spec, a1, a2, F, partial, partial_mfma, total;
+};
+
+ScratchLayout scratch_layout(const Sizes& z) {
+  ScratchLayout l;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  l.spec = take(z.spec);
+  l.a1 = take(z.a1_32);
+  l.a2 = take(z.a2_32);
+  l.F = take(z.fields32);
+  l.partial = take(z.partial_vec);
+  l.partial_mfma = take(z.partial_mfma);
+  l.total = o;
+  return l;
+}
+
+// Device address of the static scratch on device dev (looked up once per
+// device, with that device current).
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+int scratch_base(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return set_err(BISPEC_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_err(BISPEC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BISPEC_OK;
+}
+
+WsArgs ws_args(bispec_plan_s& p, double* partial) {
   WsArgs a;
   a.rows = p.mfma_rows.as<MRowBlock>();
   a.cols = p.mfma_cols.as<SlotCols>();
@@ -229,11 +283,11 @@ WsArgs ws_args(bispec_plan_s& p) {
   a.max_s = p.mfma.max_s;
   a.n_vox = p.sz.n_vox;
   a.n_krange = p.n_krange_mfma;
-  a.partial = p.partial_mfma.as<double>();
+  a.partial = partial;
   return a;
 }
 
-ContractArgs contract_args(bispec_plan_s& p, int n_krange) {
+ContractArgs contract_args(bispec_plan_s& p, int n_krange, double* partial) {
   ContractArgs a;
   a.rows = p.rows.as<RowBlock>();
   a.tiles = p.tile_list.as<Tile>();
@@ -243,7 +297,7 @@ ContractArgs contract_args(bispec_plan_s& p, int n_krange) {
   a.n_s = p.geo.n_s;
   a.n_vox = p.sz.n_vox;
   a.n_krange = n_krange;
-  a.partial = p.partial.as<double>();
+  a.partial = partial;
   a.n_tri = p.sz.n_tri;
   return a;
 }
@@ -293,7 +347,7 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
   HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), L, n, tw.as<double2>(), st));
   a1.release();
   a2.release();
-  ContractArgs ca = contract_args(p, p.n_krange_vec);
+  ContractArgs ca = contract_args(p, p.n_krange_vec, p.partial.as<double>());
   HIP_TRY(launch_contract_fp64(I.as<double>(), ca, st));
   DevBuf sums;
   HIP_TRY(dalloc(sums, (size_t)p.sz.n_tri * sizeof(double)));
@@ -384,30 +438,45 @@ hipError_t take_workspace(bispec_plan_s& p, const Workspace* shared, bool fields
   return e;
 }
 
+// Device buffers one pass writes: the plan's own workspace (or a batch lane's),
+// or pieces of the static scratch array (bispec_run_noalloc).
+struct RunBufs {
+  float2 *spec = nullptr, *a1 = nullptr, *a2 = nullptr;
+  float* F = nullptr;
+  double *partial = nullptr, *partial_mfma = nullptr;
+};
+
+RunBufs own_bufs(bispec_plan_s& p) {
+  RunBufs b;
+  b.spec = p.spec.as<float2>();
+  b.a1 = p.a1.as<float2>();
+  b.a2 = p.a2.as<float2>();
+  b.F = p.F.as<float>();
+  b.partial = p.partial.as<double>();
+  b.partial_mfma = p.partial_mfma.as<double>();
+  return b;
+}
+
 // The four stages of one pass; events only when timing (never under capture).
-int run_core(bispec_plan_s& p, const float* delta, double* B, hipStream_t s, bool timing) {
+int run_core(bispec_plan_s& p, const RunBufs& w, const float* delta, double* B, hipStream_t s, bool timing) {
   const int n = p.geo.n_g;
   if (timing) HIP_TRY(hipEventRecord(p.ev[0], s));
-  HIP_TRY(launch_forward(delta, p.spec.as<float2>(), n, (float)p.geo.beta, p.tw32.as<float2>(), s));
+  HIP_TRY(launch_forward(delta, w.spec, n, (float)p.geo.beta, p.tw32.as<float2>(), s));
   if (timing) HIP_TRY(hipEventRecord(p.ev[1], s));
   ShellLaunch L = shell_launch(p.pass32, p.shells, p.x_tiles, p.y_off, p.z_off, p.geo.n_s, n);
-  HIP_TRY(launch_data_shells(p.spec.as<float2>(), p.a1.as<float2>(), p.a2.as<float2>(), p.F.as<float>(), L,
-                             p.geo.n_est, p.tw32e.as<float2>(), s));
+  HIP_TRY(launch_data_shells(w.spec, w.a1, w.a2, w.F, L, p.geo.n_est, p.tw32e.as<float2>(), s));
   if (timing) HIP_TRY(hipEventRecord(p.ev[2], s));
   if (p.precision == BISPEC_PREC_FP32) {
-    HIP_TRY(launch_contract_fp32(p.F.as<float>(), contract_args(p, p.n_krange_vec), s));
+    HIP_TRY(launch_contract_fp32(w.F, contract_args(p, p.n_krange_vec, w.partial), s));
     if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
-    HIP_TRY(launch_reduce(p.partial.as<double>(), p.n_krange_vec, p.sz.n_tri, p.sz.n_tri, nullptr,
-                          p.norm.as<double>(), B, s));
+    HIP_TRY(launch_reduce(w.partial, p.n_krange_vec, p.sz.n_tri, p.sz.n_tri, nullptr, p.norm.as<double>(), B, s));
   } else {
-    HIP_TRY(launch_contract_bf16x3(p.F.as<float>(), ws_args(p), s));
+    HIP_TRY(launch_contract_bf16x3(w.F, ws_args(p, w.partial_mfma), s));
     if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
-    HIP_TRY(launch_reduce(p.partial_mfma.as<double>(), p.n_krange_mfma,
-                          (long long)p.mfma.n_wg * kTilesPerWg * kMTileElems, p.sz.n_tri, p.mfma_slot.as<int32_t>(),
-                          p.norm.as<double>(), B, s));
+    HIP_TRY(launch_reduce(w.partial_mfma, p.n_krange_mfma, (long long)p.mfma.n_wg * kTilesPerWg * kMTileElems,
+                          p.sz.n_tri, p.mfma_slot.as<int32_t>(), p.norm.as<double>(), B, s));
   }
   if (timing) HIP_TRY(hipEventRecord(p.ev[4], s));
-  p.ran = true;
   return BISPEC_OK;
 }
 
@@ -417,8 +486,10 @@ int many_enqueue(bispec_many_s& m, const float* delta, double* B, hipStream_t s)
   HIP_TRY(hipEventRecord(m.ev_fork, s));
   for (ManyLane* l : m.lanes) HIP_TRY(hipStreamWaitEvent(l->stream, m.ev_fork, 0));
   for (size_t i = 0; i < m.plans.size(); ++i) {
-    int st = run_core(*m.plans[i], delta + m.d_off[i], B + m.b_off[i], m.lanes[m.lane_of[i]]->stream, false);
+    int st = run_core(*m.plans[i], own_bufs(*m.plans[i]), delta + m.d_off[i], B + m.b_off[i],
+                      m.lanes[m.lane_of[i]]->stream, false);
     if (st) return st;
+    m.plans[i]->ran = true;
   }
   for (ManyLane* l : m.lanes) {
     HIP_TRY(hipEventRecord(l->ev_join, l->stream));
@@ -441,7 +512,7 @@ int autotune_mfma(bispec_plan_s& p, hipStream_t s) {
   for (int k : kTuneRanges) {
     if (k > p.n_krange_mfma_cap) continue;
     p.n_krange_mfma = k;
-    const WsArgs a = ws_args(p);
+    const WsArgs a = ws_args(p, p.partial_mfma.as<double>());
     hipError_t e = launch_contract_bf16x3(p.F.as<float>(), a, s);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_contract_bf16x3(p.F.as<float>(), a, s);
@@ -525,7 +596,15 @@ int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
     for (long long t = 0; t < p->sz.n_tri; ++t) norm[t] = p->ntri[t] > 0 ? c / (double)p->ntri[t] : NAN;
     PLAN_HIP(upload(p->norm, norm, s));
   }
-  PLAN_HIP(take_workspace(*p, shared, true));
+  if (p->sz.own_workspace) {
+    PLAN_HIP(take_workspace(*p, shared, true));
+  } else {
+    p->partial.release();
+    p->partial_mfma.release();
+    void* base = nullptr;
+    st = scratch_base(p->device, &base);
+    if (st) return st;
+  }
   if (p->cfg.flags & BISPEC_FLAG_GRAD) {
     PLAN_HIP(dalloc(p->G, p->sz.fields32));
     // terms (t, j, l) of every shell n: d(F_a1 F_a2 F_a3)/dF_n
@@ -675,7 +754,42 @@ int bispec_set_precision(bispec_plan_t p, int32_t precision) {
 
 int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream) {
   if (!p || !delta || !B) return set_err(BISPEC_EINVAL, "null argument");
-  return run_core(*p, delta, B, (hipStream_t)hip_stream, (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING) != 0);
+  if (p->cfg.flags & BISPEC_FLAG_NO_WORKSPACE)
+    return set_err(BISPEC_ESTATE, "plan was made with BISPEC_FLAG_NO_WORKSPACE: run it with bispec_run_noalloc");
+  const int st = run_core(*p, own_bufs(*p), delta, B, (hipStream_t)hip_stream,
+                          (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING) != 0);
+  if (st == BISPEC_OK) p->ran = true;
+  return st;
+}
+
+int bispec_run_noalloc(bispec_plan_t p, const float* delta, double* B, void* hip_stream) {
+  if (!p || !delta || !B) return set_err(BISPEC_EINVAL, "null argument");
+  const ScratchLayout l = scratch_layout(p->sz);
+  if (l.total > kScratchBytes) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "plan needs %.1f MiB of run scratch; the static scratch holds %.0f MiB",
+                  l.total / 1048576.0, kScratchBytes / 1048576.0);
+    return set_err(BISPEC_EINVAL, buf);
+  }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) return set_err(BISPEC_EINVAL, "the plan belongs to another device than the current one");
+  void* base = nullptr;
+  int st = scratch_base(dev, &base);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  unsigned char* b = static_cast<unsigned char*>(base);
+  // the scratch keeps the previous call's contents (of any plan): start from
+  // zero, with a fill kernel (no memset node if the caller is capturing)
+  HIP_TRY(launch_zero(b, l.total, s));
+  RunBufs w;
+  w.spec = reinterpret_cast<float2*>(b + l.spec);
+  w.a1 = reinterpret_cast<float2*>(b + l.a1);
+  w.a2 = reinterpret_cast<float2*>(b + l.a2);
+  w.F = reinterpret_cast<float*>(b + l.F);
+  w.partial = reinterpret_cast<double*>(b + l.partial);
+  w.partial_mfma = reinterpret_cast<double*>(b + l.partial_mfma);
+  return run_core(*p, w, delta, B, s, (p->cfg.flags & BISPEC_FLAG_STAGE_TIMING) != 0);
 }
 
 int bispec_grad(bispec_plan_t p, const double* gB, float* gdelta, void* hip_stream) {
@@ -737,7 +851,8 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
   size_t ws_spec = 0, ws_F = 0, ws_a1 = 0, ws_a2 = 0, ws_pv = 0, ws_pm = 0, tables = 0, temp = 0;
   std::vector<double> cost(n);
   for (int32_t i = 0; i < n; ++i) {
-    if (cfgs[i].flags & BISPEC_FLAG_GRAD) return fail(set_err(BISPEC_EINVAL, "batched plans do not take BISPEC_FLAG_GRAD"));
+    if (cfgs[i].flags & (BISPEC_FLAG_GRAD | BISPEC_FLAG_NO_WORKSPACE))
+      return fail(set_err(BISPEC_EINVAL, "batched plans do not take BISPEC_FLAG_GRAD or BISPEC_FLAG_NO_WORKSPACE"));
     bispec_plan_s* p = new (std::nothrow) bispec_plan_s();
     if (!p) return fail(set_err(BISPEC_ENOMEM, "host allocation failed"));
     p->in_batch = true;

@@ -702,7 +702,24 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// dst[0 .. n16) = 0 in 16-byte stores (grid-stride)
+__global__ void k_zero16(uint4* __restrict__ dst, long long n16) {
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += step)
+    dst[k] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 }  // namespace
+
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes % 16 != 0 || ((uintptr_t)dst & 15) != 0) return hipErrorInvalidValue;
+  const long long n16 = (long long)(bytes / 16);
+  const long long want = (n16 + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(k_zero16, dim3(blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(dst), n16);
+  return hipGetLastError();
+}
 
 size_t bf16x3_lds_bytes(int max_s) {
   return 2 * (size_t)kOct * ((size_t)(max_s + 1) * 32 + 16) + 4 * (size_t)(max_s + 1) * kBS * sizeof(__bf16);

@@ -62,7 +62,7 @@ int validate(const bispec_config& c, std::string& err) {
       break;
     default: return fail(err, BISPEC_EINVAL, "unknown tri_mode");
   }
-  if (c.flags & ~(uint32_t)(BISPEC_FLAG_GRAD | BISPEC_FLAG_STAGE_TIMING | BISPEC_FLAG_AUTOTUNE))
+  if (c.flags & ~(uint32_t)(BISPEC_FLAG_GRAD | BISPEC_FLAG_STAGE_TIMING | BISPEC_FLAG_AUTOTUNE | BISPEC_FLAG_NO_WORKSPACE))
     return fail(err, BISPEC_EINVAL, "unknown flag bits");
   return BISPEC_OK;
 }

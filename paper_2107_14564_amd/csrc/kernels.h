@@ -150,6 +150,8 @@ hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, c
 hipError_t launch_adjoint_shells(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, int n,
                                  const float2* tw, float scale, float beta, hipStream_t st);
 
+// dst[0 .. bytes) = 0 with a fill kernel (capture-safe; bytes and dst 16-byte aligned)
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
 // out[t] = norm[t] * sum_k partial[k * stride + (slot ? slot[t] : t)] (fixed order, float64; norm may be null)
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
                          const double* norm, double* out, hipStream_t st);

@@ -45,6 +45,15 @@ class Plan:
         self.runs += 1
         return out
 
+    def run_noalloc_into(self, delta: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """bispec_run_noalloc into a caller-allocated float64 [n_tri] tensor (the
+        library allocates nothing; the run buffers live in its static scratch)."""
+        self._check_field(delta)
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() != self.n_tri:
+            raise ValueError("out must be a contiguous float64 CUDA tensor of n_tri elements")
+        _abi.bispec_run_noalloc(self.handle, delta.data_ptr(), out.data_ptr(), _stream())
+        return out
+
     def grad(self, g_b: torch.Tensor) -> torch.Tensor:
         g_b = g_b.to(dtype=torch.float64, device=self.device).contiguous()
         if g_b.numel() != self.n_tri:

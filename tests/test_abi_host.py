@@ -144,3 +144,19 @@ def test_estimator_grid():
         with pytest.raises(abi.BispecError) as e:
             grid(512, 1500.0, 1.0, 100, n_est=bad)
         assert e.value.status == abi.BISPEC_EINVAL
+
+
+def test_no_workspace_flag_on_the_host():
+    """BISPEC_FLAG_NO_WORKSPACE plans keep only their tables (run bytes far
+    below a plan with a workspace) and exclude GRAD and AUTOTUNE."""
+    import paper_2107_14564_amd as P
+    c_own, _ = P.make_config(64, 300.0, 1.0, 20)
+    c_none, _ = P.make_config(64, 300.0, 1.0, 20, flags=P.FLAG_NO_WORKSPACE)
+    own = P.bispec_workspace_bytes(c_own)[0]
+    none = P.bispec_workspace_bytes(c_none)[0]
+    assert none < own / 100
+    for extra in (P.FLAG_GRAD, P.FLAG_AUTOTUNE):
+        c_bad, _ = P.make_config(64, 300.0, 1.0, 20, flags=P.FLAG_NO_WORKSPACE | extra)
+        with pytest.raises(P.BispecError) as e:
+            P.bispec_workspace_bytes(c_bad)
+        assert e.value.status == -1
