@@ -98,6 +98,22 @@ def copy_calibration(torch, dev, n_bytes: int = 1 << 30, reps: int = 3):
     return {"bytes_read": n_bytes, "bytes_written": n_bytes, "launches": reps, "kernel": "torch.neg (elementwise)"}
 
 
+def class_work(plan, tri):
+    """Algorithmic work of a plan's contraction and shell transforms: each
+    triangle's triple sum runs over its grid class's G_c^3 points (2 G_c^3 flop,
+    plus G_c^3 per distinct (a1, a2) pair product of the class); the shell
+    transforms write n_s,c G_c^3 field values per class."""
+    import numpy as np
+    tc = plan.tri_class.numpy()
+    flop, field_vox = 0.0, 0.0
+    for k, (g, lo, hi) in enumerate(zip(plan.class_grids, plan.class_shell_lo, plan.class_shell_hi)):
+        t = tri[tc == k]
+        pairs = len({(int(a), int(b)) for a, b, _ in t})
+        flop += float(g) ** 3 * (2.0 * len(t) + pairs)
+        field_vox += float(g) ** 3 * (hi - lo + 1)
+    return flop, field_vox
+
+
 def cpu_baseline(delta32, w: dict, plan_tri, plan_ntri, b_gpu) -> tuple:
     """The float64 oracle on a bounded sample of the same workload: all closable
     triangles of the first S shells at the full grid (forward FFT, S data and S
@@ -197,11 +213,8 @@ def main():
 
     n = w["n_g"]
     g = plan.n_est
-    n_vox = float(g) ** 3       # the triple sums run over the estimator grid
     tri = plan.triangles.numpy()
-    n_pairs = len({(int(a), int(b)) for a, b, _ in tri})
-    # algorithmic work of the contraction: 2 G^3 flop per triangle + G^3 per distinct shell pair product
-    flop = n_vox * (2.0 * plan.n_tri + n_pairs)
+    flop, field_vox = class_work(plan, tri)
     contract_ms = float(stages[2])
     achieved = flop / (contract_ms * 1e-3) / 1e12
     result = {
@@ -226,8 +239,11 @@ def main():
                      "traffic": measured_traffic(args.workload) if prec == P.PREC_SPLITBF16 else None,
                      "kernel": "k_contract_bf16x3" if prec == P.PREC_SPLITBF16 else "k_contract_vec<float>",
                      "algorithmic_flop": flop},
-        "fft_hbm": {"algorithmic_bytes": (8.0 * n ** 3 + 4.0 * n_vox * w["n_shells"]),
-                    "achieved_GBs": (8.0 * n ** 3 + 4.0 * n_vox * w["n_shells"]) / ((stages[0] + stages[1]) * 1e-3) / 1e9,
+        "grid_classes": [{"grid": gc, "shells": [lo, hi], "n_tri": int((plan.tri_class.numpy() == k).sum())}
+                         for k, (gc, lo, hi) in enumerate(zip(plan.class_grids, plan.class_shell_lo,
+                                                              plan.class_shell_hi))],
+        "fft_hbm": {"algorithmic_bytes": (8.0 * n ** 3 + 4.0 * field_vox),
+                    "achieved_GBs": (8.0 * n ** 3 + 4.0 * field_vox) / ((stages[0] + stages[1]) * 1e-3) / 1e9,
                     "peak_GBs": PEAK_HBM_GBS},
         "plan_s": plan_s,
         # the paper's cost unit: mode triangles (sum of N_tri over the bins) per second
@@ -271,11 +287,10 @@ def main():
             stop.synchronize()
             gms.append(start.elapsed_time(stop))
         result["grad_ms"] = float(np.mean(gms))
-        # algorithmic bytes of the adjoint: read every shell field once (G build,
-        # 4 G^3 B per shell), write G (4 G^3 per shell), the forward transforms
-        # read G (4 G^3 per shell), the last inverse writes gdelta (4 N^3)
-        g3 = float(plan.n_est) ** 3
-        gbytes = 12.0 * g3 * w["n_shells"] + 4.0 * float(n) ** 3
+        # algorithmic bytes of the adjoint: read every class field once (G build,
+        # 4 B per field value), write G (4 B), the forward transforms read G
+        # (4 B), the last inverse writes gdelta (4 N^3)
+        gbytes = 12.0 * field_vox + 4.0 * float(n) ** 3
         result["grad_hbm"] = {"algorithmic_bytes": gbytes, "achieved_GBs": gbytes / (result["grad_ms"] * 1e-3) / 1e9,
                               "peak_GBs": PEAK_HBM_GBS}
     if args.copy_calibration:
@@ -341,9 +356,12 @@ def bench_batch(args, np, torch, P):
     flop = 0.0
     for i in range(bp.n):
         tri = bp.triangles[i].numpy()
-        g = P.bispec_estimator_grid(bp_cfg(P, configs[i]))
-        n_pairs = len({(int(a), int(b)) for a, b, _ in tri})
-        flop += float(g) ** 3 * (2.0 * len(tri) + n_pairs)
+        grids, _, _, tc = P.bispec_grid_classes(bp_cfg(P, configs[i]))
+        tc = np.array(tc)
+        for k, g in enumerate(grids):
+            t = tri[tc == k]
+            n_pairs = len({(int(a), int(b)) for a, b, _ in t})
+            flop += float(g) ** 3 * (2.0 * len(t) + n_pairs)
     achieved = flop / (ms * 1e-3) / 1e12
     result = {
         "metric": "triangles/s", "value": bp.n_tri / (ms * 1e-3), "unit": "triangles/s", "n_gpus": 1,

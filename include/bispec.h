@@ -27,11 +27,18 @@
  *   - A bin is closable when a2 + a3 >= a1; only closable bins are selected.
  *   - Every used mode must lie below the aliasing cutoff: (n_shells + 1/2) w <= N_g/3,
  *     else BISPEC_ECUTOFF.
- *   - The shell fields and the triple sums live on an estimator grid of G <= N_g
- *     points per side with G > 3 max|m_i| over every shell mode: Section 2.2's
- *     aliasing argument applied to G shows that the G^3-point sums of
- *     eqs. bsfin and Ntri2 (with N_g^3 replaced by G^3) pick exactly the same
- *     closed triangles, so B and N_tri do not depend on G.  Only the forward
+ *   - The shell fields and the triple sums live on estimator grids of G <= N_g
+ *     points per side: Section 2.2's aliasing argument applied to G shows that
+ *     the G^3-point sums of eqs. bsfin and Ntri2 (with N_g^3 replaced by G^3)
+ *     pick exactly the closed triangles of a bin (a1, a2, a3) once
+ *     G > R_a1 + R_a2 + R_a3 (R_n the largest mode component of shell n; and
+ *     G > 2 R_a1, so a shell's modes keep their signed frequencies), so B and
+ *     N_tri do not depend on G.  A plan splits its triangles into grid
+ *     classes, each on the smallest grid that is exact for all of its
+ *     triangles and worth its extra shell transforms (a cost model);
+ *     bispec_grid_classes tells the split.  The largest grid, the plan's
+ *     estimator grid (bispec_estimator_grid), is the smallest supported size
+ *     above 3 max|m_i| unless n_est forces one grid.  Only the forward
  *     transform (and the last inverse of bispec_grad) runs at N_g.
  *   - delta is float32 [N_g][N_g][N_g], z fastest (C order), on the device.
  *   - B is float64 [n_tri] on the device, ordered like bispec_triangles().
@@ -90,9 +97,11 @@ enum bispec_flags {
   BISPEC_FLAG_STAGE_TIMING = 2u, /* record HIP events around each stage of run       */
   BISPEC_FLAG_AUTOTUNE = 4u,     /* time the split-bf16 contraction at plan time for  */
                                  /* 64..512 voxel ranges and keep the fastest         */
-  BISPEC_FLAG_NO_WORKSPACE = 8u  /* keep no run workspace: the plan holds its tables  */
+  BISPEC_FLAG_NO_WORKSPACE = 8u, /* keep no run workspace: the plan holds its tables */
                                  /* and N_tri only and is run by bispec_run_noalloc   */
                                  /* (excludes GRAD and AUTOTUNE; not in a batch)      */
+  BISPEC_FLAG_ONE_GRID = 16u     /* one grid class: every shell and triangle on the   */
+                                 /* estimator grid (as a nonzero n_est does)          */
 };
 
 typedef struct bispec_config {
@@ -110,8 +119,9 @@ typedef struct bispec_config {
   int32_t precision;      /* enum bispec_precision                                  */
   uint32_t flags;         /* enum bispec_flags                                      */
   int32_t n_est;          /* estimator grid G for the shell fields and triple sums:  */
-                          /*   0 = the smallest supported size above 3 max|m_i|;    */
-                          /*   else a supported size with 3 max|m_i| < n_est <= n_g */
+                          /*   0 = grid classes up to the smallest supported size   */
+                          /*   above 3 max|m_i|; else one class on this supported   */
+                          /*   size, 3 max|m_i| < n_est <= n_g                      */
 } bispec_config;
 
 /* ---- host-only queries (no GPU needed) ------------------------------------ */
@@ -129,6 +139,15 @@ int bispec_shell_stats(const bispec_config* cfg, int64_t* counts, double* mean_k
 
 /* The estimator grid G that a plan of cfg would use (see n_est). */
 int bispec_estimator_grid(const bispec_config* cfg, int32_t* n_est);
+
+/* The plan's estimator-grid classes for cfg (host only): *n_classes receives
+ * their number; for k < capacity, grid[k] is class k's grid and its shell
+ * fields cover shells shell_lo[k] .. shell_hi[k] (1-based, inclusive); if
+ * tri_class (host int32 [n_tri]) is non-null it receives each selected
+ * triangle's class (triangles ordered as bispec_query_triangles).  Classes are
+ * ordered by grid, ascending.  Any output may be null.  Errors: EINVAL, ECUTOFF. */
+int bispec_grid_classes(const bispec_config* cfg, int32_t* n_classes, int32_t* grid, int32_t* shell_lo,
+                        int32_t* shell_hi, int32_t capacity, int32_t* tri_class);
 
 /* Device bytes the plan keeps (run_bytes) and its peak during planning
  * (plan_peak_bytes, which includes the float64 unit shells). */
@@ -190,9 +209,14 @@ int bispec_set_precision(bispec_plan_t plan, int32_t precision);
  * shell FFTs, ms[2] contraction, ms[3] normalisation.  n = entries wanted (<= 4). */
 int bispec_stage_times(bispec_plan_t plan, float* ms, int32_t n);
 
-/* Inspection (tests): copy the data shell D_n of the last run on the estimator
- * grid, divided by dV N_g^{3/2} (the plan's internal scale), into dst
- * (device float32 [G^3], G from bispec_estimator_grid). */
+/* Inspection (tests): the grid on which bispec_copy_field returns shell n
+ * (the largest grid of the classes whose fields cover it).  EINVAL if no
+ * selected triangle uses a class covering the shell. */
+int bispec_field_grid(bispec_plan_t plan, int32_t shell, int32_t* grid);
+
+/* Inspection (tests): copy the data shell D_n of the last run on the grid of
+ * bispec_field_grid, divided by dV N_g^{3/2} (the plan's internal scale), into
+ * dst (device float32 [g^3], C order). */
 int bispec_copy_field(bispec_plan_t plan, int32_t shell, float* dst, void* hip_stream);
 
 /* Release a plan (not one obtained from bispec_many_plan: EINVAL). */

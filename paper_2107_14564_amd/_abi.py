@@ -16,7 +16,7 @@ BISPEC_EHIP, BISPEC_ESTATE, BISPEC_EPREC = -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECUTOFF", -3: "ENOMEM", -4: "EHIP", -5: "ESTATE", -6: "EPREC"}
 TRI_ALL, TRI_K1SET, TRI_MUT_GRID, TRI_LIST = 0, 1, 2, 3
 PREC_SPLITBF16, PREC_FP32 = 0, 1
-FLAG_GRAD, FLAG_STAGE_TIMING, FLAG_AUTOTUNE, FLAG_NO_WORKSPACE = 1, 2, 4, 8
+FLAG_GRAD, FLAG_STAGE_TIMING, FLAG_AUTOTUNE, FLAG_NO_WORKSPACE, FLAG_ONE_GRID = 1, 2, 4, 8, 16
 
 
 class BispecError(RuntimeError):
@@ -53,6 +53,9 @@ def lib() -> C.CDLL:
             "bispec_shell_stats": [cfgp, C.POINTER(I64), C.POINTER(D)],
             "bispec_workspace_bytes": [cfgp, C.POINTER(I64), C.POINTER(I64)],
             "bispec_estimator_grid": [cfgp, C.POINTER(I32)],
+            "bispec_grid_classes": [cfgp, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), I32,
+                                    C.POINTER(I32)],
+            "bispec_field_grid": [P, I32, C.POINTER(I32)],
             "bispec_plan": [cfgp, P, C.POINTER(P)],
             "bispec_num_triangles": [P, C.POINTER(I64)],
             "bispec_triangles": [P, C.POINTER(I32), C.POINTER(D), C.POINTER(I64)],
@@ -136,6 +139,26 @@ def bispec_estimator_grid(cfg) -> int:
     n = C.c_int32(0)
     _check(lib().bispec_estimator_grid(C.byref(cfg), C.byref(n)), "bispec_estimator_grid")
     return n.value
+
+
+def bispec_grid_classes(cfg):
+    """(grids, shell_lo, shell_hi, tri_class): the plan's estimator-grid classes
+    (grids ascending, inclusive 1-based shell ranges) and each triangle's class."""
+    n = C.c_int32(0)
+    _check(lib().bispec_grid_classes(C.byref(cfg), C.byref(n), None, None, None, 0, None), "bispec_grid_classes")
+    k = n.value
+    grid, lo, hi = (C.c_int32 * k)(), (C.c_int32 * k)(), (C.c_int32 * k)()
+    n_tri = C.c_int64(0)
+    _check(lib().bispec_query_triangles(C.byref(cfg), C.byref(n_tri), None, None, 0), "bispec_query_triangles")
+    tc = (C.c_int32 * max(1, n_tri.value))()
+    _check(lib().bispec_grid_classes(C.byref(cfg), C.byref(n), grid, lo, hi, k, tc), "bispec_grid_classes")
+    return list(grid), list(lo), list(hi), list(tc)[:n_tri.value]
+
+
+def bispec_field_grid(plan: int, shell: int) -> int:
+    g = C.c_int32(0)
+    _check(lib().bispec_field_grid(C.c_void_p(plan), int(shell), C.byref(g)), "bispec_field_grid")
+    return g.value
 
 
 def bispec_plan(cfg, stream: int = 0) -> int:

@@ -1,7 +1,15 @@
 // C ABI of the estimator (bispec.h): plan construction, memory management,
 // the N_tri computation at plan time and the asynchronous run.
+//
+// A plan splits its triangles into estimator-grid classes (geometry.h,
+// choose_grid_classes): class c evaluates the shell fields of its shell range
+// on its own grid G_c and contracts its triangles there.  The forward
+// transform runs once at N_g; the shell passes run per class; one grouped
+// split-bf16 launch contracts every class; a reduction per class writes B in
+// the plan's triangle order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -46,6 +54,10 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
   ~DevBuf() { release(); }
   void release() {
     if (p && owned) (void)hipFree(p);
@@ -97,10 +109,33 @@ int n_krange_for(long long groups, long long n_vox) {
 // candidate voxel-range counts of the autotuner (multiples of 8)
 constexpr int kTuneRanges[] = {64, 128, 256, 512};
 
+std::vector<float2> twiddles32(int m) {
+  std::vector<float2> t(m);
+  for (int k = 0; k < m; ++k) {
+    const double ang = 2.0 * M_PI * (double)k / (double)m;
+    t[k] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+  }
+  return t;
+}
+
+std::vector<double2> twiddles64(int m) {
+  std::vector<double2> t(m);
+  for (int k = 0; k < m; ++k) {
+    const double ang = 2.0 * M_PI * (double)k / (double)m;
+    t[k] = make_double2(std::cos(ang), -std::sin(ang));
+  }
+  return t;
+}
+
+// Byte sizes of a plan (sums or maxima over its grid classes).
 struct Sizes {
-  long long n_vox = 0, n_tri = 0;
-  size_t spec = 0, fields32 = 0, a1_32 = 0, a2_32 = 0, fields64 = 0, a1_64 = 0, a2_64 = 0, grad = 0;
-  size_t tables = 0, partial_vec = 0, partial_mfma = 0;
+  long long n_tri = 0;
+  size_t spec = 0;                              // half spectrum at N_g
+  size_t fields32 = 0;                          // every class's float32 fields (resident together)
+  size_t a1_32 = 0, a2_32 = 0;                  // largest class's pass intermediates (and the gradient's ball)
+  size_t fields64 = 0, a1_64 = 0, a2_64 = 0;    // largest class's float64 unit shells (plan time)
+  size_t partial_vec = 0, partial_mfma = 0;     // every class's partials
+  size_t grad = 0, tables = 0;
   bool own_workspace = true;   // false: BISPEC_FLAG_NO_WORKSPACE (runs use the static scratch)
   size_t workspace() const { return spec + fields32 + a1_32 + a2_32 + partial_vec + partial_mfma; }
   size_t run_total() const { return (own_workspace ? workspace() : 0) + grad + tables; }
@@ -108,6 +143,43 @@ struct Sizes {
   size_t plan_temp() const { return fields64 + a1_64 + a2_64 + n_tri * sizeof(double); }
   size_t plan_peak() const { return std::max(plan_temp() + tables + partial_vec + partial_mfma, run_total()); }
 };
+
+// One estimator-grid class: its shells, triangles, tilings, pass tables and
+// the offsets of its buffers inside the plan's.
+struct GridClass {
+  GridClassSpec spec;          // grid, shell range, triangles (plan indices)
+  ShellGeometry geo;           // its shells only (n_s = spec.n_s, n_est = spec.g)
+  Selection sel;               // its triangles with shells renumbered 1 .. n_s
+  TilePlan tiles;              // tasks of <= kMaxTilesPerTask tiles (vector kernels)
+  MfmaTiling mfma;             // span-grouped row blocks (MFMA kernel)
+  ShellPassPlan pass32;
+  long long n_vox = 0, n_tri = 0;
+  size_t fields32 = 0, fields64 = 0, partial_vec = 0, partial_mfma = 0;
+  int n_krange_vec = 8, n_krange_mfma = 8;
+  int n_krange_mfma_cap = 8;   // its MFMA partials hold this many ranges
+  long long f_off = 0;         // element offset of its fields in the plan's F (and G)
+  long long pv_off = 0, pm_off = 0;   // element offsets of its vector and MFMA partials
+  long long n_terms = 0;
+  DevBuf tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols, mfma_wgrows, mfma_slot, tri_out, shells,
+      x_tiles, y_off, z_off, tw32, g_terms, g_term_off, g_w;
+};
+
+// A class's own geometry: shells s_lo .. s_lo + n_s - 1 of g, renumbered from 1.
+ShellGeometry class_geometry(const ShellGeometry& g, const GridClassSpec& c) {
+  ShellGeometry h;
+  h.n_g = g.n_g;
+  h.n_s = c.n_s;
+  h.n_est = c.g;
+  h.box_l = g.box_l;
+  h.w = g.w;
+  h.beta = g.beta;
+  h.lo2.assign(g.lo2.begin() + c.s_lo, g.lo2.begin() + c.s_lo + c.n_s);
+  h.hi2.assign(g.hi2.begin() + c.s_lo, g.hi2.begin() + c.s_lo + c.n_s);
+  h.rad.assign(g.rad.begin() + c.s_lo, g.rad.begin() + c.s_lo + c.n_s);
+  h.counts.assign(g.counts.begin() + c.s_lo, g.counts.begin() + c.s_lo + c.n_s);
+  h.mean_k.assign(g.mean_k.begin() + c.s_lo, g.mean_k.begin() + c.s_lo + c.n_s);
+  return h;
+}
 
 }  // namespace
 
@@ -137,25 +209,21 @@ struct bispec_plan_s {
   bispec_config cfg{};
   ShellGeometry geo;
   Selection sel;
-  TilePlan tiles;        // tasks of <= kMaxTilesPerTask tiles (vector kernels)
-  MfmaTiling mfma;       // span-grouped row blocks (MFMA kernel)
-  ShellPassPlan pass32;
-  ShellPassPlan pass_ball;   // one pseudo-shell covering every shell mode at n_g (last inverse of grad)
+  std::vector<GridClass> cls;  // grid classes, grids ascending
+  ShellPassPlan pass_ball;     // one pseudo-shell covering every shell mode at n_g (last inverse of grad)
   Sizes sz;
   std::vector<int64_t> ntri;
   int precision = BISPEC_PREC_SPLITBF16;
-  int n_krange_vec = 8, n_krange_mfma = 8;
-  int n_krange_mfma_cap = 8;   // the partial buffer holds this many ranges
   bool ran = false;
   bool in_batch = false;       // owned by a bispec_many_t (workspace shared)
   int device = 0;
+  // grouped split-bf16 launch over the classes
+  std::vector<WsGroup> ws_host;
+  int ws_blocks = 0, ws_max_s = 0;
   // device memory
-  DevBuf spec, F, a1, a2, partial, partial_mfma, norm, tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols,
-      mfma_wgrows, mfma_slot, shells, x_tiles,
-      y_off, z_off, tw32, tw32e;
+  DevBuf spec, F, a1, a2, partial, partial_mfma, norm, tw32, ws_groups;
   // gradient workspace (BISPEC_FLAG_GRAD)
-  DevBuf G, g_terms, g_term_off, g_w, ball_shells, ball_x, ball_y, ball_z;
-  long long n_terms = 0;
+  DevBuf G, ball_shells, ball_x, ball_y, ball_z;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   ~bispec_plan_s() {
     for (auto& e : ev)
@@ -180,17 +248,61 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
     return set_err(BISPEC_EINVAL, "BISPEC_FLAG_NO_WORKSPACE excludes BISPEC_FLAG_GRAD and BISPEC_FLAG_AUTOTUNE");
   st = select_triangles(*cfg, p.geo, p.sel, err);
   if (st) return set_err(st, err);
-  build_tiles(p.sel, kMaxTilesPerTask, p.tiles);
-  build_mfma_tiles(p.sel, p.geo.n_s, p.mfma);
-  const long long n = p.geo.n_g, ne = p.geo.n_est;
-  plan_shell_passes(p.geo, (int)ne, false, p.pass32);
+  const long long n = p.geo.n_g;
   Sizes& s = p.sz;
-  s.n_vox = ne * ne * ne;
   s.n_tri = (long long)p.sel.tri.size();
   s.spec = (size_t)n * n * (size_t)spec_row(n) * sizeof(float2);
-  s.fields32 = (size_t)blocked_elems(s.n_vox, p.geo.n_s) * sizeof(float);
-  s.a1_32 = (size_t)p.pass32.a1_elems * sizeof(float2);
-  s.a2_32 = (size_t)p.pass32.a2_elems * sizeof(float2);
+  std::vector<GridClassSpec> specs;
+  choose_grid_classes(p.geo, p.sel, cfg->n_est != 0 || (cfg->flags & BISPEC_FLAG_ONE_GRID), specs);
+  p.cls.clear();
+  p.cls.reserve(specs.size());
+  for (GridClassSpec& spc : specs) {
+    p.cls.emplace_back();
+    GridClass& c = p.cls.back();
+    c.spec = std::move(spc);
+    c.geo = class_geometry(p.geo, c.spec);
+    c.sel.tri.reserve(c.spec.tri.size());
+    for (int32_t t : c.spec.tri) {
+      const Tri& q = p.sel.tri[t];
+      c.sel.tri.push_back({q.a1 - c.spec.s_lo, q.a2 - c.spec.s_lo, q.a3 - c.spec.s_lo});
+    }
+    build_tiles(c.sel, kMaxTilesPerTask, c.tiles);
+    build_mfma_tiles(c.sel, c.geo.n_s, c.mfma);
+    const long long g = c.spec.g;
+    plan_shell_passes(c.geo, (int)g, false, c.pass32);
+    ShellPassPlan p64;
+    plan_shell_passes(c.geo, (int)g, true, p64);
+    c.n_vox = g * g * g;
+    c.n_tri = (long long)c.sel.tri.size();
+    c.fields32 = (size_t)blocked_elems(c.n_vox, c.geo.n_s) * sizeof(float);
+    c.fields64 = (size_t)blocked_elems(c.n_vox, c.geo.n_s) * sizeof(double);
+    const long long ntasks = (long long)c.tiles.task_off.size() - 1;
+    c.n_krange_vec = n_krange_for(ntasks, c.n_vox);
+    c.n_krange_mfma = n_krange_mfma_for(c.n_vox);
+    c.n_krange_mfma_cap = c.n_krange_mfma;
+    if (cfg->flags & BISPEC_FLAG_AUTOTUNE)
+      for (int k : kTuneRanges)
+        if (k <= std::max(8LL, (c.n_vox / (64 * 4)) / 8 * 8)) c.n_krange_mfma_cap = std::max(c.n_krange_mfma_cap, k);
+    c.partial_vec = (size_t)c.n_krange_vec * c.n_tri * sizeof(double);
+    c.partial_mfma = (size_t)c.n_krange_mfma_cap * c.mfma.n_wg * kTilesPerWg * kMTileElems * sizeof(double);
+    // offsets: fields and partials of the classes back to back (256-byte aligned pieces)
+    c.f_off = (long long)(s.fields32 / sizeof(float));
+    s.fields32 += (c.fields32 + 255) / 256 * 256;
+    c.pv_off = (long long)(s.partial_vec / sizeof(double));
+    s.partial_vec += (c.partial_vec + 255) / 256 * 256;
+    c.pm_off = (long long)(s.partial_mfma / sizeof(double));
+    s.partial_mfma += (c.partial_mfma + 255) / 256 * 256;
+    s.a1_32 = std::max(s.a1_32, (size_t)c.pass32.a1_elems * sizeof(float2));
+    s.a2_32 = std::max(s.a2_32, (size_t)c.pass32.a2_elems * sizeof(float2));
+    s.fields64 = std::max(s.fields64, c.fields64);
+    s.a1_64 = std::max(s.a1_64, (size_t)p64.a1_elems * sizeof(double2));
+    s.a2_64 = std::max(s.a2_64, (size_t)p64.a2_elems * sizeof(double2));
+    s.tables += (size_t)c.geo.n_s * c.geo.n_s * c.geo.n_s * sizeof(int32_t) + c.tiles.rows.size() * sizeof(RowBlock) +
+                c.tiles.tiles.size() * sizeof(Tile) + c.mfma.rows.size() * sizeof(MRowBlock) +
+                c.mfma.cols.size() * sizeof(SlotCols) + c.mfma.wg_rows.size() * sizeof(WgRows) +
+                c.mfma.slot_of.size() * sizeof(int32_t) * 2 + c.pass32.x_tiles.size() * sizeof(int4) +
+                (size_t)g * 16 + 4096 * 4;
+  }
   if (cfg->flags & BISPEC_FLAG_GRAD) {
     // the gathered spectrum S lives on the modes of shells 1..n_s: one pseudo-shell at n_g
     ShellGeometry ball;
@@ -203,32 +315,163 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
     plan_shell_passes(ball, (int)n, false, p.pass_ball);
     s.a1_32 = std::max(s.a1_32, (size_t)p.pass_ball.a1_elems * sizeof(float2));
     s.a2_32 = std::max(s.a2_32, (size_t)p.pass_ball.a2_elems * sizeof(float2));
+    s.grad = s.fields32 + (size_t)3 * s.n_tri * (sizeof(int4) + sizeof(double));
   }
-  ShellPassPlan p64;
-  plan_shell_passes(p.geo, (int)ne, true, p64);
-  s.fields64 = (size_t)blocked_elems(s.n_vox, p.geo.n_s) * sizeof(double);
-  s.a1_64 = (size_t)p64.a1_elems * sizeof(double2);
-  s.a2_64 = (size_t)p64.a2_elems * sizeof(double2);
-  s.grad = (cfg->flags & BISPEC_FLAG_GRAD) ? s.fields32 + (size_t)3 * s.n_tri * (sizeof(int4) + sizeof(double)) : 0;
-  const long long ntasks = (long long)p.tiles.task_off.size() - 1;
-  p.n_krange_vec = n_krange_for(ntasks, s.n_vox);
-  p.n_krange_mfma = n_krange_mfma_for(s.n_vox);
-  p.n_krange_mfma_cap = p.n_krange_mfma;
-  if (cfg->flags & BISPEC_FLAG_AUTOTUNE)
-    for (int k : kTuneRanges)
-      if (k <= std::max(8LL, (s.n_vox / (64 * 4)) / 8 * 8)) p.n_krange_mfma_cap = std::max(p.n_krange_mfma_cap, k);
-  s.partial_vec = (size_t)p.n_krange_vec * s.n_tri * sizeof(double);
-  s.partial_mfma = (size_t)p.n_krange_mfma_cap * p.mfma.n_wg * kTilesPerWg * kMTileElems * sizeof(double);
-  s.tables = (size_t)p.geo.n_s * p.geo.n_s * p.geo.n_s * sizeof(int32_t) + p.tiles.rows.size() * sizeof(RowBlock) +
-             p.tiles.tiles.size() * sizeof(Tile) + p.mfma.rows.size() * sizeof(MRowBlock) +
-             p.mfma.cols.size() * sizeof(SlotCols) + p.mfma.wg_rows.size() * sizeof(WgRows) +
-             p.mfma.slot_of.size() * sizeof(int32_t) +
-             p.pass32.x_tiles.size() * sizeof(int4) + (size_t)s.n_tri * 8 +
-             (size_t)(n + ne) * 16 + 4096 * 4;
+  s.tables += (size_t)s.n_tri * 8 + (size_t)n * 16;
   s.own_workspace = !(cfg->flags & BISPEC_FLAG_NO_WORKSPACE);
   p.precision = cfg->precision;
   return BISPEC_OK;
 }
+
+// The grouped split-bf16 launch over the plan's classes, for the classes'
+// current voxel-range counts; blocks of the costliest groups first.
+void build_ws_groups(bispec_plan_s& p) {
+  p.ws_host.clear();
+  std::vector<int> order;
+  for (int k = 0; k < (int)p.cls.size(); ++k)
+    if (p.cls[k].n_tri > 0) order.push_back(k);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const GridClass &x = p.cls[a], &y = p.cls[b];
+    return (double)x.n_vox / x.n_krange_mfma > (double)y.n_vox / y.n_krange_mfma;
+  });
+  int block = 0;
+  p.ws_max_s = 0;
+  for (int k : order) {
+    GridClass& c = p.cls[k];
+    WsGroup w;
+    w.f_off = c.f_off;
+    w.p_off = c.pm_off;
+    w.rows = c.mfma_rows.as<MRowBlock>();
+    w.cols = c.mfma_cols.as<SlotCols>();
+    w.wg_rows = c.mfma_wgrows.as<WgRows>();
+    w.n_vox = c.n_vox;
+    w.n_wg = c.mfma.n_wg;
+    w.n_s = c.geo.n_s;
+    w.max_s = c.mfma.max_s;
+    w.n_krange = c.n_krange_mfma;
+    w.block0 = block;
+    block += w.n_wg * w.n_krange;
+    p.ws_max_s = std::max(p.ws_max_s, w.max_s);
+    p.ws_host.push_back(w);
+  }
+  p.ws_blocks = block;
+}
+
+ContractArgs contract_args(GridClass& c, double* partial_base) {
+  ContractArgs a;
+  a.rows = c.rows.as<RowBlock>();
+  a.tiles = c.tile_list.as<Tile>();
+  a.task_off = c.task_off.as<int32_t>();
+  a.n_tasks = (int)c.tiles.task_off.size() - 1;
+  a.tri_index = c.tri_index.as<int32_t>();
+  a.n_s = c.geo.n_s;
+  a.n_vox = c.n_vox;
+  a.n_krange = c.n_krange_vec;
+  a.partial = partial_base + c.pv_off;
+  a.n_tri = c.n_tri;
+  return a;
+}
+
+ShellLaunch shell_launch(const ShellPassPlan& pp, const DevBuf& shells, const DevBuf& xt, const DevBuf& yo,
+                         const DevBuf& zo, int n_s, int spec_n) {
+  ShellLaunch L;
+  L.n_shells = n_s;
+  L.spec_n = spec_n;
+  L.shells = shells.as<ShellDev>();
+  L.x_tiles = xt.as<int4>();
+  L.n_x_tiles = (long long)pp.x_tiles.size();
+  L.y_off = yo.as<long long>();
+  L.n_y_blocks = pp.y_off.back();
+  L.z_off = zo.as<long long>();
+  L.n_z_blocks = pp.z_off.back();
+  return L;
+}
+
+ShellLaunch class_launch(const bispec_plan_s& p, const GridClass& c) {
+  return shell_launch(c.pass32, c.shells, c.x_tiles, c.y_off, c.z_off, c.geo.n_s, p.geo.n_g);
+}
+
+size_t max_bytes_env() {
+  const char* s = std::getenv("BISPEC_MAX_BYTES");
+  if (!s || !*s) return 0;
+  return (size_t)std::strtoull(s, nullptr, 10);
+}
+
+// N_tri from the float64 unit shells (eqs. 2FT, Ntri2) on the GPU, class by
+// class on the class grids: N_tri = G_c^-3 sum_y I_a1 I_a2 I_a3.
+int compute_ntri(bispec_plan_s& p, hipStream_t st) {
+  DevBuf I, a1, a2, sums;
+  HIP_TRY(dalloc(I, p.sz.fields64));
+  HIP_TRY(dalloc(a1, p.sz.a1_64));
+  HIP_TRY(dalloc(a2, p.sz.a2_64));
+  HIP_TRY(dalloc(sums, (size_t)p.sz.n_tri * sizeof(double)));
+  // per-class pass tables stay alive until the stream has drained
+  std::vector<DevBuf> keep;
+  keep.reserve(p.cls.size() * 5);
+  std::vector<double> denom(p.sz.n_tri, 1.0);
+  for (GridClass& c : p.cls) {
+    const int g = c.spec.g;
+    ShellPassPlan pp;
+    plan_shell_passes(c.geo, g, true, pp);
+    DevBuf shells, xt, yo, zo, tw;
+    HIP_TRY(upload(shells, pp.shells, st));
+    HIP_TRY(upload(xt, pp.x_tiles, st));
+    HIP_TRY(upload(yo, pp.y_off, st));
+    HIP_TRY(upload(zo, pp.z_off, st));
+    HIP_TRY(upload(tw, twiddles64(g), st));
+    ShellLaunch L = shell_launch(pp, shells, xt, yo, zo, c.geo.n_s, p.geo.n_g);
+    HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), L, g, tw.as<double2>(), st));
+    HIP_TRY(launch_contract_fp64(I.as<double>(), contract_args(c, p.partial.as<double>()), st));
+    HIP_TRY(launch_reduce(p.partial.as<double>() + c.pv_off, c.n_krange_vec, c.n_tri, c.n_tri, nullptr, nullptr,
+                          c.tri_out.as<int32_t>(), sums.as<double>(), st));
+    for (int32_t t : c.spec.tri) denom[t] = (double)c.n_vox;
+    keep.push_back(std::move(shells));
+    keep.push_back(std::move(xt));
+    keep.push_back(std::move(yo));
+    keep.push_back(std::move(zo));
+    keep.push_back(std::move(tw));
+  }
+  std::vector<double> h(p.sz.n_tri);
+  HIP_TRY(hipMemcpyAsync(h.data(), sums.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  p.ntri.resize(p.sz.n_tri);
+  double worst = 0.0;
+  long long worst_t = -1;
+  for (long long t = 0; t < p.sz.n_tri; ++t) {
+    const double v = h[t] / denom[t];
+    const double r = std::nearbyint(v);
+    if (std::fabs(v - r) > worst) {
+      worst = std::fabs(v - r);
+      worst_t = t;
+    }
+    p.ntri[t] = (int64_t)r;
+  }
+  if (worst > 1e-3) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "N_tri sum of triangle %lld is %.6f from an integer", worst_t, worst);
+    return set_err(BISPEC_EPREC, buf);
+  }
+  return BISPEC_OK;
+}
+
+int check_memory(size_t need) {
+  size_t free_b = 0, total_b = 0;
+  hipError_t e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) return set_err(BISPEC_EHIP, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+  const size_t cap = max_bytes_env();
+  if (need > free_b || (cap && need > cap)) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "plan needs %.3f GB of device memory; %.3f GB free%s", need / 1e9, free_b / 1e9,
+                  cap ? " (or above BISPEC_MAX_BYTES)" : "");
+    return set_err(BISPEC_ENOMEM, buf);
+  }
+  return BISPEC_OK;
+}
+
+// The run workspace of a plan: its own buffers, or views of a batch's shared ones.
+struct Workspace {
+  DevBuf spec, F, a1, a2, partial, partial_mfma;
+};
 
 // Byte offsets of one pass's buffers in the static scratch (256-byte aligned).
 struct ScratchLayout {
@@ -273,127 +516,6 @@ int scratch_base(int dev, void** out) {
   return BISPEC_OK;
 }
 
-WsArgs ws_args(bispec_plan_s& p, double* partial) {
-  WsArgs a;
-  a.rows = p.mfma_rows.as<MRowBlock>();
-  a.cols = p.mfma_cols.as<SlotCols>();
-  a.wg_rows = p.mfma_wgrows.as<WgRows>();
-  a.n_wg = p.mfma.n_wg;
-  a.n_s = p.geo.n_s;
-  a.max_s = p.mfma.max_s;
-  a.n_vox = p.sz.n_vox;
-  a.n_krange = p.n_krange_mfma;
-  a.partial = partial;
-  return a;
-}
-
-ContractArgs contract_args(bispec_plan_s& p, int n_krange, double* partial) {
-  ContractArgs a;
-  a.rows = p.rows.as<RowBlock>();
-  a.tiles = p.tile_list.as<Tile>();
-  a.task_off = p.task_off.as<int32_t>();
-  a.n_tasks = (int)p.tiles.task_off.size() - 1;
-  a.tri_index = p.tri_index.as<int32_t>();
-  a.n_s = p.geo.n_s;
-  a.n_vox = p.sz.n_vox;
-  a.n_krange = n_krange;
-  a.partial = partial;
-  a.n_tri = p.sz.n_tri;
-  return a;
-}
-
-ShellLaunch shell_launch(const ShellPassPlan& pp, const DevBuf& shells, const DevBuf& xt, const DevBuf& yo,
-                         const DevBuf& zo, int n_s, int spec_n) {
-  ShellLaunch L;
-  L.n_shells = n_s;
-  L.spec_n = spec_n;
-  L.shells = shells.as<ShellDev>();
-  L.x_tiles = xt.as<int4>();
-  L.n_x_tiles = (long long)pp.x_tiles.size();
-  L.y_off = yo.as<long long>();
-  L.n_y_blocks = pp.y_off.back();
-  L.z_off = zo.as<long long>();
-  L.n_z_blocks = pp.z_off.back();
-  return L;
-}
-
-size_t max_bytes_env() {
-  const char* s = std::getenv("BISPEC_MAX_BYTES");
-  if (!s || !*s) return 0;
-  return (size_t)std::strtoull(s, nullptr, 10);
-}
-
-// N_tri from the float64 unit shells (eqs. 2FT, Ntri2) on the GPU, on the
-// estimator grid: N_tri = G^-3 sum_y I_a1 I_a2 I_a3.
-int compute_ntri(bispec_plan_s& p, hipStream_t st) {
-  const int n = p.geo.n_est;
-  ShellPassPlan pp;
-  plan_shell_passes(p.geo, n, true, pp);
-  DevBuf I, a1, a2, shells, xt, yo, zo, tw;
-  HIP_TRY(dalloc(I, p.sz.fields64));
-  HIP_TRY(dalloc(a1, p.sz.a1_64));
-  HIP_TRY(dalloc(a2, p.sz.a2_64));
-  HIP_TRY(upload(shells, pp.shells, st));
-  HIP_TRY(upload(xt, pp.x_tiles, st));
-  HIP_TRY(upload(yo, pp.y_off, st));
-  HIP_TRY(upload(zo, pp.z_off, st));
-  std::vector<double2> t64(n);
-  for (int k = 0; k < n; ++k) {
-    const double ang = 2.0 * M_PI * (double)k / (double)n;
-    t64[k] = make_double2(std::cos(ang), -std::sin(ang));
-  }
-  HIP_TRY(upload(tw, t64, st));
-  ShellLaunch L = shell_launch(pp, shells, xt, yo, zo, p.geo.n_s, p.geo.n_g);
-  HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), L, n, tw.as<double2>(), st));
-  a1.release();
-  a2.release();
-  ContractArgs ca = contract_args(p, p.n_krange_vec, p.partial.as<double>());
-  HIP_TRY(launch_contract_fp64(I.as<double>(), ca, st));
-  DevBuf sums;
-  HIP_TRY(dalloc(sums, (size_t)p.sz.n_tri * sizeof(double)));
-  HIP_TRY(launch_reduce(p.partial.as<double>(), p.n_krange_vec, p.sz.n_tri, p.sz.n_tri, nullptr, nullptr,
-                        sums.as<double>(), st));
-  std::vector<double> h(p.sz.n_tri);
-  HIP_TRY(hipMemcpyAsync(h.data(), sums.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  const double nv = (double)p.sz.n_vox;
-  p.ntri.resize(p.sz.n_tri);
-  double worst = 0.0;
-  long long worst_t = -1;
-  for (long long t = 0; t < p.sz.n_tri; ++t) {
-    const double v = h[t] / nv;
-    const double r = std::nearbyint(v);
-    if (std::fabs(v - r) > worst) { worst = std::fabs(v - r); worst_t = t; }
-    p.ntri[t] = (int64_t)r;
-  }
-  if (worst > 1e-3) {
-    char buf[256];
-    std::snprintf(buf, sizeof buf, "N_tri sum of triangle %lld is %.6f from an integer", worst_t, worst);
-    return set_err(BISPEC_EPREC, buf);
-  }
-  return BISPEC_OK;
-}
-
-
-int check_memory(size_t need) {
-  size_t free_b = 0, total_b = 0;
-  hipError_t e = hipMemGetInfo(&free_b, &total_b);
-  if (e != hipSuccess) return set_err(BISPEC_EHIP, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
-  const size_t cap = max_bytes_env();
-  if (need > free_b || (cap && need > cap)) {
-    char buf[256];
-    std::snprintf(buf, sizeof buf, "plan needs %.3f GB of device memory; %.3f GB free%s", need / 1e9, free_b / 1e9,
-                  cap ? " (or above BISPEC_MAX_BYTES)" : "");
-    return set_err(BISPEC_ENOMEM, buf);
-  }
-  return BISPEC_OK;
-}
-
-// The run workspace of a plan: its own buffers, or views of a batch's shared ones.
-struct Workspace {
-  DevBuf spec, F, a1, a2, partial, partial_mfma;
-};
-
 }  // namespace
 
 struct ManyLane {
@@ -409,8 +531,6 @@ struct ManyLane {
 namespace {
 
 constexpr int kMaxLanes = 4;
-
-
 
 hipError_t take_workspace(bispec_plan_s& p, const Workspace* shared, bool fields) {
   if (shared) {
@@ -463,18 +583,24 @@ int run_core(bispec_plan_s& p, const RunBufs& w, const float* delta, double* B, 
   if (timing) HIP_TRY(hipEventRecord(p.ev[0], s));
   HIP_TRY(launch_forward(delta, w.spec, n, (float)p.geo.beta, p.tw32.as<float2>(), s));
   if (timing) HIP_TRY(hipEventRecord(p.ev[1], s));
-  ShellLaunch L = shell_launch(p.pass32, p.shells, p.x_tiles, p.y_off, p.z_off, p.geo.n_s, n);
-  HIP_TRY(launch_data_shells(w.spec, w.a1, w.a2, w.F, L, p.geo.n_est, p.tw32e.as<float2>(), s));
+  for (GridClass& c : p.cls)
+    HIP_TRY(launch_data_shells(w.spec, w.a1, w.a2, w.F + c.f_off, class_launch(p, c), c.spec.g, c.tw32.as<float2>(),
+                               s));
   if (timing) HIP_TRY(hipEventRecord(p.ev[2], s));
   if (p.precision == BISPEC_PREC_FP32) {
-    HIP_TRY(launch_contract_fp32(w.F, contract_args(p, p.n_krange_vec, w.partial), s));
+    for (GridClass& c : p.cls) HIP_TRY(launch_contract_fp32(w.F + c.f_off, contract_args(c, w.partial), s));
     if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
-    HIP_TRY(launch_reduce(w.partial, p.n_krange_vec, p.sz.n_tri, p.sz.n_tri, nullptr, p.norm.as<double>(), B, s));
+    for (GridClass& c : p.cls)
+      HIP_TRY(launch_reduce(w.partial + c.pv_off, c.n_krange_vec, c.n_tri, c.n_tri, nullptr, p.norm.as<double>(),
+                            c.tri_out.as<int32_t>(), B, s));
   } else {
-    HIP_TRY(launch_contract_bf16x3(w.F, ws_args(p, w.partial_mfma), s));
+    HIP_TRY(launch_contract_bf16x3(w.F, w.partial_mfma, p.ws_groups.as<WsGroup>(), (int)p.ws_host.size(),
+                                   p.ws_max_s, p.ws_blocks, s));
     if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
-    HIP_TRY(launch_reduce(w.partial_mfma, p.n_krange_mfma, (long long)p.mfma.n_wg * kTilesPerWg * kMTileElems,
-                          p.sz.n_tri, p.mfma_slot.as<int32_t>(), p.norm.as<double>(), B, s));
+    for (GridClass& c : p.cls)
+      HIP_TRY(launch_reduce(w.partial_mfma + c.pm_off, c.n_krange_mfma,
+                            (long long)c.mfma.n_wg * kTilesPerWg * kMTileElems, c.n_tri, c.mfma_slot.as<int32_t>(),
+                            p.norm.as<double>(), c.tri_out.as<int32_t>(), B, s));
   }
   if (timing) HIP_TRY(hipEventRecord(p.ev[4], s));
   return BISPEC_OK;
@@ -498,40 +624,72 @@ int many_enqueue(bispec_many_s& m, const float* delta, double* B, hipStream_t s)
   return BISPEC_OK;
 }
 
-// Autotuner: the voxel-range count of the split-bf16 contraction, timed on the
-// plan's own field buffer (zero-filled; MFMA timing does not depend on values).
+// Upload the grouped-launch table of the classes' current range counts.
+int upload_ws_groups(bispec_plan_s& p, hipStream_t s) {
+  build_ws_groups(p);
+  for (const WsGroup& g : p.ws_host)
+    if (!ws_group_ok(g)) return set_err(BISPEC_EINVAL, "a grid class does not fit the split-bf16 kernel");
+  HIP_TRY(upload(p.ws_groups, p.ws_host, s));
+  return BISPEC_OK;
+}
+
+// Autotuner: the voxel-range count of each class's split-bf16 contraction,
+// timed on the plan's own field buffer (zero-filled; MFMA timing does not
+// depend on values), one class alone per launch.
 int autotune_mfma(bispec_plan_s& p, hipStream_t s) {
   if (p.precision != BISPEC_PREC_SPLITBF16) return BISPEC_OK;
   HIP_TRY(hipMemsetAsync(p.F.p, 0, p.sz.fields32, s));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  float best = 1e30f;
-  int best_k = p.n_krange_mfma;
   int st = BISPEC_OK;
-  for (int k : kTuneRanges) {
-    if (k > p.n_krange_mfma_cap) continue;
-    p.n_krange_mfma = k;
-    const WsArgs a = ws_args(p, p.partial_mfma.as<double>());
-    hipError_t e = launch_contract_bf16x3(p.F.as<float>(), a, s);  // warm-up
-    if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_contract_bf16x3(p.F.as<float>(), a, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) {
-      st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-      break;
+  DevBuf one;
+  for (GridClass& c : p.cls) {
+    if (c.n_tri == 0) continue;
+    float best = 1e30f;
+    int best_k = c.n_krange_mfma;
+    for (int k : kTuneRanges) {
+      if (k > c.n_krange_mfma_cap) continue;
+      WsGroup w;
+      w.f_off = c.f_off;
+      w.p_off = c.pm_off;
+      w.rows = c.mfma_rows.as<MRowBlock>();
+      w.cols = c.mfma_cols.as<SlotCols>();
+      w.wg_rows = c.mfma_wgrows.as<WgRows>();
+      w.n_vox = c.n_vox;
+      w.n_wg = c.mfma.n_wg;
+      w.n_s = c.geo.n_s;
+      w.max_s = c.mfma.max_s;
+      w.n_krange = k;
+      w.block0 = 0;
+      if (!ws_group_ok(w)) continue;
+      hipError_t e = upload(one, std::vector<WsGroup>{w}, s);
+      const int blocks = w.n_wg * k;
+      if (e == hipSuccess)
+        e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, w.max_s,
+                                   blocks, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r)
+        e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, w.max_s,
+                                   blocks, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_k = k;
+      }
     }
-    if (ms < best) {
-      best = ms;
-      best_k = k;
-    }
+    if (st) break;
+    c.n_krange_mfma = best_k;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  p.n_krange_mfma = best_k;
   return st;
 }
 
@@ -543,57 +701,54 @@ int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) return set_err(BISPEC_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
   }
-  const int ns = p->geo.n_s;
 #define PLAN_HIP(expr)                                                                   \
   do {                                                                                   \
     hipError_t e_ = (expr);                                                              \
     if (e_ != hipSuccess) return set_err(BISPEC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
-  // triangle index table (i-1, j-1, l-1) -> t
-  {
+  for (GridClass& c : p->cls) {
+    const int ns = c.geo.n_s;
+    // triangle index table (i-1, j-1, l-1) -> class triangle
     std::vector<int32_t> idx((size_t)ns * ns * ns, -1);
-    for (size_t t = 0; t < p->sel.tri.size(); ++t) {
-      const Tri& q = p->sel.tri[t];
+    for (size_t t = 0; t < c.sel.tri.size(); ++t) {
+      const Tri& q = c.sel.tri[t];
       idx[((size_t)(q.a1 - 1) * ns + (q.a2 - 1)) * ns + (q.a3 - 1)] = (int32_t)t;
     }
-    PLAN_HIP(upload(p->tri_index, idx, s));
+    PLAN_HIP(upload(c.tri_index, idx, s));
+    PLAN_HIP(upload(c.rows, c.tiles.rows, s));
+    PLAN_HIP(upload(c.tile_list, c.tiles.tiles, s));
+    PLAN_HIP(upload(c.task_off, c.tiles.task_off, s));
+    PLAN_HIP(upload(c.mfma_rows, c.mfma.rows, s));
+    PLAN_HIP(upload(c.mfma_cols, c.mfma.cols, s));
+    PLAN_HIP(upload(c.mfma_wgrows, c.mfma.wg_rows, s));
+    PLAN_HIP(upload(c.mfma_slot, c.mfma.slot_of, s));
+    PLAN_HIP(upload(c.tri_out, c.spec.tri, s));
   }
-  PLAN_HIP(upload(p->rows, p->tiles.rows, s));
-  PLAN_HIP(upload(p->tile_list, p->tiles.tiles, s));
-  PLAN_HIP(upload(p->task_off, p->tiles.task_off, s));
-  PLAN_HIP(upload(p->mfma_rows, p->mfma.rows, s));
-  PLAN_HIP(upload(p->mfma_cols, p->mfma.cols, s));
-  PLAN_HIP(upload(p->mfma_wgrows, p->mfma.wg_rows, s));
-  PLAN_HIP(upload(p->mfma_slot, p->mfma.slot_of, s));
   PLAN_HIP(take_workspace(*p, shared, false));
   PLAN_HIP(prepare_contract_vec());
   // N_tri first (largest memory phase), then the run workspace
   int st = compute_ntri(*p, s);
   if (st) return st;
-  PLAN_HIP(upload(p->shells, p->pass32.shells, s));
-  PLAN_HIP(upload(p->x_tiles, p->pass32.x_tiles, s));
-  PLAN_HIP(upload(p->y_off, p->pass32.y_off, s));
-  PLAN_HIP(upload(p->z_off, p->pass32.z_off, s));
+  for (GridClass& c : p->cls) {
+    PLAN_HIP(upload(c.shells, c.pass32.shells, s));
+    PLAN_HIP(upload(c.x_tiles, c.pass32.x_tiles, s));
+    PLAN_HIP(upload(c.y_off, c.pass32.y_off, s));
+    PLAN_HIP(upload(c.z_off, c.pass32.z_off, s));
+    PLAN_HIP(upload(c.tw32, twiddles32(c.spec.g), s));
+  }
   {
-    const int n = p->geo.n_g, ne = p->geo.n_est;
-    auto twiddles = [](int m) {
-      std::vector<float2> t(m);
-      for (int k = 0; k < m; ++k) {
-        const double ang = 2.0 * M_PI * (double)k / (double)m;
-        t[k] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
-      }
-      return t;
-    };
-    PLAN_HIP(upload(p->tw32, twiddles(n), s));
-    PLAN_HIP(upload(p->tw32e, twiddles(ne), s));
-    // The fields are F_s = D / (dV N^{3/2}) on G^3 points (forward transform
-    // scaled by N^{-3/2}); eq. bsfin with the sum over the G grid:
-    //   B = (dV N^{3/2})^3 sum_y F_s F_s F_s / (V N_tri G^3)
+    const int n = p->geo.n_g;
+    PLAN_HIP(upload(p->tw32, twiddles32(n), s));
+    // The fields are F_s = D / (dV N^{3/2}) on G_c^3 points (forward transform
+    // scaled by N^{-3/2}); eq. bsfin with the sum over the class grid:
+    //   B = (dV N^{3/2})^3 sum_y F_s F_s F_s / (V N_tri G_c^3)
     const double V = p->geo.box_l * p->geo.box_l * p->geo.box_l;
     const double dV = V / ((double)n * n * n);
-    const double c = dV * dV * dV * std::pow((double)n, 4.5) / (V * (double)ne * ne * ne);
     std::vector<double> norm(p->sz.n_tri);
-    for (long long t = 0; t < p->sz.n_tri; ++t) norm[t] = p->ntri[t] > 0 ? c / (double)p->ntri[t] : NAN;
+    for (const GridClass& c : p->cls) {
+      const double cc = dV * dV * dV * std::pow((double)n, 4.5) / (V * (double)c.n_vox);
+      for (int32_t t : c.spec.tri) norm[t] = p->ntri[t] > 0 ? cc / (double)p->ntri[t] : NAN;
+    }
     PLAN_HIP(upload(p->norm, norm, s));
   }
   if (p->sz.own_workspace) {
@@ -607,24 +762,28 @@ int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
   }
   if (p->cfg.flags & BISPEC_FLAG_GRAD) {
     PLAN_HIP(dalloc(p->G, p->sz.fields32));
-    // terms (t, j, l) of every shell n: d(F_a1 F_a2 F_a3)/dF_n
-    std::vector<std::vector<int4>> per(ns);
-    for (size_t t = 0; t < p->sel.tri.size(); ++t) {
-      const Tri& q = p->sel.tri[t];
-      per[q.a1 - 1].push_back(make_int4((int)t, q.a2 - 1, q.a3 - 1, 0));
-      per[q.a2 - 1].push_back(make_int4((int)t, q.a1 - 1, q.a3 - 1, 0));
-      per[q.a3 - 1].push_back(make_int4((int)t, q.a1 - 1, q.a2 - 1, 0));
+    for (GridClass& c : p->cls) {
+      const int ns = c.geo.n_s;
+      // terms (t, j, l) of every class shell n: d(F_a1 F_a2 F_a3)/dF_n, t the plan's triangle index
+      std::vector<std::vector<int4>> per(ns);
+      for (size_t k = 0; k < c.sel.tri.size(); ++k) {
+        const Tri& q = c.sel.tri[k];
+        const int t = c.spec.tri[k];
+        per[q.a1 - 1].push_back(make_int4(t, q.a2 - 1, q.a3 - 1, 0));
+        per[q.a2 - 1].push_back(make_int4(t, q.a1 - 1, q.a3 - 1, 0));
+        per[q.a3 - 1].push_back(make_int4(t, q.a1 - 1, q.a2 - 1, 0));
+      }
+      std::vector<int4> terms;
+      std::vector<int32_t> off(1, 0);
+      for (int m = 0; m < ns; ++m) {
+        terms.insert(terms.end(), per[m].begin(), per[m].end());
+        off.push_back((int32_t)terms.size());
+      }
+      c.n_terms = (long long)terms.size();
+      PLAN_HIP(upload(c.g_terms, terms, s));
+      PLAN_HIP(upload(c.g_term_off, off, s));
+      PLAN_HIP(dalloc(c.g_w, terms.size() * sizeof(double)));
     }
-    std::vector<int4> terms;
-    std::vector<int32_t> off(1, 0);
-    for (int n = 0; n < ns; ++n) {
-      terms.insert(terms.end(), per[n].begin(), per[n].end());
-      off.push_back((int32_t)terms.size());
-    }
-    p->n_terms = (long long)terms.size();
-    PLAN_HIP(upload(p->g_terms, terms, s));
-    PLAN_HIP(upload(p->g_term_off, off, s));
-    PLAN_HIP(dalloc(p->g_w, terms.size() * sizeof(double)));
     PLAN_HIP(upload(p->ball_shells, p->pass_ball.shells, s));
     PLAN_HIP(upload(p->ball_x, p->pass_ball.x_tiles, s));
     PLAN_HIP(upload(p->ball_y, p->pass_ball.y_off, s));
@@ -638,9 +797,20 @@ int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
     st = autotune_mfma(*p, s);
     if (st) return st;
   }
+  st = upload_ws_groups(*p, s);
+  if (st) return st;
   PLAN_HIP(hipStreamSynchronize(s));
 #undef PLAN_HIP
   return BISPEC_OK;
+}
+
+// The class holding shell n (1-based) on the largest grid.
+const GridClass* field_class(const bispec_plan_s& p, int shell) {
+  const GridClass* best = nullptr;
+  for (const GridClass& c : p.cls)
+    if (shell - 1 >= c.spec.s_lo && shell - 1 < c.spec.s_lo + c.spec.n_s && (!best || c.spec.g > best->spec.g))
+      best = &c;
+  return best;
 }
 
 }  // namespace
@@ -693,6 +863,31 @@ int bispec_estimator_grid(const bispec_config* cfg, int32_t* n_est) {
   int st = build_shells(*cfg, g, err);
   if (st) return set_err(st, err);
   *n_est = g.n_est;
+  return BISPEC_OK;
+}
+
+int bispec_grid_classes(const bispec_config* cfg, int32_t* n_classes, int32_t* grid, int32_t* shell_lo,
+                        int32_t* shell_hi, int32_t capacity, int32_t* tri_class) {
+  if (!cfg || !n_classes) return set_err(BISPEC_EINVAL, "null argument");
+  std::string err;
+  ShellGeometry g;
+  int st = build_shells(*cfg, g, err);
+  if (st) return set_err(st, err);
+  Selection s;
+  st = select_triangles(*cfg, g, s, err);
+  if (st) return set_err(st, err);
+  std::vector<GridClassSpec> cl;
+  choose_grid_classes(g, s, cfg->n_est != 0 || (cfg->flags & BISPEC_FLAG_ONE_GRID), cl);
+  *n_classes = (int32_t)cl.size();
+  for (int k = 0; k < (int)cl.size(); ++k) {
+    if (k < capacity) {
+      if (grid) grid[k] = cl[k].g;
+      if (shell_lo) shell_lo[k] = cl[k].s_lo + 1;
+      if (shell_hi) shell_hi[k] = cl[k].s_lo + cl[k].n_s;
+    }
+    if (tri_class)
+      for (int32_t t : cl[k].tri) tri_class[t] = k;
+  }
   return BISPEC_OK;
 }
 
@@ -798,15 +993,19 @@ int bispec_grad(bispec_plan_t p, const double* gB, float* gdelta, void* hip_stre
   if (!p->ran) return set_err(BISPEC_ESTATE, "bispec_grad needs a preceding bispec_run");
   hipStream_t s = (hipStream_t)hip_stream;
   const int n = p->geo.n_g;
-  // G_n = sum_t gB_t norm_t d(F_a1 F_a2 F_a3)/dF_n on the (scaled) fields of the last run
-  HIP_TRY(launch_gbuild(p->F.as<float>(), gB, p->norm.as<double>(), p->g_terms.as<int4>(), p->n_terms,
-                        p->g_term_off.as<int32_t>(), p->geo.n_s, p->sz.n_vox, p->g_w.as<double>(), p->G.as<float>(),
-                        s));
-  // S = sum_n mask_n Z DFT_G(G_n) * N^{-3/2}, gathered into the n_g spectrum buffer
-  ShellLaunch L = shell_launch(p->pass32, p->shells, p->x_tiles, p->y_off, p->z_off, p->geo.n_s, n);
+  // G_n = sum_t gB_t norm_t d(F_a1 F_a2 F_a3)/dF_n on each class's (scaled) fields of the last run
+  for (GridClass& c : p->cls)
+    HIP_TRY(launch_gbuild(p->F.as<float>() + c.f_off, gB, p->norm.as<double>(), c.g_terms.as<int4>(), c.n_terms,
+                          c.g_term_off.as<int32_t>(), c.geo.n_s, c.n_vox, c.g_w.as<double>(),
+                          p->G.as<float>() + c.f_off, s));
+  // S = sum_c sum_n mask_n Z DFT_{G_c}(G_n) * N^{-3/2}, gathered into the n_g spectrum buffer
   const float scale = (float)std::pow((double)n, -1.5);
-  HIP_TRY(launch_adjoint_shells(p->G.as<float>(), p->a1.as<float2>(), p->a2.as<float2>(), p->spec.as<float2>(), L,
-                                p->geo.n_est, p->tw32e.as<float2>(), scale, (float)p->geo.beta, s));
+  for (size_t k = 0; k < p->cls.size(); ++k) {
+    GridClass& c = p->cls[k];
+    HIP_TRY(launch_adjoint_shells(p->G.as<float>() + c.f_off, p->a1.as<float2>(), p->a2.as<float2>(),
+                                  p->spec.as<float2>(), class_launch(*p, c), c.spec.g, c.tw32.as<float2>(), scale,
+                                  (float)p->geo.beta, k == 0, s));
+  }
   // gdelta = unnormalised inverse transform of S on the n_g grid (one pseudo-shell: natural layout)
   ShellLaunch B = shell_launch(p->pass_ball, p->ball_shells, p->ball_x, p->ball_y, p->ball_z, 1, n);
   HIP_TRY(launch_data_shells(p->spec.as<float2>(), p->a1.as<float2>(), p->a2.as<float2>(), gdelta, B, n,
@@ -822,11 +1021,21 @@ int bispec_stage_times(bispec_plan_t p, float* ms, int32_t n) {
   return BISPEC_OK;
 }
 
+int bispec_field_grid(bispec_plan_t p, int32_t shell, int32_t* grid) {
+  if (!p || !grid) return set_err(BISPEC_EINVAL, "null argument");
+  const GridClass* c = (shell >= 1 && shell <= p->geo.n_s) ? field_class(*p, shell) : nullptr;
+  if (!c) return set_err(BISPEC_EINVAL, "shell out of range or used by no selected triangle");
+  *grid = c->spec.g;
+  return BISPEC_OK;
+}
+
 int bispec_copy_field(bispec_plan_t p, int32_t shell, float* dst, void* hip_stream) {
   if (!p || !dst) return set_err(BISPEC_EINVAL, "null argument");
-  if (shell < 1 || shell > p->geo.n_s) return set_err(BISPEC_EINVAL, "shell out of range");
+  const GridClass* c = (shell >= 1 && shell <= p->geo.n_s) ? field_class(*p, shell) : nullptr;
+  if (!c) return set_err(BISPEC_EINVAL, "shell out of range or used by no selected triangle");
   if (!p->ran) return set_err(BISPEC_ESTATE, "no run recorded");
-  HIP_TRY(launch_unblock(p->F.as<float>(), shell - 1, p->geo.n_s, p->sz.n_vox, dst, (hipStream_t)hip_stream));
+  HIP_TRY(launch_unblock(p->F.as<float>() + c->f_off, shell - 1 - c->spec.s_lo, c->geo.n_s, c->n_vox, dst,
+                         (hipStream_t)hip_stream));
   return BISPEC_OK;
 }
 
@@ -871,7 +1080,9 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
     m->d_off.push_back(m->d_off.back() + (int64_t)p->geo.n_g * p->geo.n_g * p->geo.n_g);
     m->b_off.push_back(m->b_off.back() + (int64_t)z.n_tri);
     // run-time estimate: shell fields written plus contraction tiles, per voxel
-    cost[i] = (double)z.n_vox * (p->geo.n_s + 2.0 * (double)p->mfma.tiles);
+    double c = 0.0;
+    for (const GridClass& k : p->cls) c += (double)k.n_vox * (k.geo.n_s + 2.0 * (double)k.mfma.tiles);
+    cost[i] = c;
   }
   // lanes: as many concurrent workspaces as members, kMaxLanes and memory allow
   const size_t lane_bytes = ws_spec + ws_F + ws_a1 + ws_a2 + ws_pv + ws_pm;

@@ -540,12 +540,46 @@ __device__ __forceinline__ void ws_idle(const float* __restrict__ F, const WsArg
   }
 }
 
-__global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __restrict__ F, WsArgs a) {
+// One launch over several groups (the estimator-grid classes of a plan, or of
+// every member of a batch): group q owns blocks [block0, block0 + n_wg n_krange)
+// (block0 a multiple of 8, so the local block index keeps the XCD of the
+// global one), reads its fields at F + f_off and writes its partials at
+// partial + p_off.
+__device__ __forceinline__ int ws_group_of(const WsGroup* __restrict__ groups, int n_groups, int b) {
+  int lo = 0, hi = n_groups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __restrict__ F_all,
+                                                                double* __restrict__ partial_all,
+                                                                const WsGroup* __restrict__ groups, int n_groups) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const WsGroup& grp = groups[ws_group_of(groups, n_groups, (int)blockIdx.x)];
+  WsArgs a;
+  a.rows = grp.rows;
+  a.cols = grp.cols;
+  a.wg_rows = grp.wg_rows;
+  a.n_wg = grp.n_wg;
+  a.n_s = grp.n_s;
+  a.max_s = grp.max_s;
+  a.n_vox = grp.n_vox;
+  a.n_krange = grp.n_krange;
+  a.partial = partial_all + grp.p_off;
+  const float* __restrict__ F = F_all + grp.f_off;
   const int ns1 = a.max_s + 1;
   const WsLayout y = ws_layout(ns1);
   int wg, kr;
-  xcd_map(a.n_wg, wg, kr);
+  {
+    const int b = (int)blockIdx.x - grp.block0;
+    const int xcd = b & 7, q = b >> 3;
+    wg = q % a.n_wg;
+    kr = xcd + 8 * (q / a.n_wg);
+  }
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const WgRows wr = a.wg_rows[wg];
   const int zr = wr.s_n;  // the zero row
@@ -655,6 +689,7 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
                                                               long long stride, long long n_tri,
                                                               const int32_t* __restrict__ slot,
                                                               const double* __restrict__ norm,
+                                                              const int32_t* __restrict__ out_idx,
                                                               double* __restrict__ out) {
   __shared__ double part[kRedPart][kRedTri];
   const int tl = threadIdx.x % kRedTri, p = threadIdx.x / kRedTri;
@@ -670,7 +705,8 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
     double r = 0.0;
 #pragma unroll
     for (int q = 0; q < kRedPart; ++q) r += part[q][tl];
-    out[t] = norm ? r * norm[t] : r;
+    const long long o = out_idx ? out_idx[t] : t;
+    out[o] = norm ? r * norm[o] : r;
   }
 }
 
@@ -745,14 +781,18 @@ hipError_t prepare_contract_bf16x3() {
                              (int)bf16x3_lds_bytes(kMaxSplitShells));
 }
 
-hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t st) {
+bool ws_group_ok(const WsGroup& g) {
   // every staged row fits the per-thread loads; ranges are whole voxel blocks
-  if (a.max_s * (kC2 / 8) > kWsThreads * kPf || a.max_s > a.n_s || a.max_s > kMaxSplitShells ||
-      a.n_vox % kC2 != 0)
-    return hipErrorInvalidValue;
-  const size_t lds = bf16x3_lds_bytes(a.max_s);
-  const unsigned blocks = (unsigned)a.n_wg * (unsigned)a.n_krange;
-  hipLaunchKernelGGL(k_contract_bf16x3, dim3(blocks), dim3(kWsThreads), lds, st, F, a);
+  return g.max_s * (kC2 / 8) <= kWsThreads * kPf && g.max_s <= g.n_s && g.max_s <= kMaxSplitShells &&
+         g.n_vox % kC2 == 0 && g.n_krange % 8 == 0 && g.block0 % 8 == 0 && g.n_wg >= 1;
+}
+
+hipError_t launch_contract_bf16x3(const float* F, double* partial, const WsGroup* groups_dev, int n_groups,
+                                  int max_s, int n_blocks, hipStream_t st) {
+  if (n_groups < 1 || n_blocks < 1 || max_s > kMaxSplitShells) return hipErrorInvalidValue;
+  const size_t lds = bf16x3_lds_bytes(max_s);
+  hipLaunchKernelGGL(k_contract_bf16x3, dim3((unsigned)n_blocks), dim3(kWsThreads), lds, st, F, partial, groups_dev,
+                     n_groups);
   return hipGetLastError();
 }
 
@@ -770,11 +810,11 @@ hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, c
 }
 
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
-                         const double* norm, double* out, hipStream_t st) {
+                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st) {
   if (n_tri <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_tri + kRedTri - 1) / kRedTri);
   hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(kRedTri * kRedPart), 0, st, partial, n_krange, stride, n_tri, slot,
-                     norm, out);
+                     norm, out_idx, out);
   return hipGetLastError();
 }
 

@@ -388,7 +388,8 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_y(const float2* __restrict__
 }
 
 // x: tile (shell, ky, kz0): A1_n[.][ky + R][kz] -> forward FFT along x -> for the
-// modes of shell n: S[kx][ky][kz] = scale * Z(k) * value (shells are disjoint);
+// modes of shell n: S[kx][ky][kz] += scale * Z(k) * value (the shells of one
+// launch are disjoint; launches of several grids add into the same modes);
 // S is the half spectrum of the spec_n grid
 template <int N>
 __global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__ a1, float2* __restrict__ S,
@@ -423,7 +424,8 @@ __global__ void __launch_bounds__(kThrAxis) k_g_fwd_x(const float2* __restrict__
     if (m2 < d.lo2 || m2 >= d.hi2) continue;
     const float z = 1.0f + beta * (float)((double)(kz * kz) / (double)m2);
     const long long xrow = mx < 0 ? mx + spec_n : mx;
-    S[(xrow * spec_n + yrow) * spec_row(spec_n) + kz] = scl<float>(buf[e], scale * z);
+    float2& o = S[(xrow * spec_n + yrow) * spec_row(spec_n) + kz];
+    o = add<float>(o, scl<float>(buf[e], scale * z));
   }
 }
 

@@ -62,7 +62,8 @@ int validate(const bispec_config& c, std::string& err) {
       break;
     default: return fail(err, BISPEC_EINVAL, "unknown tri_mode");
   }
-  if (c.flags & ~(uint32_t)(BISPEC_FLAG_GRAD | BISPEC_FLAG_STAGE_TIMING | BISPEC_FLAG_AUTOTUNE | BISPEC_FLAG_NO_WORKSPACE))
+  if (c.flags & ~(uint32_t)(BISPEC_FLAG_GRAD | BISPEC_FLAG_STAGE_TIMING | BISPEC_FLAG_AUTOTUNE | BISPEC_FLAG_NO_WORKSPACE |
+                            BISPEC_FLAG_ONE_GRID))
     return fail(err, BISPEC_EINVAL, "unknown flag bits");
   return BISPEC_OK;
 }
@@ -267,6 +268,96 @@ void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp) {
   if ((int)tp.tiles.size() > tp.task_off.back()) tp.task_off.push_back((int32_t)tp.tiles.size());
   tp.useful = (int64_t)s.tri.size();
   tp.slots = (int64_t)tp.tiles.size() * kRows * kCols;
+}
+
+int triangle_min_grid(const ShellGeometry& g, const Tri& t) {
+  const int r1 = g.rad[t.a1 - 1], r2 = g.rad[t.a2 - 1], r3 = g.rad[t.a3 - 1];
+  const int need = std::max(r1 + r2 + r3, 2 * std::max(r1, std::max(r2, r3))) + 1;
+  for (int q = std::max(8, need); q <= 1024; ++q)
+    if (grid_size_supported(q)) return q;
+  return 0;
+}
+
+void choose_grid_classes(const ShellGeometry& g, const Selection& s, bool one_grid,
+                         std::vector<GridClassSpec>& out) {
+  out.clear();
+  const int n_tri = (int)s.tri.size();
+  if (one_grid) {
+    GridClassSpec c;
+    c.g = g.n_est;
+    c.s_lo = 0;
+    c.n_s = g.n_s;
+    c.tri.resize(n_tri);
+    for (int t = 0; t < n_tri; ++t) c.tri[t] = t;
+    out.push_back(std::move(c));
+    return;
+  }
+  // candidate grids: the supported sizes up to the plan's estimator grid
+  std::vector<int> sizes;
+  for (int q = 8; q <= g.n_est; ++q)
+    if (grid_size_supported(q)) sizes.push_back(q);
+  const int K = (int)sizes.size();
+  std::vector<std::vector<int32_t>> bucket(K);
+  for (int t = 0; t < n_tri; ++t) {
+    const int q = std::min(triangle_min_grid(g, s.tri[t]), g.n_est);
+    const int b = (int)(std::lower_bound(sizes.begin(), sizes.end(), q) - sizes.begin());
+    bucket[std::min(b, K - 1)].push_back(t);
+  }
+  // cost of one class (seconds): shell transforms ~ shells x G^3, contraction
+  // ~ (triangles x G^3 for the matrix unit, distinct (a1, a2) pairs x G^3 for
+  // the pair products), plus a fixed cost per class (launches, tails)
+  constexpr double kFft = 2.16e-12, kTri = 4.5e-15, kPair = 1.8e-13, kFixed = 4e-5;
+  auto cls_cost = [&](int g3i, long long n_t, long long n_p, int n_sh) {
+    const double g3 = (double)g3i * g3i * g3i;
+    return n_t ? kFft * n_sh * g3 + kTri * (double)n_t * g3 + kPair * (double)n_p * g3 + kFixed : 0.0;
+  };
+  // best[j + 1]: cheapest cover of buckets 0..j; a class spans buckets i+1..j on grid sizes[j]
+  std::vector<double> best(K + 1, 1e300);
+  std::vector<int> from(K + 1, -1);
+  best[0] = 0.0;
+  for (int i = -1; i < K - 1; ++i) {
+    if (best[i + 1] >= 1e299) continue;
+    std::set<long long> pairs;
+    long long n_t = 0;
+    int lo = 1 << 30, hi = -1;
+    for (int j = i + 1; j < K; ++j) {
+      for (int32_t t : bucket[j]) {
+        const Tri& q = s.tri[t];
+        pairs.insert((long long)q.a1 * 4096 + q.a2);
+        lo = std::min(lo, q.a3 - 1);
+        hi = std::max(hi, q.a1 - 1);
+        ++n_t;
+      }
+      const double c = best[i + 1] + cls_cost(sizes[j], n_t, (long long)pairs.size(), hi - lo + 1);
+      if (c < best[j + 1]) {
+        best[j + 1] = c;
+        from[j + 1] = i;
+      }
+    }
+  }
+  std::vector<std::pair<int, int>> spans;  // (i, j): buckets i+1..j
+  for (int j = K - 1; j >= 0;) {
+    const int i = from[j + 1];
+    spans.push_back({i, j});
+    j = i;
+  }
+  std::reverse(spans.begin(), spans.end());
+  for (auto& sp : spans) {
+    GridClassSpec c;
+    c.g = sizes[sp.second];
+    int lo = 1 << 30, hi = -1;
+    for (int b = sp.first + 1; b <= sp.second; ++b)
+      for (int32_t t : bucket[b]) {
+        c.tri.push_back(t);
+        lo = std::min(lo, s.tri[t].a3 - 1);
+        hi = std::max(hi, s.tri[t].a1 - 1);
+      }
+    if (c.tri.empty()) continue;
+    std::sort(c.tri.begin(), c.tri.end());
+    c.s_lo = lo;
+    c.n_s = hi - lo + 1;
+    out.push_back(std::move(c));
+  }
 }
 
 void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {

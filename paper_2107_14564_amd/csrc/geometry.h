@@ -40,6 +40,32 @@ int select_triangles(const bispec_config& cfg, const ShellGeometry& g, Selection
 // Grid sizes the FFT kernels are built for: 2^a, 3*2^a, 5*2^a with 2^a >= 8, <= 1024.
 bool grid_size_supported(int n);
 
+// ---- estimator-grid classes ------------------------------------------------
+//
+// The G^3-point triple sum of one triangle (a1, a2, a3) picks exactly its
+// closed mode triples once no sum of three mode components can reach +-G,
+// i.e. G > R_a1 + R_a2 + R_a3 with R_n the largest component of a mode of
+// shell n (the aliasing argument of Section 2.2, eq. 3FT, applied per
+// triangle); a shell field is held on G points when G > 2 R_a1.  So each
+// triangle can be summed on the smallest supported grid above its own bound.
+// The selected triangles are split into classes of one grid each; a class
+// evaluates the shell fields of its shell range on its grid and contracts its
+// triangles there.  Classes trade voxels of the contraction against extra
+// shell transforms and launches; the partition minimises a cost model of the
+// three (calibrated on the kernels' measured rates), by dynamic programming
+// over the supported sizes up to the plan's estimator grid.
+struct GridClassSpec {
+  int32_t g = 0;              // grid of the class (points per side)
+  int32_t s_lo = 0;           // first shell of the class's fields (0-based)
+  int32_t n_s = 0;            // shells s_lo .. s_lo + n_s - 1
+  std::vector<int32_t> tri;   // indices of its triangles in the selection, ascending
+};
+// Smallest grid (supported, >= 8) on which triangle t's sum is exact.
+int triangle_min_grid(const ShellGeometry& g, const Tri& t);
+// one_grid: a single class on g.n_est over every shell (also when n_est is forced).
+void choose_grid_classes(const ShellGeometry& g, const Selection& s, bool one_grid,
+                         std::vector<GridClassSpec>& out);
+
 // FFT radix schedule of a length (product of 8,4,2,3,5); empty if unsupported.
 std::vector<int> fft_radices(int n);
 

@@ -138,22 +138,43 @@ struct WsArgs {
   int n_krange = 0;                   // multiple of 8
   double* partial = nullptr;          // device [n_krange][n_wg * kTilesPerWg][kMTileElems]
 };
+// One group of the grouped split-bf16 launch (a grid class of a plan): its
+// fields and partials as element offsets from the launch's F and partial
+// pointers, so one table serves any placement of those buffers.
+struct WsGroup {
+  long long f_off = 0;                // fields: F + f_off, voxel-blocked over n_s shells
+  long long p_off = 0;                // partials: partial + p_off, [n_krange][n_wg * kTilesPerWg][kMTileElems]
+  const MRowBlock* rows = nullptr;    // device [n_wg * kRbPerWg]
+  const SlotCols* cols = nullptr;     // device [n_wg * kSlotsPerWg]
+  const WgRows* wg_rows = nullptr;    // device [n_wg]
+  long long n_vox = 0;
+  int n_wg = 0, n_s = 0, max_s = 0;
+  int n_krange = 0;                   // multiple of 8
+  int block0 = 0;                     // first block of the group (multiple of 8); groups ascending
+  int pad_ = 0;
+};
 constexpr int kMaxSplitShells = 128;   // most shells of a split-bf16 plan
 size_t bf16x3_lds_bytes(int max_s);
+bool ws_group_ok(const WsGroup& g);
 hipError_t prepare_contract_bf16x3();   // once per plan, before any launch (and before graph capture)
-hipError_t launch_contract_bf16x3(const float* F, const WsArgs& a, hipStream_t st);
+// groups_dev: device [n_groups]; max_s: largest max_s of the groups; n_blocks:
+// sum of n_wg * n_krange
+hipError_t launch_contract_bf16x3(const float* F, double* partial, const WsGroup* groups_dev, int n_groups,
+                                  int max_s, int n_blocks, hipStream_t st);
 // Gradient: w_k = gB[t_k] norm[t_k]; G_n = sum_{terms (t, j, l) of n} w F_j F_l
 // (terms: int4 (t, j, l, 0) with 0-based shells, grouped by n via term_off[n_s + 1])
 hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, const int4* terms, long long n_terms,
                         const int32_t* term_off, int n_s, long long n_vox, double* w, float* G, hipStream_t st);
-// pruned forward transforms of every G_n, scattered (times scale * Z) into the half spectrum S
+// pruned forward transforms of every G_n, added (times scale * Z) into the half
+// spectrum S; zero_first clears S before
 hipError_t launch_adjoint_shells(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, int n,
-                                 const float2* tw, float scale, float beta, hipStream_t st);
+                                 const float2* tw, float scale, float beta, bool zero_first, hipStream_t st);
 
 // dst[0 .. bytes) = 0 with a fill kernel (capture-safe; bytes and dst 16-byte aligned)
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
-// out[t] = norm[t] * sum_k partial[k * stride + (slot ? slot[t] : t)] (fixed order, float64; norm may be null)
+// out[o] = norm[o] * sum_k partial[k * stride + (slot ? slot[t] : t)] with o = out_idx ? out_idx[t] : t,
+// for t < n_tri (fixed order, float64; norm may be null)
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
-                         const double* norm, double* out, hipStream_t st);
+                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st);
 
 }  // namespace bispec

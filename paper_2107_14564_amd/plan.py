@@ -28,6 +28,9 @@ class Plan:
                                                 triangles, precision, flags, n_est)
         self.n_g = int(n_g)
         self.n_est = _abi.bispec_estimator_grid(self.cfg)
+        # estimator-grid classes: grids, shell ranges, class of each triangle
+        self.class_grids, self.class_shell_lo, self.class_shell_hi, tc = _abi.bispec_grid_classes(self.cfg)
+        self.tri_class = torch.tensor(tc, dtype=torch.int32)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.handle = _abi.bispec_plan(self.cfg, _stream())
         abc, lab, ntri = _abi.bispec_triangles(self.handle)
@@ -69,10 +72,15 @@ class Plan:
         return _abi.bispec_stage_times(self.handle, 4)
 
     def field(self, shell: int) -> torch.Tensor:
-        """Shell field D_n / (dV n_g^{3/2}) on the estimator grid (n_est^3 points)."""
-        out = torch.empty((self.n_est,) * 3, dtype=torch.float32, device=self.device)
+        """Shell field D_n / (dV n_g^{3/2}) on the grid of field_grid(shell) (g^3 points)."""
+        g = self.field_grid(shell)
+        out = torch.empty((g,) * 3, dtype=torch.float32, device=self.device)
         _abi.bispec_copy_field(self.handle, shell, out.data_ptr(), _stream())
         return out
+
+    def field_grid(self, shell: int) -> int:
+        """The grid of the largest grid class whose fields cover this shell."""
+        return _abi.bispec_field_grid(self.handle, shell)
 
     def _check_field(self, delta):
         if (delta.dtype != torch.float32 or not delta.is_cuda or not delta.is_contiguous()

@@ -112,11 +112,15 @@ def test_known_counts():
 
 
 def test_workspace_bytes():
-    run, peak = abi.bispec_workspace_bytes(abi.make_config(512, 1500.0, 1.0, 100, rsd_beta=0.5)[0])
-    # shells live on the 320^3 estimator grid: float32 fields 100 * 320^3 * 4 B;
-    # float64 unit shells of the planning phase 100 * 320^3 * 8 B
-    assert run > 100 * 320 ** 3 * 4 and peak > 100 * 320 ** 3 * 8
-    assert run < 25e9 and peak < 45e9
+    cfg = abi.make_config(512, 1500.0, 1.0, 100, rsd_beta=0.5)[0]
+    run, peak = abi.bispec_workspace_bytes(cfg)
+    # every grid class keeps the float32 fields of its shell range on its grid;
+    # planning holds the float64 unit shells of one class at a time
+    grids, lo, hi, _ = abi.bispec_grid_classes(cfg)
+    f32 = sum((h - l + 1) * g ** 3 * 4 for g, l, h in zip(grids, lo, hi))
+    f64 = max((h - l + 1) * g ** 3 * 8 for g, l, h in zip(grids, lo, hi))
+    assert run > f32 and peak > f64
+    assert run < 1.2 * f32 + 5e9 and peak < 1.2 * max(f32, f64) + 10e9
     run512, peak512 = abi.bispec_workspace_bytes(abi.make_config(512, 1500.0, 1.0, 100, rsd_beta=0.5, n_est=512)[0])
     assert run512 > 100 * 512 ** 3 * 4 and peak512 > 100 * 512 ** 3 * 8
     assert run512 < 80e9 and peak512 < 150e9
@@ -160,3 +164,24 @@ def test_no_workspace_flag_on_the_host():
         with pytest.raises(P.BispecError) as e:
             P.bispec_workspace_bytes(c_bad)
         assert e.value.status == -1
+
+
+def test_grid_classes_of_the_headline_plan():
+    """Every triangle sits in a class whose grid is exact for it
+    (G > R_a1 + R_a2 + R_a3 and G > 2 R_a1, R_n = n for shells of width k_f) and
+    whose shell range covers its shells; the largest grid is the estimator
+    grid; forcing n_est or FLAG_ONE_GRID gives one class on that grid."""
+    cfg = abi.make_config(512, 1500.0, 1.0, 100, rsd_beta=0.5)[0]
+    tri = np.array(abi.bispec_query_triangles(cfg)[0])
+    grids, lo, hi, tc = abi.bispec_grid_classes(cfg)
+    tc = np.array(tc)
+    assert grids == sorted(grids) and grids[-1] == abi.bispec_estimator_grid(cfg) == 320
+    assert len(grids) > 1 and set(tc.tolist()) == set(range(len(grids)))
+    g = np.array(grids)[tc]
+    assert np.all(g > tri.sum(1)) and np.all(g > 2 * tri[:, 0])
+    assert np.all(tri[:, 2] >= np.array(lo)[tc]) and np.all(tri[:, 0] <= np.array(hi)[tc])
+    for one in (abi.make_config(512, 1500.0, 1.0, 100, n_est=384)[0],
+                abi.make_config(512, 1500.0, 1.0, 100, flags=abi.FLAG_ONE_GRID)[0]):
+        grids1, lo1, hi1, tc1 = abi.bispec_grid_classes(one)
+        assert len(grids1) == 1 and lo1 == [1] and hi1 == [100] and set(tc1) == {0}
+    assert abi.bispec_grid_classes(abi.make_config(512, 1500.0, 1.0, 100, n_est=384)[0])[0] == [384]

@@ -80,7 +80,8 @@ def test_estimator_grid_choice(precision):
 
 def test_fields_match_oracle():
     """Steps a and b alone: the data shell fields D_n against float64 FFTs, on
-    the estimator grid (the input grid itself, or a coarser one)."""
+    the grid of the largest grid class holding the shell (the input grid
+    itself, or a coarser one)."""
     import paper_2107_14564_amd as P
     for n_g, box, dk, n_s, beta in [(32, 300.0, 1.0, 10, 0.5), (128, 600.0, 2.0, 20, 0.0),
                                     (64, 300.0, 1.0, 8, 0.5), (96, 400.0, 1.0, 20, 0.0)]:
@@ -92,7 +93,7 @@ def test_fields_match_oracle():
         masks = fbe.shell_masks(n_g, dk, list(range(1, n_s + 1)))
         scale = (box / n_g) ** 3 * n_g ** 1.5
         for n in (1, n_s // 2, n_s):
-            ref = fbe.shell_field_at(spec, masks[n], plan.n_est) / scale
+            ref = fbe.shell_field_at(spec, masks[n], plan.field_grid(n)) / scale
             got = plan.field(n).cpu().numpy().astype(np.float64)
             err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
             say("  shell %d max err / max %.3g" % (n, err))
