@@ -149,6 +149,14 @@ int bispec_estimator_grid(const bispec_config* cfg, int32_t* n_est);
 int bispec_grid_classes(const bispec_config* cfg, int32_t* n_classes, int32_t* grid, int32_t* shell_lo,
                         int32_t* shell_hi, int32_t capacity, int32_t* tri_class);
 
+/* The split-bf16 contraction's work decomposition for cfg (host only, for
+ * tests and tuning): for each selected triangle t < capacity, tile[t] receives
+ * the index of the 16 x 16 accumulator tile that sums it (unique across the
+ * plan's grid classes) and shape[t] = 16 NT + NRB of the wavefront slot that
+ * owns the tile (NT column tiles, NRB row blocks: the kernel's code variant).
+ * Either output may be null.  Errors: EINVAL, ECUTOFF. */
+int bispec_contraction_tiles(const bispec_config* cfg, int64_t capacity, int32_t* tile, int32_t* shape);
+
 /* Device bytes the plan keeps (run_bytes) and its peak during planning
  * (plan_peak_bytes, which includes the float64 unit shells). */
 int bispec_workspace_bytes(const bispec_config* cfg, int64_t* run_bytes, int64_t* plan_peak_bytes);
@@ -218,6 +226,11 @@ int bispec_field_grid(bispec_plan_t plan, int32_t shell, int32_t* grid);
  * bispec_field_grid, divided by dV N_g^{3/2} (the plan's internal scale), into
  * dst (device float32 [g^3], C order). */
 int bispec_copy_field(bispec_plan_t plan, int32_t shell, float* dst, void* hip_stream);
+
+/* Inspection (tests): as bispec_copy_field, from grid class cls (0-based, in
+ * the order of bispec_grid_classes), whose fields cover shell; dst is device
+ * float32 [g^3] with g that class's grid. */
+int bispec_copy_class_field(bispec_plan_t plan, int32_t cls, int32_t shell, float* dst, void* hip_stream);
 
 /* Release a plan (not one obtained from bispec_many_plan: EINVAL). */
 int bispec_destroy(bispec_plan_t plan);

@@ -56,6 +56,8 @@ def lib() -> C.CDLL:
             "bispec_grid_classes": [cfgp, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), I32,
                                     C.POINTER(I32)],
             "bispec_field_grid": [P, I32, C.POINTER(I32)],
+            "bispec_contraction_tiles": [cfgp, I64, C.POINTER(I32), C.POINTER(I32)],
+            "bispec_copy_class_field": [P, I32, I32, P, P],
             "bispec_plan": [cfgp, P, C.POINTER(P)],
             "bispec_num_triangles": [P, C.POINTER(I64)],
             "bispec_triangles": [P, C.POINTER(I32), C.POINTER(D), C.POINTER(I64)],
@@ -155,6 +157,17 @@ def bispec_grid_classes(cfg):
     return list(grid), list(lo), list(hi), list(tc)[:n_tri.value]
 
 
+def bispec_contraction_tiles(cfg):
+    """(tile, shape) per selected triangle: its split-bf16 accumulator tile (unique
+    over the plan) and the 16 NT + NRB shape of the wavefront slot owning it."""
+    n_tri = C.c_int64(0)
+    _check(lib().bispec_query_triangles(C.byref(cfg), C.byref(n_tri), None, None, 0), "bispec_query_triangles")
+    n = n_tri.value
+    tile, shape = (C.c_int32 * max(1, n))(), (C.c_int32 * max(1, n))()
+    _check(lib().bispec_contraction_tiles(C.byref(cfg), n, tile, shape), "bispec_contraction_tiles")
+    return list(tile)[:n], list(shape)[:n]
+
+
 def bispec_field_grid(plan: int, shell: int) -> int:
     g = C.c_int32(0)
     _check(lib().bispec_field_grid(C.c_void_p(plan), int(shell), C.byref(g)), "bispec_field_grid")
@@ -211,6 +224,11 @@ def bispec_stage_times(plan: int, n: int = 4):
 def bispec_copy_field(plan: int, shell: int, dst_ptr: int, stream: int = 0):
     _check(lib().bispec_copy_field(C.c_void_p(plan), int(shell), C.c_void_p(dst_ptr), C.c_void_p(stream)),
            "bispec_copy_field")
+
+
+def bispec_copy_class_field(plan: int, cls: int, shell: int, dst_ptr: int, stream: int = 0):
+    _check(lib().bispec_copy_class_field(C.c_void_p(plan), int(cls), int(shell), C.c_void_p(dst_ptr),
+                                         C.c_void_p(stream)), "bispec_copy_class_field")
 
 
 def bispec_destroy(plan: int):

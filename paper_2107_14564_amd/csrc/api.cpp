@@ -891,6 +891,25 @@ int bispec_grid_classes(const bispec_config* cfg, int32_t* n_classes, int32_t* g
   return BISPEC_OK;
 }
 
+int bispec_contraction_tiles(const bispec_config* cfg, int64_t capacity, int32_t* tile, int32_t* shape) {
+  bispec_plan_s p;
+  int st = build_host(cfg, p);
+  if (st) return st;
+  int32_t base = 0;
+  for (const GridClass& c : p.cls) {
+    for (size_t k = 0; k < c.spec.tri.size(); ++k) {
+      const int32_t t = c.spec.tri[k];
+      if (t >= capacity) continue;
+      const int32_t loc = c.mfma.slot_of[k] / kMTileElems;   // tile index within the class
+      const SlotCols& sc = c.mfma.cols[loc / kSlotTiles];     // slot = work group * kSlotsPerWg + wave
+      if (tile) tile[t] = base + loc;
+      if (shape) shape[t] = sc.n * 16 + sc.n_rb;
+    }
+    base += c.mfma.n_wg * kTilesPerWg;
+  }
+  return BISPEC_OK;
+}
+
 int bispec_workspace_bytes(const bispec_config* cfg, int64_t* run_bytes, int64_t* plan_peak_bytes) {
   bispec_plan_s p;
   int st = build_host(cfg, p);
@@ -1035,6 +1054,18 @@ int bispec_copy_field(bispec_plan_t p, int32_t shell, float* dst, void* hip_stre
   if (!c) return set_err(BISPEC_EINVAL, "shell out of range or used by no selected triangle");
   if (!p->ran) return set_err(BISPEC_ESTATE, "no run recorded");
   HIP_TRY(launch_unblock(p->F.as<float>() + c->f_off, shell - 1 - c->spec.s_lo, c->geo.n_s, c->n_vox, dst,
+                         (hipStream_t)hip_stream));
+  return BISPEC_OK;
+}
+
+int bispec_copy_class_field(bispec_plan_t p, int32_t cls, int32_t shell, float* dst, void* hip_stream) {
+  if (!p || !dst) return set_err(BISPEC_EINVAL, "null argument");
+  if (cls < 0 || cls >= (int32_t)p->cls.size()) return set_err(BISPEC_EINVAL, "grid class out of range");
+  const GridClass& c = p->cls[cls];
+  if (shell - 1 < c.spec.s_lo || shell - 1 >= c.spec.s_lo + c.spec.n_s)
+    return set_err(BISPEC_EINVAL, "the class's fields do not cover this shell");
+  if (!p->ran) return set_err(BISPEC_ESTATE, "no run recorded");
+  HIP_TRY(launch_unblock(p->F.as<float>() + c.f_off, shell - 1 - c.spec.s_lo, c.geo.n_s, c.n_vox, dst,
                          (hipStream_t)hip_stream));
   return BISPEC_OK;
 }

@@ -78,6 +78,13 @@ class Plan:
         _abi.bispec_copy_field(self.handle, shell, out.data_ptr(), _stream())
         return out
 
+    def class_field(self, cls: int, shell: int) -> torch.Tensor:
+        """Shell field of grid class cls (its grid class_grids[cls], g^3 points)."""
+        g = self.class_grids[cls]
+        out = torch.empty((g,) * 3, dtype=torch.float32, device=self.device)
+        _abi.bispec_copy_class_field(self.handle, cls, shell, out.data_ptr(), _stream())
+        return out
+
     def field_grid(self, shell: int) -> int:
         """The grid of the largest grid class whose fields cover this shell."""
         return _abi.bispec_field_grid(self.handle, shell)

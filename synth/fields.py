@@ -93,6 +93,8 @@ WORKLOADS = {
     "ng256": dict(n_g=256, box_l=1000.0, power=PowerLaw(-1.0), f_ng=1.0, seed=2001),
     # precision case: N_g=512, L=1500 Mpc, P = k^-1.5, f_NG = 2 (RSD beta=0.5 applied by the estimator)
     "ng512": dict(n_g=512, box_l=1500.0, power=PowerLaw(-1.5), f_ng=2.0, seed=3001),
+    # the precision case on the smallest grid that holds its 100 shells: N_g=320, L=937.5 Mpc (same cell size)
+    "ng320": dict(n_g=320, box_l=937.5, power=PowerLaw(-1.5), f_ng=2.0, seed=3003),
     # the precision case on the paper's largest grid: N_g=1024, L=3000 Mpc (the same cell size)
     "ng1024": dict(n_g=1024, box_l=3000.0, power=PowerLaw(-1.5), f_ng=2.0, seed=3002),
     # differentiation case: N_g=256, L=1000 Mpc, P = k^-1, f_NG = 1

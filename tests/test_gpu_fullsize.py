@@ -90,9 +90,10 @@ def test_ng1024_sampled_parity():
 def test_max_shells_sampled_parity():
     """The largest split-bf16 plan: 128 shells of one k_f, which needs the
     estimator grid G = 512 (> 3 x 128), on the 512^3 benchmark field; the
-    contraction's widest row sets (128 shells staged per work group).  All
-    closable triangles among shells {1, 2, 64, 65, 127, 128} against the
-    float64 oracle, N_tri exact and the 1e-5 gate for both precisions."""
+    contraction's widest row sets (up to 128 shells staged per work group).
+    All closable triangles among shells {1, 2, 64, 65, 127, 128} and two
+    triangles of every wavefront slot shape of its tiling against the float64
+    oracle, N_tri exact and the 1e-5 gate for both precisions."""
     import paper_2107_14564_amd as P
     n_g, box, dk, n_s, beta = 512, 1500.0, 1.0, 128, 0.5
     t0 = time.time()
@@ -110,7 +111,24 @@ def test_max_shells_sampled_parity():
     index = {tuple(r): t for t, r in enumerate(tri_all.tolist())}
     sset = {1, 2, 64, 65, 127, 128}
     sample = [r for r in geometry.all_triangles(n_s).tolist() if set(r) <= sset]
-    idx = np.array([index[tuple(r)] for r in sample])
+    # and two triangles of every wavefront slot shape of the split-bf16 tiling,
+    # preferring shells already sampled (each new shell is two 512^3 oracle fields)
+    _, shape = P.bispec_contraction_tiles(P.make_config(n_g, box, dk, n_s, rsd_beta=beta)[0])
+    shape = np.array(shape)
+    chosen = {index[tuple(r)] for r in sample}
+    for sh in np.unique(shape):
+        cand = [t for t in np.nonzero(shape == sh)[0].tolist() if t not in chosen]
+        for _ in range(2):
+            if not cand:
+                break
+            t = max(cand, key=lambda q: (len(set(tri_all[q].tolist()) & sset), -q))
+            cand.remove(t)
+            chosen.add(t)
+            sset |= set(tri_all[t].tolist())
+    idx = np.array(sorted(chosen))
+    sample = tri_all[idx].tolist()
+    assert all(np.count_nonzero(shape[idx] == sh) >= min(2, np.count_nonzero(shape == sh)) for sh in np.unique(shape))
+    say("sample: %d triangles over %d shells, %d slot shapes" % (len(idx), len(sset), len(np.unique(shape))))
     ref = fbe.estimate(delta64, box, dk, np.array(sample), rsd_beta=beta, with_abs=True)
     say("oracle %.1fs on %d triangles" % (time.time() - t0, len(sample)))
     assert np.array_equal(ntri_all[idx], ref["ntri"])
