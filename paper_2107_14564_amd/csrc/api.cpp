@@ -160,8 +160,11 @@ struct GridClass {
   long long f_off = 0;         // element offset of its fields in the plan's F (and G)
   long long pv_off = 0, pm_off = 0;   // element offsets of its vector and MFMA partials
   long long n_terms = 0;
+  // adjoint field build on the matrix cores (BISPEC_FLAG_GRAD, split-bf16 plans)
+  long long adj_tiles = 0;
+  int adj_wg = 0, adj_krange = 8;
   DevBuf tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols, mfma_wgrows, mfma_slot, tri_out, shells,
-      x_tiles, y_off, z_off, tw32, g_terms, g_term_off, g_w;
+      x_tiles, y_off, z_off, tw32, g_terms, g_term_off, g_w, adj_rbs, adj_ns, adj_waves, adj_off, adj_tri, adj_W;
 };
 
 // A class's own geometry: shells s_lo .. s_lo + n_s - 1 of g, renumbered from 1.
@@ -220,8 +223,11 @@ struct bispec_plan_s {
   // grouped split-bf16 launch over the classes
   std::vector<WsGroup> ws_host;
   int ws_blocks = 0, ws_max_s = 0;
+  // grouped matrix-core adjoint build over the classes (GRAD, split-bf16)
+  bool adj_mfma = false;
+  int adj_groups_n = 0, adj_blocks = 0, adj_max_s = 0;
   // device memory
-  DevBuf spec, F, a1, a2, partial, partial_mfma, norm, tw32, ws_groups;
+  DevBuf spec, F, a1, a2, partial, partial_mfma, norm, tw32, ws_groups, adj_groups;
   // gradient workspace (BISPEC_FLAG_GRAD)
   DevBuf G, ball_shells, ball_x, ball_y, ball_z;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -784,6 +790,47 @@ int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
       PLAN_HIP(upload(c.g_term_off, off, s));
       PLAN_HIP(dalloc(c.g_w, terms.size() * sizeof(double)));
     }
+    // split-bf16 plans build the adjoint fields on the matrix cores
+    p->adj_mfma = p->precision == BISPEC_PREC_SPLITBF16 && p->geo.n_s <= kMaxSplitShells;
+    if (p->adj_mfma) {
+      std::vector<AdjGroup> groups;
+      int block = 0;
+      p->adj_max_s = 0;
+      for (GridClass& c : p->cls) {
+        AdjTables at;
+        build_adjoint_tables(c.sel, c.spec.tri, c.geo.n_s, at);
+        c.adj_tiles = at.n_tiles;
+        c.adj_wg = at.n_wg;
+        const long long chunks = c.n_vox / kAdjVox;
+        long long kr = ((2048 / c.adj_wg) + 7) / 8 * 8;
+        kr = std::min(kr, std::max(8LL, (chunks / 2) / 8 * 8));
+        c.adj_krange = (int)std::max(8LL, std::min(kr, 256LL));
+        PLAN_HIP(upload(c.adj_rbs, at.rbs, s));
+        PLAN_HIP(upload(c.adj_ns, at.ns, s));
+        PLAN_HIP(upload(c.adj_waves, at.waves, s));
+        PLAN_HIP(upload(c.adj_off, at.off, s));
+        PLAN_HIP(upload(c.adj_tri, at.tri, s));
+        PLAN_HIP(dalloc(c.adj_W, (size_t)std::max(1LL, at.n_tiles) * 1024 * sizeof(uint16_t)));
+        AdjGroup g;
+        g.f_off = c.f_off;
+        g.rbs = c.adj_rbs.as<AdjRowBlock>();
+        g.ns = c.adj_ns.as<AdjN>();
+        g.waves = c.adj_waves.as<AdjWave>();
+        g.W = c.adj_W.as<uint16_t>();
+        g.n_vox = c.n_vox;
+        g.n_s = c.geo.n_s;
+        g.n_wg = c.adj_wg;
+        g.n_krange = c.adj_krange;
+        g.block0 = block;
+        block += g.n_wg * g.n_krange;
+        p->adj_max_s = std::max(p->adj_max_s, g.n_s);
+        groups.push_back(g);
+      }
+      p->adj_groups_n = (int)groups.size();
+      p->adj_blocks = block;
+      PLAN_HIP(upload(p->adj_groups, groups, s));
+      PLAN_HIP(prepare_adjoint_mfma());
+    }
     PLAN_HIP(upload(p->ball_shells, p->pass_ball.shells, s));
     PLAN_HIP(upload(p->ball_x, p->pass_ball.x_tiles, s));
     PLAN_HIP(upload(p->ball_y, p->pass_ball.y_off, s));
@@ -1012,11 +1059,20 @@ int bispec_grad(bispec_plan_t p, const double* gB, float* gdelta, void* hip_stre
   if (!p->ran) return set_err(BISPEC_ESTATE, "bispec_grad needs a preceding bispec_run");
   hipStream_t s = (hipStream_t)hip_stream;
   const int n = p->geo.n_g;
-  // G_n = sum_t gB_t norm_t d(F_a1 F_a2 F_a3)/dF_n on each class's (scaled) fields of the last run
-  for (GridClass& c : p->cls)
-    HIP_TRY(launch_gbuild(p->F.as<float>() + c.f_off, gB, p->norm.as<double>(), c.g_terms.as<int4>(), c.n_terms,
-                          c.g_term_off.as<int32_t>(), c.geo.n_s, c.n_vox, c.g_w.as<double>(),
-                          p->G.as<float>() + c.f_off, s));
+  // G_n = sum_t gB_t norm_t d(F_a1 F_a2 F_a3)/dF_n on each class's (scaled) fields of the last run:
+  // on the matrix cores (split-bf16 plans) or with float64 vector sums (fp32 plans)
+  if (p->adj_mfma) {
+    for (GridClass& c : p->cls)
+      HIP_TRY(launch_adj_weights(gB, p->norm.as<double>(), c.adj_off.as<int32_t>(), c.adj_tri.as<int32_t>(),
+                                 c.adj_tiles, c.adj_W.as<uint16_t>(), s));
+    HIP_TRY(launch_adjoint_mfma(p->F.as<float>(), p->G.as<float>(), p->adj_groups.as<AdjGroup>(), p->adj_groups_n,
+                                p->adj_max_s, p->adj_blocks, s));
+  } else {
+    for (GridClass& c : p->cls)
+      HIP_TRY(launch_gbuild(p->F.as<float>() + c.f_off, gB, p->norm.as<double>(), c.g_terms.as<int4>(), c.n_terms,
+                            c.g_term_off.as<int32_t>(), c.geo.n_s, c.n_vox, c.g_w.as<double>(),
+                            p->G.as<float>() + c.f_off, s));
+  }
   // S = sum_c sum_n mask_n Z DFT_{G_c}(G_n) * N^{-3/2}, gathered into the n_g spectrum buffer
   const float scale = (float)std::pow((double)n, -1.5);
   for (size_t k = 0; k < p->cls.size(); ++k) {

@@ -738,6 +738,166 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ============================================================================
+// Adjoint field build on the matrix cores (kernels.h): for every grid class,
+// work group (wg, kr) holds the output shells n of its wavefronts and walks
+// the voxel chunks kr, kr + n_krange, ... of 128 voxels (four voxel blocks).
+// Per chunk the group stages every shell of the class into LDS as
+//   Ff [n_s + 1][128] float32 (row n_s all zero: padding rows of a block), and
+//   Bh, Bl [128][S_row] bf16 hi and lo (shell-contiguous per voxel; the shells
+//   past n_s stay zero), S_row = n_s rounded up to 32, plus 8,
+// then each wavefront, for each of its shells n and each row block of n:
+//   acc[vt] (16 rows x 16 voxels of voxel tile vt) = sum over its K tiles of
+//   W_hi F_hi + W_hi F_lo + W_lo F_hi (v_mfma_f32_16x16x32_bf16; W from the
+//   weight buffer, one 16-byte load of hi and of lo per lane per K tile, used
+//   for all eight voxel tiles),
+// and adds acc's rows times F_j (float64) into the shell's sums; the sum over
+// the four row groups of a lane column ends the shell, and lanes 0-15 write
+// G_n of the chunk.  Every shell n of the class belongs to exactly one
+// wavefront (shells without rows write zeros), so G is written once.
+// ============================================================================
+__host__ __device__ constexpr int adj_spad(int n_s) { return (n_s + kAdjK - 1) / kAdjK * kAdjK; }
+__host__ __device__ constexpr int adj_srow(int n_s) { return adj_spad(n_s) + 8; }
+
+__device__ __forceinline__ int adj_group_of(const AdjGroup* __restrict__ groups, int n_groups, int b) {
+  int lo = 0, hi = n_groups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_adj_weights(const double* __restrict__ gB, const double* __restrict__ norm,
+                              const int32_t* __restrict__ off, const int32_t* __restrict__ tri, long long n_tiles,
+                              uint16_t* __restrict__ W) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // tile * 64 + lane
+  if (q >= n_tiles * 64) return;
+  const long long tile = q >> 6;
+  const int lane = (int)(q & 63);
+  u32x4 hi, lo;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float h[2], l[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const long long slot = q * 8 + 2 * e + u;
+      double w = 0.0;
+      for (int k = off[slot]; k < off[slot + 1]; ++k) w += gB[tri[k]] * norm[tri[k]];
+      h[u] = (float)w;
+      l[u] = (float)(w - (double)(float)(__bf16)h[u]);
+    }
+    float h0, h1;
+    hi[e] = bf16_pair(h[0], h[1], h0, h1);
+    lo[e] = bf16_pack(l[0], l[1]);
+  }
+  *reinterpret_cast<u32x4*>(W + tile * 1024 + lane * 8) = hi;
+  *reinterpret_cast<u32x4*>(W + tile * 1024 + 512 + lane * 8) = lo;
+}
+
+__global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __restrict__ F_all,
+                                                                 float* __restrict__ G_all,
+                                                                 const AdjGroup* __restrict__ groups, int n_groups) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const AdjGroup& grp = groups[adj_group_of(groups, n_groups, (int)blockIdx.x)];
+  const int b = (int)blockIdx.x - grp.block0;
+  const int xcd = b & 7, qb = b >> 3;
+  const int wg = qb % grp.n_wg, kr = xcd + 8 * (qb / grp.n_wg);
+  const int ns = grp.n_s, srow = adj_srow(ns);
+  constexpr int kThr = kAdjWaves * 64;
+  float* Ff = reinterpret_cast<float*>(smem_raw);
+  __bf16* Bh = reinterpret_cast<__bf16*>(smem_raw + (size_t)(ns + 1) * kAdjVox * 4);
+  __bf16* Bl = Bh + kAdjVox * srow;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < kAdjVox; e += kThr) Ff[ns * kAdjVox + e] = 0.f;
+  for (int e = tid; e < kAdjVox * (srow - ns); e += kThr) {
+    const int v = e / (srow - ns), c = ns + e % (srow - ns);
+    Bh[v * srow + c] = (__bf16)0.f;
+    Bl[v * srow + c] = (__bf16)0.f;
+  }
+  const float* __restrict__ F = F_all + grp.f_off;
+  float* __restrict__ G = G_all + grp.f_off;
+  const long long n_chunks = grp.n_vox / kAdjVox;
+  const AdjWave wv = grp.waves[wg * kAdjWaves + w];
+  const int total = 4 * ns * 32;
+  for (long long c = kr; c < n_chunks; c += grp.n_krange) {
+    __syncthreads();  // the previous chunk's reads (and the zeroing) are done
+    // stage: the chunk's four voxel blocks are contiguous in F (element e:
+    // block e / (32 n_s), shell (e / 32) % n_s, voxel e % 32); eight loads in flight
+    const float* src = F + c * (long long)total;
+    for (int e0 = tid; e0 < total; e0 += 8 * kThr) {
+      float val[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThr;
+        val[u] = e < total ? src[e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kThr;
+        if (e >= total) continue;
+        const int blk = e / (ns * 32), r = e - blk * ns * 32, sh = r >> 5, vox = blk * 32 + (r & 31);
+        Ff[sh * kAdjVox + vox] = val[u];
+        const __bf16 h = (__bf16)val[u];
+        Bh[vox * srow + sh] = h;
+        Bl[vox * srow + sh] = (__bf16)(val[u] - (float)h);
+      }
+    }
+    __syncthreads();
+    for (int e = wv.e0; e < wv.e1; ++e) {
+      const AdjN nn = grp.ns[e];
+      double sacc[8];
+#pragma unroll
+      for (int vt = 0; vt < 8; ++vt) sacc[vt] = 0.0;
+      for (int r = nn.rb0; r < nn.rb1; ++r) {
+        const AdjRowBlock& rb = grp.rbs[r];
+        const int kt0 = rb.kt0, nkt = rb.nkt;
+        const uint16_t* wt = grp.W + (long long)rb.w_tile * 1024 + lane * 8;
+        f32x4 acc[8];
+#pragma unroll
+        for (int vt = 0; vt < 8; ++vt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[vt][v] = 0.f;
+        for (int kt = 0; kt < nkt; ++kt) {
+          const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(wt + kt * 1024);
+          const bf16x8 alo = *reinterpret_cast<const bf16x8*>(wt + kt * 1024 + 512);
+          const int l0 = (kt0 + kt) * kAdjK + 8 * (lane >> 4);
+#pragma unroll
+          for (int vt = 0; vt < 8; ++vt) {
+            const int vox = vt * 16 + (lane & 15);
+            const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(Bh + vox * srow + l0);
+            const bf16x8 blo = *reinterpret_cast<const bf16x8*>(Bl + vox * srow + l0);
+            ws_mfma3(ahi, alo, bhi, blo, acc[vt]);
+          }
+        }
+        // row 4 (lane / 16) + v of the block, voxel lane % 16 of each voxel tile
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = rb.j[4 * (lane >> 4) + v];
+          const float* fj = Ff + (j > 0 ? j - 1 : ns) * kAdjVox + (lane & 15);
+#pragma unroll
+          for (int vt = 0; vt < 8; ++vt) sacc[vt] += (double)acc[vt][v] * (double)fj[vt * 16];
+        }
+      }
+#pragma unroll
+      for (int vt = 0; vt < 8; ++vt) {
+        double t = sacc[vt];
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        sacc[vt] = t;
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int vt = 0; vt < 8; ++vt) {
+          const int vox = vt * 16 + lane;
+          G[(c * 4 + (vox >> 5)) * (long long)ns * 32 + (long long)(nn.n - 1) * 32 + (vox & 31)] = (float)sacc[vt];
+        }
+      }
+    }
+  }
+}
+
 // dst[0 .. n16) = 0 in 16-byte stores (grid-stride)
 __global__ void k_zero16(uint4* __restrict__ dst, long long n16) {
   const long long step = (long long)gridDim.x * blockDim.x;
@@ -746,6 +906,32 @@ __global__ void k_zero16(uint4* __restrict__ dst, long long n16) {
 }
 
 }  // namespace
+
+size_t adj_lds_bytes(int max_s) {
+  return (size_t)(max_s + 1) * kAdjVox * sizeof(float) + 2 * (size_t)kAdjVox * adj_srow(max_s) * sizeof(__bf16);
+}
+
+hipError_t prepare_adjoint_mfma() {
+  return hipFuncSetAttribute((const void*)k_adjoint_mfma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)adj_lds_bytes(kMaxSplitShells));
+}
+
+hipError_t launch_adj_weights(const double* gB, const double* norm, const int32_t* off, const int32_t* tri,
+                              long long n_tiles, uint16_t* W, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  const long long n = n_tiles * 64;
+  hipLaunchKernelGGL(k_adj_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gB, norm, off, tri, n_tiles,
+                     W);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_mfma(const float* F, float* G, const AdjGroup* groups_dev, int n_groups, int max_s,
+                               int n_blocks, hipStream_t st) {
+  if (n_groups < 1 || n_blocks < 1 || max_s > kMaxSplitShells) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_adjoint_mfma, dim3((unsigned)n_blocks), dim3(kAdjWaves * 64), adj_lds_bytes(max_s), st, F, G,
+                     groups_dev, n_groups);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st) {
   if (bytes == 0) return hipSuccess;

@@ -585,4 +585,93 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
   for (size_t t = 0; t < s.tri.size(); ++t) mt.slot_of[t] = where.at({s.tri[t].a1, s.tri[t].a2, s.tri[t].a3});
 }
 
+void build_adjoint_tables(const Selection& sel, const std::vector<int32_t>& tri_global, int n_s, AdjTables& at) {
+  // (n, j) -> l -> triangles
+  std::vector<std::map<int, std::map<int, std::vector<int32_t>>>> rows(n_s + 1);
+  for (size_t k = 0; k < sel.tri.size(); ++k) {
+    const Tri& q = sel.tri[k];
+    const int32_t t = tri_global[k];
+    rows[q.a1][q.a2][q.a3].push_back(t);
+    rows[q.a2][q.a1][q.a3].push_back(t);
+    rows[q.a3][q.a1][q.a2].push_back(t);
+  }
+  std::vector<std::vector<int32_t>> slot_tris;  // per slot (tile * 512 + lane * 8 + i)
+  std::vector<long long> cost(n_s + 1, 0);
+  at.rbs.clear();
+  std::vector<std::pair<int32_t, int32_t>> n_rb(n_s + 1, {0, 0});
+  for (int n = 1; n <= n_s; ++n) {
+    struct R { int j, lmin, lmax; };
+    std::vector<R> rr;
+    for (auto& jr : rows[n]) rr.push_back({jr.first, jr.second.begin()->first, jr.second.rbegin()->first});
+    std::sort(rr.begin(), rr.end(), [](const R& a, const R& b) {
+      return a.lmin != b.lmin ? a.lmin < b.lmin : (a.lmax != b.lmax ? a.lmax < b.lmax : a.j < b.j);
+    });
+    n_rb[n].first = (int32_t)at.rbs.size();
+    for (size_t r0 = 0; r0 < rr.size(); r0 += kAdjRows) {
+      AdjRowBlock rb{};
+      int lmin = 1 << 30, lmax = 0;
+      for (int r = 0; r < kAdjRows; ++r) {
+        if (r0 + r < rr.size()) {
+          rb.j[r] = (int16_t)rr[r0 + r].j;
+          lmin = std::min(lmin, rr[r0 + r].lmin);
+          lmax = std::max(lmax, rr[r0 + r].lmax);
+        } else {
+          rb.j[r] = 0;
+        }
+      }
+      rb.kt0 = (int16_t)((lmin - 1) / kAdjK);
+      rb.nkt = (int16_t)((lmax - 1) / kAdjK - rb.kt0 + 1);
+      rb.w_tile = (int32_t)at.n_tiles;
+      at.n_tiles += rb.nkt;
+      slot_tris.resize((size_t)at.n_tiles * 512);
+      for (int r = 0; r < kAdjRows && r0 + r < rr.size(); ++r) {
+        const int j = rr[r0 + r].j;
+        for (auto& lt : rows[n][j]) {
+          const int k = (lt.first - 1) - rb.kt0 * kAdjK;   // K index within the block's tiles
+          const int tile = rb.w_tile + k / kAdjK, kk = k % kAdjK;
+          const int lane = r + 16 * (kk / 8), i = kk % 8;
+          auto& v = slot_tris[(size_t)tile * 512 + lane * 8 + i];
+          v.insert(v.end(), lt.second.begin(), lt.second.end());
+        }
+      }
+      cost[n] += 3LL * 8 * rb.nkt + 12;   // MFMAs per chunk, plus the row block's own work
+      at.rbs.push_back(rb);
+    }
+    n_rb[n].second = (int32_t)at.rbs.size();
+  }
+  at.off.assign(1, 0);
+  at.tri.clear();
+  for (auto& v : slot_tris) {
+    at.tri.insert(at.tri.end(), v.begin(), v.end());
+    at.off.push_back((int32_t)at.tri.size());
+  }
+  // shells to wavefronts: longest first onto the least-loaded of n_wg * kAdjWaves
+  long long total = 0, biggest = 0;
+  for (int n = 1; n <= n_s; ++n) {
+    total += cost[n] + 4;
+    biggest = std::max(biggest, cost[n] + 4);
+  }
+  const long long per_wave = std::max(biggest, (long long)(3 * 8 * 12));
+  at.n_wg = (int)std::min<long long>(32, std::max<long long>(1, (total + per_wave * kAdjWaves - 1) / (per_wave * kAdjWaves)));
+  const int n_bins = at.n_wg * kAdjWaves;
+  std::vector<std::vector<int>> bin(n_bins);
+  std::vector<long long> load(n_bins, 0);
+  std::vector<int> order;
+  for (int n = 1; n <= n_s; ++n) order.push_back(n);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  for (int n : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    bin[k].push_back(n);
+    load[k] += cost[n] + 4;
+  }
+  at.ns.clear();
+  at.waves.assign(n_bins, AdjWave{0, 0});
+  for (int k = 0; k < n_bins; ++k) {
+    std::sort(bin[k].begin(), bin[k].end());
+    at.waves[k].e0 = (int32_t)at.ns.size();
+    for (int n : bin[k]) at.ns.push_back(AdjN{n, n_rb[n].first, n_rb[n].second});
+    at.waves[k].e1 = (int32_t)at.ns.size();
+  }
+}
+
 }  // namespace bispec

@@ -156,4 +156,41 @@ struct MfmaTiling {
 
 void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt);
 
+// ---- adjoint field build on the matrix cores ------------------------------
+// G_n(x) = sum_j F_j(x) H_(n,j)(x),  H_(n,j)(x) = sum_l W[(n,j), l] F_l(x), where
+// W[(n,j), l] sums gB_t norm_t over the terms (t; j, l) of d(F_a1 F_a2 F_a3)/dF_n
+// (j the larger of the other two shells).  Rows (n, j) of one n form row blocks
+// of kAdjRows; a row block meets K tiles of kAdjK consecutive shells l (0-based
+// shells 32 kt .. 32 kt + 31).  A K tile's weights sit in the MFMA row-operand
+// layout: slot (tile, lane, i) holds row lane % 16, K index 8 (lane / 16) + i.
+constexpr int kAdjRows = 16;
+constexpr int kAdjK = 32;
+constexpr int kAdjWaves = 8;        // wavefronts per work group of the kernel
+struct AdjRowBlock {
+  int16_t j[kAdjRows];  // 1-based j of each row, 0 = padding row
+  int32_t w_tile;       // first K tile of the block in the weight buffer
+  int16_t kt0, nkt;     // K tiles kt0 .. kt0 + nkt - 1
+};
+struct AdjN {
+  int32_t n;            // 1-based output shell
+  int32_t rb0, rb1;     // its row blocks
+};
+struct AdjWave {
+  int32_t e0, e1;       // the AdjN entries of one wavefront
+};
+// Row blocks, weight-slot lists (CSR: slot q = tile * 512 + lane * 8 + i lists
+// the triangles whose terms fall on it; a triangle with two equal shells is
+// listed twice where its two terms coincide) and the assignment of every
+// output shell 1..n_s to one wavefront of n_wg * kAdjWaves.
+struct AdjTables {
+  std::vector<AdjRowBlock> rbs;
+  std::vector<AdjN> ns;
+  std::vector<AdjWave> waves;
+  std::vector<int32_t> off, tri;
+  long long n_tiles = 0;
+  int n_wg = 1;
+};
+// s: triangles on shells 1..n_s; tri_id[k]: the index reported for triangle k
+void build_adjoint_tables(const Selection& s, const std::vector<int32_t>& tri_id, int n_s, AdjTables& at);
+
 }  // namespace bispec

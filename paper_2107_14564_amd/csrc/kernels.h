@@ -165,6 +165,26 @@ hipError_t launch_contract_bf16x3(const float* F, double* partial, const WsGroup
 // (terms: int4 (t, j, l, 0) with 0-based shells, grouped by n via term_off[n_s + 1])
 hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, const int4* terms, long long n_terms,
                         const int32_t* term_off, int n_s, long long n_vox, double* w, float* G, hipStream_t st);
+// ---- adjoint field build on the matrix cores (row blocks: geometry.h) --------
+constexpr int kAdjVox = 128;        // voxels per staged chunk (four voxel blocks)
+struct AdjGroup {
+  long long f_off = 0;            // fields and adjoint fields: F + f_off, G + f_off (voxel-blocked, n_s shells)
+  const AdjRowBlock* rbs = nullptr;
+  const AdjN* ns = nullptr;
+  const AdjWave* waves = nullptr; // [n_wg * kAdjWaves]
+  const uint16_t* W = nullptr;    // [tiles][2 (hi, lo)][64 lanes][8] bf16 bits
+  long long n_vox = 0;
+  int n_s = 0, n_wg = 0, n_krange = 0, block0 = 0;
+};
+size_t adj_lds_bytes(int max_s);
+hipError_t prepare_adjoint_mfma();   // once per plan (LDS limit)
+// W of one class: tile-lane slot q = (tile * 64 + lane) * 8 + i takes
+// sum_{k in [off[q], off[q+1])} gB[tri[k]] norm[tri[k]], split into hi and lo bf16
+hipError_t launch_adj_weights(const double* gB, const double* norm, const int32_t* off, const int32_t* tri,
+                              long long n_tiles, uint16_t* W, hipStream_t st);
+hipError_t launch_adjoint_mfma(const float* F, float* G, const AdjGroup* groups_dev, int n_groups, int max_s,
+                               int n_blocks, hipStream_t st);
+
 // pruned forward transforms of every G_n, added (times scale * Z) into the half
 // spectrum S; zero_first clears S before
 hipError_t launch_adjoint_shells(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, int n,

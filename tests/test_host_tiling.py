@@ -1,4 +1,4 @@
-"""The contraction's work decomposition on the host: a small C++ checker is
+"""The contraction's and the adjoint's work decompositions on the host: small C++ checkers are
 built against geometry.cpp and run for several configurations (every selected
 triangle maps to exactly one accumulator element that decodes back to it, its
 shells are staged by its work group, and the vector-kernel tiles cover it)."""
@@ -38,4 +38,25 @@ def checker(tmp_path_factory):
 @pytest.mark.parametrize("args", CASES, ids=lambda a: "_".join(a[:5]))
 def test_tiling_covers_every_triangle_once(checker, args):
     r = subprocess.run([checker, *args], capture_output=True, text=True, timeout=120)
-    assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout + r.stderr
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
+
+
+@pytest.fixture(scope="module")
+def adjoint_checker(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("adjoint") / "adjoint_check")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                    os.path.join(ROOT, "tests", "host", "adjoint_check.cpp"), os.path.join(CSRC, "geometry.cpp"),
+                    "-o", exe], check=True, capture_output=True)
+    return exe
+
+
+@pytest.mark.parametrize("args", CASES[:7], ids=lambda a: "_".join(a[:5]))
+def test_adjoint_tables_rebuild_the_adjoint_fields(adjoint_checker, args):
+    """The matrix-core adjoint's row blocks and weight slots, read the way the
+    kernel reads them, give G_n = sum_t c_t d(F_a1 F_a2 F_a3)/dF_n exactly (random
+    weights and field values, every grid class); every shell in one wavefront."""
+    r = subprocess.run([adjoint_checker, *args], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
