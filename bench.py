@@ -239,9 +239,11 @@ def main():
                      "traffic": measured_traffic(args.workload) if prec == P.PREC_SPLITBF16 else None,
                      "kernel": "k_contract_bf16x3" if prec == P.PREC_SPLITBF16 else "k_contract_vec<float>",
                      "algorithmic_flop": flop},
-        "grid_classes": [{"grid": gc, "shells": [lo, hi], "n_tri": int((plan.tri_class.numpy() == k).sum())}
-                         for k, (gc, lo, hi) in enumerate(zip(plan.class_grids, plan.class_shell_lo,
-                                                              plan.class_shell_hi))],
+        "grid_classes": [dict(grid=gc, shells=[lo, hi], n_tri=int((plan.tri_class.numpy() == k).sum()),
+                              n_krange=cp["n_krange"], max_cols=cp["max_cols"], n_wg=cp["n_wg"],
+                              tune=cp["tune_source"])
+                         for k, (gc, lo, hi, cp) in enumerate(zip(plan.class_grids, plan.class_shell_lo,
+                                                                  plan.class_shell_hi, plan.classes()))],
         "fft_hbm": {"algorithmic_bytes": (8.0 * n ** 3 + 4.0 * field_vox),
                     "achieved_GBs": (8.0 * n ** 3 + 4.0 * field_vox) / ((stages[0] + stages[1]) * 1e-3) / 1e9,
                     "peak_GBs": PEAK_HBM_GBS},
@@ -353,6 +355,12 @@ def bench_batch(args, np, torch, P):
     stop.record(stream)
     stop.synchronize()
     eager_ms = start.elapsed_time(stop) / max(1, min(3, args.steps))
+    # the grid classes and the autotuner's choices, over all members
+    tuning = {}
+    for i in range(bp.n):
+        for c in bp.classes(i):
+            key = "G%d_cols%d_ranges%d_%s" % (c["grid"], c["max_cols"], c["n_krange"], c["tune_source"])
+            tuning[key] = tuning.get(key, 0) + 1
     flop = 0.0
     for i in range(bp.n):
         tri = bp.triangles[i].numpy()
@@ -371,6 +379,8 @@ def bench_batch(args, np, torch, P):
                    "n_shells_range": [min(m["n_shells"] for m in members), max(m["n_shells"] for m in members)],
                    "n_tri": bp.n_tri, "precision": args.precision, "autotune": bool(args.autotune)},
         "eager_ms_per_step": eager_ms,
+        "contraction_launches_per_step": 1,
+        "class_tuning": tuning,
         "realisations_per_s": bp.n / (ms * 1e-3),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None, "kernel": "whole step (all kernels)",

@@ -95,8 +95,12 @@ enum bispec_precision {
 enum bispec_flags {
   BISPEC_FLAG_GRAD = 1u,         /* allocate the workspace for bispec_grad            */
   BISPEC_FLAG_STAGE_TIMING = 2u, /* record HIP events around each stage of run       */
-  BISPEC_FLAG_AUTOTUNE = 4u,     /* time the split-bf16 contraction at plan time for  */
-                                 /* 64..512 voxel ranges and keep the fastest         */
+  BISPEC_FLAG_AUTOTUNE = 4u,     /* per grid class, time the split-bf16 contraction   */
+                                 /* at plan time for column-tile windows {8, 4} x     */
+                                 /* 64..512 voxel ranges on pseudo-random fields and  */
+                                 /* keep the fastest; with BISPEC_TUNE_CACHE naming a */
+                                 /* file, choices are read from and appended to it    */
+                                 /* (JSON lines keyed by a hash of the class)         */
   BISPEC_FLAG_NO_WORKSPACE = 8u, /* keep no run workspace: the plan holds its tables */
                                  /* and N_tri only and is run by bispec_run_noalloc   */
                                  /* (excludes GRAD and AUTOTUNE; not in a batch)      */
@@ -216,6 +220,15 @@ int bispec_set_precision(bispec_plan_t plan, int32_t precision);
  * caller synchronises the stream first): ms[0] forward FFT, ms[1] inverse
  * shell FFTs, ms[2] contraction, ms[3] normalisation.  n = entries wanted (<= 4). */
 int bispec_stage_times(bispec_plan_t plan, float* ms, int32_t n);
+
+/* The plan's grid classes as built (after autotuning): for k < capacity,
+ * grid[k], the split-bf16 contraction's voxel-range count n_krange[k],
+ * column-tile window max_cols[k] and work groups per range n_wg[k], the
+ * autotuned time of one contraction launch of the class alone tuned_ms[k]
+ * (0 if not tuned) and tune_source[k] (0 default, 1 timed at plan time, 2 read
+ * from the tuning cache).  Any output array may be null. */
+int bispec_plan_classes(bispec_plan_t plan, int32_t capacity, int32_t* n_classes, int32_t* grid, int32_t* n_krange,
+                        int32_t* max_cols, int32_t* n_wg, float* tuned_ms, int32_t* tune_source);
 
 /* Inspection (tests): the grid on which bispec_copy_field returns shell n
  * (the largest grid of the classes whose fields cover it).  EINVAL if no

@@ -71,6 +71,12 @@ struct DevBuf {
     bytes = o.bytes;
     owned = false;
   }
+  void view(const DevBuf& o, size_t offset, size_t n) {
+    release();
+    p = static_cast<unsigned char*>(o.p) + offset;
+    bytes = n;
+    owned = false;
+  }
   template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 
@@ -106,8 +112,10 @@ int n_krange_for(long long groups, long long n_vox) {
   return (int)k;
 }
 
-// candidate voxel-range counts of the autotuner (multiples of 8)
+// candidates of the autotuner: voxel-range counts (multiples of 8) and
+// column-tile windows of the MFMA tiling
 constexpr int kTuneRanges[] = {64, 128, 256, 512};
+constexpr int kTuneCols[] = {8, 4};
 
 std::vector<float2> twiddles32(int m) {
   std::vector<float2> t(m);
@@ -157,6 +165,10 @@ struct GridClass {
   size_t fields32 = 0, fields64 = 0, partial_vec = 0, partial_mfma = 0;
   int n_krange_vec = 8, n_krange_mfma = 8;
   int n_krange_mfma_cap = 8;   // its MFMA partials hold this many ranges
+  int max_cols = kMaxColTiles; // column-tile window of its MFMA tiling (a tuned tile shape)
+  int wg_cap = 1;              // its MFMA partials hold this many work groups per range
+  float tuned_ms = 0.f;        // autotuner: time of the chosen shape (0 = not tuned)
+  int tune_source = 0;         // 0 default, 1 timed at plan time, 2 from the tuning cache
   long long f_off = 0;         // element offset of its fields in the plan's F (and G)
   long long pv_off = 0, pm_off = 0;   // element offsets of its vector and MFMA partials
   long long n_terms = 0;
@@ -205,6 +217,12 @@ struct bispec_many_s {
   hipGraphExec_t exec = nullptr;
   const float* g_delta = nullptr;      // pointers baked into the graph
   double* g_B = nullptr;
+  // every member's fields and MFMA partials stay resident (members view them
+  // at offsets), so one grouped launch contracts all split-bf16 members
+  DevBuf F_all, pm_all, ws_groups;
+  std::vector<size_t> f_at, pm_at;     // byte offsets of member i's pieces
+  int ws_n = 0, ws_blocks = 0, ws_max_s = 0;
+  hipEvent_t ev_mid = nullptr;         // the grouped contraction is done
   ~bispec_many_s();
 };
 
@@ -290,7 +308,14 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
       for (int k : kTuneRanges)
         if (k <= std::max(8LL, (c.n_vox / (64 * 4)) / 8 * 8)) c.n_krange_mfma_cap = std::max(c.n_krange_mfma_cap, k);
     c.partial_vec = (size_t)c.n_krange_vec * c.n_tri * sizeof(double);
-    c.partial_mfma = (size_t)c.n_krange_mfma_cap * c.mfma.n_wg * kTilesPerWg * kMTileElems * sizeof(double);
+    c.wg_cap = c.mfma.n_wg;
+    if (cfg->flags & BISPEC_FLAG_AUTOTUNE)
+      for (int mc : kTuneCols) {
+        MfmaTiling alt;
+        build_mfma_tiles(c.sel, c.geo.n_s, alt, mc);
+        c.wg_cap = std::max(c.wg_cap, alt.n_wg);
+      }
+    c.partial_mfma = (size_t)c.n_krange_mfma_cap * c.wg_cap * kTilesPerWg * kMTileElems * sizeof(double);
     // offsets: fields and partials of the classes back to back (256-byte aligned pieces)
     c.f_off = (long long)(s.fields32 / sizeof(float));
     s.fields32 += (c.fields32 + 255) / 256 * 256;
@@ -329,6 +354,20 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   return BISPEC_OK;
 }
 
+// Voxel ranges of a batch member's classes: at most cap (a multiple of 8), so
+// that the batch's one grouped launch has a few thousand work groups and
+// small partials; recomputes the MFMA partial sizes and offsets.
+void cap_mfma_ranges(bispec_plan_s& p, int cap) {
+  p.sz.partial_mfma = 0;
+  for (GridClass& c : p.cls) {
+    c.n_krange_mfma = std::max(8, std::min(c.n_krange_mfma, cap));
+    c.n_krange_mfma_cap = std::max(8, std::min(c.n_krange_mfma_cap, cap));
+    c.partial_mfma = (size_t)c.n_krange_mfma_cap * c.wg_cap * kTilesPerWg * kMTileElems * sizeof(double);
+    c.pm_off = (long long)(p.sz.partial_mfma / sizeof(double));
+    p.sz.partial_mfma += (c.partial_mfma + 255) / 256 * 256;
+  }
+}
+
 // The grouped split-bf16 launch over the plan's classes, for the classes'
 // current voxel-range counts; blocks of the costliest groups first.
 void build_ws_groups(bispec_plan_s& p) {
@@ -361,6 +400,17 @@ void build_ws_groups(bispec_plan_s& p) {
     p.ws_host.push_back(w);
   }
   p.ws_blocks = block;
+}
+
+// Append a plan's class groups to a batch table, its fields and partials at
+// element offsets f_base (floats) and p_base (doubles) of the batch buffers.
+void append_ws_groups(bispec_plan_s& p, long long f_base, long long p_base, std::vector<WsGroup>& out) {
+  for (const WsGroup& g : p.ws_host) {
+    WsGroup w = g;
+    w.f_off += f_base;
+    w.p_off += p_base;
+    out.push_back(w);
+  }
 }
 
 ContractArgs contract_args(GridClass& c, double* partial_base) {
@@ -540,12 +590,13 @@ constexpr int kMaxLanes = 4;
 
 hipError_t take_workspace(bispec_plan_s& p, const Workspace* shared, bool fields) {
   if (shared) {
+    // a batch member: lane buffers (spectrum, pass intermediates, vector
+    // partials) shared; its fields and MFMA partials are its own pieces of the
+    // batch's resident buffers (views set before plan_build)
     if (!fields) {
       p.partial.view(shared->partial);
-      p.partial_mfma.view(shared->partial_mfma);
     } else {
       p.spec.view(shared->spec);
-      p.F.view(shared->F);
       p.a1.view(shared->a1);
       p.a2.view(shared->a2);
     }
@@ -583,6 +634,32 @@ RunBufs own_bufs(bispec_plan_s& p) {
   return b;
 }
 
+// The forward transform and shell passes of one pass (batch lanes).
+int run_fields(bispec_plan_s& p, const RunBufs& w, const float* delta, hipStream_t s) {
+  HIP_TRY(launch_forward(delta, w.spec, p.geo.n_g, (float)p.geo.beta, p.tw32.as<float2>(), s));
+  for (GridClass& c : p.cls)
+    HIP_TRY(launch_data_shells(w.spec, w.a1, w.a2, w.F + c.f_off, class_launch(p, c), c.spec.g, c.tw32.as<float2>(),
+                               s));
+  return BISPEC_OK;
+}
+
+// The per-class reductions of the split-bf16 partials into B.
+int run_reduce_mfma(bispec_plan_s& p, const RunBufs& w, double* B, hipStream_t s) {
+  for (GridClass& c : p.cls)
+    HIP_TRY(launch_reduce(w.partial_mfma + c.pm_off, c.n_krange_mfma, (long long)c.mfma.n_wg * kTilesPerWg * kMTileElems,
+                          c.n_tri, c.mfma_slot.as<int32_t>(), p.norm.as<double>(), c.tri_out.as<int32_t>(), B, s));
+  return BISPEC_OK;
+}
+
+// The vector (fp32) contraction and its reductions.
+int run_contract_fp32(bispec_plan_s& p, const RunBufs& w, double* B, hipStream_t s) {
+  for (GridClass& c : p.cls) HIP_TRY(launch_contract_fp32(w.F + c.f_off, contract_args(c, w.partial), s));
+  for (GridClass& c : p.cls)
+    HIP_TRY(launch_reduce(w.partial + c.pv_off, c.n_krange_vec, c.n_tri, c.n_tri, nullptr, p.norm.as<double>(),
+                          c.tri_out.as<int32_t>(), B, s));
+  return BISPEC_OK;
+}
+
 // The four stages of one pass; events only when timing (never under capture).
 int run_core(bispec_plan_s& p, const RunBufs& w, const float* delta, double* B, hipStream_t s, bool timing) {
   const int n = p.geo.n_g;
@@ -612,20 +689,41 @@ int run_core(bispec_plan_s& p, const RunBufs& w, const float* delta, double* B, 
   return BISPEC_OK;
 }
 
-// Enqueue every member of the batch on its lane, forked from and joined back
-// into stream s (which may be capturing).
+// Enqueue a batch pass, forked from and joined back into stream s (which may
+// be capturing): each member's forward transform and shell passes (and, for
+// fp32 members, its contraction and reductions) on its lane; then one grouped
+// split-bf16 contraction of every split member's classes on s; then the split
+// members' reductions on the lanes again.
 int many_enqueue(bispec_many_s& m, const float* delta, double* B, hipStream_t s) {
   HIP_TRY(hipEventRecord(m.ev_fork, s));
   for (ManyLane* l : m.lanes) HIP_TRY(hipStreamWaitEvent(l->stream, m.ev_fork, 0));
   for (size_t i = 0; i < m.plans.size(); ++i) {
-    int st = run_core(*m.plans[i], own_bufs(*m.plans[i]), delta + m.d_off[i], B + m.b_off[i],
-                      m.lanes[m.lane_of[i]]->stream, false);
+    bispec_plan_s& p = *m.plans[i];
+    const hipStream_t ls = m.lanes[m.lane_of[i]]->stream;
+    int st = run_fields(p, own_bufs(p), delta + m.d_off[i], ls);
+    if (!st && p.precision == BISPEC_PREC_FP32) st = run_contract_fp32(p, own_bufs(p), B + m.b_off[i], ls);
     if (st) return st;
-    m.plans[i]->ran = true;
+    p.ran = true;
   }
   for (ManyLane* l : m.lanes) {
     HIP_TRY(hipEventRecord(l->ev_join, l->stream));
     HIP_TRY(hipStreamWaitEvent(s, l->ev_join, 0));
+  }
+  if (m.ws_n > 0) {
+    HIP_TRY(launch_contract_bf16x3(m.F_all.as<float>(), m.pm_all.as<double>(), m.ws_groups.as<WsGroup>(), m.ws_n,
+                                   m.ws_max_s, m.ws_blocks, s));
+    HIP_TRY(hipEventRecord(m.ev_mid, s));
+    for (ManyLane* l : m.lanes) HIP_TRY(hipStreamWaitEvent(l->stream, m.ev_mid, 0));
+    for (size_t i = 0; i < m.plans.size(); ++i) {
+      bispec_plan_s& p = *m.plans[i];
+      if (p.precision == BISPEC_PREC_FP32) continue;
+      int st = run_reduce_mfma(p, own_bufs(p), B + m.b_off[i], m.lanes[m.lane_of[i]]->stream);
+      if (st) return st;
+    }
+    for (ManyLane* l : m.lanes) {
+      HIP_TRY(hipEventRecord(l->ev_join, l->stream));
+      HIP_TRY(hipStreamWaitEvent(s, l->ev_join, 0));
+    }
   }
   return BISPEC_OK;
 }
@@ -639,12 +737,86 @@ int upload_ws_groups(bispec_plan_s& p, hipStream_t s) {
   return BISPEC_OK;
 }
 
-// Autotuner: the voxel-range count of each class's split-bf16 contraction,
-// timed on the plan's own field buffer (zero-filled; MFMA timing does not
-// depend on values), one class alone per launch.
+// Tuning cache: JSON lines {"key": "<hex>", "max_cols": c, "n_krange": k, "ms": t}
+// in the file named by BISPEC_TUNE_CACHE (none: no cache).  The key hashes
+// what the timing depends on: the class grid, its shells and triangles.
+unsigned long long class_key(const GridClass& c) {
+  unsigned long long h = 1469598103934665603ULL;  // FNV-1a, 64 bit
+  auto mix = [&h](long long v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (unsigned long long)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ULL;
+    }
+  };
+  mix(c.spec.g);
+  mix(c.geo.n_s);
+  mix((long long)c.sel.tri.size());
+  for (const Tri& t : c.sel.tri) mix(((long long)t.a1 << 32) | ((long long)t.a2 << 16) | t.a3);
+  return h;
+}
+
+std::mutex g_tune_mu;
+
+bool tune_cache_get(unsigned long long key, int& max_cols, int& n_krange, float& ms) {
+  const char* path = std::getenv("BISPEC_TUNE_CACHE");
+  if (!path || !*path) return false;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char want[40], line[512];
+  std::snprintf(want, sizeof want, "\"key\": \"%016llx\"", key);
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    if (!std::strstr(line, want)) continue;
+    int mc = 0, kr = 0;
+    float t = 0.f;
+    const char* a = std::strstr(line, "\"max_cols\":");
+    const char* b = std::strstr(line, "\"n_krange\":");
+    const char* d = std::strstr(line, "\"ms\":");
+    if (a && b && d && std::sscanf(a + 11, "%d", &mc) == 1 && std::sscanf(b + 11, "%d", &kr) == 1 &&
+        std::sscanf(d + 5, "%f", &t) == 1) {
+      max_cols = mc;
+      n_krange = kr;
+      ms = t;
+      found = true;   // the last matching line wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_put(unsigned long long key, const GridClass& c) {
+  const char* path = std::getenv("BISPEC_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%016llx\", \"grid\": %d, \"n_shells\": %d, \"n_tri\": %lld, \"max_cols\": %d, "
+               "\"n_krange\": %d, \"ms\": %.4f}\n", key, c.spec.g, c.geo.n_s, c.n_tri, c.max_cols, c.n_krange_mfma,
+               c.tuned_ms);
+  std::fclose(f);
+}
+
+// Rebuild a class's MFMA tiling for a column-tile window and upload its tables.
+hipError_t retile_class(GridClass& c, int max_cols, hipStream_t s) {
+  if (c.max_cols == max_cols) return hipSuccess;
+  c.mfma = MfmaTiling();
+  build_mfma_tiles(c.sel, c.geo.n_s, c.mfma, max_cols);
+  c.max_cols = max_cols;
+  hipError_t e = upload(c.mfma_rows, c.mfma.rows, s);
+  if (e == hipSuccess) e = upload(c.mfma_cols, c.mfma.cols, s);
+  if (e == hipSuccess) e = upload(c.mfma_wgrows, c.mfma.wg_rows, s);
+  if (e == hipSuccess) e = upload(c.mfma_slot, c.mfma.slot_of, s);
+  return e;
+}
+
+// Autotuner: per class, the column-tile window of its MFMA tiling and the
+// voxel-range count of its contraction, each candidate timed alone on
+// pseudo-random fields in the plan's own field buffer; choices are read from
+// and written to the tuning cache.
 int autotune_mfma(bispec_plan_s& p, hipStream_t s) {
   if (p.precision != BISPEC_PREC_SPLITBF16) return BISPEC_OK;
-  HIP_TRY(hipMemsetAsync(p.F.p, 0, p.sz.fields32, s));
+  HIP_TRY(launch_fill_random(p.F.as<float>(), (long long)(p.sz.fields32 / sizeof(float)), 0x5eedULL, s));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -652,47 +824,77 @@ int autotune_mfma(bispec_plan_s& p, hipStream_t s) {
   DevBuf one;
   for (GridClass& c : p.cls) {
     if (c.n_tri == 0) continue;
-    float best = 1e30f;
-    int best_k = c.n_krange_mfma;
-    for (int k : kTuneRanges) {
-      if (k > c.n_krange_mfma_cap) continue;
-      WsGroup w;
-      w.f_off = c.f_off;
-      w.p_off = c.pm_off;
-      w.rows = c.mfma_rows.as<MRowBlock>();
-      w.cols = c.mfma_cols.as<SlotCols>();
-      w.wg_rows = c.mfma_wgrows.as<WgRows>();
-      w.n_vox = c.n_vox;
-      w.n_wg = c.mfma.n_wg;
-      w.n_s = c.geo.n_s;
-      w.max_s = c.mfma.max_s;
-      w.n_krange = k;
-      w.block0 = 0;
-      if (!ws_group_ok(w)) continue;
-      hipError_t e = upload(one, std::vector<WsGroup>{w}, s);
-      const int blocks = w.n_wg * k;
-      if (e == hipSuccess)
-        e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, w.max_s,
-                                   blocks, s);  // warm-up
-      if (e == hipSuccess) e = hipEventRecord(e0, s);
-      for (int r = 0; r < 3 && e == hipSuccess; ++r)
-        e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, w.max_s,
-                                   blocks, s);
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-        break;
-      }
-      if (ms < best) {
-        best = ms;
-        best_k = k;
+    const unsigned long long key = class_key(c);
+    int mc_c = 0, kr_c = 0;
+    float ms_c = 0.f;
+    if (tune_cache_get(key, mc_c, kr_c, ms_c) && mc_c >= 1 && mc_c <= kMaxColTiles && kr_c >= 8 &&
+        kr_c % 8 == 0 && kr_c <= c.n_krange_mfma_cap) {
+      hipError_t e = retile_class(c, mc_c, s);
+      if (e != hipSuccess) { st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e)); break; }
+      if (c.mfma.n_wg <= c.wg_cap) {
+        c.n_krange_mfma = kr_c;
+        c.tuned_ms = ms_c;
+        c.tune_source = 2;
+        continue;
       }
     }
+    float best = 1e30f;
+    int best_k = c.n_krange_mfma, best_mc = c.max_cols;
+    // range candidates: the tuner's sizes that fit the class's partials, and its default
+    std::vector<int> ranges;
+    for (int k : kTuneRanges)
+      if (k <= c.n_krange_mfma_cap) ranges.push_back(k);
+    if (std::find(ranges.begin(), ranges.end(), c.n_krange_mfma) == ranges.end()) ranges.push_back(c.n_krange_mfma);
+    for (int mc : kTuneCols) {
+      hipError_t e = retile_class(c, mc, s);
+      if (e != hipSuccess) { st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e)); break; }
+      if (c.mfma.n_wg > c.wg_cap) continue;
+      for (int k : ranges) {
+        WsGroup w;
+        w.f_off = c.f_off;
+        w.p_off = c.pm_off;
+        w.rows = c.mfma_rows.as<MRowBlock>();
+        w.cols = c.mfma_cols.as<SlotCols>();
+        w.wg_rows = c.mfma_wgrows.as<WgRows>();
+        w.n_vox = c.n_vox;
+        w.n_wg = c.mfma.n_wg;
+        w.n_s = c.geo.n_s;
+        w.max_s = c.mfma.max_s;
+        w.n_krange = k;
+        w.block0 = 0;
+        if (!ws_group_ok(w)) continue;
+        e = upload(one, std::vector<WsGroup>{w}, s);
+        const int blocks = w.n_wg * k;
+        if (e == hipSuccess)
+          e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, w.max_s,
+                                     blocks, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r)
+          e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, w.max_s,
+                                     blocks, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          best_k = k;
+          best_mc = mc;
+        }
+      }
+      if (st) break;
+    }
     if (st) break;
+    hipError_t e = retile_class(c, best_mc, s);
+    if (e != hipSuccess) { st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e)); break; }
     c.n_krange_mfma = best_k;
+    c.tuned_ms = best / 3.f;
+    c.tune_source = 1;
+    tune_cache_put(key, c);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1096,6 +1298,22 @@ int bispec_stage_times(bispec_plan_t p, float* ms, int32_t n) {
   return BISPEC_OK;
 }
 
+int bispec_plan_classes(bispec_plan_t p, int32_t capacity, int32_t* n_classes, int32_t* grid, int32_t* n_krange,
+                        int32_t* max_cols, int32_t* n_wg, float* tuned_ms, int32_t* tune_source) {
+  if (!p || !n_classes) return set_err(BISPEC_EINVAL, "null argument");
+  *n_classes = (int32_t)p->cls.size();
+  for (int k = 0; k < (int)p->cls.size() && k < capacity; ++k) {
+    const GridClass& c = p->cls[k];
+    if (grid) grid[k] = c.spec.g;
+    if (n_krange) n_krange[k] = c.n_krange_mfma;
+    if (max_cols) max_cols[k] = c.max_cols;
+    if (n_wg) n_wg[k] = c.mfma.n_wg;
+    if (tuned_ms) tuned_ms[k] = c.tuned_ms;
+    if (tune_source) tune_source[k] = c.tune_source;
+  }
+  return BISPEC_OK;
+}
+
 int bispec_field_grid(bispec_plan_t p, int32_t shell, int32_t* grid) {
   if (!p || !grid) return set_err(BISPEC_EINVAL, "null argument");
   const GridClass* c = (shell >= 1 && shell <= p->geo.n_s) ? field_class(*p, shell) : nullptr;
@@ -1144,8 +1362,9 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
   hipStream_t s = (hipStream_t)hip_stream;
   m->d_off.assign(1, 0);
   m->b_off.assign(1, 0);
-  size_t ws_spec = 0, ws_F = 0, ws_a1 = 0, ws_a2 = 0, ws_pv = 0, ws_pm = 0, tables = 0, temp = 0;
+  size_t ws_spec = 0, ws_a1 = 0, ws_a2 = 0, ws_pv = 0, tables = 0, temp = 0;
   std::vector<double> cost(n);
+  long long n_classes = 0;
   for (int32_t i = 0; i < n; ++i) {
     if (cfgs[i].flags & (BISPEC_FLAG_GRAD | BISPEC_FLAG_NO_WORKSPACE))
       return fail(set_err(BISPEC_EINVAL, "batched plans do not take BISPEC_FLAG_GRAD or BISPEC_FLAG_NO_WORKSPACE"));
@@ -1155,24 +1374,36 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
     m->plans.push_back(p);
     int st = build_host(&cfgs[i], *p);
     if (st) return fail(st);
+    n_classes += (long long)p->cls.size();
+  }
+  // voxel ranges per class for a few thousand work groups in the grouped launch
+  const int range_cap = (int)std::max(8LL, std::min(256LL, (4096 / std::max(1LL, n_classes)) / 8 * 8));
+  size_t f_total = 0, pm_total = 0;
+  m->f_at.resize(n);
+  m->pm_at.resize(n);
+  for (int32_t i = 0; i < n; ++i) {
+    bispec_plan_s* p = m->plans[i];
+    cap_mfma_ranges(*p, range_cap);
     const Sizes& z = p->sz;
     ws_spec = std::max(ws_spec, z.spec);
-    ws_F = std::max(ws_F, z.fields32);
     ws_a1 = std::max(ws_a1, z.a1_32);
     ws_a2 = std::max(ws_a2, z.a2_32);
     ws_pv = std::max(ws_pv, z.partial_vec);
-    ws_pm = std::max(ws_pm, z.partial_mfma);
+    m->f_at[i] = f_total;
+    f_total += (z.fields32 + 255) / 256 * 256;
+    m->pm_at[i] = pm_total;
+    pm_total += (z.partial_mfma + 255) / 256 * 256;
     tables += z.tables;
     temp = std::max(temp, z.plan_temp());
     m->d_off.push_back(m->d_off.back() + (int64_t)p->geo.n_g * p->geo.n_g * p->geo.n_g);
     m->b_off.push_back(m->b_off.back() + (int64_t)z.n_tri);
-    // run-time estimate: shell fields written plus contraction tiles, per voxel
+    // run-time estimate of a member's lane work: shell fields written
     double c = 0.0;
-    for (const GridClass& k : p->cls) c += (double)k.n_vox * (k.geo.n_s + 2.0 * (double)k.mfma.tiles);
+    for (const GridClass& k : p->cls) c += (double)k.n_vox * k.geo.n_s;
     cost[i] = c;
   }
   // lanes: as many concurrent workspaces as members, kMaxLanes and memory allow
-  const size_t lane_bytes = ws_spec + ws_F + ws_a1 + ws_a2 + ws_pv + ws_pm;
+  const size_t lane_bytes = ws_spec + ws_a1 + ws_a2 + ws_pv;
   size_t free_b = 0, total_b = 0;
   {
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
@@ -1181,8 +1412,8 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
   const size_t cap = max_bytes_env();
   const size_t avail = cap ? std::min(free_b, cap) : free_b;
   int n_lanes = std::min<int>(kMaxLanes, n);
-  while (n_lanes > 1 && (size_t)n_lanes * lane_bytes + tables + temp > avail) --n_lanes;
-  int st = check_memory((size_t)n_lanes * lane_bytes + tables + temp);
+  while (n_lanes > 1 && (size_t)n_lanes * lane_bytes + f_total + pm_total + tables + temp > avail) --n_lanes;
+  int st = check_memory((size_t)n_lanes * lane_bytes + f_total + pm_total + tables + temp);
   if (st) return fail(st);
   // members to lanes: longest first onto the least-loaded lane
   {
@@ -1202,23 +1433,49 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
     if (!l) return fail(set_err(BISPEC_ENOMEM, "host allocation failed"));
     m->lanes.push_back(l);
     hipError_t e = dalloc(l->ws.spec, ws_spec);
-    if (e == hipSuccess) e = dalloc(l->ws.F, ws_F);
     if (e == hipSuccess) e = dalloc(l->ws.a1, ws_a1);
     if (e == hipSuccess) e = dalloc(l->ws.a2, ws_a2);
     if (e == hipSuccess) e = dalloc(l->ws.partial, ws_pv);
-    if (e == hipSuccess) e = dalloc(l->ws.partial_mfma, ws_pm);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&l->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("batch lane: ") + hipGetErrorString(e)));
   }
   {
-    hipError_t e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
-    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e)));
+    hipError_t e = dalloc(m->F_all, f_total);
+    if (e == hipSuccess) e = dalloc(m->pm_all, pm_total);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_mid, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("batch buffers: ") + hipGetErrorString(e)));
   }
-  // the plans take views of their lane's workspace (owned by the lane)
+  // the plans take views of their lane's workspace and of their pieces of the
+  // resident field and partial buffers
+  std::vector<WsGroup> groups;
   for (int32_t i = 0; i < n; ++i) {
-    st = plan_build(*m->plans[i], s, &m->lanes[m->lane_of[i]]->ws);
+    bispec_plan_s* p = m->plans[i];
+    p->F.view(m->F_all, m->f_at[i], p->sz.fields32);
+    p->partial_mfma.view(m->pm_all, m->pm_at[i], p->sz.partial_mfma);
+    st = plan_build(*p, s, &m->lanes[m->lane_of[i]]->ws);
     if (st) return fail(st);
+    if (p->precision != BISPEC_PREC_FP32)
+      append_ws_groups(*p, (long long)(m->f_at[i] / sizeof(float)), (long long)(m->pm_at[i] / sizeof(double)), groups);
+  }
+  // one grouped launch over every split member's classes: costliest first
+  std::stable_sort(groups.begin(), groups.end(), [](const WsGroup& a, const WsGroup& b) {
+    return (double)a.n_vox / a.n_krange * a.n_wg > (double)b.n_vox / b.n_krange * b.n_wg;
+  });
+  int block = 0;
+  for (WsGroup& g : groups) {
+    g.block0 = block;
+    block += g.n_wg * g.n_krange;
+    m->ws_max_s = std::max(m->ws_max_s, g.max_s);
+    if (!ws_group_ok(g)) return fail(set_err(BISPEC_EINVAL, "a grid class does not fit the split-bf16 kernel"));
+  }
+  m->ws_n = (int)groups.size();
+  m->ws_blocks = block;
+  if (m->ws_n > 0) {
+    hipError_t e = upload(m->ws_groups, groups, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("batch table: ") + hipGetErrorString(e)));
   }
   *out = m;
   return BISPEC_OK;
@@ -1276,6 +1533,7 @@ int bispec_destroy_many(bispec_many_t m) {
 }  // extern "C"
 
 bispec_many_s::~bispec_many_s() {
+  if (ev_mid) (void)hipEventDestroy(ev_mid);
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);

@@ -898,6 +898,18 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
   }
 }
 
+// dst[i] = uniform in [-1, 1) from a 64-bit hash of (seed, i) (splitmix64 finaliser)
+__global__ void k_fill_random(float* __restrict__ dst, long long n, unsigned long long seed) {
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ULL * (unsigned long long)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    dst[i] = (float)((double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
+  }
+}
+
 // dst[0 .. n16) = 0 in 16-byte stores (grid-stride)
 __global__ void k_zero16(uint4* __restrict__ dst, long long n16) {
   const long long step = (long long)gridDim.x * blockDim.x;
@@ -930,6 +942,13 @@ hipError_t launch_adjoint_mfma(const float* F, float* G, const AdjGroup* groups_
   if (n_groups < 1 || n_blocks < 1 || max_s > kMaxSplitShells) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_adjoint_mfma, dim3((unsigned)n_blocks), dim3(kAdjWaves * 64), adj_lds_bytes(max_s), st, F, G,
                      groups_dev, n_groups);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_random(float* dst, long long n, unsigned long long seed, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const long long want = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)(want < 8192 ? want : 8192)), dim3(256), 0, st, dst, n, seed);
   return hipGetLastError();
 }
 

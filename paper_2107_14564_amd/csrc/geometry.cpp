@@ -360,7 +360,8 @@ void choose_grid_classes(const ShellGeometry& g, const Selection& s, bool one_gr
   }
 }
 
-void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
+void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt, int max_cols) {
+  max_cols = std::max(1, std::min(max_cols, kMaxColTiles));
   std::map<std::pair<int, int>, std::vector<int>> pl;
   for (const Tri& t : s.tri) pl[{t.a1, t.a2}].push_back(t.a3);
   struct P { int i, j, lo, hi; };
@@ -369,7 +370,7 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt) {
   for (auto& kv : pl) {
     std::map<int, std::pair<int, int>> per_window;  // window -> (min l, max l)
     for (int l : kv.second) {
-      const int wdw = ((l - 1) / kMCols) / kMaxColTiles;
+      const int wdw = ((l - 1) / kMCols) / max_cols;
       auto it = per_window.find(wdw);
       if (it == per_window.end()) per_window[wdw] = {l, l};
       else it->second = {std::min(it->second.first, l), std::max(it->second.second, l)};

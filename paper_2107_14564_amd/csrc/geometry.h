@@ -154,7 +154,10 @@ struct MfmaTiling {
   int32_t max_s = 0;              // largest s_n
 };
 
-void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt);
+// max_cols (1..kMaxColTiles): the column-tile window, i.e. the most column
+// tiles one slot may hold (a tile-shape parameter of the autotuner; narrower
+// windows give more, shorter slots whose row operands stream).
+void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt, int max_cols = kMaxColTiles);
 
 // ---- adjoint field build on the matrix cores ------------------------------
 // G_n(x) = sum_j F_j(x) H_(n,j)(x),  H_(n,j)(x) = sum_l W[(n,j), l] F_l(x), where

@@ -190,6 +190,8 @@ hipError_t launch_adjoint_mfma(const float* F, float* G, const AdjGroup* groups_
 hipError_t launch_adjoint_shells(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, int n,
                                  const float2* tw, float scale, float beta, bool zero_first, hipStream_t st);
 
+// dst[0 .. n) = pseudo-random values in [-1, 1) (autotuner timing fields)
+hipError_t launch_fill_random(float* dst, long long n, unsigned long long seed, hipStream_t st);
 // dst[0 .. bytes) = 0 with a fill kernel (capture-safe; bytes and dst 16-byte aligned)
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
 // out[o] = norm[o] * sum_k partial[k * stride + (slot ? slot[t] : t)] with o = out_idx ? out_idx[t] : t,

@@ -85,6 +85,11 @@ class Plan:
         _abi.bispec_copy_class_field(self.handle, cls, shell, out.data_ptr(), _stream())
         return out
 
+    def classes(self):
+        """The grid classes as built: grid, voxel ranges, column-tile window,
+        work groups, autotuned time and its source, per class."""
+        return _abi.bispec_plan_classes(self.handle)
+
     def field_grid(self, shell: int) -> int:
         """The grid of the largest grid class whose fields cover this shell."""
         return _abi.bispec_field_grid(self.handle, shell)
@@ -182,6 +187,10 @@ class BatchPlan:
             raise ValueError("out must be a contiguous float64 tensor of the batch's total n_tri")
         _abi.bispec_run_many(self.handle, packed.data_ptr(), out.data_ptr(), use_graph, _stream())
         return out
+
+    def classes(self, i: int):
+        """Member i's grid classes as built (see Plan.classes)."""
+        return _abi.bispec_plan_classes(_abi.bispec_many_plan(self.handle, i))
 
     def split(self, b: torch.Tensor):
         return [b[self.b_off[i]:self.b_off[i + 1]] for i in range(self.n)]

@@ -100,20 +100,37 @@ def test_batch_members_match_single_plans():
     bp.close()
 
 
-def test_autotuned_plan():
-    """FLAG_AUTOTUNE picks the voxel-range count by timing; results stay within tolerance."""
+def test_autotuned_plan(tmp_path, monkeypatch):
+    """FLAG_AUTOTUNE picks each grid class's column-tile window and voxel-range
+    count by timing; results stay within tolerance.  With BISPEC_TUNE_CACHE set,
+    the choices are written to the cache, and a second plan of the same
+    configuration reads them back (same choices, bit-identical B)."""
     import torch
     import paper_2107_14564_amd as P
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("BISPEC_TUNE_CACHE", str(cache))
     n_g, box = 64, 300.0
     d = quadratic_ng_field(gaussian_field(n_g, box, PowerLaw(-1.0), 71), 1.0).astype(np.float32)
     plan = P.Plan(n_g, box, 1.0, 20, rsd_beta=0.5, flags=P.FLAG_AUTOTUNE)
+    tuned = plan.classes()
+    say("autotuned classes %s" % tuned)
+    assert all(c["tune_source"] == "timed" and c["tuned_ms"] > 0 and c["max_cols"] in (4, 8)
+               and c["n_krange"] in (64, 128, 256, 512) for c in tuned)
     B = plan.run(torch.from_numpy(d).cuda()).cpu().numpy()
     ref = fbe.estimate(d.astype(np.float64), box, 1.0, plan.triangles.numpy(), rsd_beta=0.5, with_abs=True)
     mt = metrics(B, ref["B"], ref["S"])
     say("autotuned %s" % mt)
     assert np.array_equal(plan.ntri.numpy(), ref["ntri"])
     assert mt["e_cond"] <= TOL and mt["e_norm"] <= TOL
+    assert len(cache.read_text().splitlines()) == len(tuned)
+    plan2 = P.Plan(n_g, box, 1.0, 20, rsd_beta=0.5, flags=P.FLAG_AUTOTUNE)
+    again = plan2.classes()
+    assert [c["tune_source"] for c in again] == ["cache"] * len(tuned)
+    assert [(c["max_cols"], c["n_krange"]) for c in again] == [(c["max_cols"], c["n_krange"]) for c in tuned]
+    B2 = plan2.run(torch.from_numpy(d).cuda()).cpu().numpy()
+    assert np.array_equal(B, B2)
     plan.close()
+    plan2.close()
 
 
 def test_batch_rejects_grad_flag():
