@@ -11,4 +11,6 @@ Modules
   adjoint   gradient of a linear functional of B with respect to delta(x)
   analytic  tree-level B of the quadratic non-Gaussian field (eq. bana) and the
             linear-RSD monopole (eq. RSD)
+  polyspectrum  the fourth-order polyspectrum estimator (Section 4: four shell
+            fields, cutoff 2 pi N_g / (4 L)) and its closed-4-tuple sum
 """
