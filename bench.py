@@ -43,6 +43,9 @@ WORKLOADS = {
                                 sel=dict(tri_mode=2, k1_shells=list(range(2, 41, 2)), n_mu=20, n_t=20)),
     "ng32_10shells_grid": dict(field="ng32", n_g=32, box_l=300.0, dk=1.0, n_shells=10, rsd_beta=0.0,
                                sel=dict(tri_mode=2, k1_shells=list(range(5, 11)), n_mu=10, n_t=10)),
+    # the fourth-order polyspectrum (Section 4): all 35 345 bins of 30 shells on a 128^3 grid
+    "ng128_30shells_order4": dict(field="ng128", n_g=128, box_l=600.0, dk=1.0, n_shells=30, rsd_beta=0.5,
+                                  sel=dict(order=4)),
     # differentiation workload: 30 shells, a1 in {29, 30} (494 triangles); --grad times bispec_grad too
     "ng256_30shells_grad": dict(field="ng256_grad", n_g=256, box_l=1000.0, dk=1.0, n_shells=30, rsd_beta=0.0,
                                 sel=dict(tri_mode=1, k1_shells=[29, 30])),
@@ -108,8 +111,9 @@ def class_work(plan, tri):
     flop, field_vox = 0.0, 0.0
     for k, (g, lo, hi) in enumerate(zip(plan.class_grids, plan.class_shell_lo, plan.class_shell_hi)):
         t = tri[tc == k]
-        pairs = len({(int(a), int(b)) for a, b, _ in t})
-        flop += float(g) ** 3 * (2.0 * len(t) + pairs)
+        # order 4: T = sum P_(a1,a2) P_(a3,a4), pairs from both halves of each bin
+        pairs = {(int(r[0]), int(r[1])) for r in t} | ({(int(r[2]), int(r[3])) for r in t} if t.shape[1] == 4 else set())
+        flop += float(g) ** 3 * (2.0 * len(t) + len(pairs))
         field_vox += float(g) ** 3 * (hi - lo + 1)
     return flop, field_vox
 
@@ -122,17 +126,26 @@ def cpu_baseline(delta32, w: dict, plan_tri, plan_ntri, b_gpu) -> tuple:
     (e_norm, max e_cond, N_tri equality)."""
     import numpy as np
 
-    from oracle import fbe, geometry
+    from oracle import fbe, geometry, polyspectrum
     cores = os.cpu_count() or 1
     d64 = delta32.astype(np.float64)
-    s_shells = 6 if delta32.shape[0] <= 512 else 2   # 12 (4) float64 fields of N^3 on the host, ~10 s
-    tri = geometry.all_triangles(s_shells)
     t0 = time.perf_counter()
-    ref = fbe.estimate(d64, w["box_l"], w["dk"], tri, rsd_beta=w["rsd_beta"], with_abs=True)
+    if plan_tri.shape[1] == 4:
+        s_shells = 10   # 20 float64 fields of 128^3 and 1001 quadruples, ~10 s
+        tri = polyspectrum.all_quads(s_shells)
+        ref = polyspectrum.fft_estimate(d64, w["box_l"], w["dk"], tri, rsd_beta=w["rsd_beta"], with_abs=True)
+        ref = {"B": ref["T4"], "S": ref["S"], "ntri": ref["nquad"]}
+        what, unit = "quadruples", "quadruples/s"
+    else:
+        s_shells = 6 if delta32.shape[0] <= 512 else 2   # 12 (4) float64 fields of N^3 on the host, ~10 s
+        tri = geometry.all_triangles(s_shells)
+        ref = fbe.estimate(d64, w["box_l"], w["dk"], tri, rsd_beta=w["rsd_beta"], with_abs=True)
+        what, unit = "triangles", "triangles/s"
     dt = time.perf_counter() - t0
-    base = {"value": len(tri) / dt, "unit": "triangles/s", "cores": cores, "kind": "oracle",
-            "sample": "all %d closable triangles of shells 1-%d at N_g=%d (float64 FFTs, fields, triple sums "
-                      "and their summation scale, N_tri) in %.2f s" % (len(tri), s_shells, delta32.shape[0], dt),
+    base = {"value": len(tri) / dt, "unit": unit, "cores": cores, "kind": "oracle",
+            "sample": "all %d closable %s of shells 1-%d at N_g=%d (float64 FFTs, fields, multiple sums "
+                      "and their summation scale, bin counts) in %.2f s" % (len(tri), what, s_shells,
+                                                                           delta32.shape[0], dt),
             "seconds": dt}
     index = {tuple(int(v) for v in r): t for t, r in enumerate(plan_tri)}
     idx = np.array([index.get(tuple(int(v) for v in r), -1) for r in tri])
@@ -217,10 +230,14 @@ def main():
     flop, field_vox = class_work(plan, tri)
     contract_ms = float(stages[2])
     achieved = flop / (contract_ms * 1e-3) / 1e12
+    order4 = plan.order == 4
+    unit = "quadruples/s" if order4 else "triangles/s"
+    kernel = ("k_contract4<false>" if order4 else "k_contract_bf16x3") if prec == P.PREC_SPLITBF16 \
+        else "k_contract_vec<float>"
     result = {
-        "metric": "triangles/s",
+        "metric": unit,
         "value": plan.n_tri / (ms * 1e-3),
-        "unit": "triangles/s",
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -236,8 +253,9 @@ def main():
                       "normalise": stages[3]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS,
-                     "traffic": measured_traffic(args.workload) if prec == P.PREC_SPLITBF16 else None,
-                     "kernel": "k_contract_bf16x3" if prec == P.PREC_SPLITBF16 else "k_contract_vec<float>",
+                     "traffic": measured_traffic(args.workload) if prec == P.PREC_SPLITBF16 and not order4
+                     else None,
+                     "kernel": kernel,
                      "algorithmic_flop": flop},
         "grid_classes": [dict(grid=gc, shells=[lo, hi], n_tri=int((plan.tri_class.numpy() == k).sum()),
                               n_krange=cp["n_krange"], max_cols=cp["max_cols"], n_wg=cp["n_wg"],
@@ -252,7 +270,7 @@ def main():
         "mode_triangles_per_s": float(plan.ntri.numpy().astype(np.float64).sum()) / (ms * 1e-3),
     }
     result["fft_hbm"]["frac"] = result["fft_hbm"]["achieved_GBs"] / PEAK_HBM_GBS
-    if not args.no_fp32_compare and prec == P.PREC_SPLITBF16:
+    if not args.no_fp32_compare and prec == P.PREC_SPLITBF16 and not order4:
         plan.set_precision(P.PREC_FP32)
         plan.run(delta)
         torch.cuda.synchronize()

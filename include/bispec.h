@@ -126,6 +126,14 @@ typedef struct bispec_config {
                           /*   0 = grid classes up to the smallest supported size   */
                           /*   above 3 max|m_i|; else one class on this supported   */
                           /*   size, 3 max|m_i| < n_est <= n_g                      */
+  int32_t order;          /* 0 or 3: the bispectrum; 4: the fourth-order           */
+                          /*   polyspectrum (Section 4): bins of four shells       */
+                          /*   a1 >= a2 >= a3 >= a4 with a2 + a3 + a4 >= a1,        */
+                          /*   T = sum_x D D D D / (V N_quad N_g^3), N_quad =       */
+                          /*   N_g^-3 sum_x I I I I; cutoff (n_s + 1/2) w <= N_g/4; */
+                          /*   one grid G > 4 max|m_i|; selection ALL, K1SET or     */
+                          /*   LIST (rows of 4); split-bf16 only; no GRAD,          */
+                          /*   NO_WORKSPACE or batch                                */
 } bispec_config;
 
 /* ---- host-only queries (no GPU needed) ------------------------------------ */
@@ -136,6 +144,10 @@ typedef struct bispec_config {
  * rows.  Errors: EINVAL, ECUTOFF. */
 int bispec_query_triangles(const bispec_config* cfg, int64_t* n_tri, int32_t* abc,
                            double* k1_mu_t, int64_t capacity);
+
+/* Selected quadruples of an order-4 cfg (as bispec_query_triangles, four
+ * columns: abcd host int32 [capacity][4]).  Errors: EINVAL, ECUTOFF. */
+int bispec_query_quads(const bispec_config* cfg, int64_t* n_quad, int32_t* abcd, int64_t capacity);
 
 /* Per-shell mode counts (host int64 [n_shells], both halves of k-space) and
  * mean |k| (host double [n_shells], in k units), Section 2.1's k_n. */
@@ -212,6 +224,11 @@ int bispec_run_noalloc(bispec_plan_t plan, const float* delta, double* B, void* 
  * gB: device float64 [n_tri]; gdelta: device float32 [N_g^3] (overwritten).
  * Errors: ESTATE when no run preceded or the plan lacks BISPEC_FLAG_GRAD. */
 int bispec_grad(bispec_plan_t plan, const double* gB, float* gdelta, void* hip_stream);
+
+/* Host copies of an order-4 plan's bins: abcd [n][4] int32 and nquad [n] int64
+ * (the exact closed-quadruple counts); bispec_num_triangles gives n.  Either
+ * may be null.  EINVAL for a bispectrum plan. */
+int bispec_quads(bispec_plan_t plan, int32_t* abcd, int64_t* nquad);
 
 /* Switch the contraction arithmetic of an existing plan (enum bispec_precision). */
 int bispec_set_precision(bispec_plan_t plan, int32_t precision);

@@ -31,7 +31,7 @@ class bispec_config(C.Structure):
         ("rsd_beta", C.c_double), ("tri_mode", C.c_int32), ("n_k1", C.c_int32),
         ("k1_shells", C.POINTER(C.c_int32)), ("n_mu", C.c_int32), ("n_t", C.c_int32),
         ("n_list", C.c_int64), ("list", C.POINTER(C.c_int32)), ("precision", C.c_int32),
-        ("flags", C.c_uint32), ("n_est", C.c_int32),
+        ("flags", C.c_uint32), ("n_est", C.c_int32), ("order", C.c_int32),
     ]
 
 
@@ -58,6 +58,8 @@ def lib() -> C.CDLL:
             "bispec_field_grid": [P, I32, C.POINTER(I32)],
             "bispec_contraction_tiles": [cfgp, I64, C.POINTER(I32), C.POINTER(I32)],
             "bispec_copy_class_field": [P, I32, I32, P, P],
+            "bispec_query_quads": [cfgp, C.POINTER(I64), C.POINTER(I32), I64],
+            "bispec_quads": [P, C.POINTER(I32), C.POINTER(I64)],
             "bispec_plan_classes": [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
                                     C.POINTER(I32), C.POINTER(C.c_float), C.POINTER(I32)],
             "bispec_plan": [cfgp, P, C.POINTER(P)],
@@ -100,17 +102,18 @@ def _i32_array(values):
 
 
 def make_config(n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=TRI_ALL, k1_shells=None, n_mu=0, n_t=0,
-                triangles=None, precision=PREC_SPLITBF16, flags=0, n_est=0):
+                triangles=None, precision=PREC_SPLITBF16, flags=0, n_est=0, order=0):
     """A bispec_config plus the ctypes arrays it points into (keep both alive)."""
     k1, nk1 = _i32_array(k1_shells)
     flat = None if triangles is None else [int(v) for row in triangles for v in row]
     lst, nflat = _i32_array(flat)
+    width = 4 if int(order) == 4 else 3
     cfg = bispec_config(n_g=int(n_g), n_shells=int(n_shells), box_l=float(box_l), dk=float(dk),
                         rsd_beta=float(rsd_beta), tri_mode=int(tri_mode), n_k1=nk1,
                         k1_shells=C.cast(k1, C.POINTER(C.c_int32)) if k1 is not None else None,
-                        n_mu=int(n_mu), n_t=int(n_t), n_list=nflat // 3,
+                        n_mu=int(n_mu), n_t=int(n_t), n_list=nflat // width,
                         list=C.cast(lst, C.POINTER(C.c_int32)) if lst is not None else None,
-                        precision=int(precision), flags=int(flags), n_est=int(n_est))
+                        precision=int(precision), flags=int(flags), n_est=int(n_est), order=int(order))
     return cfg, (k1, lst)
 
 
@@ -153,7 +156,10 @@ def bispec_grid_classes(cfg):
     k = n.value
     grid, lo, hi = (C.c_int32 * k)(), (C.c_int32 * k)(), (C.c_int32 * k)()
     n_tri = C.c_int64(0)
-    _check(lib().bispec_query_triangles(C.byref(cfg), C.byref(n_tri), None, None, 0), "bispec_query_triangles")
+    if cfg.order == 4:
+        _check(lib().bispec_query_quads(C.byref(cfg), C.byref(n_tri), None, 0), "bispec_query_quads")
+    else:
+        _check(lib().bispec_query_triangles(C.byref(cfg), C.byref(n_tri), None, None, 0), "bispec_query_triangles")
     tc = (C.c_int32 * max(1, n_tri.value))()
     _check(lib().bispec_grid_classes(C.byref(cfg), C.byref(n), grid, lo, hi, k, tc), "bispec_grid_classes")
     return list(grid), list(lo), list(hi), list(tc)[:n_tri.value]
@@ -181,6 +187,25 @@ def bispec_plan_classes(plan: int):
     _check(lib().bispec_plan_classes(C.c_void_p(plan), k, C.byref(n), g, kr, mc, wg, ms, src), "bispec_plan_classes")
     return [dict(grid=g[i], n_krange=kr[i], max_cols=mc[i], n_wg=wg[i], tuned_ms=float(ms[i]),
                  tune_source=("default", "timed", "cache")[src[i]]) for i in range(k)]
+
+
+def bispec_query_quads(cfg):
+    """Selected quadruples (a1, a2, a3, a4) of an order-4 configuration."""
+    n = C.c_int64(0)
+    _check(lib().bispec_query_quads(C.byref(cfg), C.byref(n), None, 0), "bispec_query_quads")
+    q = (C.c_int32 * max(1, 4 * n.value))()
+    _check(lib().bispec_query_quads(C.byref(cfg), C.byref(n), q, n.value), "bispec_query_quads")
+    return [tuple(q[4 * t:4 * t + 4]) for t in range(n.value)]
+
+
+def bispec_quads(plan: int):
+    """(abcd, nquad) of an order-4 plan."""
+    n = C.c_int64(0)
+    _check(lib().bispec_num_triangles(C.c_void_p(plan), C.byref(n)), "bispec_num_triangles")
+    q = (C.c_int32 * max(1, 4 * n.value))()
+    nq = (C.c_int64 * max(1, n.value))()
+    _check(lib().bispec_quads(C.c_void_p(plan), q, nq), "bispec_quads")
+    return [tuple(q[4 * t:4 * t + 4]) for t in range(n.value)], list(nq)[:n.value]
 
 
 def bispec_field_grid(plan: int, shell: int) -> int:

@@ -241,6 +241,12 @@ struct bispec_plan_s {
   // grouped split-bf16 launch over the classes
   std::vector<WsGroup> ws_host;
   int ws_blocks = 0, ws_max_s = 0;
+  // order 4 (the fourth-order polyspectrum): bins, pair tiling and its tables
+  bool quad = false;
+  std::vector<Quad> quads;
+  QuadTiling qt;
+  int n_krange4 = 8;
+  DevBuf q_pairs, q_rb, q_cb, q_tiles, q_wave, q_slot;
   // grouped matrix-core adjoint build over the classes (GRAD, split-bf16)
   bool adj_mfma = false;
   int adj_groups_n = 0, adj_blocks = 0, adj_max_s = 0;
@@ -257,6 +263,56 @@ struct bispec_plan_s {
 
 namespace {
 
+// Order-4 plans: one grid class over every shell on the estimator grid
+// (G > 4 max|m_i|), the quadruples and their pair tiling.
+int build_host_quad(const bispec_config* cfg, bispec_plan_s& p) {
+  std::string err;
+  if (cfg->precision != BISPEC_PREC_SPLITBF16)
+    return set_err(BISPEC_EINVAL, "order-4 plans contract in split-bf16 only");
+  if (cfg->flags & (BISPEC_FLAG_GRAD | BISPEC_FLAG_NO_WORKSPACE | BISPEC_FLAG_AUTOTUNE))
+    return set_err(BISPEC_EINVAL, "order-4 plans take no GRAD, NO_WORKSPACE or AUTOTUNE flag");
+  int st = select_quads(*cfg, p.geo, p.quads, err);
+  if (st) return set_err(st, err);
+  build_quad_tiles(p.quads, p.geo.n_s, p.qt);
+  if (p.qt.n_pairs > kMaxQuadPairs)
+    return set_err(BISPEC_EINVAL, "order-4 plans stage at most 496 shell pairs (all bins of 31 shells)");
+  p.quad = true;
+  const long long n = p.geo.n_g;
+  Sizes& s = p.sz;
+  s.n_tri = (long long)p.quads.size();
+  s.spec = (size_t)n * n * (size_t)spec_row(n) * sizeof(float2);
+  p.cls.clear();
+  p.cls.emplace_back();
+  GridClass& c = p.cls.back();
+  c.spec.g = p.geo.n_est;
+  c.spec.s_lo = 0;
+  c.spec.n_s = p.geo.n_s;
+  c.geo = class_geometry(p.geo, c.spec);
+  const long long g = c.spec.g;
+  plan_shell_passes(c.geo, (int)g, false, c.pass32);
+  ShellPassPlan p64;
+  plan_shell_passes(c.geo, (int)g, true, p64);
+  c.n_vox = g * g * g;
+  c.fields32 = (size_t)blocked_elems(c.n_vox, c.geo.n_s) * sizeof(float);
+  c.fields64 = (size_t)blocked_elems(c.n_vox, c.geo.n_s) * sizeof(double);
+  c.f_off = 0;
+  s.fields32 = (c.fields32 + 255) / 256 * 256;
+  s.a1_32 = (size_t)c.pass32.a1_elems * sizeof(float2);
+  s.a2_32 = (size_t)c.pass32.a2_elems * sizeof(float2);
+  s.fields64 = c.fields64;
+  s.a1_64 = (size_t)p64.a1_elems * sizeof(double2);
+  s.a2_64 = (size_t)p64.a2_elems * sizeof(double2);
+  p.n_krange4 = n_krange_mfma_for(c.n_vox);
+  s.partial_mfma = (size_t)p.n_krange4 * p.qt.n_wg * kTilesPerWg * kMTileElems * sizeof(double);
+  s.partial_vec = 0;
+  s.tables = p.qt.pair_ij.size() * 4 + p.qt.rb_pairs.size() * 4 + p.qt.cb_pairs.size() * 4 + p.qt.tiles.size() * 4 +
+             p.qt.slot_of.size() * 4 + c.pass32.x_tiles.size() * sizeof(int4) + (size_t)s.n_tri * 16 +
+             (size_t)(n + g) * 16 + 4096 * 4;
+  s.own_workspace = true;
+  p.precision = cfg->precision;
+  return BISPEC_OK;
+}
+
 int build_host(const bispec_config* cfg, bispec_plan_s& p) {
   if (!cfg) return set_err(BISPEC_EINVAL, "null config");
   std::string err;
@@ -270,6 +326,7 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
     return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 128");
   if ((cfg->flags & BISPEC_FLAG_NO_WORKSPACE) && (cfg->flags & (BISPEC_FLAG_GRAD | BISPEC_FLAG_AUTOTUNE)))
     return set_err(BISPEC_EINVAL, "BISPEC_FLAG_NO_WORKSPACE excludes BISPEC_FLAG_GRAD and BISPEC_FLAG_AUTOTUNE");
+  if (cfg->order == 4) return build_host_quad(cfg, p);
   st = select_triangles(*cfg, p.geo, p.sel, err);
   if (st) return set_err(st, err);
   const long long n = p.geo.n_g;
@@ -428,6 +485,22 @@ ContractArgs contract_args(GridClass& c, double* partial_base) {
   return a;
 }
 
+Quad4Args quad_args(bispec_plan_s& p, double* partial) {
+  Quad4Args a;
+  a.pair_ij = p.q_pairs.as<int32_t>();
+  a.rb_pairs = p.q_rb.as<int32_t>();
+  a.cb_pairs = p.q_cb.as<int32_t>();
+  a.tiles = p.q_tiles.as<int4>();
+  a.wave_t0 = p.q_wave.as<int32_t>();
+  a.n_pairs = p.qt.n_pairs;
+  a.n_s = p.geo.n_s;
+  a.n_wg = p.qt.n_wg;
+  a.n_krange = p.n_krange4;
+  a.n_vox = p.cls[0].n_vox;
+  a.partial = partial;
+  return a;
+}
+
 ShellLaunch shell_launch(const ShellPassPlan& pp, const DevBuf& shells, const DevBuf& xt, const DevBuf& yo,
                          const DevBuf& zo, int n_s, int spec_n) {
   ShellLaunch L;
@@ -507,6 +580,97 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
     std::snprintf(buf, sizeof buf, "N_tri sum of triangle %lld is %.6f from an integer", worst_t, worst);
     return set_err(BISPEC_EPREC, buf);
   }
+  return BISPEC_OK;
+}
+
+// N_quad from the float64 unit shells (eq. 2FT) on the estimator grid:
+// N_quad = G^-3 sum_y I_a1 I_a2 I_a3 I_a4, rounded and checked.
+int compute_nquad(bispec_plan_s& p, hipStream_t st) {
+  GridClass& c = p.cls[0];
+  const int g = c.spec.g;
+  DevBuf I, a1, a2, sums, shells, xt, yo, zo, tw;
+  HIP_TRY(dalloc(I, p.sz.fields64));
+  HIP_TRY(dalloc(a1, p.sz.a1_64));
+  HIP_TRY(dalloc(a2, p.sz.a2_64));
+  HIP_TRY(dalloc(sums, (size_t)p.sz.n_tri * sizeof(double)));
+  ShellPassPlan pp;
+  plan_shell_passes(c.geo, g, true, pp);
+  HIP_TRY(upload(shells, pp.shells, st));
+  HIP_TRY(upload(xt, pp.x_tiles, st));
+  HIP_TRY(upload(yo, pp.y_off, st));
+  HIP_TRY(upload(zo, pp.z_off, st));
+  HIP_TRY(upload(tw, twiddles64(g), st));
+  ShellLaunch L = shell_launch(pp, shells, xt, yo, zo, c.geo.n_s, p.geo.n_g);
+  HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), L, g, tw.as<double2>(), st));
+  HIP_TRY(launch_contract4_f64(I.as<double>(), quad_args(p, p.partial_mfma.as<double>()), st));
+  HIP_TRY(launch_reduce(p.partial_mfma.as<double>(), p.n_krange4, (long long)p.qt.n_wg * kTilesPerWg * kMTileElems,
+                        p.sz.n_tri, p.q_slot.as<int32_t>(), nullptr, nullptr, sums.as<double>(), st));
+  std::vector<double> h(p.sz.n_tri);
+  HIP_TRY(hipMemcpyAsync(h.data(), sums.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  p.ntri.resize(p.sz.n_tri);
+  double worst = 0.0;
+  long long worst_t = -1;
+  for (long long t = 0; t < p.sz.n_tri; ++t) {
+    const double v = h[t] / (double)c.n_vox;
+    const double r = std::nearbyint(v);
+    if (std::fabs(v - r) > worst) {
+      worst = std::fabs(v - r);
+      worst_t = t;
+    }
+    p.ntri[t] = (int64_t)r;
+  }
+  if (worst > 1e-3) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "N_quad sum of bin %lld is %.6f from an integer", worst_t, worst);
+    return set_err(BISPEC_EPREC, buf);
+  }
+  return BISPEC_OK;
+}
+
+// Device side of an order-4 plan.
+int plan_build_quad(bispec_plan_s& p, hipStream_t s) {
+#define PLAN_HIP(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return set_err(BISPEC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  PLAN_HIP(hipGetDevice(&p.device));
+  PLAN_HIP(upload(p.q_pairs, p.qt.pair_ij, s));
+  PLAN_HIP(upload(p.q_rb, p.qt.rb_pairs, s));
+  PLAN_HIP(upload(p.q_cb, p.qt.cb_pairs, s));
+  PLAN_HIP(upload(p.q_tiles, p.qt.tiles, s));
+  PLAN_HIP(upload(p.q_wave, p.qt.wave_t0, s));
+  PLAN_HIP(upload(p.q_slot, p.qt.slot_of, s));
+  PLAN_HIP(dalloc(p.partial_mfma, p.sz.partial_mfma));
+  PLAN_HIP(prepare_contract4());
+  int st = compute_nquad(p, s);
+  if (st) return st;
+  GridClass& c = p.cls[0];
+  PLAN_HIP(upload(c.shells, c.pass32.shells, s));
+  PLAN_HIP(upload(c.x_tiles, c.pass32.x_tiles, s));
+  PLAN_HIP(upload(c.y_off, c.pass32.y_off, s));
+  PLAN_HIP(upload(c.z_off, c.pass32.z_off, s));
+  PLAN_HIP(upload(c.tw32, twiddles32(c.spec.g), s));
+  const int n = p.geo.n_g;
+  PLAN_HIP(upload(p.tw32, twiddles32(n), s));
+  // T = (dV N^{3/2})^4 sum_y F_s F_s F_s F_s / (V N_quad G^3)
+  const double V = p.geo.box_l * p.geo.box_l * p.geo.box_l;
+  const double dV = V / ((double)n * n * n);
+  const double cc = dV * dV * dV * dV * std::pow((double)n, 6.0) / (V * (double)c.n_vox);
+  std::vector<double> norm(p.sz.n_tri);
+  for (long long t = 0; t < p.sz.n_tri; ++t) norm[t] = p.ntri[t] > 0 ? cc / (double)p.ntri[t] : NAN;
+  PLAN_HIP(upload(p.norm, norm, s));
+  PLAN_HIP(dalloc(p.spec, p.sz.spec));
+  PLAN_HIP(dalloc(p.a1, p.sz.a1_32));
+  PLAN_HIP(dalloc(p.a2, p.sz.a2_32));
+  PLAN_HIP(dalloc(p.F, p.sz.fields32));
+  PLAN_HIP(dalloc(p.partial, 16));
+  if (p.cfg.flags & BISPEC_FLAG_STAGE_TIMING)
+    for (auto& e : p.ev) PLAN_HIP(hipEventCreate(&e));
+  PLAN_HIP(prepare_forward());
+  PLAN_HIP(hipStreamSynchronize(s));
+#undef PLAN_HIP
   return BISPEC_OK;
 }
 
@@ -670,7 +834,12 @@ int run_core(bispec_plan_s& p, const RunBufs& w, const float* delta, double* B, 
     HIP_TRY(launch_data_shells(w.spec, w.a1, w.a2, w.F + c.f_off, class_launch(p, c), c.spec.g, c.tw32.as<float2>(),
                                s));
   if (timing) HIP_TRY(hipEventRecord(p.ev[2], s));
-  if (p.precision == BISPEC_PREC_FP32) {
+  if (p.quad) {
+    HIP_TRY(launch_contract4_bf16x3(w.F, quad_args(p, w.partial_mfma), s));
+    if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
+    HIP_TRY(launch_reduce(w.partial_mfma, p.n_krange4, (long long)p.qt.n_wg * kTilesPerWg * kMTileElems, p.sz.n_tri,
+                          p.q_slot.as<int32_t>(), p.norm.as<double>(), nullptr, B, s));
+  } else if (p.precision == BISPEC_PREC_FP32) {
     for (GridClass& c : p.cls) HIP_TRY(launch_contract_fp32(w.F + c.f_off, contract_args(c, w.partial), s));
     if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
     for (GridClass& c : p.cls)
@@ -1071,6 +1240,7 @@ const char* bispec_last_error(void) { return g_err.c_str(); }
 int bispec_query_triangles(const bispec_config* cfg, int64_t* n_tri, int32_t* abc, double* k1_mu_t,
                            int64_t capacity) {
   if (!cfg || !n_tri) return set_err(BISPEC_EINVAL, "null argument");
+  if (cfg->order == 4) return set_err(BISPEC_EINVAL, "an order-4 configuration: use bispec_query_quads");
   std::string err;
   ShellGeometry g;
   int st = build_shells(*cfg, g, err);
@@ -1122,6 +1292,20 @@ int bispec_grid_classes(const bispec_config* cfg, int32_t* n_classes, int32_t* g
   ShellGeometry g;
   int st = build_shells(*cfg, g, err);
   if (st) return set_err(st, err);
+  if (cfg->order == 4) {  // one grid for every bin
+    std::vector<Quad> q;
+    st = select_quads(*cfg, g, q, err);
+    if (st) return set_err(st, err);
+    *n_classes = 1;
+    if (capacity > 0) {
+      if (grid) grid[0] = g.n_est;
+      if (shell_lo) shell_lo[0] = 1;
+      if (shell_hi) shell_hi[0] = g.n_s;
+    }
+    if (tri_class)
+      for (size_t t = 0; t < q.size(); ++t) tri_class[t] = 0;
+    return BISPEC_OK;
+  }
   Selection s;
   st = select_triangles(*cfg, g, s, err);
   if (st) return set_err(st, err);
@@ -1141,6 +1325,7 @@ int bispec_grid_classes(const bispec_config* cfg, int32_t* n_classes, int32_t* g
 }
 
 int bispec_contraction_tiles(const bispec_config* cfg, int64_t capacity, int32_t* tile, int32_t* shape) {
+  if (cfg && cfg->order == 4) return set_err(BISPEC_EINVAL, "order-4 configurations use the pair tiling");
   bispec_plan_s p;
   int st = build_host(cfg, p);
   if (st) return st;
@@ -1175,12 +1360,49 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
   if (!p) return set_err(BISPEC_ENOMEM, "host allocation failed");
   int st = build_host(cfg, *p);
   if (st == BISPEC_OK) st = check_memory(p->sz.plan_peak());
-  if (st == BISPEC_OK) st = plan_build(*p, (hipStream_t)hip_stream, nullptr);
+  if (st == BISPEC_OK)
+    st = p->quad ? plan_build_quad(*p, (hipStream_t)hip_stream) : plan_build(*p, (hipStream_t)hip_stream, nullptr);
   if (st != BISPEC_OK) {
     delete p;
     return st;
   }
   *out = p;
+  return BISPEC_OK;
+}
+
+int bispec_query_quads(const bispec_config* cfg, int64_t* n_quad, int32_t* abcd, int64_t capacity) {
+  if (!cfg || !n_quad) return set_err(BISPEC_EINVAL, "null argument");
+  if (cfg->order != 4) return set_err(BISPEC_EINVAL, "not an order-4 configuration");
+  std::string err;
+  ShellGeometry g;
+  int st = build_shells(*cfg, g, err);
+  if (st) return set_err(st, err);
+  std::vector<Quad> q;
+  st = select_quads(*cfg, g, q, err);
+  if (st) return set_err(st, err);
+  *n_quad = (int64_t)q.size();
+  for (int64_t t = 0; t < std::min<int64_t>(*n_quad, capacity); ++t)
+    if (abcd) {
+      abcd[4 * t] = q[t].a1;
+      abcd[4 * t + 1] = q[t].a2;
+      abcd[4 * t + 2] = q[t].a3;
+      abcd[4 * t + 3] = q[t].a4;
+    }
+  return BISPEC_OK;
+}
+
+int bispec_quads(bispec_plan_t p, int32_t* abcd, int64_t* nquad) {
+  if (!p) return set_err(BISPEC_EINVAL, "null plan");
+  if (!p->quad) return set_err(BISPEC_EINVAL, "not an order-4 plan");
+  for (long long t = 0; t < p->sz.n_tri; ++t) {
+    if (abcd) {
+      abcd[4 * t] = p->quads[t].a1;
+      abcd[4 * t + 1] = p->quads[t].a2;
+      abcd[4 * t + 2] = p->quads[t].a3;
+      abcd[4 * t + 3] = p->quads[t].a4;
+    }
+    if (nquad) nquad[t] = p->ntri[t];
+  }
   return BISPEC_OK;
 }
 
@@ -1192,6 +1414,7 @@ int bispec_num_triangles(bispec_plan_t p, int64_t* n_tri) {
 
 int bispec_triangles(bispec_plan_t p, int32_t* abc, double* k1_mu_t, int64_t* ntri) {
   if (!p) return set_err(BISPEC_EINVAL, "null plan");
+  if (p->quad) return set_err(BISPEC_EINVAL, "an order-4 plan: use bispec_quads");
   for (long long t = 0; t < p->sz.n_tri; ++t) {
     if (abc) {
       abc[3 * t] = p->sel.tri[t].a1;
@@ -1211,6 +1434,8 @@ int bispec_set_precision(bispec_plan_t p, int32_t precision) {
     return set_err(BISPEC_EINVAL, "unknown precision");
   if (precision == BISPEC_PREC_SPLITBF16 && p->geo.n_s > kMaxSplitShells)
     return set_err(BISPEC_EINVAL, "split-bf16 contraction supports n_shells <= 128");
+  if (p->quad && precision != BISPEC_PREC_SPLITBF16)
+    return set_err(BISPEC_EINVAL, "order-4 plans contract in split-bf16 only");
   p->precision = precision;
   return BISPEC_OK;
 }
@@ -1227,6 +1452,7 @@ int bispec_run(bispec_plan_t p, const float* delta, double* B, void* hip_stream)
 
 int bispec_run_noalloc(bispec_plan_t p, const float* delta, double* B, void* hip_stream) {
   if (!p || !delta || !B) return set_err(BISPEC_EINVAL, "null argument");
+  if (p->quad) return set_err(BISPEC_EINVAL, "order-4 plans run with bispec_run");
   const ScratchLayout l = scratch_layout(p->sz);
   if (l.total > kScratchBytes) {
     char buf[200];
@@ -1305,9 +1531,9 @@ int bispec_plan_classes(bispec_plan_t p, int32_t capacity, int32_t* n_classes, i
   for (int k = 0; k < (int)p->cls.size() && k < capacity; ++k) {
     const GridClass& c = p->cls[k];
     if (grid) grid[k] = c.spec.g;
-    if (n_krange) n_krange[k] = c.n_krange_mfma;
+    if (n_krange) n_krange[k] = p->quad ? p->n_krange4 : c.n_krange_mfma;
     if (max_cols) max_cols[k] = c.max_cols;
-    if (n_wg) n_wg[k] = c.mfma.n_wg;
+    if (n_wg) n_wg[k] = p->quad ? p->qt.n_wg : c.mfma.n_wg;
     if (tuned_ms) tuned_ms[k] = c.tuned_ms;
     if (tune_source) tune_source[k] = c.tune_source;
   }
@@ -1368,6 +1594,7 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
   for (int32_t i = 0; i < n; ++i) {
     if (cfgs[i].flags & (BISPEC_FLAG_GRAD | BISPEC_FLAG_NO_WORKSPACE))
       return fail(set_err(BISPEC_EINVAL, "batched plans do not take BISPEC_FLAG_GRAD or BISPEC_FLAG_NO_WORKSPACE"));
+    if (cfgs[i].order == 4) return fail(set_err(BISPEC_EINVAL, "batched plans are bispectrum plans"));
     bispec_plan_s* p = new (std::nothrow) bispec_plan_s();
     if (!p) return fail(set_err(BISPEC_ENOMEM, "host allocation failed"));
     p->in_batch = true;

@@ -16,6 +16,8 @@
 // that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace bispec {
@@ -898,6 +900,152 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
   }
 }
 
+// ============================================================================
+// Order-4 contraction (Section 4's polyspectrum with p = 4):
+//   T(a1, a2, a3, a4) = sum_x P_(a1,a2)(x) P_(a3,a4)(x),  P_(i,j) = F_i F_j,
+// a GEMM of row pairs against column pairs over the voxels.  Work group
+// (wg, kr) walks the voxel blocks kr, kr + n_krange, ... (32 voxels each): it
+// stages the block's fields (float32 or float64) in LDS, forms every pair
+// product of the plan once per block into LDS (split into bf16 hi and lo, or
+// kept in float64), and each wavefront adds its tiles' 16 x 16 products:
+//   split-bf16: 3 v_mfma_f32_16x16x32_bf16 per tile (hi hi + hi lo + lo hi),
+//     float32 chains of kFlushChunks blocks flushed into float64 partials;
+//   float64: 8 v_mfma_f64_16x16x4_f64 per tile (K = 4 voxels each), float64
+//     throughout (the exact N_quad of the unit shells).
+// Row block rb's lane r (0..15) holds pair rb_pairs[16 rb + r] (the zero pair
+// for padding), likewise for columns.  The split-bf16 accumulator's element
+// (v, lane) is row 4 (lane / 16) + v, column lane % 16, as in the triple
+// contraction; the float64 MFMA's is row 4 v + lane / 16, column lane % 16,
+// and is stored at the position the first layout gives that (row, column), so
+// one slot table serves both.
+// ============================================================================
+constexpr int kQStride = kC2 + 8;   // bf16 elements per pair row (80 bytes: bank spread)
+
+template <bool F64>
+__global__ void __launch_bounds__(kWsThreads) k_contract4(const void* __restrict__ Fv, Quad4Args a) {
+  typedef typename std::conditional<F64, double, float>::type T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const T* __restrict__ F = reinterpret_cast<const T*>(Fv);
+  int wg, kr;
+  xcd_map(a.n_wg, wg, kr);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int ns = a.n_s, np = a.n_pairs;
+  // LDS: fields [ns + 1][32] (row ns zero), then the pair products
+  T* ff = reinterpret_cast<T*>(smem_raw);
+  unsigned char* pbase = smem_raw + (size_t)(ns + 1) * kC2 * sizeof(T);
+  for (int e = tid; e < kC2; e += kWsThreads) ff[ns * kC2 + e] = (T)0;
+  // the zero pair row
+  if constexpr (F64) {
+    double* pp = reinterpret_cast<double*>(pbase);
+    for (int e = tid; e < kC2; e += kWsThreads) pp[np * kC2 + e] = 0.0;
+  } else {
+    __bf16* ph = reinterpret_cast<__bf16*>(pbase);
+    __bf16* pl = ph + (size_t)(np + 1) * kQStride;
+    for (int e = tid; e < kQStride; e += kWsThreads) {
+      ph[np * kQStride + e] = (__bf16)0.f;
+      pl[np * kQStride + e] = (__bf16)0.f;
+    }
+  }
+  // this wavefront's tiles (<= kSlotTiles) and its lane's row and column pairs
+  const int wid = wg * kSlotsPerWg + w;
+  const int t0 = a.wave_t0[wid], nt = a.wave_t0[wid + 1] - t0;
+  int prow[kSlotTiles], pcol[kSlotTiles];
+#pragma unroll
+  for (int k = 0; k < kSlotTiles; ++k) {
+    if (k < nt) {
+      const int4 td = a.tiles[t0 + k];
+      prow[k] = a.rb_pairs[td.y * 16 + (lane & 15)];
+      pcol[k] = a.cb_pairs[td.z * 16 + (lane & 15)];
+    } else {
+      prow[k] = pcol[k] = np;
+    }
+  }
+  typedef typename std::conditional<F64, double, float>::type A;
+  typedef A acc4 __attribute__((ext_vector_type(4)));
+  acc4 acc[kSlotTiles];
+#pragma unroll
+  for (int k = 0; k < kSlotTiles; ++k)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[k][v] = (A)0;
+  double* out = a.partial + (long long)kr * a.n_wg * kTilesPerWg * kMTileElems;
+  const long long n_blocks = a.n_vox / kC2;
+  bool first = true;
+  int chain = 0;
+  for (long long blk = kr; blk < n_blocks; blk += a.n_krange) {
+    __syncthreads();   // the previous block's reads are done
+    const T* src = F + blk * (long long)ns * kC2;
+    for (int e = tid; e < ns * kC2; e += kWsThreads) ff[e] = src[e];
+    __syncthreads();
+    for (int e = tid; e < np * kC2; e += kWsThreads) {
+      const int p = e / kC2, v = e % kC2;
+      const int ij = a.pair_ij[p];
+      const T prod = ff[(ij & 0xffff) * kC2 + v] * ff[(ij >> 16) * kC2 + v];
+      if constexpr (F64) {
+        reinterpret_cast<double*>(pbase)[p * kC2 + v] = prod;
+      } else {
+        __bf16* ph = reinterpret_cast<__bf16*>(pbase);
+        __bf16* pl = ph + (size_t)(np + 1) * kQStride;
+        const __bf16 h = (__bf16)prod;
+        ph[p * kQStride + v] = h;
+        pl[p * kQStride + v] = (__bf16)(prod - (float)h);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSlotTiles; ++k) {
+      if (k >= nt) continue;
+      if constexpr (F64) {
+        const double* pp = reinterpret_cast<const double*>(pbase);
+#pragma unroll
+        for (int q = 0; q < kC2 / 4; ++q) {
+          const int v = 4 * q + (lane >> 4);
+          acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(pp[prow[k] * kC2 + v], pp[pcol[k] * kC2 + v], acc[k], 0, 0,
+                                                        0);
+        }
+      } else {
+        const __bf16* ph = reinterpret_cast<const __bf16*>(pbase);
+        const __bf16* pl = ph + (size_t)(np + 1) * kQStride;
+        const int o = 8 * (lane >> 4);
+        const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(ph + prow[k] * kQStride + o);
+        const bf16x8 alo = *reinterpret_cast<const bf16x8*>(pl + prow[k] * kQStride + o);
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(ph + pcol[k] * kQStride + o);
+        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(pl + pcol[k] * kQStride + o);
+        ws_mfma3(ahi, alo, bhi, blo, acc[k]);
+      }
+    }
+    if (!F64 && ++chain == kFlushChunks) {
+      // float32 chains into the float64 partials
+#pragma unroll
+      for (int k = 0; k < kSlotTiles; ++k) {
+        if (k >= nt) continue;
+        double* o = out + ((long long)wg * kTilesPerWg + w * kSlotTiles + k) * kMTileElems + lane;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          o[v * 64] = first ? (double)acc[k][v] : o[v * 64] + (double)acc[k][v];
+          acc[k][v] = (A)0;
+        }
+      }
+      chain = 0;
+      first = false;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kSlotTiles; ++k) {
+    if (k >= nt) continue;
+    double* o = out + ((long long)wg * kTilesPerWg + w * kSlotTiles + k) * kMTileElems;
+    if constexpr (F64) {
+      // (v, lane) is (row 4 v + lane / 16, column lane % 16): position
+      // (lane / 16) * 64 + 16 v + lane % 16 in the split layout
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[(lane >> 4) * 64 + 16 * v + (lane & 15)] = (double)acc[k][v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        o[v * 64 + lane] = first ? (double)acc[k][v] : o[v * 64 + lane] + (double)acc[k][v];
+    }
+  }
+}
+
 // dst[i] = uniform in [-1, 1) from a 64-bit hash of (seed, i) (splitmix64 finaliser)
 __global__ void k_fill_random(float* __restrict__ dst, long long n, unsigned long long seed) {
   const long long step = (long long)gridDim.x * blockDim.x;
@@ -942,6 +1090,33 @@ hipError_t launch_adjoint_mfma(const float* F, float* G, const AdjGroup* groups_
   if (n_groups < 1 || n_blocks < 1 || max_s > kMaxSplitShells) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_adjoint_mfma, dim3((unsigned)n_blocks), dim3(kAdjWaves * 64), adj_lds_bytes(max_s), st, F, G,
                      groups_dev, n_groups);
+  return hipGetLastError();
+}
+
+size_t quad4_lds_bytes(int n_pairs, int n_s, bool f64) {
+  return f64 ? (size_t)(n_s + 1) * kC2 * 8 + (size_t)(n_pairs + 1) * kC2 * 8
+             : (size_t)(n_s + 1) * kC2 * 4 + 2 * (size_t)(n_pairs + 1) * kQStride * 2;
+}
+
+hipError_t prepare_contract4() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_contract4<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)quad4_lds_bytes(kMaxQuadPairs, 128, false));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_contract4<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)quad4_lds_bytes(kMaxQuadPairs, 128, true));
+}
+
+hipError_t launch_contract4_bf16x3(const float* F, const Quad4Args& a, hipStream_t st) {
+  if (a.n_pairs < 1 || a.n_pairs > kMaxQuadPairs || a.n_s > 128 || a.n_vox % kC2 || a.n_krange % 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_contract4<false>, dim3((unsigned)(a.n_wg * a.n_krange)), dim3(kWsThreads),
+                     quad4_lds_bytes(a.n_pairs, a.n_s, false), st, (const void*)F, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_contract4_f64(const double* F, const Quad4Args& a, hipStream_t st) {
+  if (a.n_pairs < 1 || a.n_pairs > kMaxQuadPairs || a.n_s > 128 || a.n_vox % kC2 || a.n_krange % 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_contract4<true>, dim3((unsigned)(a.n_wg * a.n_krange)), dim3(kWsThreads),
+                     quad4_lds_bytes(a.n_pairs, a.n_s, true), st, (const void*)F, a);
   return hipGetLastError();
 }
 

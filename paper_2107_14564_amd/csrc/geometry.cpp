@@ -44,9 +44,14 @@ int validate(const bispec_config& c, std::string& err) {
   if (!std::isfinite(c.rsd_beta)) return fail(err, BISPEC_EINVAL, "rsd_beta must be finite");
   if (c.precision != BISPEC_PREC_SPLITBF16 && c.precision != BISPEC_PREC_FP32)
     return fail(err, BISPEC_EINVAL, "unknown precision");
-  // eq. 3FT: all shell modes below 2 pi N_g / (3 L)  <=>  (n_s + 1/2) w <= N_g / 3
-  if ((c.n_shells + 0.5) * c.dk * 3.0 > (double)c.n_g)
-    return fail(err, BISPEC_ECUTOFF, "shells reach k >= 2 pi N_g/(3L): need (n_shells + 1/2) dk <= n_g/3");
+  if (c.order != 0 && c.order != 3 && c.order != 4) return fail(err, BISPEC_EINVAL, "order must be 0, 3 or 4");
+  // eq. 3FT and Section 4: all shell modes below 2 pi N_g / (p L)  <=>  (n_s + 1/2) w <= N_g / p
+  const int p = c.order == 4 ? 4 : 3;
+  if ((c.n_shells + 0.5) * c.dk * p > (double)c.n_g)
+    return fail(err, BISPEC_ECUTOFF, p == 4 ? "shells reach k >= 2 pi N_g/(4L): need (n_shells + 1/2) dk <= n_g/4"
+                                            : "shells reach k >= 2 pi N_g/(3L): need (n_shells + 1/2) dk <= n_g/3");
+  if (c.order == 4 && c.tri_mode == BISPEC_TRI_MUT_GRID)
+    return fail(err, BISPEC_EINVAL, "order 4 takes the ALL, K1SET or LIST selections");
   switch (c.tri_mode) {
     case BISPEC_TRI_ALL: break;
     case BISPEC_TRI_K1SET:
@@ -97,12 +102,13 @@ int build_shells(const bispec_config& c, ShellGeometry& g, std::string& err) {
     g.rad[n - 1] = (int32_t)r;
   }
   // estimator grid: the triple sums over G^3 points are exact when no sum of
-  // three mode components can reach +-G, i.e. G > 3 max|m_i| (Section 2.2)
+  // three mode components can reach +-G, i.e. G > 3 max|m_i| (Section 2.2);
+  // four for the order-4 sums
   const int R = g.rad[g.n_s - 1];
-  const int need = 3 * R + 1;
+  const int need = (c.order == 4 ? 4 : 3) * R + 1;
   if (c.n_est != 0) {
     if (c.n_est < need || c.n_est > c.n_g)
-      return fail(err, BISPEC_EINVAL, "n_est must satisfy 3 max|m_i| < n_est <= n_g");
+      return fail(err, BISPEC_EINVAL, "n_est must satisfy p max|m_i| < n_est <= n_g (p = 3, or 4 for order 4)");
     g.n_est = c.n_est;
   } else {
     g.n_est = c.n_g;
@@ -195,6 +201,101 @@ int select_triangles(const bispec_config& c, const ShellGeometry& g, Selection& 
     s.k1_mu_t.push_back(k2 / k1);
   }
   return BISPEC_OK;
+}
+
+int select_quads(const bispec_config& c, const ShellGeometry& g, std::vector<Quad>& q, std::string& err) {
+  std::set<std::tuple<int, int, int, int>> pick;
+  const int ns = g.n_s;
+  auto closable = [](int a1, int a2, int a3, int a4) {
+    return a1 >= a2 && a2 >= a3 && a3 >= a4 && a4 >= 1 && a2 + a3 + a4 >= a1;
+  };
+  if (c.tri_mode == BISPEC_TRI_ALL || c.tri_mode == BISPEC_TRI_K1SET) {
+    std::vector<char> use(ns + 1, c.tri_mode == BISPEC_TRI_ALL);
+    if (c.tri_mode == BISPEC_TRI_K1SET)
+      for (int k = 0; k < c.n_k1; ++k) use[c.k1_shells[k]] = 1;
+    for (int a1 = 1; a1 <= ns; ++a1) {
+      if (!use[a1]) continue;
+      for (int a2 = 1; a2 <= a1; ++a2)
+        for (int a3 = 1; a3 <= a2; ++a3)
+          for (int a4 = 1; a4 <= a3; ++a4)
+            if (a2 + a3 + a4 >= a1) pick.insert({a1, a2, a3, a4});
+    }
+  } else if (c.tri_mode == BISPEC_TRI_LIST) {
+    for (int64_t r = 0; r < c.n_list; ++r) {
+      const int a1 = c.list[4 * r], a2 = c.list[4 * r + 1], a3 = c.list[4 * r + 2], a4 = c.list[4 * r + 3];
+      if (a1 > ns || !closable(a1, a2, a3, a4))
+        return fail(err, BISPEC_EINVAL, "list row is not a closable quadruple within n_shells");
+      if (!pick.insert({a1, a2, a3, a4}).second) return fail(err, BISPEC_EINVAL, "duplicate list row");
+    }
+  } else {
+    return fail(err, BISPEC_EINVAL, "order 4 takes the ALL, K1SET or LIST selections");
+  }
+  if (pick.empty()) return fail(err, BISPEC_EINVAL, "no quadruple selected");
+  q.clear();
+  for (auto& p : pick) q.push_back({std::get<0>(p), std::get<1>(p), std::get<2>(p), std::get<3>(p)});
+  return BISPEC_OK;
+}
+
+void build_quad_tiles(const std::vector<Quad>& q, int n_shells, QuadTiling& qt) {
+  (void)n_shells;
+  // row pairs ordered by a2 then a1, column pairs by a3 then a4: bins (a2 >= a3)
+  // then fill one side of the tile grid's diagonal
+  std::map<std::pair<int, int>, int> rkey, ckey, pid;
+  for (const Quad& b : q) {
+    rkey[{b.a2, b.a1}] = 0;
+    ckey[{b.a3, b.a4}] = 0;
+    pid[{b.a1, b.a2}] = 0;
+    pid[{b.a3, b.a4}] = 0;
+  }
+  qt.pair_ij.clear();
+  for (auto& kv : pid) {
+    kv.second = (int)qt.pair_ij.size();
+    qt.pair_ij.push_back((kv.first.first - 1) | ((kv.first.second - 1) << 16));
+  }
+  qt.n_pairs = (int32_t)qt.pair_ij.size();
+  qt.pair_ij.push_back(-1);  // the zero pair (the kernels map it to the zero row)
+  auto blocks = [&](std::map<std::pair<int, int>, int>& keys, bool rows, std::vector<int32_t>& out) {
+    int k = 0;
+    out.clear();
+    for (auto& kv : keys) {
+      kv.second = k++;
+      const std::pair<int, int> ij = rows ? std::make_pair(kv.first.second, kv.first.first) : kv.first;
+      out.push_back(pid.at(ij));
+    }
+    while (out.size() % 16) out.push_back(qt.n_pairs);
+  };
+  blocks(rkey, true, qt.rb_pairs);
+  blocks(ckey, false, qt.cb_pairs);
+  // tiles with a selected bin, dealt to wavefronts in order
+  std::map<std::pair<int, int>, std::vector<int>> tile_bins;
+  for (size_t t = 0; t < q.size(); ++t) {
+    const int r = rkey.at({q[t].a2, q[t].a1}), cc = ckey.at({q[t].a3, q[t].a4});
+    tile_bins[{r / 16, cc / 16}].push_back((int)t);
+  }
+  const int n_tiles = (int)tile_bins.size();
+  const int n_waves = (n_tiles + kSlotTiles - 1) / kSlotTiles;
+  qt.n_wg = std::max(1, (n_waves + kSlotsPerWg - 1) / kSlotsPerWg);
+  // spread the tiles evenly over every wavefront of the work groups
+  const int waves_total = qt.n_wg * kSlotsPerWg;
+  qt.wave_t0.assign(waves_total + 1, 0);
+  qt.tiles.clear();
+  qt.slot_of.assign(q.size(), -1);
+  auto it = tile_bins.begin();
+  for (int w = 0; w < waves_total; ++w) {
+    const int take = n_tiles / waves_total + (w < n_tiles % waves_total ? 1 : 0);
+    const int wg = w / kSlotsPerWg, wave = w % kSlotsPerWg;
+    qt.wave_t0[w] = (int32_t)(qt.tiles.size() / 4);
+    for (int k = 0; k < take; ++k, ++it) {
+      const int slot = wg * kTilesPerWg + wave * kSlotTiles + k;
+      qt.tiles.insert(qt.tiles.end(), {slot, it->first.first, it->first.second, 0});
+      for (int t : it->second) {
+        const int r = rkey.at({q[t].a2, q[t].a1}) % 16, cc = ckey.at({q[t].a3, q[t].a4}) % 16;
+        const int lane = cc + 16 * (r >> 2), v = r & 3;
+        qt.slot_of[t] = slot * kMTileElems + v * 64 + lane;
+      }
+    }
+  }
+  qt.wave_t0[waves_total] = (int32_t)(qt.tiles.size() / 4);
 }
 
 void build_tiles(const Selection& s, int max_tiles_per_task, TilePlan& tp) {

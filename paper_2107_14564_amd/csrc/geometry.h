@@ -32,6 +32,29 @@ struct Selection {
   std::vector<double> k1_mu_t;   // [n_tri][3]
 };
 
+// Order-4 bins (Section 4's polyspectrum with p = 4): a1 >= a2 >= a3 >= a4 >= 1,
+// a2 + a3 + a4 >= a1.
+struct Quad {
+  int32_t a1, a2, a3, a4;
+};
+int select_quads(const bispec_config& cfg, const ShellGeometry& g, std::vector<Quad>& q, std::string& err);
+
+// The order-4 contraction T = sum_x P_(a1,a2) P_(a3,a4) as a GEMM of row pairs
+// (a1, a2) against column pairs (a3, a4), K = voxels: row blocks and column
+// blocks of 16 pairs, 16 x 16 tiles holding at least one selected bin; tiles
+// dealt to wavefronts (<= kSlotTiles each, kSlotsPerWg per work group), so a
+// tile's partial sums sit at slot = wg * kTilesPerWg + wave * kSlotTiles + k.
+struct QuadTiling {
+  std::vector<int32_t> pair_ij;   // pair p: (i | j << 16), 0-based shells; entry n_pairs: the zero pair
+  std::vector<int32_t> rb_pairs;  // [n_rb][16] pair indices (n_pairs = padding)
+  std::vector<int32_t> cb_pairs;  // [n_cb][16]
+  std::vector<int32_t> tiles;     // [n_tiles][4]: slot, row block, column block, 0
+  std::vector<int32_t> wave_t0;   // [n_wg * kSlotsPerWg + 1]: tiles of wavefront w are [wave_t0[w], wave_t0[w+1])
+  std::vector<int32_t> slot_of;   // per bin: slot * 256 + element (16 x 16 accumulator layout)
+  int32_t n_pairs = 0, n_wg = 0;
+};
+void build_quad_tiles(const std::vector<Quad>& q, int n_shells, QuadTiling& qt);
+
 // Validates cfg (everything except memory).  Returns a bispec_status.
 int validate(const bispec_config& cfg, std::string& err);
 int build_shells(const bispec_config& cfg, ShellGeometry& g, std::string& err);

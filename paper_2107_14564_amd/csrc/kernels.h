@@ -190,6 +190,25 @@ hipError_t launch_adjoint_mfma(const float* F, float* G, const AdjGroup* groups_
 hipError_t launch_adjoint_shells(const float* G, float2* a1, float2* a2, float2* S, const ShellLaunch& L, int n,
                                  const float2* tw, float scale, float beta, bool zero_first, hipStream_t st);
 
+// ---- order-4 contraction (QuadTiling, geometry.h) --------------------------
+struct Quad4Args {
+  const int32_t* pair_ij = nullptr;   // device [n_pairs + 1]
+  const int32_t* rb_pairs = nullptr;  // device [n_rb * 16]
+  const int32_t* cb_pairs = nullptr;  // device [n_cb * 16]
+  const int4* tiles = nullptr;        // device [n_tiles]: slot, row block, column block
+  const int32_t* wave_t0 = nullptr;   // device [n_wg * kSlotsPerWg + 1]
+  int n_pairs = 0, n_s = 0, n_wg = 0, n_krange = 0;
+  long long n_vox = 0;
+  double* partial = nullptr;          // device [n_krange][n_wg * kTilesPerWg][kMTileElems]
+};
+size_t quad4_lds_bytes(int n_pairs, int n_s, bool f64);
+constexpr int kMaxQuadPairs = 496;    // pair products staged per chunk
+hipError_t prepare_contract4();
+// sum_x P_(i,j) P_(k,l): float32 fields on split-bf16 MFMAs, or float64 fields
+// (the unit shells, for N_quad) on float64 MFMAs
+hipError_t launch_contract4_bf16x3(const float* F, const Quad4Args& a, hipStream_t st);
+hipError_t launch_contract4_f64(const double* F, const Quad4Args& a, hipStream_t st);
+
 // dst[0 .. n) = pseudo-random values in [-1, 1) (autotuner timing fields)
 hipError_t launch_fill_random(float* dst, long long n, unsigned long long seed, hipStream_t st);
 // dst[0 .. bytes) = 0 with a fill kernel (capture-safe; bytes and dst 16-byte aligned)

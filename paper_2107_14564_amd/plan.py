@@ -21,11 +21,12 @@ class Plan:
     """
 
     def __init__(self, n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=_abi.TRI_ALL, k1_shells=None, n_mu=0,
-                 n_t=0, triangles=None, precision=_abi.PREC_SPLITBF16, flags=0, n_est=0):
+                 n_t=0, triangles=None, precision=_abi.PREC_SPLITBF16, flags=0, n_est=0, order=0):
         if not torch.cuda.is_available():
             raise RuntimeError("Plan needs a HIP device")
         self.cfg, self._keep = _abi.make_config(n_g, box_l, dk, n_shells, rsd_beta, tri_mode, k1_shells, n_mu, n_t,
-                                                triangles, precision, flags, n_est)
+                                                triangles, precision, flags, n_est, order)
+        self.order = 4 if int(order) == 4 else 3
         self.n_g = int(n_g)
         self.n_est = _abi.bispec_estimator_grid(self.cfg)
         # estimator-grid classes: grids, shell ranges, class of each triangle
@@ -33,9 +34,14 @@ class Plan:
         self.tri_class = torch.tensor(tc, dtype=torch.int32)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.handle = _abi.bispec_plan(self.cfg, _stream())
-        abc, lab, ntri = _abi.bispec_triangles(self.handle)
+        if self.order == 4:
+            # bins of four shells; ntri holds N_quad
+            abc, ntri = _abi.bispec_quads(self.handle)
+            self.labels = torch.zeros((len(abc), 0), dtype=torch.float64)
+        else:
+            abc, lab, ntri = _abi.bispec_triangles(self.handle)
+            self.labels = torch.tensor(lab, dtype=torch.float64)
         self.triangles = torch.tensor(abc, dtype=torch.int32)
-        self.labels = torch.tensor(lab, dtype=torch.float64)
         self.ntri = torch.tensor(ntri, dtype=torch.int64)
         self.n_tri = len(abc)
         # counts bispec_run calls: the plan's shell fields belong to the last run

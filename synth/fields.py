@@ -97,6 +97,8 @@ WORKLOADS = {
     "ng320": dict(n_g=320, box_l=937.5, power=PowerLaw(-1.5), f_ng=2.0, seed=3003),
     # the precision case on the paper's largest grid: N_g=1024, L=3000 Mpc (the same cell size)
     "ng1024": dict(n_g=1024, box_l=3000.0, power=PowerLaw(-1.5), f_ng=2.0, seed=3002),
+    # fourth-order case: N_g=128, L=600 Mpc, P = k^-1, f_NG = 1
+    "ng128": dict(n_g=128, box_l=600.0, power=PowerLaw(-1.0), f_ng=1.0, seed=4128),
     # differentiation case: N_g=256, L=1000 Mpc, P = k^-1, f_NG = 1
     "ng256_grad": dict(n_g=256, box_l=1000.0, power=PowerLaw(-1.0), f_ng=1.0, seed=5001),
 }

@@ -60,3 +60,27 @@ def test_adjoint_tables_rebuild_the_adjoint_fields(adjoint_checker, args):
     weights and field values, every grid class); every shell in one wavefront."""
     r = subprocess.run([adjoint_checker, *args], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
+
+
+QUAD_CASES = [("48", "10", "200", "1", "0"), ("128", "30", "600", "1", "0"), ("16", "3", "100", "1", "0"),
+              ("64", "10", "300", "1.5", "1", "10", "9"), ("16", "1", "100", "1", "0")]
+
+
+@pytest.fixture(scope="module")
+def quad_checker(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("quad") / "quad_check")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                    os.path.join(ROOT, "tests", "host", "quad_check.cpp"), os.path.join(CSRC, "geometry.cpp"),
+                    "-o", exe], check=True, capture_output=True)
+    return exe
+
+
+@pytest.mark.parametrize("args", QUAD_CASES, ids=lambda a: "_".join(a[:5]))
+def test_quad_tiling_decodes_every_bin(quad_checker, args):
+    """The order-4 pair tiling: each quadruple in one accumulator element that
+    decodes back to its two pairs; wavefronts hold at most 16 tiles."""
+    r = subprocess.run([quad_checker, *args], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout + r.stderr
