@@ -259,7 +259,7 @@ def main():
                      "algorithmic_flop": flop},
         "grid_classes": [dict(grid=gc, shells=[lo, hi], n_tri=int((plan.tri_class.numpy() == k).sum()),
                               n_krange=cp["n_krange"], max_cols=cp["max_cols"], n_wg=cp["n_wg"],
-                              tune=cp["tune_source"])
+                              rep=cp["rep"], tune=cp["tune_source"])
                          for k, (gc, lo, hi, cp) in enumerate(zip(plan.class_grids, plan.class_shell_lo,
                                                                   plan.class_shell_hi, plan.classes()))],
         "fft_hbm": {"algorithmic_bytes": (8.0 * n ** 3 + 4.0 * field_vox),

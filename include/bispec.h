@@ -239,13 +239,15 @@ int bispec_set_precision(bispec_plan_t plan, int32_t precision);
 int bispec_stage_times(bispec_plan_t plan, float* ms, int32_t n);
 
 /* The plan's grid classes as built (after autotuning): for k < capacity,
- * grid[k], the split-bf16 contraction's voxel-range count n_krange[k],
- * column-tile window max_cols[k] and work groups per range n_wg[k], the
- * autotuned time of one contraction launch of the class alone tuned_ms[k]
- * (0 if not tuned) and tune_source[k] (0 default, 1 timed at plan time, 2 read
- * from the tuning cache).  Any output array may be null. */
+ * grid[k], the split-bf16 contraction's voxel-range count n_krange[k] (ranges
+ * of work groups), column-tile window max_cols[k], work groups per range
+ * n_wg[k], replicas rep[k] (a class whose tiling fits one work group with few
+ * busy wavefronts runs rep copies of it on rep consecutive voxel blocks per
+ * step: 1, 2 or 3), the autotuned time of one contraction launch of the class
+ * alone tuned_ms[k] (0 if not tuned) and tune_source[k] (0 default, 1 timed at
+ * plan time, 2 read from the tuning cache).  Any output array may be null. */
 int bispec_plan_classes(bispec_plan_t plan, int32_t capacity, int32_t* n_classes, int32_t* grid, int32_t* n_krange,
-                        int32_t* max_cols, int32_t* n_wg, float* tuned_ms, int32_t* tune_source);
+                        int32_t* max_cols, int32_t* n_wg, int32_t* rep, float* tuned_ms, int32_t* tune_source);
 
 /* Inspection (tests): the grid on which bispec_copy_field returns shell n
  * (the largest grid of the classes whose fields cover it).  EINVAL if no

@@ -61,7 +61,7 @@ def lib() -> C.CDLL:
             "bispec_query_quads": [cfgp, C.POINTER(I64), C.POINTER(I32), I64],
             "bispec_quads": [P, C.POINTER(I32), C.POINTER(I64)],
             "bispec_plan_classes": [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
-                                    C.POINTER(I32), C.POINTER(C.c_float), C.POINTER(I32)],
+                                    C.POINTER(I32), C.POINTER(I32), C.POINTER(C.c_float), C.POINTER(I32)],
             "bispec_plan": [cfgp, P, C.POINTER(P)],
             "bispec_num_triangles": [P, C.POINTER(I64)],
             "bispec_triangles": [P, C.POINTER(I32), C.POINTER(D), C.POINTER(I64)],
@@ -179,13 +179,14 @@ def bispec_contraction_tiles(cfg):
 def bispec_plan_classes(plan: int):
     """Per grid class of a built plan: dict(grid, n_krange, max_cols, n_wg, tuned_ms, tune_source)."""
     n = C.c_int32(0)
-    _check(lib().bispec_plan_classes(C.c_void_p(plan), 0, C.byref(n), None, None, None, None, None, None),
+    _check(lib().bispec_plan_classes(C.c_void_p(plan), 0, C.byref(n), None, None, None, None, None, None, None),
            "bispec_plan_classes")
     k = n.value
-    g, kr, mc, wg, src = ((C.c_int32 * max(1, k))() for _ in range(5))
+    g, kr, mc, wg, rp, src = ((C.c_int32 * max(1, k))() for _ in range(6))
     ms = (C.c_float * max(1, k))()
-    _check(lib().bispec_plan_classes(C.c_void_p(plan), k, C.byref(n), g, kr, mc, wg, ms, src), "bispec_plan_classes")
-    return [dict(grid=g[i], n_krange=kr[i], max_cols=mc[i], n_wg=wg[i], tuned_ms=float(ms[i]),
+    _check(lib().bispec_plan_classes(C.c_void_p(plan), k, C.byref(n), g, kr, mc, wg, rp, ms, src),
+           "bispec_plan_classes")
+    return [dict(grid=g[i], n_krange=kr[i], max_cols=mc[i], n_wg=wg[i], rep=rp[i], tuned_ms=float(ms[i]),
                  tune_source=("default", "timed", "cache")[src[i]]) for i in range(k)]
 
 

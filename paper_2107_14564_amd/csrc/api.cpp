@@ -166,7 +166,9 @@ struct GridClass {
   int n_krange_vec = 8, n_krange_mfma = 8;
   int n_krange_mfma_cap = 8;   // its MFMA partials hold this many ranges
   int max_cols = kMaxColTiles; // column-tile window of its MFMA tiling (a tuned tile shape)
-  int wg_cap = 1;              // its MFMA partials hold this many work groups per range
+  int tiles_cap = 1;           // its MFMA partials hold this many tiles (times replicas) per range
+  int rep = 1;                 // replicas of the one-work-group slot set (split-bf16)
+  int tile_stride = 0;         // tiles per voxel range of its MFMA partials
   float tuned_ms = 0.f;        // autotuner: time of the chosen shape (0 = not tuned)
   int tune_source = 0;         // 0 default, 1 timed at plan time, 2 from the tuning cache
   long long f_off = 0;         // element offset of its fields in the plan's F (and G)
@@ -221,7 +223,8 @@ struct bispec_many_s {
   // at offsets), so one grouped launch contracts all split-bf16 members
   DevBuf F_all, pm_all, ws_groups;
   std::vector<size_t> f_at, pm_at;     // byte offsets of member i's pieces
-  int ws_n = 0, ws_blocks = 0, ws_max_s = 0;
+  int ws_n = 0, ws_blocks = 0;
+  size_t ws_lds = 0;
   hipEvent_t ev_mid = nullptr;         // the grouped contraction is done
   ~bispec_many_s();
 };
@@ -240,7 +243,8 @@ struct bispec_plan_s {
   int device = 0;
   // grouped split-bf16 launch over the classes
   std::vector<WsGroup> ws_host;
-  int ws_blocks = 0, ws_max_s = 0;
+  int ws_blocks = 0;
+  size_t ws_lds = 0;
   // order 4 (the fourth-order polyspectrum): bins, pair tiling and its tables
   bool quad = false;
   std::vector<Quad> quads;
@@ -365,14 +369,16 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
       for (int k : kTuneRanges)
         if (k <= std::max(8LL, (c.n_vox / (64 * 4)) / 8 * 8)) c.n_krange_mfma_cap = std::max(c.n_krange_mfma_cap, k);
     c.partial_vec = (size_t)c.n_krange_vec * c.n_tri * sizeof(double);
-    c.wg_cap = c.mfma.n_wg;
+    c.rep = ws_max_rep(c.mfma);
+    c.tile_stride = ws_tile_stride(c.mfma);
+    c.tiles_cap = c.rep * c.tile_stride;
     if (cfg->flags & BISPEC_FLAG_AUTOTUNE)
       for (int mc : kTuneCols) {
         MfmaTiling alt;
         build_mfma_tiles(c.sel, c.geo.n_s, alt, mc);
-        c.wg_cap = std::max(c.wg_cap, alt.n_wg);
+        c.tiles_cap = std::max(c.tiles_cap, ws_max_rep(alt) * ws_tile_stride(alt));
       }
-    c.partial_mfma = (size_t)c.n_krange_mfma_cap * c.wg_cap * kTilesPerWg * kMTileElems * sizeof(double);
+    c.partial_mfma = (size_t)c.n_krange_mfma_cap * c.tiles_cap * kMTileElems * sizeof(double);
     // offsets: fields and partials of the classes back to back (256-byte aligned pieces)
     c.f_off = (long long)(s.fields32 / sizeof(float));
     s.fields32 += (c.fields32 + 255) / 256 * 256;
@@ -419,10 +425,32 @@ void cap_mfma_ranges(bispec_plan_s& p, int cap) {
   for (GridClass& c : p.cls) {
     c.n_krange_mfma = std::max(8, std::min(c.n_krange_mfma, cap));
     c.n_krange_mfma_cap = std::max(8, std::min(c.n_krange_mfma_cap, cap));
-    c.partial_mfma = (size_t)c.n_krange_mfma_cap * c.wg_cap * kTilesPerWg * kMTileElems * sizeof(double);
+    c.partial_mfma = (size_t)c.n_krange_mfma_cap * c.tiles_cap * kMTileElems * sizeof(double);
     c.pm_off = (long long)(p.sz.partial_mfma / sizeof(double));
     p.sz.partial_mfma += (c.partial_mfma + 255) / 256 * 256;
   }
+}
+
+// Voxel ranges of a class's split-bf16 partials (work-group ranges times replicas).
+int mfma_ranges(const GridClass& c) { return c.rep * c.n_krange_mfma; }
+
+// The launch group of a class for n_krange work-group ranges.
+WsGroup class_group(const GridClass& c, int n_krange) {
+  WsGroup w;
+  w.f_off = c.f_off;
+  w.p_off = c.pm_off;
+  w.rows = c.mfma_rows.as<MRowBlock>();
+  w.cols = c.mfma_cols.as<SlotCols>();
+  w.wg_rows = c.mfma_wgrows.as<WgRows>();
+  w.n_vox = c.n_vox;
+  w.n_wg = c.mfma.n_wg;
+  w.n_s = c.geo.n_s;
+  w.max_s = c.mfma.max_s;
+  w.n_krange = n_krange;
+  w.rep = c.rep;
+  w.tile_stride = c.tile_stride;
+  w.block0 = 0;
+  return w;
 }
 
 // The grouped split-bf16 launch over the plan's classes, for the classes'
@@ -437,23 +465,13 @@ void build_ws_groups(bispec_plan_s& p) {
     return (double)x.n_vox / x.n_krange_mfma > (double)y.n_vox / y.n_krange_mfma;
   });
   int block = 0;
-  p.ws_max_s = 0;
+  p.ws_lds = 0;
   for (int k : order) {
     GridClass& c = p.cls[k];
-    WsGroup w;
-    w.f_off = c.f_off;
-    w.p_off = c.pm_off;
-    w.rows = c.mfma_rows.as<MRowBlock>();
-    w.cols = c.mfma_cols.as<SlotCols>();
-    w.wg_rows = c.mfma_wgrows.as<WgRows>();
-    w.n_vox = c.n_vox;
-    w.n_wg = c.mfma.n_wg;
-    w.n_s = c.geo.n_s;
-    w.max_s = c.mfma.max_s;
-    w.n_krange = c.n_krange_mfma;
+    WsGroup w = class_group(c, c.n_krange_mfma);
     w.block0 = block;
     block += w.n_wg * w.n_krange;
-    p.ws_max_s = std::max(p.ws_max_s, w.max_s);
+    p.ws_lds = std::max(p.ws_lds, bf16x3_lds_bytes(w.max_s, w.rep));
     p.ws_host.push_back(w);
   }
   p.ws_blocks = block;
@@ -810,7 +828,7 @@ int run_fields(bispec_plan_s& p, const RunBufs& w, const float* delta, hipStream
 // The per-class reductions of the split-bf16 partials into B.
 int run_reduce_mfma(bispec_plan_s& p, const RunBufs& w, double* B, hipStream_t s) {
   for (GridClass& c : p.cls)
-    HIP_TRY(launch_reduce(w.partial_mfma + c.pm_off, c.n_krange_mfma, (long long)c.mfma.n_wg * kTilesPerWg * kMTileElems,
+    HIP_TRY(launch_reduce(w.partial_mfma + c.pm_off, mfma_ranges(c), (long long)c.tile_stride * kMTileElems,
                           c.n_tri, c.mfma_slot.as<int32_t>(), p.norm.as<double>(), c.tri_out.as<int32_t>(), B, s));
   return BISPEC_OK;
 }
@@ -847,11 +865,11 @@ int run_core(bispec_plan_s& p, const RunBufs& w, const float* delta, double* B, 
                             c.tri_out.as<int32_t>(), B, s));
   } else {
     HIP_TRY(launch_contract_bf16x3(w.F, w.partial_mfma, p.ws_groups.as<WsGroup>(), (int)p.ws_host.size(),
-                                   p.ws_max_s, p.ws_blocks, s));
+                                   p.ws_lds, p.ws_blocks, s));
     if (timing) HIP_TRY(hipEventRecord(p.ev[3], s));
     for (GridClass& c : p.cls)
-      HIP_TRY(launch_reduce(w.partial_mfma + c.pm_off, c.n_krange_mfma,
-                            (long long)c.mfma.n_wg * kTilesPerWg * kMTileElems, c.n_tri, c.mfma_slot.as<int32_t>(),
+      HIP_TRY(launch_reduce(w.partial_mfma + c.pm_off, mfma_ranges(c),
+                            (long long)c.tile_stride * kMTileElems, c.n_tri, c.mfma_slot.as<int32_t>(),
                             p.norm.as<double>(), c.tri_out.as<int32_t>(), B, s));
   }
   if (timing) HIP_TRY(hipEventRecord(p.ev[4], s));
@@ -880,7 +898,7 @@ int many_enqueue(bispec_many_s& m, const float* delta, double* B, hipStream_t s)
   }
   if (m.ws_n > 0) {
     HIP_TRY(launch_contract_bf16x3(m.F_all.as<float>(), m.pm_all.as<double>(), m.ws_groups.as<WsGroup>(), m.ws_n,
-                                   m.ws_max_s, m.ws_blocks, s));
+                                   m.ws_lds, m.ws_blocks, s));
     HIP_TRY(hipEventRecord(m.ev_mid, s));
     for (ManyLane* l : m.lanes) HIP_TRY(hipStreamWaitEvent(l->stream, m.ev_mid, 0));
     for (size_t i = 0; i < m.plans.size(); ++i) {
@@ -972,6 +990,8 @@ hipError_t retile_class(GridClass& c, int max_cols, hipStream_t s) {
   c.mfma = MfmaTiling();
   build_mfma_tiles(c.sel, c.geo.n_s, c.mfma, max_cols);
   c.max_cols = max_cols;
+  c.rep = ws_max_rep(c.mfma);
+  c.tile_stride = ws_tile_stride(c.mfma);
   hipError_t e = upload(c.mfma_rows, c.mfma.rows, s);
   if (e == hipSuccess) e = upload(c.mfma_cols, c.mfma.cols, s);
   if (e == hipSuccess) e = upload(c.mfma_wgrows, c.mfma.wg_rows, s);
@@ -1000,7 +1020,7 @@ int autotune_mfma(bispec_plan_s& p, hipStream_t s) {
         kr_c % 8 == 0 && kr_c <= c.n_krange_mfma_cap) {
       hipError_t e = retile_class(c, mc_c, s);
       if (e != hipSuccess) { st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e)); break; }
-      if (c.mfma.n_wg <= c.wg_cap) {
+      if (c.rep * c.tile_stride <= c.tiles_cap) {
         c.n_krange_mfma = kr_c;
         c.tuned_ms = ms_c;
         c.tune_source = 2;
@@ -1017,30 +1037,20 @@ int autotune_mfma(bispec_plan_s& p, hipStream_t s) {
     for (int mc : kTuneCols) {
       hipError_t e = retile_class(c, mc, s);
       if (e != hipSuccess) { st = set_err(BISPEC_EHIP, std::string("autotune: ") + hipGetErrorString(e)); break; }
-      if (c.mfma.n_wg > c.wg_cap) continue;
+      if (c.rep * c.tile_stride > c.tiles_cap) continue;
       for (int k : ranges) {
-        WsGroup w;
-        w.f_off = c.f_off;
-        w.p_off = c.pm_off;
-        w.rows = c.mfma_rows.as<MRowBlock>();
-        w.cols = c.mfma_cols.as<SlotCols>();
-        w.wg_rows = c.mfma_wgrows.as<WgRows>();
-        w.n_vox = c.n_vox;
-        w.n_wg = c.mfma.n_wg;
-        w.n_s = c.geo.n_s;
-        w.max_s = c.mfma.max_s;
-        w.n_krange = k;
-        w.block0 = 0;
+        const WsGroup w = class_group(c, k);
         if (!ws_group_ok(w)) continue;
         e = upload(one, std::vector<WsGroup>{w}, s);
         const int blocks = w.n_wg * k;
+        const size_t lds = bf16x3_lds_bytes(w.max_s, w.rep);
         if (e == hipSuccess)
-          e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, w.max_s,
-                                     blocks, s);  // warm-up
+          e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, lds, blocks,
+                                     s);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         for (int r = 0; r < 3 && e == hipSuccess; ++r)
-          e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, w.max_s,
-                                     blocks, s);
+          e = launch_contract_bf16x3(p.F.as<float>(), p.partial_mfma.as<double>(), one.as<WsGroup>(), 1, lds, blocks,
+                                     s);
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -1525,7 +1535,7 @@ int bispec_stage_times(bispec_plan_t p, float* ms, int32_t n) {
 }
 
 int bispec_plan_classes(bispec_plan_t p, int32_t capacity, int32_t* n_classes, int32_t* grid, int32_t* n_krange,
-                        int32_t* max_cols, int32_t* n_wg, float* tuned_ms, int32_t* tune_source) {
+                        int32_t* max_cols, int32_t* n_wg, int32_t* rep, float* tuned_ms, int32_t* tune_source) {
   if (!p || !n_classes) return set_err(BISPEC_EINVAL, "null argument");
   *n_classes = (int32_t)p->cls.size();
   for (int k = 0; k < (int)p->cls.size() && k < capacity; ++k) {
@@ -1534,6 +1544,7 @@ int bispec_plan_classes(bispec_plan_t p, int32_t capacity, int32_t* n_classes, i
     if (n_krange) n_krange[k] = p->quad ? p->n_krange4 : c.n_krange_mfma;
     if (max_cols) max_cols[k] = c.max_cols;
     if (n_wg) n_wg[k] = p->quad ? p->qt.n_wg : c.mfma.n_wg;
+    if (rep) rep[k] = p->quad ? 1 : c.rep;
     if (tuned_ms) tuned_ms[k] = c.tuned_ms;
     if (tune_source) tune_source[k] = c.tune_source;
   }
@@ -1694,7 +1705,7 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
   for (WsGroup& g : groups) {
     g.block0 = block;
     block += g.n_wg * g.n_krange;
-    m->ws_max_s = std::max(m->ws_max_s, g.max_s);
+    m->ws_lds = std::max(m->ws_lds, bf16x3_lds_bytes(g.max_s, g.rep));
     if (!ws_group_ok(g)) return fail(set_err(BISPEC_EINVAL, "a grid class does not fit the split-bf16 kernel"));
   }
   m->ws_n = (int)groups.size();

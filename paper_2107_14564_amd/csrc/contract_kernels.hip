@@ -259,11 +259,12 @@ constexpr int kOct = kC2 / 8;        // voxel octets per chunk (one per 16 lanes
 constexpr int kBS = kC2 + 16;        // bf16 row stride (elements): 24 dwords
 constexpr int kFlushChunks = 256;    // 8192 voxels per float32 accumulation chain
 constexpr int kWsThreads = kSlotsPerWg * 64;
-constexpr int kPf = 1;               // 8-voxel row segments per thread per chunk (2 float4 each)
 static_assert(kC2 == kVoxBlock, "chunks are voxel blocks");
 
-// LDS byte layout for ns1 rows per buffer (row ns1 - 1 is all zero):
-//   F32 [2][kOct][ns1 * 8 + 4] fp32 | Bh [2][ns1][kBS] bf16 | Bl [2][ns1][kBS] bf16
+// LDS byte layout for ns1 rows per buffer (row ns1 - 1 is all zero) and nsub
+// = 2 rep buffers (double buffering of one voxel block per replica; buffer
+// b rep + r holds replica r's block of chunk parity b):
+//   F32 [nsub][kOct][ns1 * 8 + 4] fp32 | Bh [nsub][ns1][kBS] bf16 | Bl [nsub][ns1][kBS] bf16
 // The fp32 rows are split by voxel octet: plane k holds octet k of every row
 // (32 bytes per row) and the planes are 16 bytes longer than their rows, an
 // odd number of 16-byte bank groups.
@@ -273,13 +274,13 @@ struct WsLayout {
   unsigned bh0, bl0;       // byte offsets of the Bh and Bl regions
 };
 
-__device__ __forceinline__ WsLayout ws_layout(int ns1) {
+__host__ __device__ __forceinline__ WsLayout ws_layout(int ns1, int nsub) {
   WsLayout y;
   y.f_plane = (unsigned)ns1 * 32 + 16;
   y.f_buf = kOct * y.f_plane;
   y.b_buf = (unsigned)ns1 * kBS * 2;
-  y.bh0 = 2 * y.f_buf;
-  y.bl0 = y.bh0 + 2 * y.b_buf;
+  y.bh0 = nsub * y.f_buf;
+  y.bl0 = y.bh0 + nsub * y.b_buf;
   return y;
 }
 
@@ -301,58 +302,64 @@ __device__ __forceinline__ unsigned bf16_pack(float v0, float v1) {
   return __builtin_bit_cast(unsigned, h);
 }
 
-// voxel block blk: rows s_lo .. s_lo + s_n - 1, each 4 octets of 8 voxels
-// (two float4, contiguous in global memory).  Staging index idx takes row
-// 16 (idx / 64) + idx % 16, octet (idx / 16) % 4: lanes 0-31 of a wave, which
-// LDS serves together, store 16 rows at two octets, on distinct banks in
-// both layouts; a wave still covers 16 whole rows (2 KiB contiguous) of
-// global memory.
+// Staging of one voxel block per replica and chunk: rows s_lo .. s_lo + s_n - 1,
+// each 4 octets of 8 voxels (two float4, contiguous in global memory).  Thread
+// tid serves replica rs = tid / (64 g16), g16 = ceil(s_n / 16), and within it
+// staging index idx = tid % (64 g16): row 16 (idx / 64) + idx % 16, octet
+// (idx / 16) % 4.  Lanes 0-31 of a wave, which LDS serves together, store 16
+// rows at two octets, on distinct banks in both layouts; a wave still covers
+// 16 whole rows (2 KiB contiguous) of global memory.
 struct Seg {
   float4 a, b;
 };
 
-__device__ __forceinline__ int seg_row(int idx) { return 16 * (idx >> 6) + (idx & 15); }
-__device__ __forceinline__ int seg_oct(int idx) { return (idx >> 4) & 3; }
+struct WsStage {
+  int rs, row, oct;
+  bool on;   // the thread stages a row
+};
 
-__device__ __forceinline__ void ws_load(const float* __restrict__ F, int n_s, long long blk, const WgRows& wr,
-                                        Seg (&pf)[kPf], int tid) {
+__device__ __forceinline__ WsStage ws_stage_of(int tid, int s_n, int rep) {
+  const int per = 64 * ((s_n + 15) >> 4);
+  WsStage q;
+  q.rs = tid / per;
+  const int idx = tid - q.rs * per;
+  q.row = 16 * (idx >> 6) + (idx & 15);
+  q.oct = (idx >> 4) & 3;
+  q.on = q.rs < rep && q.row < s_n;
+  return q;
+}
+
+// this thread's segment of replica rs's block blk0 + rs (if it exists)
+__device__ __forceinline__ bool ws_load(const float* __restrict__ F, int n_s, long long blk0, long long n_blocks,
+                                        const WgRows& wr, const WsStage& q, Seg& pf) {
+  const long long blk = blk0 + q.rs;
+  if (!q.on || blk >= n_blocks) return false;
   const float4* base = reinterpret_cast<const float4*>(F + blk * (long long)n_s * kC2 + (long long)wr.s_lo * kC2);
-#pragma unroll
-  for (int u = 0; u < kPf; ++u) {
-    const int idx = tid + u * kWsThreads, r = seg_row(idx);
-    if (r < wr.s_n) {
-      const int o = 2 * (kOct * r + seg_oct(idx));
-      pf[u].a = base[o];
-      pf[u].b = base[o + 1];
-    }
-  }
+  const int o = 2 * (kOct * q.row + q.oct);
+  pf.a = base[o];
+  pf.b = base[o + 1];
+  return true;
 }
 
 // fp32 row segment, and the bf16 split hi = bf16(v), lo = bf16(v - hi) of
-// every value: four 16-byte stores per thread
-__device__ __forceinline__ void ws_store(unsigned char* lds, const WsLayout& y, int s_n, int buf,
-                                         const Seg (&pf)[kPf], int tid) {
+// every value, into buffer sub: four 16-byte stores
+__device__ __forceinline__ void ws_store(unsigned char* lds, const WsLayout& y, int sub, const WsStage& q,
+                                         const Seg& pf) {
+  const unsigned r = q.row, k = q.oct, x = 8 * k;
+  unsigned char* f = lds + sub * y.f_buf + k * y.f_plane + r * 32;
+  *reinterpret_cast<float4*>(f) = pf.a;
+  *reinterpret_cast<float4*>(f + 16) = pf.b;
+  const float v[8] = {pf.a.x, pf.a.y, pf.a.z, pf.a.w, pf.b.x, pf.b.y, pf.b.z, pf.b.w};
+  u32x4 hi, lo;
 #pragma unroll
-  for (int u = 0; u < kPf; ++u) {
-    const int idx = tid + u * kWsThreads;
-    if (seg_row(idx) < s_n) {
-      const unsigned r = seg_row(idx), k = seg_oct(idx), x = 8 * k;
-      unsigned char* f = lds + buf * y.f_buf + k * y.f_plane + r * 32;
-      *reinterpret_cast<float4*>(f) = pf[u].a;
-      *reinterpret_cast<float4*>(f + 16) = pf[u].b;
-      const float v[8] = {pf[u].a.x, pf[u].a.y, pf[u].a.z, pf[u].a.w, pf[u].b.x, pf[u].b.y, pf[u].b.z, pf[u].b.w};
-      u32x4 hi, lo;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float h0, h1;
-        hi[e] = bf16_pair(v[2 * e], v[2 * e + 1], h0, h1);
-        lo[e] = bf16_pack(v[2 * e] - h0, v[2 * e + 1] - h1);
-      }
-      const unsigned o = buf * y.b_buf + (r * kBS + x) * 2;
-      *reinterpret_cast<u32x4*>(lds + y.bh0 + o) = hi;
-      *reinterpret_cast<u32x4*>(lds + y.bl0 + o) = lo;
-    }
+  for (int e = 0; e < 4; ++e) {
+    float h0, h1;
+    hi[e] = bf16_pair(v[2 * e], v[2 * e + 1], h0, h1);
+    lo[e] = bf16_pack(v[2 * e] - h0, v[2 * e + 1] - h1);
   }
+  const unsigned o = sub * y.b_buf + (r * kBS + x) * 2;
+  *reinterpret_cast<u32x4*>(lds + y.bh0 + o) = hi;
+  *reinterpret_cast<u32x4*>(lds + y.bl0 + o) = lo;
 }
 
 // Row operand of one row block for 8 voxels: F_i and F_j (8 floats each) are
@@ -470,14 +477,22 @@ __device__ __forceinline__ void ws_flush(double* out, bool first, f32x4* acc) {
   }
 }
 
-// The whole voxel range of one wave.  Range kr takes the voxel blocks kr,
-// kr + n_krange, kr + 2 n_krange, ...: every float32 chain samples the whole
+// Chunk c of a work group stages, for each replica r, voxel block
+// rep kr + r + c rep n_krange (when it exists) into buffer (c & 1) rep + r.
+// Replica r's voxel range rep kr + r thus takes the blocks rep kr + r,
+// + rep n_krange, + 2 rep n_krange, ...: every float32 chain samples the whole
 // box, so its partial sums cancel like the total instead of growing with a
-// slab's coherent sum.
+// slab's coherent sum.  n_chunks: chunks of the work group (those of replica
+// 0, the longest); n_mine: those of this wave's replica.
+struct WsChunks {
+  long long blk0, step, n_blocks;   // replica 0's first block, blocks per chunk step, blocks of the box
+  int n_chunks, n_mine, rep, sub;   // sub: this wave's replica (its buffer within a parity)
+};
+
 template <int NT, int NRB>
 __device__ __forceinline__ void ws_run(const float* __restrict__ F, const WsArgs& a, unsigned char* lds,
-                                       const WsLayout& y, const WgRows& wr, int kr, int n_chunks, int tid,
-                                       const SlotCols& sc, const MRowBlock* rows, double* out) {
+                                       const WsLayout& y, const WgRows& wr, const WsChunks& ch, const WsStage& q,
+                                       int tid, const SlotCols& sc, const MRowBlock* rows, double* out) {
   const int lane = tid & 63, kg = lane >> 4, zr = wr.s_n;
   // this lane's rows (pair shells) and columns as byte offsets in buffer 0
   unsigned fo[NRB], go[NRB], co[NT];
@@ -500,44 +515,37 @@ __device__ __forceinline__ void ws_run(const float* __restrict__ F, const WsArgs
   for (int k = 0; k < NRB * NT; ++k)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[k][v] = 0.f;
-  const long long kstep = a.n_krange;
-  Seg pf[kPf];
-  if (n_chunks > 0) {
-    ws_load(F, a.n_s, kr, wr, pf, tid);
-    ws_store(lds, y, wr.s_n, 0, pf, tid);
-  }
+  Seg pf;
+  if (ch.n_chunks > 0 && ws_load(F, a.n_s, ch.blk0, ch.n_blocks, wr, q, pf)) ws_store(lds, y, q.rs, q, pf);
   __syncthreads();
   bool first = true;
   int chain = 0;
-  for (int c = 0; c < n_chunks; ++c) {
-    const bool more = c + 1 < n_chunks;
-    if (more) ws_load(F, a.n_s, kr + (c + 1) * kstep, wr, pf, tid);
-    ws_compute<NT, NRB>(lds, y, c & 1, fo, go, co, acc);
-    if (++chain == kFlushChunks || !more) {
-      ws_flush<NT, NRB>(out, first, acc);
-      chain = 0;
-      first = false;
+  for (int c = 0; c < ch.n_chunks; ++c) {
+    const bool more = c + 1 < ch.n_chunks;
+    const bool got = more && ws_load(F, a.n_s, ch.blk0 + (c + 1) * ch.step, ch.n_blocks, wr, q, pf);
+    if (c < ch.n_mine) {
+      ws_compute<NT, NRB>(lds, y, (c & 1) * ch.rep + ch.sub, fo, go, co, acc);
+      if (++chain == kFlushChunks || c + 1 == ch.n_mine) {
+        ws_flush<NT, NRB>(out, first, acc);
+        chain = 0;
+        first = false;
+      }
     }
-    if (more) ws_store(lds, y, wr.s_n, (c & 1) ^ 1, pf, tid);
+    if (got) ws_store(lds, y, ((c + 1) & 1) * ch.rep + q.rs, q, pf);
     __syncthreads();
   }
 }
 
 // A wave without a slot only stages its share of every chunk.
 __device__ __forceinline__ void ws_idle(const float* __restrict__ F, const WsArgs& a, unsigned char* lds,
-                                        const WsLayout& y, const WgRows& wr, int kr, int n_chunks, int tid) {
-  Seg pf[kPf];
-  if (n_chunks > 0) {
-    ws_load(F, a.n_s, kr, wr, pf, tid);
-    ws_store(lds, y, wr.s_n, 0, pf, tid);
-  }
+                                        const WsLayout& y, const WgRows& wr, const WsChunks& ch, const WsStage& q) {
+  Seg pf;
+  if (ch.n_chunks > 0 && ws_load(F, a.n_s, ch.blk0, ch.n_blocks, wr, q, pf)) ws_store(lds, y, q.rs, q, pf);
   __syncthreads();
-  for (int c = 0; c < n_chunks; ++c) {
-    // buffer (c + 1) & 1 was last read in chunk c - 1, before the previous barrier
-    if (c + 1 < n_chunks) {
-      ws_load(F, a.n_s, kr + (c + 1) * (long long)a.n_krange, wr, pf, tid);
-      ws_store(lds, y, wr.s_n, (c + 1) & 1, pf, tid);
-    }
+  for (int c = 0; c < ch.n_chunks; ++c) {
+    // buffers of parity (c + 1) & 1 were last read in chunk c - 1, before the previous barrier
+    if (c + 1 < ch.n_chunks && ws_load(F, a.n_s, ch.blk0 + (c + 1) * ch.step, ch.n_blocks, wr, q, pf))
+      ws_store(lds, y, ((c + 1) & 1) * ch.rep + q.rs, q, pf);
     __syncthreads();
   }
 }
@@ -571,43 +579,54 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
   a.max_s = grp.max_s;
   a.n_vox = grp.n_vox;
   a.n_krange = grp.n_krange;
+  a.rep = grp.rep;
+  a.tile_stride = grp.tile_stride;
   a.partial = partial_all + grp.p_off;
   const float* __restrict__ F = F_all + grp.f_off;
-  const int ns1 = a.max_s + 1;
-  const WsLayout y = ws_layout(ns1);
+  const int ns1 = a.max_s + 1, rep = a.rep;
+  const WsLayout y = ws_layout(ns1, 2 * rep);
   int wg, kr;
   {
     const int b = (int)blockIdx.x - grp.block0;
-    const int xcd = b & 7, q = b >> 3;
-    wg = q % a.n_wg;
-    kr = xcd + 8 * (q / a.n_wg);
+    const int xcd = b & 7, qq = b >> 3;
+    wg = qq % a.n_wg;
+    kr = xcd + 8 * (qq / a.n_wg);
   }
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const WgRows wr = a.wg_rows[wg];
   const int zr = wr.s_n;  // the zero row
   // zero row of each buffer, never overwritten afterwards
-  for (int e = tid; e < 2 * kOct * 8; e += kWsThreads)
+  for (int e = tid; e < 2 * rep * kOct * 8; e += kWsThreads)
     *reinterpret_cast<float*>(smem_raw + (e / 8) * y.f_plane + zr * 32 + (e % 8) * 4) = 0.f;
-  for (int e = tid; e < 2 * kBS; e += kWsThreads) {
+  for (int e = tid; e < 2 * rep * kBS; e += kWsThreads) {
     const unsigned o = (e / kBS) * y.b_buf + (zr * kBS + e % kBS) * 2;
     *reinterpret_cast<__bf16*>(smem_raw + y.bh0 + o) = (__bf16)0.f;
     *reinterpret_cast<__bf16*>(smem_raw + y.bl0 + o) = (__bf16)0.f;
   }
-  const SlotCols sc = a.cols[wg * kSlotsPerWg + w];
-  const MRowBlock* rows = a.rows + wg * kRbPerWg + w * kMaxRbPerSlot;
-  // partial[kr][tile][element] with tile = wg*kTilesPerWg + w*kSlotTiles + (q*NT + t)
+  // wave w runs slot w % wpr of replica w / wpr
+  const int wpr = kSlotsPerWg / rep, r = w / wpr, ws = w - r * wpr;
+  const SlotCols sc = a.cols[wg * kSlotsPerWg + ws];
+  const MRowBlock* rows = a.rows + wg * kRbPerWg + ws * kMaxRbPerSlot;
+  // this replica's voxel range kr rep + r of rep n_krange; partial[range][tile][element]
+  // with tile = wg*kTilesPerWg + ws*kSlotTiles + (q*NT + t) < tile_stride for busy slots
+  const long long kre = (long long)kr * rep + r, n_kre = (long long)a.n_krange * rep;
   double* out = a.partial +
-                ((long long)kr * a.n_wg * kTilesPerWg + (long long)wg * kTilesPerWg + (long long)w * kSlotTiles) *
-                    kMTileElems +
-                lane;
-  const long long n_blocks = a.n_vox / kC2;
-  const int n_chunks = kr < n_blocks ? (int)((n_blocks - kr + a.n_krange - 1) / a.n_krange) : 0;
-  if (n_chunks == 0)  // empty range: its partials are zero
+                (kre * a.tile_stride + (long long)wg * kTilesPerWg + (long long)ws * kSlotTiles) * kMTileElems + lane;
+  WsChunks ch;
+  ch.n_blocks = a.n_vox / kC2;
+  ch.blk0 = (long long)kr * rep;
+  ch.step = n_kre;
+  ch.rep = rep;
+  ch.sub = r;
+  ch.n_chunks = ch.blk0 < ch.n_blocks ? (int)((ch.n_blocks - ch.blk0 + n_kre - 1) / n_kre) : 0;
+  ch.n_mine = kre < ch.n_blocks ? (int)((ch.n_blocks - kre + n_kre - 1) / n_kre) : 0;
+  if (ch.n_mine == 0 && sc.n > 0)  // empty range: a busy slot's partials are zero
     for (int e = 0; e < kSlotTiles * 4; ++e) out[(long long)(e >> 2) * kMTileElems + (e & 3) * 64] = 0.0;
+  const WsStage q = ws_stage_of(tid, wr.s_n, rep);
   // every wave passes the same barriers whatever its variant (uniform per wave)
   switch (sc.n * 16 + sc.n_rb) {
 #define WS_CASE(N, R) \
-  case N * 16 + R: ws_run<N, R>(F, a, smem_raw, y, wr, kr, n_chunks, tid, sc, rows, out); break;
+  case N * 16 + R: ws_run<N, R>(F, a, smem_raw, y, wr, ch, q, tid, sc, rows, out); break;
     WS_CASE(1, 1) WS_CASE(1, 2) WS_CASE(1, 3) WS_CASE(1, 4) WS_CASE(1, 5) WS_CASE(1, 6) WS_CASE(1, 7) WS_CASE(1, 8)
     WS_CASE(2, 1) WS_CASE(2, 2) WS_CASE(2, 3) WS_CASE(2, 4) WS_CASE(2, 5) WS_CASE(2, 6) WS_CASE(2, 7) WS_CASE(2, 8)
     WS_CASE(3, 1) WS_CASE(3, 2) WS_CASE(3, 3) WS_CASE(3, 4) WS_CASE(3, 5)
@@ -615,7 +634,7 @@ __global__ void __launch_bounds__(kWsThreads) k_contract_bf16x3(const float* __r
     WS_CASE(5, 1) WS_CASE(5, 2) WS_CASE(5, 3)
     WS_CASE(6, 1) WS_CASE(6, 2) WS_CASE(7, 1) WS_CASE(7, 2) WS_CASE(8, 1) WS_CASE(8, 2)
 #undef WS_CASE
-    default: ws_idle(F, a, smem_raw, y, wr, kr, n_chunks, tid); break;
+    default: ws_idle(F, a, smem_raw, y, wr, ch, q); break;
   }
 }
 
@@ -1137,8 +1156,35 @@ hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-size_t bf16x3_lds_bytes(int max_s) {
-  return 2 * (size_t)kOct * ((size_t)(max_s + 1) * 32 + 16) + 4 * (size_t)(max_s + 1) * kBS * sizeof(__bf16);
+size_t bf16x3_lds_bytes(int max_s, int rep) {
+  const WsLayout y = ws_layout(max_s + 1, 2 * rep);
+  return (size_t)y.bl0 + 2 * (size_t)rep * y.b_buf;
+}
+
+// Tiles per voxel range in the partials: every work group's kTilesPerWg, or for
+// one work group the tiles of slots 0 .. top (its highest busy slot).
+int ws_tile_stride(const MfmaTiling& mt) {
+  if (mt.n_wg != 1) return mt.n_wg * kTilesPerWg;
+  int top = 0;
+  for (int k = 0; k < kSlotsPerWg && k < (int)mt.cols.size(); ++k)
+    if (mt.cols[k].n > 0 && mt.cols[k].n_rb > 0) top = k;
+  return (top + 1) * kSlotTiles;
+}
+
+// Replicas need one work group whose used slots all sit below 12 / rep (the
+// slot placement fills SIMD 0..3 first, so few slots take the low positions),
+// rep g16 staging waves' worth of rows (g16 = ceil(s_n / 16), one 8-voxel
+// segment per thread) and their LDS.
+int ws_max_rep(const MfmaTiling& mt) {
+  if (mt.n_wg != 1 || mt.wg_rows.empty()) return 1;
+  int top = -1;
+  for (int k = 0; k < kSlotsPerWg && k < (int)mt.cols.size(); ++k)
+    if (mt.cols[k].n > 0 && mt.cols[k].n_rb > 0) top = k;
+  const int g16 = (mt.wg_rows[0].s_n + 15) / 16;
+  for (int rep = 3; rep >= 2; --rep)
+    if (top < kSlotsPerWg / rep && rep * g16 * 64 <= kWsThreads && bf16x3_lds_bytes(mt.max_s, rep) <= kWsLdsMax)
+      return rep;
+  return 1;
 }
 
 hipError_t launch_contract_fp32(const float* F, const ContractArgs& a, hipStream_t st) { return launch_vec<float>(F, a, st); }
@@ -1158,21 +1204,25 @@ hipError_t prepare_contract_vec() {
 // split-bf16 maximum); done at plan time so launches stay capture-safe.
 hipError_t prepare_contract_bf16x3() {
   return hipFuncSetAttribute((const void*)k_contract_bf16x3, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bf16x3_lds_bytes(kMaxSplitShells));
+                             (int)kWsLdsMax);
 }
 
 bool ws_group_ok(const WsGroup& g) {
-  // every staged row fits the per-thread loads; ranges are whole voxel blocks
-  return g.max_s * (kC2 / 8) <= kWsThreads * kPf && g.max_s <= g.n_s && g.max_s <= kMaxSplitShells &&
-         g.n_vox % kC2 == 0 && g.n_krange % 8 == 0 && g.block0 % 8 == 0 && g.n_wg >= 1;
+  // every staged row of every replica fits the per-thread loads (rows of a work
+  // group <= max_s); ranges are whole voxel blocks; replicas need one work group
+  return g.rep >= 1 && g.rep <= 3 && (g.rep == 1 || g.n_wg == 1) &&
+         (g.n_wg == 1 ? g.tile_stride >= kSlotTiles && g.tile_stride <= kTilesPerWg
+                      : g.tile_stride == g.n_wg * kTilesPerWg) &&
+         g.rep * 64 * ((g.max_s + 15) / 16) <= kWsThreads && g.max_s <= g.n_s && g.max_s <= kMaxSplitShells &&
+         bf16x3_lds_bytes(g.max_s, g.rep) <= kWsLdsMax && g.n_vox % kC2 == 0 && g.n_krange % 8 == 0 &&
+         g.block0 % 8 == 0 && g.n_wg >= 1;
 }
 
 hipError_t launch_contract_bf16x3(const float* F, double* partial, const WsGroup* groups_dev, int n_groups,
-                                  int max_s, int n_blocks, hipStream_t st) {
-  if (n_groups < 1 || n_blocks < 1 || max_s > kMaxSplitShells) return hipErrorInvalidValue;
-  const size_t lds = bf16x3_lds_bytes(max_s);
-  hipLaunchKernelGGL(k_contract_bf16x3, dim3((unsigned)n_blocks), dim3(kWsThreads), lds, st, F, partial, groups_dev,
-                     n_groups);
+                                  size_t lds_bytes, int n_blocks, hipStream_t st) {
+  if (n_groups < 1 || n_blocks < 1 || lds_bytes > kWsLdsMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_contract_bf16x3, dim3((unsigned)n_blocks), dim3(kWsThreads), lds_bytes, st, F, partial,
+                     groups_dev, n_groups);
   return hipGetLastError();
 }
 

@@ -632,6 +632,19 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt, int max_
             }
       if (!improved) break;
     }
+    // compact placement: busy slots first in each bin, and within a group the
+    // SIMDs (interchangeable) ordered by busy slots, so a group with few busy
+    // slots uses the lowest positions (which lets the kernel replicate it)
+    for (auto& bv : bin)
+      std::stable_partition(bv.begin(), bv.end(), [](const Slot& sl) { return sl.sc.n != 0; });
+    auto busy = [](const std::vector<Slot>& bv) {
+      int k = 0;
+      for (const Slot& sl : bv) k += sl.sc.n != 0;
+      return k;
+    };
+    for (int w = 0; w < n_wg; ++w)
+      std::stable_sort(bin.begin() + w * kSimds, bin.begin() + (w + 1) * kSimds,
+                       [&](const std::vector<Slot>& a, const std::vector<Slot>& b) { return busy(a) > busy(b); });
     slots.assign((size_t)n_wg * kSlotsPerWg, Slot{});
     for (int b = 0; b < n_bins; ++b) {
       const int w = b / kSimds, q = b % kSimds;

@@ -136,14 +136,16 @@ struct WsArgs {
   int max_s = 0;                      // most shells staged by one work group (LDS sizing)
   long long n_vox = 0;
   int n_krange = 0;                   // multiple of 8
-  double* partial = nullptr;          // device [n_krange][n_wg * kTilesPerWg][kMTileElems]
+  int rep = 1;                        // replicas of the slot set (voxel ranges per work group)
+  int tile_stride = 0;                // tiles per voxel range in the partials
+  double* partial = nullptr;          // device [rep * n_krange][tile_stride][kMTileElems]
 };
 // One group of the grouped split-bf16 launch (a grid class of a plan): its
 // fields and partials as element offsets from the launch's F and partial
 // pointers, so one table serves any placement of those buffers.
 struct WsGroup {
   long long f_off = 0;                // fields: F + f_off, voxel-blocked over n_s shells
-  long long p_off = 0;                // partials: partial + p_off, [n_krange][n_wg * kTilesPerWg][kMTileElems]
+  long long p_off = 0;                // partials: partial + p_off, [rep * n_krange][tile_stride][kMTileElems]
   const MRowBlock* rows = nullptr;    // device [n_wg * kRbPerWg]
   const SlotCols* cols = nullptr;     // device [n_wg * kSlotsPerWg]
   const WgRows* wg_rows = nullptr;    // device [n_wg]
@@ -151,16 +153,29 @@ struct WsGroup {
   int n_wg = 0, n_s = 0, max_s = 0;
   int n_krange = 0;                   // multiple of 8
   int block0 = 0;                     // first block of the group (multiple of 8); groups ascending
+  // replicas (1..3, n_wg = 1 when above 1): the work group's waves run rep
+  // copies of slots 0 .. kSlotsPerWg / rep - 1, copy r on voxel range
+  // rep * kr + r of rep * n_krange ranges
+  int rep = 1;
+  // tiles per voxel range in the partials: n_wg * kTilesPerWg, or for one work
+  // group only its busy slots' (slots 0 .. top), (top + 1) * kSlotTiles
+  int tile_stride = 0;
   int pad_ = 0;
 };
 constexpr int kMaxSplitShells = 128;   // most shells of a split-bf16 plan
-size_t bf16x3_lds_bytes(int max_s);
+constexpr size_t kWsLdsMax = 160 * 1024;   // LDS of one work group on gfx950
+size_t bf16x3_lds_bytes(int max_s, int rep = 1);
+// the largest replica count a one-work-group tiling allows (slots used, rows
+// staged, LDS): 1 when n_wg > 1
+int ws_max_rep(const MfmaTiling& mt);
+// tiles per voxel range of a tiling's partials (the tile_stride of its group)
+int ws_tile_stride(const MfmaTiling& mt);
 bool ws_group_ok(const WsGroup& g);
 hipError_t prepare_contract_bf16x3();   // once per plan, before any launch (and before graph capture)
-// groups_dev: device [n_groups]; max_s: largest max_s of the groups; n_blocks:
-// sum of n_wg * n_krange
+// groups_dev: device [n_groups]; lds_bytes: the largest bf16x3_lds_bytes(max_s,
+// rep) of the groups; n_blocks: sum of n_wg * n_krange
 hipError_t launch_contract_bf16x3(const float* F, double* partial, const WsGroup* groups_dev, int n_groups,
-                                  int max_s, int n_blocks, hipStream_t st);
+                                  size_t lds_bytes, int n_blocks, hipStream_t st);
 // Gradient: w_k = gB[t_k] norm[t_k]; G_n = sum_{terms (t, j, l) of n} w F_j F_l
 // (terms: int4 (t, j, l, 0) with 0-based shells, grouped by n via term_off[n_s + 1])
 hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, const int4* terms, long long n_terms,

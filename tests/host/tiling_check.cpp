@@ -67,8 +67,12 @@ static int check_selection(const Selection& s, int n_shells, const char* what) {
   }
   for (const Tri& t : s.tri)
     if (!cov.count({t.a1, t.a2, t.a3})) { std::printf("vector tiling misses (%d,%d,%d)\n", t.a1, t.a2, t.a3); { std::printf("  in %s\n", what); return 1; } }
-  std::printf("%s: n_tri=%zu work_groups=%d tiles=%lld max_s=%d\n", what, s.tri.size(), mt.n_wg, (long long)mt.tiles,
-              mt.max_s);
+  // the highest busy slot position of work group 0 (replicas need it below 12 / rep)
+  int top = -1;
+  for (int k = 0; k < kSlotsPerWg; ++k)
+    if (mt.cols[k].n > 0 && mt.cols[k].n_rb > 0) top = k;
+  std::printf("%s: n_tri=%zu work_groups=%d tiles=%lld max_s=%d top_slot=%d rows0=%d\n", what, s.tri.size(), mt.n_wg,
+              (long long)mt.tiles, mt.max_s, top, mt.wg_rows[0].s_n);
   return 0;
 }
 
