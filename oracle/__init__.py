@@ -13,4 +13,7 @@ Modules
             linear-RSD monopole (eq. RSD)
   polyspectrum  the fourth-order polyspectrum estimator (Section 4: four shell
             fields, cutoff 2 pi N_g / (4 L)) and its closed-4-tuple sum
+  multipoles  Legendre moments (l = 0, 2, 4) of the redshift-space bispectrum
+            in the angle of the first side to the line of sight (Section 3.1)
+            and their weighted closed-triangle sum
 """
