@@ -43,6 +43,9 @@ WORKLOADS = {
                                 sel=dict(tri_mode=2, k1_shells=list(range(2, 41, 2)), n_mu=20, n_t=20)),
     "ng32_10shells_grid": dict(field="ng32", n_g=32, box_l=300.0, dk=1.0, n_shells=10, rsd_beta=0.0,
                                sel=dict(tri_mode=2, k1_shells=list(range(5, 11)), n_mu=10, n_t=10)),
+    # the redshift-space quadrupole (Section 3.1, Legendre weight on the first side): 60 shells at 512^3
+    "ng512_60shells_rsd_quadrupole": dict(field="ng512", n_g=512, box_l=1500.0, dk=1.0, n_shells=60, rsd_beta=0.5,
+                                          sel=dict(ell=2)),
     # the fourth-order polyspectrum (Section 4): all 35 345 bins of 30 shells on a 128^3 grid
     "ng128_30shells_order4": dict(field="ng128", n_g=128, box_l=600.0, dk=1.0, n_shells=30, rsd_beta=0.5,
                                   sel=dict(order=4)),
@@ -114,11 +117,12 @@ def class_work(plan, tri):
         # order 4: T = sum P_(a1,a2) P_(a3,a4), pairs from both halves of each bin
         pairs = {(int(r[0]), int(r[1])) for r in t} | ({(int(r[2]), int(r[3])) for r in t} if t.shape[1] == 4 else set())
         flop += float(g) ** 3 * (2.0 * len(t) + len(pairs))
-        field_vox += float(g) ** 3 * (hi - lo + 1)
+        # a multipole plan writes a weighted copy of every class shell as well
+        field_vox += float(g) ** 3 * (hi - lo + 1) * (2 if getattr(plan, "ell", 0) else 1)
     return flop, field_vox
 
 
-def cpu_baseline(delta32, w: dict, plan_tri, plan_ntri, b_gpu) -> tuple:
+def cpu_baseline(delta32, w: dict, plan_tri, plan_ntri, b_gpu, ell: int = 0) -> tuple:
     """The float64 oracle on a bounded sample of the same workload: all closable
     triangles of the first S shells at the full grid (forward FFT, S data and S
     unit shells, the triple sums and their summation scale, N_tri).  Returns the
@@ -126,7 +130,7 @@ def cpu_baseline(delta32, w: dict, plan_tri, plan_ntri, b_gpu) -> tuple:
     (e_norm, max e_cond, N_tri equality)."""
     import numpy as np
 
-    from oracle import fbe, geometry, polyspectrum
+    from oracle import fbe, geometry, multipoles, polyspectrum
     cores = os.cpu_count() or 1
     d64 = delta32.astype(np.float64)
     t0 = time.perf_counter()
@@ -139,7 +143,10 @@ def cpu_baseline(delta32, w: dict, plan_tri, plan_ntri, b_gpu) -> tuple:
     else:
         s_shells = 6 if delta32.shape[0] <= 512 else 2   # 12 (4) float64 fields of N^3 on the host, ~10 s
         tri = geometry.all_triangles(s_shells)
-        ref = fbe.estimate(d64, w["box_l"], w["dk"], tri, rsd_beta=w["rsd_beta"], with_abs=True)
+        if ell:
+            ref = multipoles.estimate(d64, w["box_l"], w["dk"], tri, ell, rsd_beta=w["rsd_beta"], with_abs=True)
+        else:
+            ref = fbe.estimate(d64, w["box_l"], w["dk"], tri, rsd_beta=w["rsd_beta"], with_abs=True)
         what, unit = "triangles", "triangles/s"
     dt = time.perf_counter() - t0
     base = {"value": len(tri) / dt, "unit": unit, "cores": cores, "kind": "oracle",
@@ -248,7 +255,8 @@ def main():
         "dtype": "bf16x3-fp32acc" if prec == P.PREC_SPLITBF16 else "fp32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_g": n, "n_est": g, "box_l": w["box_l"], "n_shells": w["n_shells"],
-                   "dk_kf": w["dk"], "rsd_beta": w["rsd_beta"], "n_tri": plan.n_tri, "precision": args.precision},
+                   "dk_kf": w["dk"], "rsd_beta": w["rsd_beta"], "n_tri": plan.n_tri, "precision": args.precision,
+                   "ell": plan.ell, "order": plan.order},
         "stages_ms": {"forward_fft": stages[0], "shell_ffts": stages[1], "contraction": stages[2],
                       "normalise": stages[3]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
@@ -317,7 +325,8 @@ def main():
         result["copy_calibration"] = copy_calibration(torch, dev)
     if not args.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"], result["error_vs_oracle"] = cpu_baseline(delta32, w, tri, plan.ntri.numpy(), b_host)
+        result["cpu_baseline"], result["error_vs_oracle"] = cpu_baseline(delta32, w, tri, plan.ntri.numpy(), b_host,
+                                                                          plan.ell)
     plan.close()
     print(json.dumps(result), flush=True)
 

@@ -134,6 +134,13 @@ typedef struct bispec_config {
                           /*   one grid G > 4 max|m_i|; selection ALL, K1SET or     */
                           /*   LIST (rows of 4); split-bf16 only; no GRAD,          */
                           /*   NO_WORKSPACE or batch                                */
+  int32_t ell;            /* Legendre multipole of the redshift-space bispectrum   */
+                          /*   (Section 3.1, line of sight z), 0, 2 or 4: every    */
+                          /*   closed triangle weighted by L_ell(mu_1), mu_1 =     */
+                          /*   k1_z/|k1| of its first side (shell a1), and B times */
+                          /*   (2 ell + 1); 0 = the bispectrum itself.  ell > 0:  */
+                          /*   order 3, no GRAD; a grid class with more than 64    */
+                          /*   shells (split-bf16) or 128 (fp32) is refused        */
 } bispec_config;
 
 /* ---- host-only queries (no GPU needed) ------------------------------------ */

@@ -31,7 +31,7 @@ class bispec_config(C.Structure):
         ("rsd_beta", C.c_double), ("tri_mode", C.c_int32), ("n_k1", C.c_int32),
         ("k1_shells", C.POINTER(C.c_int32)), ("n_mu", C.c_int32), ("n_t", C.c_int32),
         ("n_list", C.c_int64), ("list", C.POINTER(C.c_int32)), ("precision", C.c_int32),
-        ("flags", C.c_uint32), ("n_est", C.c_int32), ("order", C.c_int32),
+        ("flags", C.c_uint32), ("n_est", C.c_int32), ("order", C.c_int32), ("ell", C.c_int32),
     ]
 
 
@@ -102,7 +102,7 @@ def _i32_array(values):
 
 
 def make_config(n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=TRI_ALL, k1_shells=None, n_mu=0, n_t=0,
-                triangles=None, precision=PREC_SPLITBF16, flags=0, n_est=0, order=0):
+                triangles=None, precision=PREC_SPLITBF16, flags=0, n_est=0, order=0, ell=0):
     """A bispec_config plus the ctypes arrays it points into (keep both alive)."""
     k1, nk1 = _i32_array(k1_shells)
     flat = None if triangles is None else [int(v) for row in triangles for v in row]
@@ -113,7 +113,8 @@ def make_config(n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=TRI_ALL, k1_she
                         k1_shells=C.cast(k1, C.POINTER(C.c_int32)) if k1 is not None else None,
                         n_mu=int(n_mu), n_t=int(n_t), n_list=nflat // width,
                         list=C.cast(lst, C.POINTER(C.c_int32)) if lst is not None else None,
-                        precision=int(precision), flags=int(flags), n_est=int(n_est), order=int(order))
+                        precision=int(precision), flags=int(flags), n_est=int(n_est), order=int(order),
+                        ell=int(ell))
     return cfg, (k1, lst)
 
 

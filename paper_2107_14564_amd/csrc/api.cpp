@@ -346,10 +346,32 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
     GridClass& c = p.cls.back();
     c.spec = std::move(spc);
     c.geo = class_geometry(p.geo, c.spec);
+    int first_off = 0;
+    if (cfg->ell) {
+      // multipoles: weighted copies of the class's shells after its own
+      // (fields n_s .. 2 n_s - 1 carry L_ell(mu)), the first side of every
+      // triangle on them (Section 3.1 with the weight on shell a1)
+      const int ns = c.geo.n_s;
+      if (2 * ns > (cfg->precision == BISPEC_PREC_SPLITBF16 ? kMaxSplitShells : 256))
+        return set_err(BISPEC_EINVAL, "multipoles: a grid class spans more than 64 shells (split-bf16) or 128 (fp32)");
+      auto twice = [ns](auto& v) {
+        const auto head = v;
+        v.insert(v.end(), head.begin(), head.begin() + ns);
+      };
+      twice(c.geo.lo2);
+      twice(c.geo.hi2);
+      twice(c.geo.rad);
+      twice(c.geo.counts);
+      twice(c.geo.mean_k);
+      c.geo.ell.assign(ns, 0);
+      c.geo.ell.resize(2 * (size_t)ns, cfg->ell);
+      c.geo.n_s = 2 * ns;
+      first_off = ns;
+    }
     c.sel.tri.reserve(c.spec.tri.size());
     for (int32_t t : c.spec.tri) {
       const Tri& q = p.sel.tri[t];
-      c.sel.tri.push_back({q.a1 - c.spec.s_lo, q.a2 - c.spec.s_lo, q.a3 - c.spec.s_lo});
+      c.sel.tri.push_back({q.a1 - c.spec.s_lo + first_off, q.a2 - c.spec.s_lo, q.a3 - c.spec.s_lo});
     }
     build_tiles(c.sel, kMaxTilesPerTask, c.tiles);
     build_mfma_tiles(c.sel, c.geo.n_s, c.mfma);
@@ -1128,12 +1150,13 @@ int plan_build(bispec_plan_s& pr, hipStream_t s, const Workspace* shared) {
     PLAN_HIP(upload(p->tw32, twiddles32(n), s));
     // The fields are F_s = D / (dV N^{3/2}) on G_c^3 points (forward transform
     // scaled by N^{-3/2}); eq. bsfin with the sum over the class grid:
-    //   B = (dV N^{3/2})^3 sum_y F_s F_s F_s / (V N_tri G_c^3)
+    //   B = (dV N^{3/2})^3 sum_y F_s F_s F_s / (V N_tri G_c^3),
+    // times 2 ell + 1 for a multipole
     const double V = p->geo.box_l * p->geo.box_l * p->geo.box_l;
     const double dV = V / ((double)n * n * n);
     std::vector<double> norm(p->sz.n_tri);
     for (const GridClass& c : p->cls) {
-      const double cc = dV * dV * dV * std::pow((double)n, 4.5) / (V * (double)c.n_vox);
+      const double cc = (2.0 * p->cfg.ell + 1.0) * dV * dV * dV * std::pow((double)n, 4.5) / (V * (double)c.n_vox);
       for (int32_t t : c.spec.tri) norm[t] = p->ntri[t] > 0 ? cc / (double)p->ntri[t] : NAN;
     }
     PLAN_HIP(upload(p->norm, norm, s));

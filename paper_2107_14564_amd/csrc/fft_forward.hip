@@ -79,6 +79,8 @@ void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p
     d.hi2 = g.hi2[sn];
     d.rad = g.rad[sn];
     d.wrow = shell_row(d.rad, f64);
+    d.ell = g.ell.empty() ? 0 : g.ell[sn];
+    d.pad_ = 0;
     const long long R = d.rad;
     d.a1_off = a1;
     d.a2_off = a2;

@@ -174,6 +174,11 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ s
               const long long xrow = mx < 0 ? mx + spec_n : mx;
               const float2 x = spec[(xrow * spec_n + yrow) * spec_row(spec_n) + kz];
               v = mk<T>((T)x.x, (T)x.y);
+              if (d.ell) {  // Legendre weight L_ell(mu), mu^2 = m_z^2 / |m|^2 (line of sight z)
+                const T u = (T)((double)(kz * kz) / (double)m2);
+                const T wl = d.ell == 2 ? (T)1.5 * u - (T)0.5 : ((T)35 * u * u - (T)30 * u + (T)3) / (T)8;
+                v = mk<T>(v.x * wl, v.y * wl);
+              }
             }
           }
         }

@@ -52,6 +52,10 @@ int validate(const bispec_config& c, std::string& err) {
                                             : "shells reach k >= 2 pi N_g/(3L): need (n_shells + 1/2) dk <= n_g/3");
   if (c.order == 4 && c.tri_mode == BISPEC_TRI_MUT_GRID)
     return fail(err, BISPEC_EINVAL, "order 4 takes the ALL, K1SET or LIST selections");
+  if (c.ell != 0 && c.ell != 2 && c.ell != 4) return fail(err, BISPEC_EINVAL, "ell must be 0, 2 or 4");
+  if (c.ell != 0 && c.order == 4) return fail(err, BISPEC_EINVAL, "multipoles are defined for the bispectrum only");
+  if (c.ell != 0 && (c.flags & BISPEC_FLAG_GRAD))
+    return fail(err, BISPEC_EINVAL, "BISPEC_FLAG_GRAD is not available for multipoles (ell > 0)");
   switch (c.tri_mode) {
     case BISPEC_TRI_ALL: break;
     case BISPEC_TRI_K1SET:

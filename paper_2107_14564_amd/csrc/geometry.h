@@ -25,6 +25,8 @@ struct ShellGeometry {
   std::vector<int32_t> rad;
   std::vector<int64_t> counts;   // modes per shell over the whole lattice
   std::vector<double> mean_k;    // mean |k| per shell (k units)
+  // Legendre order of the weight L_ell(k_z/|k|) on each shell's field (empty: none)
+  std::vector<int32_t> ell;
 };
 
 struct Selection {

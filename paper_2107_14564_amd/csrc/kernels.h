@@ -62,6 +62,8 @@ struct ShellDev {
   long long a2_off;     // element offset of A2_n
   int rad;              // R = floor(sqrt(hi2 - 1))
   int wrow;             // row length of A1_n and A2_n: shell_row(R) >= R + 1
+  int ell;              // data fields: weight L_ell(m_z/|m|) on every mode (0: none)
+  int pad_;
 };
 
 struct ShellLaunch {

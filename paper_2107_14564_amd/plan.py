@@ -17,15 +17,19 @@ class Plan:
     dk (units of 2 pi / box_l), n_shells, optional RSD beta, a triangle
     selection (tri_mode with k1_shells / n_mu / n_t / triangles), the
     contraction precision, flags and the estimator grid n_est (0 = automatic:
-    the smallest supported size above three times the largest mode component).
+    the smallest supported size above three times the largest mode component),
+    order 4 for the fourth-order polyspectrum, and ell = 2 or 4 for a Legendre
+    multipole of the redshift-space bispectrum (weight L_ell(mu) on the first
+    side, line of sight z, times 2 ell + 1).
     """
 
     def __init__(self, n_g, box_l, dk, n_shells, rsd_beta=0.0, tri_mode=_abi.TRI_ALL, k1_shells=None, n_mu=0,
-                 n_t=0, triangles=None, precision=_abi.PREC_SPLITBF16, flags=0, n_est=0, order=0):
+                 n_t=0, triangles=None, precision=_abi.PREC_SPLITBF16, flags=0, n_est=0, order=0, ell=0):
         if not torch.cuda.is_available():
             raise RuntimeError("Plan needs a HIP device")
         self.cfg, self._keep = _abi.make_config(n_g, box_l, dk, n_shells, rsd_beta, tri_mode, k1_shells, n_mu, n_t,
-                                                triangles, precision, flags, n_est, order)
+                                                triangles, precision, flags, n_est, order, ell)
+        self.ell = int(ell)
         self.order = 4 if int(order) == 4 else 3
         self.n_g = int(n_g)
         self.n_est = _abi.bispec_estimator_grid(self.cfg)
