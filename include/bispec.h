@@ -191,9 +191,21 @@ int bispec_workspace_bytes(const bispec_config* cfg, int64_t* run_bytes, int64_t
  * (eqs. 2FT, Ntri2), round and check them (EPREC), then free the unit shells.
  * hip_stream: a hipStream_t (null = default stream); the call synchronises it.
  * *out receives the plan (owned by the caller; release with bispec_destroy).
+ * Voxel-slab streaming: when the plan with whole shell fields resident does
+ * not fit (hipMemGetInfo, BISPEC_MAX_BYTES), the number of x-slabs per grid
+ * class is doubled until it does (at least the env var BISPEC_SLABS, default
+ * 1): the fields, second-pass intermediates and partial sums then hold one
+ * slab of x-planes, every run computes a class's x pass once and, slab by
+ * slab, its y and z passes and the slab's triple sums, added into B in slab
+ * order (the same for N_tri at plan time).  Not for order 4 or GRAD plans;
+ * bispec_copy_field of a streamed plan is ESTATE; its stage times put the
+ * contraction in the shell-pass stage.
  * Errors: EINVAL, ECUTOFF, ENOMEM (checked before any allocation against
  * hipMemGetInfo and the env var BISPEC_MAX_BYTES), EHIP, EPREC. */
 int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out);
+
+/* x-slabs per grid class of a plan (1: whole fields resident). */
+int bispec_plan_slabs(bispec_plan_t plan, int32_t* slabs);
 
 int bispec_num_triangles(bispec_plan_t plan, int64_t* n_tri);
 

@@ -63,6 +63,7 @@ def lib() -> C.CDLL:
             "bispec_plan_classes": [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
                                     C.POINTER(I32), C.POINTER(I32), C.POINTER(C.c_float), C.POINTER(I32)],
             "bispec_plan": [cfgp, P, C.POINTER(P)],
+            "bispec_plan_slabs": [P, C.POINTER(I32)],
             "bispec_num_triangles": [P, C.POINTER(I64)],
             "bispec_triangles": [P, C.POINTER(I32), C.POINTER(D), C.POINTER(I64)],
             "bispec_run": [P, P, P, P],
@@ -189,6 +190,13 @@ def bispec_plan_classes(plan: int):
            "bispec_plan_classes")
     return [dict(grid=g[i], n_krange=kr[i], max_cols=mc[i], n_wg=wg[i], rep=rp[i], tuned_ms=float(ms[i]),
                  tune_source=("default", "timed", "cache")[src[i]]) for i in range(k)]
+
+
+def bispec_plan_slabs(plan: int) -> int:
+    """x-slabs per grid class of a built plan (1: whole fields resident)."""
+    n = C.c_int32(0)
+    _check(lib().bispec_plan_slabs(C.c_void_p(plan), C.byref(n)), "bispec_plan_slabs")
+    return n.value
 
 
 def bispec_query_quads(cfg):

@@ -162,6 +162,10 @@ struct GridClass {
   MfmaTiling mfma;             // span-grouped row blocks (MFMA kernel)
   ShellPassPlan pass32;
   long long n_vox = 0, n_tri = 0;
+  // voxel-slab streaming: the grid in slabs of slab_x x-planes (the last may
+  // be shorter); fields, second-pass intermediates and partials hold one slab
+  int slab_x = 0, n_slab = 1;
+  long long slab_vox = 0;      // voxels of a full slab (n_vox when the grid is one slab)
   size_t fields32 = 0, fields64 = 0, partial_vec = 0, partial_mfma = 0;
   int n_krange_vec = 8, n_krange_mfma = 8;
   int n_krange_mfma_cap = 8;   // its MFMA partials hold this many ranges
@@ -178,7 +182,12 @@ struct GridClass {
   long long adj_tiles = 0;
   int adj_wg = 0, adj_krange = 8;
   DevBuf tri_index, rows, tile_list, task_off, mfma_rows, mfma_cols, mfma_wgrows, mfma_slot, tri_out, shells,
-      x_tiles, y_off, z_off, tw32, g_terms, g_term_off, g_w, adj_rbs, adj_ns, adj_waves, adj_off, adj_tri, adj_W;
+      x_tiles, y_off, z_off, tw32, g_terms, g_term_off, g_w, adj_rbs, adj_ns, adj_waves, adj_off, adj_tri, adj_W,
+      ws_slab;                 // streamed plans: launch groups of a full slab and of the last slab
+  WsGroup ws_slab_host[2];
+  // x-planes of slab k and its voxels
+  int slab_planes(int k) const { return (int)std::min<long long>(slab_x, (long long)spec.g - (long long)k * slab_x); }
+  long long slab_voxels(int k) const { return (long long)slab_planes(k) * spec.g * spec.g; }
 };
 
 // A class's own geometry: shells s_lo .. s_lo + n_s - 1 of g, renumbered from 1.
@@ -238,6 +247,7 @@ struct bispec_plan_s {
   Sizes sz;
   std::vector<int64_t> ntri;
   int precision = BISPEC_PREC_SPLITBF16;
+  int slabs = 1;               // x-slabs per grid class (1: whole grids resident)
   bool ran = false;
   bool in_batch = false;       // owned by a bispec_many_t (workspace shared)
   int device = 0;
@@ -317,8 +327,13 @@ int build_host_quad(const bispec_config* cfg, bispec_plan_s& p) {
   return BISPEC_OK;
 }
 
-int build_host(const bispec_config* cfg, bispec_plan_s& p) {
+// slabs > 1: every grid class streams its fields in that many x-slabs (at
+// least one plane each): the run buffers then hold one slab.
+int build_host(const bispec_config* cfg, bispec_plan_s& p, int slabs = 1) {
   if (!cfg) return set_err(BISPEC_EINVAL, "null config");
+  p.slabs = std::max(1, slabs);
+  if (p.slabs > 1 && (cfg->flags & BISPEC_FLAG_GRAD))
+    return set_err(BISPEC_EINVAL, "BISPEC_FLAG_GRAD needs the whole fields resident (no slab streaming)");
   std::string err;
   p.cfg = *cfg;
   p.cfg.k1_shells = nullptr;
@@ -376,20 +391,23 @@ int build_host(const bispec_config* cfg, bispec_plan_s& p) {
     build_tiles(c.sel, kMaxTilesPerTask, c.tiles);
     build_mfma_tiles(c.sel, c.geo.n_s, c.mfma);
     const long long g = c.spec.g;
-    plan_shell_passes(c.geo, (int)g, false, c.pass32);
-    ShellPassPlan p64;
-    plan_shell_passes(c.geo, (int)g, true, p64);
     c.n_vox = g * g * g;
+    c.slab_x = (int)std::max<long long>(1, (g + p.slabs - 1) / p.slabs);
+    c.n_slab = (int)((g + c.slab_x - 1) / c.slab_x);
+    c.slab_vox = (long long)c.slab_x * g * g;
+    plan_shell_passes(c.geo, (int)g, false, c.pass32, c.slab_x);
+    ShellPassPlan p64;
+    plan_shell_passes(c.geo, (int)g, true, p64, c.slab_x);
     c.n_tri = (long long)c.sel.tri.size();
-    c.fields32 = (size_t)blocked_elems(c.n_vox, c.geo.n_s) * sizeof(float);
-    c.fields64 = (size_t)blocked_elems(c.n_vox, c.geo.n_s) * sizeof(double);
+    c.fields32 = (size_t)blocked_elems(c.slab_vox, c.geo.n_s) * sizeof(float);
+    c.fields64 = (size_t)blocked_elems(c.slab_vox, c.geo.n_s) * sizeof(double);
     const long long ntasks = (long long)c.tiles.task_off.size() - 1;
-    c.n_krange_vec = n_krange_for(ntasks, c.n_vox);
-    c.n_krange_mfma = n_krange_mfma_for(c.n_vox);
+    c.n_krange_vec = n_krange_for(ntasks, c.slab_vox);
+    c.n_krange_mfma = n_krange_mfma_for(c.slab_vox);
     c.n_krange_mfma_cap = c.n_krange_mfma;
     if (cfg->flags & BISPEC_FLAG_AUTOTUNE)
       for (int k : kTuneRanges)
-        if (k <= std::max(8LL, (c.n_vox / (64 * 4)) / 8 * 8)) c.n_krange_mfma_cap = std::max(c.n_krange_mfma_cap, k);
+        if (k <= std::max(8LL, (c.slab_vox / (64 * 4)) / 8 * 8)) c.n_krange_mfma_cap = std::max(c.n_krange_mfma_cap, k);
     c.partial_vec = (size_t)c.n_krange_vec * c.n_tri * sizeof(double);
     c.rep = ws_max_rep(c.mfma);
     c.tile_stride = ws_tile_stride(c.mfma);
@@ -464,7 +482,7 @@ WsGroup class_group(const GridClass& c, int n_krange) {
   w.rows = c.mfma_rows.as<MRowBlock>();
   w.cols = c.mfma_cols.as<SlotCols>();
   w.wg_rows = c.mfma_wgrows.as<WgRows>();
-  w.n_vox = c.n_vox;
+  w.n_vox = c.slab_vox;
   w.n_wg = c.mfma.n_wg;
   w.n_s = c.geo.n_s;
   w.max_s = c.mfma.max_s;
@@ -518,7 +536,7 @@ ContractArgs contract_args(GridClass& c, double* partial_base) {
   a.n_tasks = (int)c.tiles.task_off.size() - 1;
   a.tri_index = c.tri_index.as<int32_t>();
   a.n_s = c.geo.n_s;
-  a.n_vox = c.n_vox;
+  a.n_vox = c.slab_vox;
   a.n_krange = c.n_krange_vec;
   a.partial = partial_base + c.pv_off;
   a.n_tri = c.n_tri;
@@ -560,6 +578,14 @@ ShellLaunch class_launch(const bispec_plan_s& p, const GridClass& c) {
   return shell_launch(c.pass32, c.shells, c.x_tiles, c.y_off, c.z_off, c.geo.n_s, p.geo.n_g);
 }
 
+// The y and z passes of slab k of a class (x-planes k slab_x .. + slab_planes(k)).
+ShellLaunch slab_of(ShellLaunch L, const GridClass& c, int k) {
+  L.x0 = k * c.slab_x;
+  L.x_end = L.x0 + c.slab_planes(k);
+  L.n_lines = (long long)c.slab_planes(k) * c.spec.g;
+  return L;
+}
+
 size_t max_bytes_env() {
   const char* s = std::getenv("BISPEC_MAX_BYTES");
   if (!s || !*s) return 0;
@@ -581,7 +607,7 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
   for (GridClass& c : p.cls) {
     const int g = c.spec.g;
     ShellPassPlan pp;
-    plan_shell_passes(c.geo, g, true, pp);
+    plan_shell_passes(c.geo, g, true, pp, c.slab_x);   // A2 and the y/z blocks of one slab (a2_64 is that size)
     DevBuf shells, xt, yo, zo, tw;
     HIP_TRY(upload(shells, pp.shells, st));
     HIP_TRY(upload(xt, pp.x_tiles, st));
@@ -589,10 +615,26 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
     HIP_TRY(upload(zo, pp.z_off, st));
     HIP_TRY(upload(tw, twiddles64(g), st));
     ShellLaunch L = shell_launch(pp, shells, xt, yo, zo, c.geo.n_s, p.geo.n_g);
-    HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), L, g, tw.as<double2>(), st));
-    HIP_TRY(launch_contract_fp64(I.as<double>(), contract_args(c, p.partial.as<double>()), st));
-    HIP_TRY(launch_reduce(p.partial.as<double>() + c.pv_off, c.n_krange_vec, c.n_tri, c.n_tri, nullptr, nullptr,
-                          c.tri_out.as<int32_t>(), sums.as<double>(), st));
+    if (c.n_slab == 1) {
+      HIP_TRY(launch_unit_shells(a1.as<double2>(), a2.as<double2>(), I.as<double>(), L, g, tw.as<double2>(), st));
+      HIP_TRY(launch_contract_fp64(I.as<double>(), contract_args(c, p.partial.as<double>()), st));
+      HIP_TRY(launch_reduce(p.partial.as<double>() + c.pv_off, c.n_krange_vec, c.n_tri, c.n_tri, nullptr, nullptr,
+                            c.tri_out.as<int32_t>(), sums.as<double>(), st));
+    } else {
+      // streamed: the x pass once, then per x-slab the y and z passes, the
+      // contraction of the slab's voxels and its sums added in slab order
+      HIP_TRY(launch_inv_x_unit_f64(a1.as<double2>(), L, g, tw.as<double2>(), st));
+      for (int k = 0; k < c.n_slab; ++k) {
+        const ShellLaunch Lk = slab_of(L, c, k);
+        HIP_TRY(launch_inv_y_f64(a1.as<double2>(), a2.as<double2>(), Lk, g, tw.as<double2>(), st));
+        HIP_TRY(launch_c2r_f64(a2.as<double2>(), I.as<double>(), Lk, g, tw.as<double2>(), st));
+        ContractArgs ca = contract_args(c, p.partial.as<double>());
+        ca.n_vox = c.slab_voxels(k);
+        HIP_TRY(launch_contract_fp64(I.as<double>(), ca, st));
+        HIP_TRY(launch_reduce(p.partial.as<double>() + c.pv_off, c.n_krange_vec, c.n_tri, c.n_tri, nullptr, nullptr,
+                              c.tri_out.as<int32_t>(), sums.as<double>(), st, k > 0));
+      }
+    }
     for (int32_t t : c.spec.tri) denom[t] = (double)c.n_vox;
     keep.push_back(std::move(shells));
     keep.push_back(std::move(xt));
@@ -604,20 +646,25 @@ int compute_ntri(bispec_plan_s& p, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(h.data(), sums.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   p.ntri.resize(p.sz.n_tri);
+  // the float64 grid sum of a count of n carries a rounding error of about
+  // 1e-13 n at G = 1024 (unit fields of ~1e6 modes, strong cancellation):
+  // accept |v - round(v)| <= 1e-3 + 4e-12 |v|, far below 1/2 for any count
   double worst = 0.0;
   long long worst_t = -1;
   for (long long t = 0; t < p.sz.n_tri; ++t) {
     const double v = h[t] / denom[t];
     const double r = std::nearbyint(v);
-    if (std::fabs(v - r) > worst) {
-      worst = std::fabs(v - r);
+    const double excess = std::fabs(v - r) - (1e-3 + 4e-12 * std::fabs(v));
+    if (worst_t < 0 || excess > worst) {
+      worst = excess;
       worst_t = t;
     }
     p.ntri[t] = (int64_t)r;
   }
-  if (worst > 1e-3) {
+  if (worst > 0.0) {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "N_tri sum of triangle %lld is %.6f from an integer", worst_t, worst);
+    std::snprintf(buf, sizeof buf, "N_tri sum of triangle %lld is %.6f beyond its rounding tolerance from an integer",
+                  worst_t, worst);
     return set_err(BISPEC_EPREC, buf);
   }
   return BISPEC_OK;
@@ -864,12 +911,58 @@ int run_contract_fp32(bispec_plan_s& p, const RunBufs& w, double* B, hipStream_t
   return BISPEC_OK;
 }
 
+// A streamed pass after the forward transform: per class the x pass once,
+// then per x-slab the y and z passes into the one-slab field buffer, the
+// slab's contraction (split-bf16: one group for a full and one for the last
+// slab; fp32: the vector kernels on the slab's voxels) and its reduction
+// added into B in slab order.
+int run_streamed(bispec_plan_s& p, const RunBufs& w, double* B, hipStream_t s) {
+  for (GridClass& c : p.cls) {
+    const ShellLaunch L = class_launch(p, c);
+    const int g = c.spec.g;
+    HIP_TRY(launch_inv_x_f32(w.spec, w.a1, L, g, c.tw32.as<float2>(), s));
+    for (int k = 0; k < c.n_slab; ++k) {
+      const ShellLaunch Lk = slab_of(L, c, k);
+      HIP_TRY(launch_inv_y_f32(w.a1, w.a2, Lk, g, c.tw32.as<float2>(), s));
+      HIP_TRY(launch_c2r_f32(w.a2, w.F + c.f_off, Lk, g, c.tw32.as<float2>(), s));
+      if (p.precision == BISPEC_PREC_FP32) {
+        ContractArgs ca = contract_args(c, w.partial);
+        ca.n_vox = c.slab_voxels(k);
+        HIP_TRY(launch_contract_fp32(w.F + c.f_off, ca, s));
+        HIP_TRY(launch_reduce(w.partial + c.pv_off, c.n_krange_vec, c.n_tri, c.n_tri, nullptr, p.norm.as<double>(),
+                              c.tri_out.as<int32_t>(), B, s, k > 0));
+      } else {
+        const bool last = k + 1 == c.n_slab && c.slab_planes(k) != c.slab_x;
+        const WsGroup& grp = c.ws_slab_host[last ? 1 : 0];
+        HIP_TRY(launch_contract_bf16x3(w.F, w.partial_mfma, c.ws_slab.as<WsGroup>() + (last ? 1 : 0), 1,
+                                       bf16x3_lds_bytes(grp.max_s, grp.rep), grp.n_wg * grp.n_krange, s));
+        HIP_TRY(launch_reduce(w.partial_mfma + c.pm_off, mfma_ranges(c), (long long)c.tile_stride * kMTileElems,
+                              c.n_tri, c.mfma_slot.as<int32_t>(), p.norm.as<double>(), c.tri_out.as<int32_t>(), B, s,
+                              k > 0));
+      }
+    }
+  }
+  return BISPEC_OK;
+}
+
 // The four stages of one pass; events only when timing (never under capture).
+// A streamed plan interleaves shell passes and contraction per slab: its
+// shell stage then holds both and its contraction stage is empty.
 int run_core(bispec_plan_s& p, const RunBufs& w, const float* delta, double* B, hipStream_t s, bool timing) {
   const int n = p.geo.n_g;
   if (timing) HIP_TRY(hipEventRecord(p.ev[0], s));
   HIP_TRY(launch_forward(delta, w.spec, n, (float)p.geo.beta, p.tw32.as<float2>(), s));
   if (timing) HIP_TRY(hipEventRecord(p.ev[1], s));
+  if (p.slabs > 1) {
+    const int st = run_streamed(p, w, B, s);
+    if (st) return st;
+    if (timing) {
+      HIP_TRY(hipEventRecord(p.ev[2], s));
+      HIP_TRY(hipEventRecord(p.ev[3], s));
+      HIP_TRY(hipEventRecord(p.ev[4], s));
+    }
+    return BISPEC_OK;
+  }
   for (GridClass& c : p.cls)
     HIP_TRY(launch_data_shells(w.spec, w.a1, w.a2, w.F + c.f_off, class_launch(p, c), c.spec.g, c.tw32.as<float2>(),
                                s));
@@ -943,6 +1036,17 @@ int upload_ws_groups(bispec_plan_s& p, hipStream_t s) {
   for (const WsGroup& g : p.ws_host)
     if (!ws_group_ok(g)) return set_err(BISPEC_EINVAL, "a grid class does not fit the split-bf16 kernel");
   HIP_TRY(upload(p.ws_groups, p.ws_host, s));
+  if (p.slabs > 1)
+    for (GridClass& c : p.cls) {
+      // one-group tables of a full slab and of the (shorter) last slab
+      for (int q = 0; q < 2; ++q) {
+        WsGroup w = class_group(c, c.n_krange_mfma);
+        w.n_vox = q == 0 ? c.slab_vox : c.slab_voxels(c.n_slab - 1);
+        if (!ws_group_ok(w)) return set_err(BISPEC_EINVAL, "a slab does not fit the split-bf16 kernel");
+        c.ws_slab_host[q] = w;
+      }
+      HIP_TRY(upload(c.ws_slab, std::vector<WsGroup>(c.ws_slab_host, c.ws_slab_host + 2), s));
+    }
   return BISPEC_OK;
 }
 
@@ -1386,13 +1490,28 @@ int bispec_workspace_bytes(const bispec_config* cfg, int64_t* run_bytes, int64_t
   return BISPEC_OK;
 }
 
+constexpr int kMaxSlabs = 1024;   // at most one x-plane per slab of the largest grid
+
 int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) {
   if (!out) return set_err(BISPEC_EINVAL, "null output");
   *out = nullptr;
-  bispec_plan_s* p = new (std::nothrow) bispec_plan_s();
-  if (!p) return set_err(BISPEC_ENOMEM, "host allocation failed");
-  int st = build_host(cfg, *p);
-  if (st == BISPEC_OK) st = check_memory(p->sz.plan_peak());
+  // x-slabs per grid class: BISPEC_SLABS (at least), doubled while the plan
+  // does not fit the device (whole fields first; streaming keeps one slab)
+  int slabs = 1;
+  if (const char* e = std::getenv("BISPEC_SLABS")) slabs = std::max(1, std::atoi(e));
+  const bool streamable = cfg && cfg->order != 4 && !(cfg->flags & BISPEC_FLAG_GRAD);
+  if (!streamable) slabs = 1;
+  bispec_plan_s* p = nullptr;
+  int st = BISPEC_OK;
+  for (;;) {
+    p = new (std::nothrow) bispec_plan_s();
+    if (!p) return set_err(BISPEC_ENOMEM, "host allocation failed");
+    st = build_host(cfg, *p, slabs);
+    if (st == BISPEC_OK) st = check_memory(p->sz.plan_peak());
+    if (st != BISPEC_ENOMEM || !streamable || slabs >= kMaxSlabs) break;
+    delete p;
+    slabs *= 2;
+  }
   if (st == BISPEC_OK)
     st = p->quad ? plan_build_quad(*p, (hipStream_t)hip_stream) : plan_build(*p, (hipStream_t)hip_stream, nullptr);
   if (st != BISPEC_OK) {
@@ -1400,6 +1519,12 @@ int bispec_plan(const bispec_config* cfg, void* hip_stream, bispec_plan_t* out) 
     return st;
   }
   *out = p;
+  return BISPEC_OK;
+}
+
+int bispec_plan_slabs(bispec_plan_t p, int32_t* slabs) {
+  if (!p || !slabs) return set_err(BISPEC_EINVAL, "null argument");
+  *slabs = p->slabs;
   return BISPEC_OK;
 }
 
@@ -1587,6 +1712,7 @@ int bispec_copy_field(bispec_plan_t p, int32_t shell, float* dst, void* hip_stre
   const GridClass* c = (shell >= 1 && shell <= p->geo.n_s) ? field_class(*p, shell) : nullptr;
   if (!c) return set_err(BISPEC_EINVAL, "shell out of range or used by no selected triangle");
   if (!p->ran) return set_err(BISPEC_ESTATE, "no run recorded");
+  if (p->slabs > 1) return set_err(BISPEC_ESTATE, "a streamed plan keeps one x-slab of its fields");
   HIP_TRY(launch_unblock(p->F.as<float>() + c->f_off, shell - 1 - c->spec.s_lo, c->geo.n_s, c->n_vox, dst,
                          (hipStream_t)hip_stream));
   return BISPEC_OK;
@@ -1599,6 +1725,7 @@ int bispec_copy_class_field(bispec_plan_t p, int32_t cls, int32_t shell, float* 
   if (shell - 1 < c.spec.s_lo || shell - 1 >= c.spec.s_lo + c.spec.n_s)
     return set_err(BISPEC_EINVAL, "the class's fields do not cover this shell");
   if (!p->ran) return set_err(BISPEC_ESTATE, "no run recorded");
+  if (p->slabs > 1) return set_err(BISPEC_ESTATE, "a streamed plan keeps one x-slab of its fields");
   HIP_TRY(launch_unblock(p->F.as<float>() + c.f_off, shell - 1 - c.spec.s_lo, c.geo.n_s, c.n_vox, dst,
                          (hipStream_t)hip_stream));
   return BISPEC_OK;

@@ -711,7 +711,7 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
                                                               const int32_t* __restrict__ slot,
                                                               const double* __restrict__ norm,
                                                               const int32_t* __restrict__ out_idx,
-                                                              double* __restrict__ out) {
+                                                              double* __restrict__ out, int accumulate) {
   __shared__ double part[kRedPart][kRedTri];
   const int tl = threadIdx.x % kRedTri, p = threadIdx.x / kRedTri;
   const long long t = (long long)blockIdx.x * kRedTri + tl;
@@ -727,7 +727,8 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
 #pragma unroll
     for (int q = 0; q < kRedPart; ++q) r += part[q][tl];
     const long long o = out_idx ? out_idx[t] : t;
-    out[o] = norm ? r * norm[o] : r;
+    const double v = norm ? r * norm[o] : r;
+    out[o] = accumulate ? out[o] + v : v;   // accumulate: the slabs of a streamed grid, in order
   }
 }
 
@@ -1240,11 +1241,11 @@ hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, c
 }
 
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
-                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st) {
+                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st, bool accumulate) {
   if (n_tri <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_tri + kRedTri - 1) / kRedTri);
   hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(kRedTri * kRedPart), 0, st, partial, n_krange, stride, n_tri, slot,
-                     norm, out_idx, out);
+                     norm, out_idx, out, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 

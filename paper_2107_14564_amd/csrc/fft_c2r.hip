@@ -13,7 +13,7 @@ static hipError_t c2r(const V2<T>* a2, OutT* out, const ShellLaunch& L, int n, c
 #define BISPEC_CASE(NN)                                                                                        \
   case NN:                                                                                                     \
     hipLaunchKernelGGL((k_c2r_z<T, OutT, NN>), grid, dim3(kThrZ), 0, st, a2, out, L.z_off, L.n_shells, \
-                       L.shells, tw);                                                                     \
+                       L.shells, tw, L.n_lines > 0 ? L.n_lines : (long long)n * n);                  \
     break;
     BISPEC_FOR_EACH_N(BISPEC_CASE)
 #undef BISPEC_CASE

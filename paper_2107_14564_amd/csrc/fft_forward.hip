@@ -65,7 +65,8 @@ hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, c
   }
 }
 
-void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p) {
+void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p, int nx) {
+  if (nx <= 0 || nx > n) nx = n;
   const int twc = fft_tile_cols(n, f64);
   const int nl = fft_z_lines(n / 2, f64);
   p.shells.resize(g.n_s);
@@ -85,13 +86,13 @@ void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p
     d.a1_off = a1;
     d.a2_off = a2;
     a1 += (long long)n * (2 * R + 1) * d.wrow;
-    a2 += (long long)n * n * d.wrow;
+    a2 += (long long)nx * n * d.wrow;
     for (long long ky = -R; ky <= R; ++ky)
       for (long long kz0 = 0; kz0 <= R; kz0 += twc)
         if (ky * ky + kz0 * kz0 < d.hi2) p.x_tiles.push_back(make_int4(sn, (int)ky, (int)kz0, 0));
     const long long n_ct = (R + 1 + twc - 1) / twc;
-    p.y_off.push_back(p.y_off.back() + (long long)n * n_ct);
-    p.z_off.push_back(p.z_off.back() + ((long long)n * n + nl - 1) / nl);
+    p.y_off.push_back(p.y_off.back() + (long long)nx * n_ct);
+    p.z_off.push_back(p.z_off.back() + ((long long)nx * n + nl - 1) / nl);
   }
   p.a1_elems = a1;
   p.a2_elems = a2;

@@ -12,7 +12,8 @@ static hipError_t inv_y(const V2<T>* a1, V2<T>* a2, const ShellLaunch& L, int n,
   switch (n) {
 #define BISPEC_CASE(NN)                                                                                    \
   case NN:                                                                                                 \
-    hipLaunchKernelGGL((k_inv_y<T, NN>), grid, dim3(kThrAxis), 0, st, a1, a2, L.y_off, L.n_shells, L.shells, tw); \
+    hipLaunchKernelGGL((k_inv_y<T, NN>), grid, dim3(kThrAxis), 0, st, a1, a2, L.y_off, L.n_shells, L.shells, tw, \
+                       L.x0, L.x_end > 0 ? L.x_end : n);                                                      \
     break;
     BISPEC_FOR_EACH_N(BISPEC_CASE)
 #undef BISPEC_CASE

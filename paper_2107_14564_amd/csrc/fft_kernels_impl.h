@@ -197,11 +197,15 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ s
 }
 
 // ---- (b) inverse y pass of every shell ----------------------------------------
-// Block -> (shell, x, kz tile) through the per-shell prefix sums tile_off.
+// Block -> (shell, x, kz tile) through the per-shell prefix sums tile_off, for
+// the planes x0 + x < x_end of a slab (x local to the slab: A2 holds the
+// slab's planes; blocks beyond x_end, in a slab shorter than the tables', do
+// nothing).
 template <typename T, int N>
 __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1, V2<T>* __restrict__ a2,
                                                     const long long* __restrict__ tile_off, int n_shells,
-                                                    const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw) {
+                                                    const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw,
+                                                    int x0, int x_end) {
   constexpr int TW = fft_tile_cols(N, sizeof(T) == 8);
   __shared__ V2<T> buf[N * TW];
   __shared__ V2<T> twl[N];
@@ -212,10 +216,11 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1
   const int n_ct = (R + 1 + TW - 1) / TW;
   const long long local = b - tile_off[sn];
   const int x = (int)(local / n_ct);
+  if (x0 + x >= x_end) return;  // uniform over the block, before any barrier
   const int kz0 = (int)(local % n_ct) * TW;
   const int cols = min(TW, R + 1 - kz0);
   const int wy = 2 * R + 1, wz = d.wrow;  // row stride (padded)
-  const V2<T>* src = a1 + d.a1_off + (long long)x * wy * wz;
+  const V2<T>* src = a1 + d.a1_off + (long long)(x0 + x) * wy * wz;
   staged_copy<N * TW, kThrAxis, V2<T>>(
       [&](int e) {
         const int q = e / TW, c = e % TW;
@@ -241,22 +246,24 @@ __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1
 // Per (x, y) line: X_k (k = 0..M, zero beyond R), Z'_k = (X_k + X*_{M-k})
 // + i W_N^{-k} (X_k - X*_{M-k}) for k < M, M-point inverse FFT; the
 // unnormalised real line is (Re z_m, Im z_m) at (2m, 2m+1), written
-// voxel-blocked.  Every shell has N^2 lines, hence the same number of blocks
-// (blk_off[sn] = sn * blocks per shell; the table is not read).
+// voxel-blocked.  Every shell has n_lines lines (N^2, or the lines of an
+// x-slab: its voxels are then numbered from the slab's first), hence the same
+// number of blocks (blk_off[sn] = sn * blocks per shell; the table is not
+// read).
 template <typename T, typename OutT, int N>
 __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, OutT* __restrict__ out,
                                                  const long long* __restrict__ blk_off, int n_shells,
-                                                 const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw) {
+                                                 const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw,
+                                                 long long n_lines) {
   constexpr int M = N / 2;
   constexpr int NL = fft_z_lines(M, sizeof(T) == 8);
   constexpr int LS = M + 1;
   __shared__ V2<T> buf[NL * LS];
   __shared__ V2<T> twl[N];
-  // every shell has the same N^2 lines, so the same number of blocks; the
-  // shell runs fastest, so blocks in flight together write neighbouring
+  // every shell has the same n_lines lines, so the same number of blocks;
+  // the shell runs fastest, so blocks in flight together write neighbouring
   // 128-byte pieces of the same voxel blocks (DRAM pages) instead of one
   // piece per 12.8 KB of the field
-  const long long n_lines = (long long)N * N;
   const long long b = blockIdx.x;
   const int sn = (int)(b % n_shells);
   const ShellDev d = sh[sn];

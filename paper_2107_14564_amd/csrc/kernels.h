@@ -76,6 +76,11 @@ struct ShellLaunch {
   long long n_y_blocks = 0;
   const long long* z_off = nullptr;   // device prefix sums [n_shells + 1]
   long long n_z_blocks = 0;
+  // an x-slab of the grid (0: the whole grid): the y pass takes planes
+  // x0 .. x_end - 1 (A2 and the fields hold only those), the z pass n_lines
+  // lines (the slab's planes times n)
+  int x0 = 0, x_end = 0;
+  long long n_lines = 0;
 };
 
 // host-side description of the shell passes; device arrays are uploaded by the caller
@@ -86,7 +91,8 @@ struct ShellPassPlan {
   long long a1_elems = 0, a2_elems = 0;
 };
 // passes of every shell of g on a grid of n points per side
-void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p);
+// nx: x-planes per slab (A2 and the y and z blocks cover nx planes; 0 = n)
+void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p, int nx = 0);
 
 hipError_t prepare_forward();   // once per plan, before any launch (and before graph capture)
 hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, const float2* tw, hipStream_t st);
@@ -231,8 +237,9 @@ hipError_t launch_fill_random(float* dst, long long n, unsigned long long seed, 
 // dst[0 .. bytes) = 0 with a fill kernel (capture-safe; bytes and dst 16-byte aligned)
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
 // out[o] = norm[o] * sum_k partial[k * stride + (slot ? slot[t] : t)] with o = out_idx ? out_idx[t] : t,
-// for t < n_tri (fixed order, float64; norm may be null)
+// for t < n_tri (fixed order, float64; norm may be null); accumulate: out[o] += that
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
-                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st);
+                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st,
+                         bool accumulate = false);
 
 }  // namespace bispec

@@ -50,6 +50,8 @@ class Plan:
         self.n_tri = len(abc)
         # counts bispec_run calls: the plan's shell fields belong to the last run
         self.runs = 0
+        # x-slabs per grid class (1: whole fields resident; more: streamed)
+        self.slabs = _abi.bispec_plan_slabs(self.handle)
 
     def run(self, delta: torch.Tensor) -> torch.Tensor:
         self._check_field(delta)
