@@ -527,6 +527,56 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt, int max_
       slots.push_back(sl);
     }
   }
+  // Fewer work groups per voxel range: every work group of a range stages its
+  // rows of every voxel block, so a group is worth saving.  While the slots
+  // need one group more than a tighter packing would, merge two slots whose
+  // column sets together span at most kMaxColTiles tiles into one slot shape
+  // the kernel runs (its row blocks then also meet the other's column tiles:
+  // those tiles are computed and never read), fewest wasted tiles first; keep
+  // the merges only if they remove a group.
+  {
+    auto groups_of = [](size_t n) { return (n + kSlotsPerWg - 1) / kSlotsPerWg; };
+    auto tiles_of = [](const Slot& sl) { return sl.sc.n * sl.sc.n_rb; };
+    auto merge = [&](const Slot& a, const Slot& b, Slot& m) {
+      std::set<int> cols(a.sc.col0, a.sc.col0 + a.sc.n);
+      cols.insert(b.sc.col0, b.sc.col0 + b.sc.n);
+      const int nt = (int)cols.size(), nrb = a.sc.n_rb + b.sc.n_rb;
+      if (nt > kMaxColTiles || nrb > kMaxRbPerSlot || nrb > slot_row_blocks(nt) || nt * nrb > kSlotTiles) return false;
+      m = Slot{};
+      m.sc.n = nt;
+      m.sc.n_rb = nrb;
+      int k = 0;
+      for (int c : cols) m.sc.col0[k++] = c;
+      for (int q = 0; q < a.sc.n_rb; ++q) m.rb[q] = a.rb[q];
+      for (int q = 0; q < b.sc.n_rb; ++q) m.rb[a.sc.n_rb + q] = b.rb[q];
+      return true;
+    };
+    const size_t g0 = groups_of(slots.size());
+    if (g0 > 1) {
+      std::vector<Slot> work = slots;
+      const size_t want = (g0 - 1) * kSlotsPerWg;
+      while (work.size() > want) {
+        int bi = -1, bj = -1, best = 1 << 30;
+        Slot bm{};
+        for (size_t i = 0; i < work.size(); ++i)
+          for (size_t j = i + 1; j < work.size(); ++j) {
+            Slot m{};
+            if (!merge(work[i], work[j], m)) continue;
+            const int waste = tiles_of(m) - tiles_of(work[i]) - tiles_of(work[j]);
+            if (waste < best) {
+              best = waste;
+              bi = (int)i;
+              bj = (int)j;
+              bm = m;
+            }
+          }
+        if (bi < 0) break;
+        work[bi] = bm;
+        work.erase(work.begin() + bj);
+      }
+      if (work.size() <= want) slots.swap(work);
+    }
+  }
   // LDS bank conflicts of the row reads: LDS has 128 banks of 4 bytes and
   // serves a 16-byte read for lanes 0-31, then 32-63; lanes 0-31 hold the 16
   // pairs of one row block at two voxel octets.  The kernel keeps each octet
