@@ -767,18 +767,20 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
 // Per chunk the group stages every shell of the class into LDS as
 //   Ff [n_s + 1][128] float32 (row n_s all zero: padding rows of a block), and
 //   Bh, Bl [128][S_row] bf16 hi and lo (shell-contiguous per voxel; the shells
-//   past n_s stay zero), S_row = n_s rounded up to 32, plus 8,
+//   past n_s stay zero, up to the end of any K tile, which reaches at most 31
+//   shells past the last), S_row = n_s + 31 rounded up to 32, plus 8,
 // then each wavefront, for each of its shells n and each row block of n:
 //   acc[vt] (16 rows x 16 voxels of voxel tile vt) = sum over its K tiles of
 //   W_hi F_hi + W_hi F_lo + W_lo F_hi (v_mfma_f32_16x16x32_bf16; W from the
 //   weight buffer, one 16-byte load of hi and of lo per lane per K tile, used
 //   for all eight voxel tiles),
-// and adds acc's rows times F_j (float64) into the shell's sums; the sum over
-// the four row groups of a lane column ends the shell, and lanes 0-15 write
+// and adds acc's rows times F_j (each lane's four rows summed in float32, then
+// added in float64) into the shell's sums; the sum over the four row groups of
+// a lane column ends the shell, and lanes 0-15 write
 // G_n of the chunk.  Every shell n of the class belongs to exactly one
 // wavefront (shells without rows write zeros), so G is written once.
 // ============================================================================
-__host__ __device__ constexpr int adj_spad(int n_s) { return (n_s + kAdjK - 1) / kAdjK * kAdjK; }
+__host__ __device__ constexpr int adj_spad(int n_s) { return (n_s + 31 + kAdjK - 1) / kAdjK * kAdjK; }
 __host__ __device__ constexpr int adj_srow(int n_s) { return adj_spad(n_s) + 8; }
 
 __device__ __forceinline__ int adj_group_of(const AdjGroup* __restrict__ groups, int n_groups, int b) {
@@ -874,7 +876,7 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
       for (int vt = 0; vt < 8; ++vt) sacc[vt] = 0.0;
       for (int r = nn.rb0; r < nn.rb1; ++r) {
         const AdjRowBlock& rb = grp.rbs[r];
-        const int kt0 = rb.kt0, nkt = rb.nkt;
+        const int l8 = rb.l8, nkt = rb.nkt;
         const uint16_t* wt = grp.W + (long long)rb.w_tile * 1024 + lane * 8;
         f32x4 acc[8];
 #pragma unroll
@@ -884,7 +886,7 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
         for (int kt = 0; kt < nkt; ++kt) {
           const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(wt + kt * 1024);
           const bf16x8 alo = *reinterpret_cast<const bf16x8*>(wt + kt * 1024 + 512);
-          const int l0 = (kt0 + kt) * kAdjK + 8 * (lane >> 4);
+          const int l0 = 8 * l8 + kt * kAdjK + 8 * (lane >> 4);
 #pragma unroll
           for (int vt = 0; vt < 8; ++vt) {
             const int vox = vt * 16 + (lane & 15);
@@ -893,13 +895,20 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
             ws_mfma3(ahi, alo, bhi, blo, acc[vt]);
           }
         }
-        // row 4 (lane / 16) + v of the block, voxel lane % 16 of each voxel tile
+        // row 4 (lane / 16) + v of the block, voxel lane % 16 of each voxel tile:
+        // the lane's four rows times F_j, summed in float32, then added in float64
+        const float* fj[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int j = rb.j[4 * (lane >> 4) + v];
-          const float* fj = Ff + (j > 0 ? j - 1 : ns) * kAdjVox + (lane & 15);
+          fj[v] = Ff + (j > 0 ? j - 1 : ns) * kAdjVox + (lane & 15);
+        }
 #pragma unroll
-          for (int vt = 0; vt < 8; ++vt) sacc[vt] += (double)acc[vt][v] * (double)fj[vt * 16];
+        for (int vt = 0; vt < 8; ++vt) {
+          float s = acc[vt][0] * fj[0][vt * 16];
+#pragma unroll
+          for (int v = 1; v < 4; ++v) s = __builtin_fmaf(acc[vt][v], fj[v][vt * 16], s);
+          sacc[vt] += (double)s;
         }
       }
 #pragma unroll

@@ -788,15 +788,15 @@ void build_adjoint_tables(const Selection& sel, const std::vector<int32_t>& tri_
           rb.j[r] = 0;
         }
       }
-      rb.kt0 = (int16_t)((lmin - 1) / kAdjK);
-      rb.nkt = (int16_t)((lmax - 1) / kAdjK - rb.kt0 + 1);
+      rb.l8 = (int16_t)((lmin - 1) / 8);
+      rb.nkt = (int16_t)((lmax - 1 - 8 * rb.l8) / kAdjK + 1);
       rb.w_tile = (int32_t)at.n_tiles;
       at.n_tiles += rb.nkt;
       slot_tris.resize((size_t)at.n_tiles * 512);
       for (int r = 0; r < kAdjRows && r0 + r < rr.size(); ++r) {
         const int j = rr[r0 + r].j;
         for (auto& lt : rows[n][j]) {
-          const int k = (lt.first - 1) - rb.kt0 * kAdjK;   // K index within the block's tiles
+          const int k = (lt.first - 1) - 8 * rb.l8;   // K index within the block's tiles
           const int tile = rb.w_tile + k / kAdjK, kk = k % kAdjK;
           const int lane = r + 16 * (kk / 8), i = kk % 8;
           auto& v = slot_tris[(size_t)tile * 512 + lane * 8 + i];

@@ -188,16 +188,18 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt, int max_
 // G_n(x) = sum_j F_j(x) H_(n,j)(x),  H_(n,j)(x) = sum_l W[(n,j), l] F_l(x), where
 // W[(n,j), l] sums gB_t norm_t over the terms (t; j, l) of d(F_a1 F_a2 F_a3)/dF_n
 // (j the larger of the other two shells).  Rows (n, j) of one n form row blocks
-// of kAdjRows; a row block meets K tiles of kAdjK consecutive shells l (0-based
-// shells 32 kt .. 32 kt + 31).  A K tile's weights sit in the MFMA row-operand
-// layout: slot (tile, lane, i) holds row lane % 16, K index 8 (lane / 16) + i.
+// of kAdjRows; a row block meets nkt K tiles of kAdjK consecutive shells l from
+// an 8-aligned first shell (0-based shells 8 l8 + 32 kt .. 8 l8 + 32 kt + 31,
+// so the tiles end at most 31 shells past the block's last l).  A K tile's
+// weights sit in the MFMA row-operand layout: slot (tile, lane, i) holds row
+// lane % 16, K index 8 (lane / 16) + i.
 constexpr int kAdjRows = 16;
 constexpr int kAdjK = 32;
 constexpr int kAdjWaves = 8;        // wavefronts per work group of the kernel
 struct AdjRowBlock {
   int16_t j[kAdjRows];  // 1-based j of each row, 0 = padding row
   int32_t w_tile;       // first K tile of the block in the weight buffer
-  int16_t kt0, nkt;     // K tiles kt0 .. kt0 + nkt - 1
+  int16_t l8, nkt;      // K tile kt (0 .. nkt - 1) starts at 0-based shell 8 l8 + kAdjK kt
 };
 struct AdjN {
   int32_t n;            // 1-based output shell

@@ -91,13 +91,18 @@ int main(int argc, char** argv) {
           std::printf("class %zu: row block %d tiles out of range\n", ci, r);
           return 1;
         }
+        // the tiles end within 31 shells past the last (the zero padding the kernel stages)
+        if (rb.l8 < 0 || 8 * rb.l8 + kAdjK * rb.nkt > ns + 31) {
+          std::printf("class %zu: row block %d tiles reach past the padded shells\n", ci, r);
+          return 1;
+        }
         for (int row = 0; row < kAdjRows; ++row) {
           const int j = rb.j[row];
           for (int v = 0; v < kVox; ++v) {
             double h = 0.0;
             for (int kt = 0; kt < rb.nkt; ++kt)
               for (int kk = 0; kk < kAdjK; ++kk) {
-                const int l = (rb.kt0 + kt) * kAdjK + kk;   // 0-based shell
+                const int l = 8 * rb.l8 + kt * kAdjK + kk;   // 0-based shell
                 const int lane = row + 16 * (kk / 8), i = kk % 8;
                 const double w = W[(size_t)(rb.w_tile + kt) * 512 + lane * 8 + i];
                 if (l >= ns) {
