@@ -290,7 +290,8 @@ int bispec_destroy(bispec_plan_t plan);
 /* The same estimator over n configurations (any mix of n_g, shells, selection,
  * precision; no BISPEC_FLAG_GRAD), e.g. an ensemble of realisations as in the
  * validation of Section 3.  One shared run workspace sized for the largest
- * member; tables and N_tri per member.  hip_stream as for bispec_plan.
+ * member; tables and N_tri per member; identical consecutive members run as
+ * cohorts (bispec_many_units).  hip_stream as for bispec_plan.
  * Errors: as bispec_plan, plus EINVAL for n < 1 or a GRAD flag. */
 int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bispec_many_t* out);
 
@@ -299,6 +300,15 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
  * results, ordered as bispec_triangles of that member).  delta_off and b_off
  * are host int64 [n + 1]; n (host) receives the member count.  Any may be null. */
 int bispec_many_layout(bispec_many_t batch, int32_t* n, int64_t* delta_off, int64_t* b_off);
+
+/* Launch units of the batch: runs of identical consecutive members (same
+ * configuration, split-bf16, no BISPEC_FLAG_AUTOTUNE; e.g. the realisations of
+ * an ensemble) form cohorts whose forward transforms, shell passes and
+ * reductions run as one launch per pass for all their members (cohorts are
+ * split so their per-member spectra and pass intermediates stay within 8 GiB);
+ * every other member is a unit of its own.  n_units (host) receives the number
+ * of units, n_cohort_members (may be null) the number of members in cohorts. */
+int bispec_many_units(bispec_many_t batch, int32_t* n_units, int32_t* n_cohort_members);
 
 /* Member i as a plan handle for bispec_num_triangles / bispec_triangles /
  * bispec_stage_times queries (owned by the batch: never bispec_destroy it). */

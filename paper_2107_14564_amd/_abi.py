@@ -76,6 +76,7 @@ def lib() -> C.CDLL:
             "bispec_plan_many": [cfgp, I32, P, C.POINTER(P)],
             "bispec_many_layout": [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64)],
             "bispec_many_plan": [P, I32, C.POINTER(P)],
+            "bispec_many_units": [P, C.POINTER(I32), C.POINTER(I32)],
             "bispec_run_many": [P, P, P, I32, P],
             "bispec_destroy_many": [P],
         }
@@ -300,6 +301,13 @@ def bispec_many_layout(batch: int):
     b = (C.c_int64 * (n.value + 1))()
     _check(lib().bispec_many_layout(C.c_void_p(batch), None, d, b), "bispec_many_layout")
     return list(d), list(b)
+
+
+def bispec_many_units(batch: int):
+    """(launch units, members in cohorts) of a batch."""
+    u, c = C.c_int32(0), C.c_int32(0)
+    _check(lib().bispec_many_units(C.c_void_p(batch), C.byref(u), C.byref(c)), "bispec_many_units")
+    return u.value, c.value
 
 
 def bispec_many_plan(batch: int, i: int) -> int:

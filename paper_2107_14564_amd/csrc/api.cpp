@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -235,6 +236,18 @@ struct bispec_many_s {
   int ws_n = 0, ws_blocks = 0;
   size_t ws_lds = 0;
   hipEvent_t ev_mid = nullptr;         // the grouped contraction is done
+  // cohorts: runs of m >= 2 consecutive identical split-bf16 members (the
+  // realisations of one configuration) whose forward transforms, shell passes
+  // and reductions run as one launch each (grid y = member), with a spectrum
+  // and pass intermediates per member; units are the cohorts and the members
+  // outside any, in member order, each run on one lane
+  struct Unit {
+    int i0 = 0, m = 1;                 // members i0 .. i0 + m - 1
+    DevBuf spec, a1, a2;               // m > 1: per member, at m times the strides below
+    size_t spec_b = 0, a1_b = 0, a2_b = 0;
+  };
+  std::vector<std::unique_ptr<Unit>> units;
+  std::vector<int> unit_lane;
   ~bispec_many_s();
 };
 
@@ -996,16 +1009,55 @@ int run_core(bispec_plan_s& p, const RunBufs& w, const float* delta, double* B, 
 // fp32 members, its contraction and reductions) on its lane; then one grouped
 // split-bf16 contraction of every split member's classes on s; then the split
 // members' reductions on the lanes again.
+// A cohort's forward transforms and shell passes: one launch per pass for all
+// its members (the tables of its first member serve all of them).
+int run_fields_cohort(bispec_many_s& m, const bispec_many_s::Unit& u, const float* delta, hipStream_t s) {
+  bispec_plan_s& p = *m.plans[u.i0];
+  const long long n = p.geo.n_g;
+  const long long spec_el = (long long)(u.spec_b / sizeof(float2));
+  HIP_TRY(launch_forward(delta + m.d_off[u.i0], u.spec.as<float2>(), (int)n, (float)p.geo.beta, p.tw32.as<float2>(),
+                         s, u.m, n * n * n, spec_el));
+  for (GridClass& c : p.cls) {
+    ShellLaunch L = class_launch(p, c);
+    L.n_members = u.m;
+    L.spec_stride = spec_el;
+    L.a1_stride = (long long)(u.a1_b / sizeof(float2));
+    L.a2_stride = (long long)(u.a2_b / sizeof(float2));
+    L.f_stride = (long long)((m.f_at[u.i0 + 1] - m.f_at[u.i0]) / sizeof(float));
+    HIP_TRY(launch_data_shells(u.spec.as<float2>(), u.a1.as<float2>(), u.a2.as<float2>(), p.F.as<float>() + c.f_off,
+                               L, c.spec.g, c.tw32.as<float2>(), s));
+  }
+  return BISPEC_OK;
+}
+
+// A cohort's reductions of its split-bf16 partials: one launch per class.
+int run_reduce_cohort(bispec_many_s& m, const bispec_many_s::Unit& u, double* B, hipStream_t s) {
+  bispec_plan_s& p = *m.plans[u.i0];
+  const long long pm_el = (long long)((m.pm_at[u.i0 + 1] - m.pm_at[u.i0]) / sizeof(double));
+  const long long b_el = m.b_off[u.i0 + 1] - m.b_off[u.i0];
+  for (GridClass& c : p.cls)
+    HIP_TRY(launch_reduce(p.partial_mfma.as<double>() + c.pm_off, mfma_ranges(c),
+                          (long long)c.tile_stride * kMTileElems, c.n_tri, c.mfma_slot.as<int32_t>(),
+                          p.norm.as<double>(), c.tri_out.as<int32_t>(), B + m.b_off[u.i0], s, false, u.m, pm_el, b_el));
+  return BISPEC_OK;
+}
+
 int many_enqueue(bispec_many_s& m, const float* delta, double* B, hipStream_t s) {
   HIP_TRY(hipEventRecord(m.ev_fork, s));
   for (ManyLane* l : m.lanes) HIP_TRY(hipStreamWaitEvent(l->stream, m.ev_fork, 0));
-  for (size_t i = 0; i < m.plans.size(); ++i) {
-    bispec_plan_s& p = *m.plans[i];
-    const hipStream_t ls = m.lanes[m.lane_of[i]]->stream;
-    int st = run_fields(p, own_bufs(p), delta + m.d_off[i], ls);
-    if (!st && p.precision == BISPEC_PREC_FP32) st = run_contract_fp32(p, own_bufs(p), B + m.b_off[i], ls);
-    if (st) return st;
-    p.ran = true;
+  for (size_t k = 0; k < m.units.size(); ++k) {
+    const bispec_many_s::Unit& u = *m.units[k];
+    const hipStream_t ls = m.lanes[m.unit_lane[k]]->stream;
+    if (u.m > 1) {
+      const int st = run_fields_cohort(m, u, delta, ls);
+      if (st) return st;
+    } else {
+      bispec_plan_s& p = *m.plans[u.i0];
+      int st = run_fields(p, own_bufs(p), delta + m.d_off[u.i0], ls);
+      if (!st && p.precision == BISPEC_PREC_FP32) st = run_contract_fp32(p, own_bufs(p), B + m.b_off[u.i0], ls);
+      if (st) return st;
+    }
+    for (int i = u.i0; i < u.i0 + u.m; ++i) m.plans[i]->ran = true;
   }
   for (ManyLane* l : m.lanes) {
     HIP_TRY(hipEventRecord(l->ev_join, l->stream));
@@ -1016,10 +1068,12 @@ int many_enqueue(bispec_many_s& m, const float* delta, double* B, hipStream_t s)
                                    m.ws_lds, m.ws_blocks, s));
     HIP_TRY(hipEventRecord(m.ev_mid, s));
     for (ManyLane* l : m.lanes) HIP_TRY(hipStreamWaitEvent(l->stream, m.ev_mid, 0));
-    for (size_t i = 0; i < m.plans.size(); ++i) {
-      bispec_plan_s& p = *m.plans[i];
+    for (size_t k = 0; k < m.units.size(); ++k) {
+      const bispec_many_s::Unit& u = *m.units[k];
+      bispec_plan_s& p = *m.plans[u.i0];
       if (p.precision == BISPEC_PREC_FP32) continue;
-      int st = run_reduce_mfma(p, own_bufs(p), B + m.b_off[i], m.lanes[m.lane_of[i]]->stream);
+      const hipStream_t ls = m.lanes[m.unit_lane[k]]->stream;
+      const int st = u.m > 1 ? run_reduce_cohort(m, u, B, ls) : run_reduce_mfma(p, own_bufs(p), B + m.b_off[u.i0], ls);
       if (st) return st;
     }
     for (ManyLane* l : m.lanes) {
@@ -1790,7 +1844,63 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
     for (const GridClass& k : p->cls) c += (double)k.n_vox * k.geo.n_s;
     cost[i] = c;
   }
-  // lanes: as many concurrent workspaces as members, kMaxLanes and memory allow
+  // units: cohorts of identical consecutive members (split-bf16, no autotuning:
+  // their tables are then equal) in chunks within kCohortBytes of per-member
+  // spectra and pass intermediates, and the other members one by one
+  auto r256 = [](size_t v) { return (v + 255) / 256 * 256; };
+  auto same = [&](int a, int b) {
+    const bispec_config &x = cfgs[a], &y = cfgs[b];
+    const bispec_plan_s &pa = *m->plans[a], &pb = *m->plans[b];
+    if (pa.precision != BISPEC_PREC_SPLITBF16 || pb.precision != BISPEC_PREC_SPLITBF16) return false;
+    if (((x.flags | y.flags) & BISPEC_FLAG_AUTOTUNE) || x.flags != y.flags || pa.slabs != 1 || pb.slabs != 1)
+      return false;
+    if (x.n_g != y.n_g || x.n_shells != y.n_shells || x.box_l != y.box_l || x.dk != y.dk ||
+        x.rsd_beta != y.rsd_beta || x.n_est != y.n_est || x.ell != y.ell)
+      return false;
+    if (pa.sel.tri.size() != pb.sel.tri.size() || pa.cls.size() != pb.cls.size()) return false;
+    for (size_t k = 0; k < pa.sel.tri.size(); ++k) {
+      const Tri &u = pa.sel.tri[k], &v = pb.sel.tri[k];
+      if (u.a1 != v.a1 || u.a2 != v.a2 || u.a3 != v.a3) return false;
+    }
+    for (size_t k = 0; k < pa.cls.size(); ++k)
+      if (pa.cls[k].spec.g != pb.cls[k].spec.g || pa.cls[k].spec.s_lo != pb.cls[k].spec.s_lo ||
+          pa.cls[k].spec.n_s != pb.cls[k].spec.n_s || pa.cls[k].spec.tri != pb.cls[k].spec.tri)
+        return false;
+    return pa.sz.spec == pb.sz.spec && pa.sz.a1_32 == pb.sz.a1_32 && pa.sz.a2_32 == pb.sz.a2_32 &&
+           pa.sz.fields32 == pb.sz.fields32 && pa.sz.partial_mfma == pb.sz.partial_mfma;
+  };
+  constexpr size_t kCohortBytes = 8ULL << 30;
+  constexpr int kCohortMax = 1024;
+  auto make_units = [&](bool cohorts) {
+    m->units.clear();
+    size_t bytes = 0;
+    for (int i = 0; i < n;) {
+      int j = i + 1;
+      if (cohorts)
+        while (j < n && same(i, j)) ++j;
+      const Sizes& z = m->plans[i]->sz;
+      const size_t per = r256(z.spec) + r256(z.a1_32) + r256(z.a2_32);
+      const int chunk = (int)std::max<size_t>(1, std::min<size_t>(kCohortMax, kCohortBytes / std::max<size_t>(1, per)));
+      for (int k = i; k < j; k += chunk) {
+        std::unique_ptr<bispec_many_s::Unit> u(new (std::nothrow) bispec_many_s::Unit());
+        if (!u) return (size_t)-1;
+        u->i0 = k;
+        u->m = std::min(chunk, j - k);
+        if (u->m > 1) {
+          u->spec_b = r256(z.spec);
+          u->a1_b = r256(z.a1_32);
+          u->a2_b = r256(z.a2_32);
+          bytes += (size_t)u->m * per;
+        }
+        m->units.push_back(std::move(u));
+      }
+      i = j;
+    }
+    return bytes;
+  };
+  size_t cohort_bytes = make_units(true);
+  if (cohort_bytes == (size_t)-1) return fail(set_err(BISPEC_ENOMEM, "host allocation failed"));
+  // lanes: as many concurrent workspaces as units, kMaxLanes and memory allow
   const size_t lane_bytes = ws_spec + ws_a1 + ws_a2 + ws_pv;
   size_t free_b = 0, total_b = 0;
   {
@@ -1799,22 +1909,42 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
   }
   const size_t cap = max_bytes_env();
   const size_t avail = cap ? std::min(free_b, cap) : free_b;
-  int n_lanes = std::min<int>(kMaxLanes, n);
-  while (n_lanes > 1 && (size_t)n_lanes * lane_bytes + f_total + pm_total + tables + temp > avail) --n_lanes;
-  int st = check_memory((size_t)n_lanes * lane_bytes + f_total + pm_total + tables + temp);
+  const size_t fixed = f_total + pm_total + tables + temp;
+  int n_lanes = std::min<int>(kMaxLanes, (int)m->units.size());
+  while (n_lanes > 1 && (size_t)n_lanes * lane_bytes + cohort_bytes + fixed > avail) --n_lanes;
+  if (cohort_bytes > 0 && lane_bytes + cohort_bytes + fixed > avail) {
+    cohort_bytes = make_units(false);   // no room for per-member workspaces: members one by one
+    if (cohort_bytes == (size_t)-1) return fail(set_err(BISPEC_ENOMEM, "host allocation failed"));
+    n_lanes = std::min<int>(kMaxLanes, (int)m->units.size());
+    while (n_lanes > 1 && (size_t)n_lanes * lane_bytes + fixed > avail) --n_lanes;
+  }
+  int st = check_memory((size_t)n_lanes * lane_bytes + cohort_bytes + fixed);
   if (st) return fail(st);
-  // members to lanes: longest first onto the least-loaded lane
+  // units to lanes: costliest first onto the least-loaded lane
   {
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    const int n_units = (int)m->units.size();
+    std::vector<double> ucost(n_units, 0.0);
+    for (int k = 0; k < n_units; ++k)
+      for (int i = m->units[k]->i0; i < m->units[k]->i0 + m->units[k]->m; ++i) ucost[k] += cost[i];
+    std::vector<int> order(n_units);
+    for (int k = 0; k < n_units; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ucost[x] > ucost[y]; });
     std::vector<double> load(n_lanes, 0.0);
+    m->unit_lane.assign(n_units, 0);
     m->lane_of.assign(n, 0);
-    for (int i : order) {
-      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      m->lane_of[i] = k;
-      load[k] += cost[i];
+    for (int k : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      m->unit_lane[k] = l;
+      load[l] += ucost[k];
+      for (int i = m->units[k]->i0; i < m->units[k]->i0 + m->units[k]->m; ++i) m->lane_of[i] = l;
     }
+  }
+  for (auto& u : m->units) {
+    if (u->m < 2) continue;
+    hipError_t e = dalloc(u->spec, (size_t)u->m * u->spec_b);
+    if (e == hipSuccess) e = dalloc(u->a1, (size_t)u->m * u->a1_b);
+    if (e == hipSuccess) e = dalloc(u->a2, (size_t)u->m * u->a2_b);
+    if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("batch cohort: ") + hipGetErrorString(e)));
   }
   for (int k = 0; k < n_lanes; ++k) {
     ManyLane* l = new (std::nothrow) ManyLane();
@@ -1875,6 +2005,18 @@ int bispec_many_layout(bispec_many_t m, int32_t* n, int64_t* delta_off, int64_t*
   for (size_t i = 0; i < m->d_off.size(); ++i) {
     if (delta_off) delta_off[i] = m->d_off[i];
     if (b_off) b_off[i] = m->b_off[i];
+  }
+  return BISPEC_OK;
+}
+
+int bispec_many_units(bispec_many_t m, int32_t* n_units, int32_t* n_cohort_members) {
+  if (!m || !n_units) return set_err(BISPEC_EINVAL, "bad argument");
+  *n_units = (int32_t)m->units.size();
+  if (n_cohort_members) {
+    int32_t c = 0;
+    for (const auto& u : m->units)
+      if (u->m > 1) c += u->m;
+    *n_cohort_members = c;
   }
   return BISPEC_OK;
 }

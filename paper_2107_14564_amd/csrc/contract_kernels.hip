@@ -711,7 +711,10 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
                                                               const int32_t* __restrict__ slot,
                                                               const double* __restrict__ norm,
                                                               const int32_t* __restrict__ out_idx,
-                                                              double* __restrict__ out, int accumulate) {
+                                                              double* __restrict__ out, int accumulate,
+                                                              long long p_stride, long long out_stride) {
+  partial += blockIdx.y * p_stride;   // member of a cohort (grid y)
+  out += blockIdx.y * out_stride;
   __shared__ double part[kRedPart][kRedTri];
   const int tl = threadIdx.x % kRedTri, p = threadIdx.x / kRedTri;
   const long long t = (long long)blockIdx.x * kRedTri + tl;
@@ -1250,11 +1253,13 @@ hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, c
 }
 
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
-                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st, bool accumulate) {
+                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st, bool accumulate,
+                         int members, long long p_stride, long long out_stride) {
   if (n_tri <= 0) return hipSuccess;
+  if (members < 1) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)((n_tri + kRedTri - 1) / kRedTri);
-  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(kRedTri * kRedPart), 0, st, partial, n_krange, stride, n_tri, slot,
-                     norm, out_idx, out, accumulate ? 1 : 0);
+  hipLaunchKernelGGL(k_reduce, dim3(blocks, (unsigned)members), dim3(kRedTri * kRedPart), 0, st, partial, n_krange,
+                     stride, n_tri, slot, norm, out_idx, out, accumulate ? 1 : 0, p_stride, out_stride);
   return hipGetLastError();
 }
 

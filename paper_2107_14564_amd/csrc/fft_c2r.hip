@@ -8,12 +8,12 @@ using namespace fftk;
 template <typename T, typename OutT>
 static hipError_t c2r(const V2<T>* a2, OutT* out, const ShellLaunch& L, int n, const V2<T>* tw, hipStream_t st) {
   if (L.n_z_blocks <= 0) return hipSuccess;
-  const dim3 grid((unsigned)L.n_z_blocks);
+  const dim3 grid((unsigned)L.n_z_blocks, (unsigned)L.n_members);
   switch (n) {
 #define BISPEC_CASE(NN)                                                                                        \
   case NN:                                                                                                     \
     hipLaunchKernelGGL((k_c2r_z<T, OutT, NN>), grid, dim3(kThrZ), 0, st, a2, out, L.z_off, L.n_shells, \
-                       L.shells, tw, L.n_lines > 0 ? L.n_lines : (long long)n * n);                  \
+                       L.shells, tw, L.n_lines > 0 ? L.n_lines : (long long)n * n, L.a2_stride, L.f_stride); \
     break;
     BISPEC_FOR_EACH_N(BISPEC_CASE)
 #undef BISPEC_CASE

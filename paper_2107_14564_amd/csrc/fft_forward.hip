@@ -9,25 +9,27 @@ using namespace fftk;
 namespace {
 
 template <int N>
-hipError_t forward_n(const float* delta, float2* spec, float beta, const float2* tw, hipStream_t st) {
+hipError_t forward_n(const float* delta, float2* spec, float beta, const float2* tw, hipStream_t st, int members,
+                     long long delta_stride, long long spec_stride) {
   constexpr int M = N / 2;
   const float axis_scale = 1.0f / sqrtf((float)N);  // unitary overall: N^{-3/2}
   {
     constexpr int NL = fft_z_lines(M, false);
     const long long n_lines = (long long)N * N;
     const unsigned blocks = (unsigned)((n_lines + NL - 1) / NL);
-    hipLaunchKernelGGL(k_r2c_z<N>, dim3(blocks), dim3(kThrZ), 0, st, delta, spec, tw, axis_scale);
+    hipLaunchKernelGGL(k_r2c_z<N>, dim3(blocks, members), dim3(kThrZ), 0, st, delta, spec, tw, axis_scale,
+                       delta_stride, spec_stride);
   }
   constexpr int TW = fwd_tile_cols(N);
   constexpr unsigned kLds = fwd_dyn_lds(N);
   const int n_ct = (M + 1 + TW - 1) / TW;
   // y: lines [x][.][kz], stride P = spec_row(N), planes x
   constexpr long long P = spec_row(N);
-  hipLaunchKernelGGL(k_fft_axis<N>, dim3(N * n_ct), dim3(kThrAxis), kLds, st, spec, P, M + 1, (long long)N * P, tw,
-                     -1.0f, axis_scale, 0, 0.0f);
+  hipLaunchKernelGGL(k_fft_axis<N>, dim3(N * n_ct, members), dim3(kThrAxis), kLds, st, spec, P, M + 1, (long long)N * P,
+                     tw, -1.0f, axis_scale, 0, 0.0f, spec_stride);
   // x: lines [.][ky][kz], stride N P, planes ky; RSD factor applied here
-  hipLaunchKernelGGL(k_fft_axis<N>, dim3(N * n_ct), dim3(kThrAxis), kLds, st, spec, (long long)N * P, M + 1, P, tw,
-                     -1.0f, axis_scale, beta != 0.0f ? 1 : 0, beta);
+  hipLaunchKernelGGL(k_fft_axis<N>, dim3(N * n_ct, members), dim3(kThrAxis), kLds, st, spec, (long long)N * P, M + 1, P,
+                     tw, -1.0f, axis_scale, beta != 0.0f ? 1 : 0, beta, spec_stride);
   return hipGetLastError();
 }
 
@@ -55,10 +57,12 @@ hipError_t prepare_forward() {
   return e;
 }
 
-hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, const float2* tw, hipStream_t st) {
+hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, const float2* tw, hipStream_t st,
+                          int members, long long delta_stride, long long spec_stride) {
+  if (members < 1) return hipErrorInvalidValue;
   switch (n) {
 #define BISPEC_CASE(NN) \
-  case NN: return forward_n<NN>(delta, spec, beta, tw, st);
+  case NN: return forward_n<NN>(delta, spec, beta, tw, st, members, delta_stride, spec_stride);
     BISPEC_FOR_EACH_N(BISPEC_CASE)
 #undef BISPEC_CASE
     default: return hipErrorInvalidValue;

@@ -9,11 +9,12 @@ template <typename T, bool UNIT>
 static hipError_t inv_x(const float2* spec, V2<T>* a1, const ShellLaunch& L, int n, const V2<T>* tw,
                         hipStream_t st) {
   if (L.n_x_tiles <= 0) return hipSuccess;
-  const dim3 grid((unsigned)L.n_x_tiles);
+  const dim3 grid((unsigned)L.n_x_tiles, (unsigned)L.n_members);
   switch (n) {
 #define BISPEC_CASE(NN)                                                                                     \
   case NN:                                                                                                  \
-    hipLaunchKernelGGL((k_inv_x<T, UNIT, NN>), grid, dim3(kThrAxis), 0, st, spec, L.spec_n, a1, L.x_tiles, L.shells, tw); \
+    hipLaunchKernelGGL((k_inv_x<T, UNIT, NN>), grid, dim3(kThrAxis), 0, st, spec, L.spec_n, a1, L.x_tiles, L.shells, tw, \
+                       L.spec_stride, L.a1_stride);                                                        \
     break;
     BISPEC_FOR_EACH_N(BISPEC_CASE)
 #undef BISPEC_CASE

@@ -25,6 +25,11 @@
 //
 // Strided passes stage a tile of TW consecutive kz columns times the whole
 // line in LDS (interleaved layout); contiguous passes stage whole lines.
+//
+// Cohorts: every pass also runs several identical problems in one launch
+// (realisations of one configuration): blockIdx.y is the member, whose input
+// and output sit at blockIdx.y times the given element strides (0 and one
+// member for a single problem).
 #pragma once
 
 #include "fft_core.h"
@@ -68,7 +73,10 @@ __device__ __forceinline__ void stage_twiddles(V2<T>* twl, const V2<T>* __restri
 // then X_k = (Z_k + Z*_{M-k})/2 + W_N^k (Z_k - Z*_{M-k})/(2i), k = 0..M.
 template <int N>
 __global__ void __launch_bounds__(kThrZ) k_r2c_z(const float* __restrict__ in, float2* __restrict__ out,
-                                                 const float2* __restrict__ tw, float scale) {
+                                                 const float2* __restrict__ tw, float scale, long long in_stride,
+                                                 long long out_stride) {
+  in += blockIdx.y * in_stride;
+  out += blockIdx.y * out_stride;
   constexpr int M = N / 2;
   constexpr int NL = fft_z_lines(M, false);
   constexpr int LS = M + 1;
@@ -110,7 +118,9 @@ __global__ void __launch_bounds__(kThrZ) k_r2c_z(const float* __restrict__ in, f
 template <int N>
 __global__ void __launch_bounds__(kThrAxis) k_fft_axis(float2* __restrict__ data, long long stride, int n_cols,
                                                        long long outer_stride, const float2* __restrict__ tw,
-                                                       float sign, float scale, int rsd_pass, float beta) {
+                                                       float sign, float scale, int rsd_pass, float beta,
+                                                       long long m_stride) {
+  data += blockIdx.y * m_stride;
   constexpr int TW = fwd_tile_cols(N);
   constexpr bool kDyn = fwd_dyn_lds(N) > 0;
   __shared__ float2 sbuf[kDyn ? 1 : N * TW];
@@ -149,7 +159,10 @@ __global__ void __launch_bounds__(kThrAxis) k_fft_axis(float2* __restrict__ data
 template <typename T, bool UNIT, int N>
 __global__ void __launch_bounds__(kThrAxis) k_inv_x(const float2* __restrict__ spec, int spec_n,
                                                     V2<T>* __restrict__ a1, const int4* __restrict__ tiles,
-                                                    const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw) {
+                                                    const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw,
+                                                    long long spec_stride, long long a1_stride) {
+  if (spec) spec += blockIdx.y * spec_stride;
+  a1 += blockIdx.y * a1_stride;
   constexpr int TW = fft_tile_cols(N, sizeof(T) == 8);
   __shared__ V2<T> buf[N * TW];
   __shared__ V2<T> twl[N];
@@ -205,7 +218,9 @@ template <typename T, int N>
 __global__ void __launch_bounds__(kThrAxis) k_inv_y(const V2<T>* __restrict__ a1, V2<T>* __restrict__ a2,
                                                     const long long* __restrict__ tile_off, int n_shells,
                                                     const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw,
-                                                    int x0, int x_end) {
+                                                    int x0, int x_end, long long a1_stride, long long a2_stride) {
+  a1 += blockIdx.y * a1_stride;
+  a2 += blockIdx.y * a2_stride;
   constexpr int TW = fft_tile_cols(N, sizeof(T) == 8);
   __shared__ V2<T> buf[N * TW];
   __shared__ V2<T> twl[N];
@@ -254,7 +269,9 @@ template <typename T, typename OutT, int N>
 __global__ void __launch_bounds__(kThrZ) k_c2r_z(const V2<T>* __restrict__ a2, OutT* __restrict__ out,
                                                  const long long* __restrict__ blk_off, int n_shells,
                                                  const ShellDev* __restrict__ sh, const V2<T>* __restrict__ tw,
-                                                 long long n_lines) {
+                                                 long long n_lines, long long a2_stride, long long out_stride) {
+  a2 += blockIdx.y * a2_stride;
+  out += blockIdx.y * out_stride;
   constexpr int M = N / 2;
   constexpr int NL = fft_z_lines(M, sizeof(T) == 8);
   constexpr int LS = M + 1;

@@ -81,6 +81,10 @@ struct ShellLaunch {
   // lines (the slab's planes times n)
   int x0 = 0, x_end = 0;
   long long n_lines = 0;
+  // a cohort of identical problems in one launch (grid y = member): member m's
+  // spectrum, A1, A2 and fields at m times these element strides
+  int n_members = 1;
+  long long spec_stride = 0, a1_stride = 0, a2_stride = 0, f_stride = 0;
 };
 
 // host-side description of the shell passes; device arrays are uploaded by the caller
@@ -95,7 +99,10 @@ struct ShellPassPlan {
 void plan_shell_passes(const ShellGeometry& g, int n, bool f64, ShellPassPlan& p, int nx = 0);
 
 hipError_t prepare_forward();   // once per plan, before any launch (and before graph capture)
-hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, const float2* tw, hipStream_t st);
+// members > 1: a cohort of identical problems, member m at delta + m delta_stride
+// and spec + m spec_stride (elements)
+hipError_t launch_forward(const float* delta, float2* spec, int n, float beta, const float2* tw, hipStream_t st,
+                          int members = 1, long long delta_stride = 0, long long spec_stride = 0);
 // the three inverse passes of every shell (fft_inv_x.hip, fft_inv_y.hip, fft_c2r.hip)
 hipError_t launch_inv_x_f32(const float2* spec, float2* a1, const ShellLaunch& L, int n, const float2* tw,
                             hipStream_t st);
@@ -237,9 +244,10 @@ hipError_t launch_fill_random(float* dst, long long n, unsigned long long seed, 
 // dst[0 .. bytes) = 0 with a fill kernel (capture-safe; bytes and dst 16-byte aligned)
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
 // out[o] = norm[o] * sum_k partial[k * stride + (slot ? slot[t] : t)] with o = out_idx ? out_idx[t] : t,
-// for t < n_tri (fixed order, float64; norm may be null); accumulate: out[o] += that
+// for t < n_tri (fixed order, float64; norm may be null); accumulate: out[o] += that.
+// members > 1: a cohort, member m reading partial + m p_stride and writing out + m out_stride
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
                          const double* norm, const int32_t* out_idx, double* out, hipStream_t st,
-                         bool accumulate = false);
+                         bool accumulate = false, int members = 1, long long p_stride = 0, long long out_stride = 0);
 
 }  // namespace bispec

@@ -174,6 +174,8 @@ class BatchPlan:
             self.triangles.append(torch.tensor(abc, dtype=torch.int32))
             self.ntri.append(torch.tensor(ntri, dtype=torch.int64))
         self.n_tri = self.b_off[-1]
+        # launch units: cohorts of identical consecutive members and single members
+        self.n_units, self.n_cohort_members = _abi.bispec_many_units(self.handle)
 
     def pack(self, deltas) -> torch.Tensor:
         """One contiguous float32 device buffer of the members' fields."""

@@ -100,6 +100,45 @@ def test_batch_members_match_single_plans():
     bp.close()
 
 
+def test_batch_cohorts():
+    """Identical consecutive members form cohorts (one launch per pass for all of
+    them, each member at its own strides): a batch A A A B A A has the units
+    (A A A), B, (A A); every member computes exactly what the same plan alone
+    computes on its field, graph replays equal direct launches, and the last
+    member of each cohort matches the oracle."""
+    import torch
+    import paper_2107_14564_amd as P
+    a = dict(n_g=48, box_l=200.0, dk=1.0, n_shells=12, rsd_beta=0.5)
+    b = dict(n_g=32, box_l=300.0, dk=1.0, n_shells=10, rsd_beta=0.0)
+    cfgs = [a, a, a, b, a, a]
+    bp = P.BatchPlan(cfgs)
+    say("cohort batch: %d units, %d members in cohorts" % (bp.n_units, bp.n_cohort_members))
+    assert (bp.n_units, bp.n_cohort_members) == (3, 5)
+    fields = [quadratic_ng_field(gaussian_field(c["n_g"], c["box_l"], PowerLaw(-1.0), 300 + i), 1.0)
+              .astype(np.float32) for i, c in enumerate(cfgs)]
+    packed = bp.pack([torch.from_numpy(f) for f in fields])
+    b_eager = bp.run(packed, use_graph=False).cpu().numpy()
+    b_graph = bp.run(packed, use_graph=True).cpu().numpy()
+    assert np.array_equal(b_graph, b_eager)
+    for i, c in enumerate(cfgs):
+        c = dict(c)
+        plan = P.Plan(c.pop("n_g"), c.pop("box_l"), c.pop("dk"), c.pop("n_shells"), **c)
+        single = plan.run(torch.from_numpy(fields[i]).cuda()).cpu().numpy()
+        got = b_eager[bp.b_off[i]:bp.b_off[i + 1]]
+        say("  member %d max |batch - single| = %.3g" % (i, float(np.max(np.abs(got - single)))))
+        assert np.array_equal(single, got), i
+        plan.close()
+    for i in (2, 5):
+        c = cfgs[i]
+        ref = fbe.estimate(fields[i].astype(np.float64), c["box_l"], c["dk"], bp.triangles[i].numpy(),
+                           rsd_beta=c["rsd_beta"], with_abs=True)
+        mt = metrics(b_eager[bp.b_off[i]:bp.b_off[i + 1]], ref["B"], ref["S"])
+        say("  member %d vs oracle %s" % (i, mt))
+        assert np.array_equal(bp.ntri[i].numpy(), ref["ntri"])
+        assert mt["e_cond"] <= TOL and mt["e_norm"] <= TOL
+    bp.close()
+
+
 def test_autotuned_plan(tmp_path, monkeypatch):
     """FLAG_AUTOTUNE picks each grid class's column-tile window and voxel-range
     count by timing; results stay within tolerance.  With BISPEC_TUNE_CACHE set,
