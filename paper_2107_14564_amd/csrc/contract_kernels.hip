@@ -766,17 +766,18 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
 // ============================================================================
 // Adjoint field build on the matrix cores (kernels.h): for every grid class,
 // work group (wg, kr) holds the output shells n of its wavefronts and walks
-// the voxel chunks kr, kr + n_krange, ... of 128 voxels (four voxel blocks).
-// Per chunk the group stages every shell of the class into LDS as
-//   Ff [n_s + 1][128] float32 (row n_s all zero: padding rows of a block), and
-//   Bh, Bl [128][S_row] bf16 hi and lo (shell-contiguous per voxel; the shells
+// the voxel chunks kr, kr + n_krange, ... of kAdjVox = 64 voxels (two voxel
+// blocks; 128-voxel chunks, one work group per CU, ran 21 % slower, 32-voxel
+// ones 14 %).  Per chunk the group stages every shell of the class into LDS as
+//   Ff [n_s + 1][64] float32 (row n_s all zero: padding rows of a block), and
+//   Bh, Bl [64][S_row] bf16 hi and lo (shell-contiguous per voxel; the shells
 //   past n_s stay zero, up to the end of any K tile, which reaches at most 31
 //   shells past the last), S_row = n_s + 31 rounded up to 32, plus 8,
 // then each wavefront, for each of its shells n and each row block of n:
 //   acc[vt] (16 rows x 16 voxels of voxel tile vt) = sum over its K tiles of
 //   W_hi F_hi + W_hi F_lo + W_lo F_hi (v_mfma_f32_16x16x32_bf16; W from the
 //   weight buffer, one 16-byte load of hi and of lo per lane per K tile, used
-//   for all eight voxel tiles),
+//   for all four voxel tiles),
 // and adds acc's rows times F_j (each lane's four rows summed in float32, then
 // added in float64) into the shell's sums; the sum over the four row groups of
 // a lane column ends the shell, and lanes 0-15 write
@@ -847,7 +848,8 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
   float* __restrict__ G = G_all + grp.f_off;
   const long long n_chunks = grp.n_vox / kAdjVox;
   const AdjWave wv = grp.waves[wg * kAdjWaves + w];
-  const int total = 4 * ns * 32;
+  constexpr int kVt = kAdjVox / 16, kBlk = kAdjVox / 32;   // voxel tiles and voxel blocks of a chunk
+  const int total = kBlk * ns * 32;
   for (long long c = kr; c < n_chunks; c += grp.n_krange) {
     __syncthreads();  // the previous chunk's reads (and the zeroing) are done
     // stage: the chunk's four voxel blocks are contiguous in F (element e:
@@ -874,16 +876,16 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
     __syncthreads();
     for (int e = wv.e0; e < wv.e1; ++e) {
       const AdjN nn = grp.ns[e];
-      double sacc[8];
+      double sacc[kVt];
 #pragma unroll
-      for (int vt = 0; vt < 8; ++vt) sacc[vt] = 0.0;
+      for (int vt = 0; vt < kVt; ++vt) sacc[vt] = 0.0;
       for (int r = nn.rb0; r < nn.rb1; ++r) {
         const AdjRowBlock& rb = grp.rbs[r];
         const int l8 = rb.l8, nkt = rb.nkt;
         const uint16_t* wt = grp.W + (long long)rb.w_tile * 1024 + lane * 8;
-        f32x4 acc[8];
+        f32x4 acc[kVt];
 #pragma unroll
-        for (int vt = 0; vt < 8; ++vt)
+        for (int vt = 0; vt < kVt; ++vt)
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc[vt][v] = 0.f;
         for (int kt = 0; kt < nkt; ++kt) {
@@ -891,7 +893,7 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
           const bf16x8 alo = *reinterpret_cast<const bf16x8*>(wt + kt * 1024 + 512);
           const int l0 = 8 * l8 + kt * kAdjK + 8 * (lane >> 4);
 #pragma unroll
-          for (int vt = 0; vt < 8; ++vt) {
+          for (int vt = 0; vt < kVt; ++vt) {
             const int vox = vt * 16 + (lane & 15);
             const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(Bh + vox * srow + l0);
             const bf16x8 blo = *reinterpret_cast<const bf16x8*>(Bl + vox * srow + l0);
@@ -907,7 +909,7 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
           fj[v] = Ff + (j > 0 ? j - 1 : ns) * kAdjVox + (lane & 15);
         }
 #pragma unroll
-        for (int vt = 0; vt < 8; ++vt) {
+        for (int vt = 0; vt < kVt; ++vt) {
           float s = acc[vt][0] * fj[0][vt * 16];
 #pragma unroll
           for (int v = 1; v < 4; ++v) s = __builtin_fmaf(acc[vt][v], fj[v][vt * 16], s);
@@ -915,7 +917,7 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
         }
       }
 #pragma unroll
-      for (int vt = 0; vt < 8; ++vt) {
+      for (int vt = 0; vt < kVt; ++vt) {
         double t = sacc[vt];
         t += __shfl_xor(t, 16);
         t += __shfl_xor(t, 32);
@@ -923,9 +925,9 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
       }
       if (lane < 16) {
 #pragma unroll
-        for (int vt = 0; vt < 8; ++vt) {
+        for (int vt = 0; vt < kVt; ++vt) {
           const int vox = vt * 16 + lane;
-          G[(c * 4 + (vox >> 5)) * (long long)ns * 32 + (long long)(nn.n - 1) * 32 + (vox & 31)] = (float)sacc[vt];
+          G[(c * kBlk + (vox >> 5)) * (long long)ns * 32 + (long long)(nn.n - 1) * 32 + (vox & 31)] = (float)sacc[vt];
         }
       }
     }

@@ -196,7 +196,7 @@ hipError_t launch_contract_bf16x3(const float* F, double* partial, const WsGroup
 hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, const int4* terms, long long n_terms,
                         const int32_t* term_off, int n_s, long long n_vox, double* w, float* G, hipStream_t st);
 // ---- adjoint field build on the matrix cores (row blocks: geometry.h) --------
-constexpr int kAdjVox = 128;        // voxels per staged chunk (four voxel blocks)
+constexpr int kAdjVox = 64;         // voxels per staged chunk (two voxel blocks; two work groups fit a CU)
 struct AdjGroup {
   long long f_off = 0;            // fields and adjoint fields: F + f_off, G + f_off (voxel-blocked, n_s shells)
   const AdjRowBlock* rbs = nullptr;
