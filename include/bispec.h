@@ -239,8 +239,18 @@ int bispec_run(bispec_plan_t plan, const float* delta, double* B, void* hip_stre
 int bispec_run_noalloc(bispec_plan_t plan, const float* delta, double* B, void* hip_stream);
 
 /* Vector-Jacobian product of the last bispec_run on this plan (needs
- * BISPEC_FLAG_GRAD): gdelta(x) = sum_t gB_t dB_t/d delta(x).
+ * BISPEC_FLAG_GRAD): gdelta(x) = sum_t gB_t dB_t/d delta(x), the derivative of
+ * eq. bsfin through eq. iFT: per shell n the adjoint field
+ * G_n(x) = sum over the bins t with a side in shell n of
+ * gB_t / (V N_tri,t N_g^3) times the product of the bin's other two fields at x,
+ * then each G_n forward-transformed and restricted to the modes of shell n
+ * (times Z(k) for RSD), summed, and transformed back to the grid (the adjoint
+ * of eq. iFT and of the forward transform).  Split-bf16 plans build G_n on the
+ * matrix cores (float32 chains, float64 sums), float32 plans on the vector ALU
+ * in float64; the transforms run in float32.
  * gB: device float64 [n_tri]; gdelta: device float32 [N_g^3] (overwritten).
+ * Asynchronous on hip_stream; allocates nothing (the plan holds the adjoint
+ * buffers).
  * Errors: ESTATE when no run preceded or the plan lacks BISPEC_FLAG_GRAD. */
 int bispec_grad(bispec_plan_t plan, const double* gB, float* gdelta, void* hip_stream);
 
