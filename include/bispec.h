@@ -272,7 +272,7 @@ int bispec_stage_times(bispec_plan_t plan, float* ms, int32_t n);
  * of work groups), column-tile window max_cols[k], work groups per range
  * n_wg[k], replicas rep[k] (a class whose tiling fits one work group with few
  * busy wavefronts runs rep copies of it on rep consecutive voxel blocks per
- * step: 1, 2 or 3), the autotuned time of one contraction launch of the class
+ * step: 1, 2, 3, 4 or 6), the autotuned time of one contraction launch of the class
  * alone tuned_ms[k] (0 if not tuned) and tune_source[k] (0 default, 1 timed at
  * plan time, 2 read from the tuning cache).  Any output array may be null. */
 int bispec_plan_classes(bispec_plan_t plan, int32_t capacity, int32_t* n_classes, int32_t* grid, int32_t* n_krange,

@@ -1189,14 +1189,14 @@ int ws_tile_stride(const MfmaTiling& mt) {
 // Replicas need one work group whose used slots all sit below 12 / rep (the
 // slot placement fills SIMD 0..3 first, so few slots take the low positions),
 // rep g16 staging waves' worth of rows (g16 = ceil(s_n / 16), one 8-voxel
-// segment per thread) and their LDS.
+// segment per thread) and their LDS; rep divides the 12 wavefronts.
 int ws_max_rep(const MfmaTiling& mt) {
   if (mt.n_wg != 1 || mt.wg_rows.empty()) return 1;
   int top = -1;
   for (int k = 0; k < kSlotsPerWg && k < (int)mt.cols.size(); ++k)
     if (mt.cols[k].n > 0 && mt.cols[k].n_rb > 0) top = k;
   const int g16 = (mt.wg_rows[0].s_n + 15) / 16;
-  for (int rep = 3; rep >= 2; --rep)
+  for (int rep : {6, 4, 3, 2})
     if (top < kSlotsPerWg / rep && rep * g16 * 64 <= kWsThreads && bf16x3_lds_bytes(mt.max_s, rep) <= kWsLdsMax)
       return rep;
   return 1;
@@ -1225,7 +1225,7 @@ hipError_t prepare_contract_bf16x3() {
 bool ws_group_ok(const WsGroup& g) {
   // every staged row of every replica fits the per-thread loads (rows of a work
   // group <= max_s); ranges are whole voxel blocks; replicas need one work group
-  return g.rep >= 1 && g.rep <= 3 && (g.rep == 1 || g.n_wg == 1) &&
+  return g.rep >= 1 && g.rep <= 6 && kSlotsPerWg % g.rep == 0 && (g.rep == 1 || g.n_wg == 1) &&
          (g.n_wg == 1 ? g.tile_stride >= kSlotTiles && g.tile_stride <= kTilesPerWg
                       : g.tile_stride == g.n_wg * kTilesPerWg) &&
          g.rep * 64 * ((g.max_s + 15) / 16) <= kWsThreads && g.max_s <= g.n_s && g.max_s <= kMaxSplitShells &&

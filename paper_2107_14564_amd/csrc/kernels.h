@@ -168,7 +168,7 @@ struct WsGroup {
   int n_wg = 0, n_s = 0, max_s = 0;
   int n_krange = 0;                   // multiple of 8
   int block0 = 0;                     // first block of the group (multiple of 8); groups ascending
-  // replicas (1..3, n_wg = 1 when above 1): the work group's waves run rep
+  // replicas (1, 2, 3, 4 or 6; n_wg = 1 when above 1): the work group's waves run rep
   // copies of slots 0 .. kSlotsPerWg / rep - 1, copy r on voxel range
   // rep * kr + r of rep * n_krange ranges
   int rep = 1;

@@ -169,18 +169,21 @@ def test_deterministic_and_precision_switch():
 
 
 def test_replicated_slot_sets():
-    """Classes whose tiling fits one work group with few busy wavefronts run 2 or
-    3 replicas of it on consecutive voxel blocks (own voxel ranges, own
-    partials): N_g = 128, 36 shells has a G = 96 class at 2 replicas and a
-    G = 128 class at 3; N_g = 64, 20 shells one class at 3 with a ragged last
-    step (8192 blocks over 768 ranges).  All triangles against the oracle."""
+    """Classes whose tiling fits one work group with few busy wavefronts run
+    several replicas of it (a divisor of the 12 wavefronts: 2, 3, 4 or 6) on
+    consecutive voxel blocks (own voxel ranges, own partials), with a ragged
+    last step where the voxel blocks do not fill the replicas' ranges.  The
+    plans below have classes at 2 and 6 replicas (N_g = 128, 36 shells), at 1
+    and 4 (N_g = 128, 40 shells) and at 6 (N_g = 64, 20 shells: 8192 blocks
+    over 1536 ranges).  All triangles against the oracle."""
     import paper_2107_14564_amd as P
     seen = set()
-    for n_g, box, n_s, beta in ((128, 512.0, 36, 0.5), (64, 256.0, 20, 0.0)):
+    for n_g, box, n_s, beta in ((128, 512.0, 36, 0.5), (128, 512.0, 40, 0.0), (64, 256.0, 20, 0.0)):
         plan = P.Plan(n_g, box, 1.0, n_s, rsd_beta=beta)
         reps = [c["rep"] for c in plan.classes()]
         say("  n_g=%d n_s=%d classes %s" % (n_g, n_s, plan.classes()))
         seen.update(reps)
         plan.close()
         _check(n_g, box, 1.0, n_s, beta, 300 + n_g, P.PREC_SPLITBF16)
-    assert {2, 3} <= seen, seen
+    say("  replica counts seen %s" % sorted(seen))
+    assert {2, 4, 6} <= seen, seen
