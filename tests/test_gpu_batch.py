@@ -102,18 +102,20 @@ def test_batch_members_match_single_plans():
 
 def test_batch_cohorts():
     """Identical consecutive members form cohorts (one launch per pass for all of
-    them, each member at its own strides): a batch A A A B A A has the units
-    (A A A), B, (A A); every member computes exactly what the same plan alone
-    computes on its field, graph replays equal direct launches, and the last
-    member of each cohort matches the oracle."""
+    them, each member at its own strides): a batch A A A B A A C C (C a
+    quadrupole plan) has the units (A A A), B, (A A), (C C); every member
+    computes exactly what the same plan alone computes on its field, graph
+    replays equal direct launches, and the last member of each A cohort
+    matches the oracle."""
     import torch
     import paper_2107_14564_amd as P
     a = dict(n_g=48, box_l=200.0, dk=1.0, n_shells=12, rsd_beta=0.5)
     b = dict(n_g=32, box_l=300.0, dk=1.0, n_shells=10, rsd_beta=0.0)
-    cfgs = [a, a, a, b, a, a]
+    c = dict(n_g=32, box_l=300.0, dk=1.0, n_shells=8, rsd_beta=0.5, ell=2)
+    cfgs = [a, a, a, b, a, a, c, c]
     bp = P.BatchPlan(cfgs)
     say("cohort batch: %d units, %d members in cohorts" % (bp.n_units, bp.n_cohort_members))
-    assert (bp.n_units, bp.n_cohort_members) == (3, 5)
+    assert (bp.n_units, bp.n_cohort_members) == (4, 7)
     fields = [quadratic_ng_field(gaussian_field(c["n_g"], c["box_l"], PowerLaw(-1.0), 300 + i), 1.0)
               .astype(np.float32) for i, c in enumerate(cfgs)]
     packed = bp.pack([torch.from_numpy(f) for f in fields])
