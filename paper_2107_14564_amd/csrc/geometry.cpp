@@ -773,14 +773,39 @@ void build_adjoint_tables(const Selection& sel, const std::vector<int32_t>& tri_
     std::vector<R> rr;
     for (auto& jr : rows[n]) rr.push_back({jr.first, jr.second.begin()->first, jr.second.rbegin()->first});
     std::sort(rr.begin(), rr.end(), [](const R& a, const R& b) {
-      return a.lmin != b.lmin ? a.lmin < b.lmin : (a.lmax != b.lmax ? a.lmax < b.lmax : a.j < b.j);
+      return a.lmax != b.lmax ? a.lmax < b.lmax : (a.lmin != b.lmin ? a.lmin < b.lmin : a.j < b.j);
     });
+    // rows in that order cut into consecutive blocks of <= kAdjRows rows: the
+    // cut with the fewest K tiles (plus 2/5 of a tile per block for its
+    // epilogue), by dynamic programming over the cut points
+    auto tiles_of = [](int lo, int hi) { return (hi - 1 - (lo - 1) / 8 * 8) / kAdjK + 1; };
+    const int nr = (int)rr.size();
+    std::vector<double> best(nr + 1, 1e300);
+    std::vector<int> cut(nr + 1, 0);
+    best[0] = 0.0;
+    for (int e = 1; e <= nr; ++e) {
+      int lo = 1 << 30, hi = 0;
+      for (int s = e - 1; s >= 0 && s >= e - kAdjRows; --s) {
+        lo = std::min(lo, rr[s].lmin);
+        hi = std::max(hi, rr[s].lmax);
+        const double c = best[s] + tiles_of(lo, hi) + 0.4;
+        if (c < best[e]) {
+          best[e] = c;
+          cut[e] = s;
+        }
+      }
+    }
+    std::vector<std::pair<int, int>> blocks;   // [first, end) rows
+    for (int e = nr; e > 0; e = cut[e]) blocks.push_back({cut[e], e});
+    std::reverse(blocks.begin(), blocks.end());
     n_rb[n].first = (int32_t)at.rbs.size();
-    for (size_t r0 = 0; r0 < rr.size(); r0 += kAdjRows) {
+    for (const auto& bl : blocks) {
+      const size_t r0 = (size_t)bl.first;
+      const int nrows = bl.second - bl.first;
       AdjRowBlock rb{};
       int lmin = 1 << 30, lmax = 0;
       for (int r = 0; r < kAdjRows; ++r) {
-        if (r0 + r < rr.size()) {
+        if (r < nrows) {
           rb.j[r] = (int16_t)rr[r0 + r].j;
           lmin = std::min(lmin, rr[r0 + r].lmin);
           lmax = std::max(lmax, rr[r0 + r].lmax);
@@ -793,7 +818,7 @@ void build_adjoint_tables(const Selection& sel, const std::vector<int32_t>& tri_
       rb.w_tile = (int32_t)at.n_tiles;
       at.n_tiles += rb.nkt;
       slot_tris.resize((size_t)at.n_tiles * 512);
-      for (int r = 0; r < kAdjRows && r0 + r < rr.size(); ++r) {
+      for (int r = 0; r < nrows; ++r) {
         const int j = rr[r0 + r].j;
         for (auto& lt : rows[n][j]) {
           const int k = (lt.first - 1) - 8 * rb.l8;   // K index within the block's tiles

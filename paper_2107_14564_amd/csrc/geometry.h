@@ -187,8 +187,9 @@ void build_mfma_tiles(const Selection& s, int n_shells, MfmaTiling& mt, int max_
 // ---- adjoint field build on the matrix cores ------------------------------
 // G_n(x) = sum_j F_j(x) H_(n,j)(x),  H_(n,j)(x) = sum_l W[(n,j), l] F_l(x), where
 // W[(n,j), l] sums gB_t norm_t over the terms (t; j, l) of d(F_a1 F_a2 F_a3)/dF_n
-// (j the larger of the other two shells).  Rows (n, j) of one n form row blocks
-// of kAdjRows; a row block meets nkt K tiles of kAdjK consecutive shells l from
+// (j the larger of the other two shells).  Rows (n, j) of one n, ordered by
+// their last l, are cut into row blocks of at most kAdjRows rows (the cut with
+// the fewest K tiles); a row block meets nkt K tiles of kAdjK consecutive shells l from
 // an 8-aligned first shell (0-based shells 8 l8 + 32 kt .. 8 l8 + 32 kt + 31,
 // so the tiles end at most 31 shells past the block's last l).  A K tile's
 // weights sit in the MFMA row-operand layout: slot (tile, lane, i) holds row
