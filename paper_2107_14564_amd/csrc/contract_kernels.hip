@@ -769,10 +769,11 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
 // the voxel chunks kr, kr + n_krange, ... of kAdjVox = 64 voxels (two voxel
 // blocks; 128-voxel chunks, one work group per CU, ran 21 % slower, 32-voxel
 // ones 14 %).  Per chunk the group stages every shell of the class into LDS as
-//   Ff [n_s + 1][64] float32 (row n_s all zero: padding rows of a block), and
 //   Bh, Bl [64][S_row] bf16 hi and lo (shell-contiguous per voxel; the shells
 //   past n_s stay zero, up to the end of any K tile, which reaches at most 31
-//   shells past the last), S_row = n_s + 31 rounded up to 32, plus 8,
+//   shells past the last), S_row = 128 + 31 rounded up to 32, plus 8, for
+//   every class (a compile-time stride folds the LDS offsets into the reads),
+//   and Ff [n_s + 1][64] float32 (row n_s all zero: padding rows of a block),
 // then each wavefront, for each of its shells n and each row block of n:
 //   acc[vt] (16 rows x 16 voxels of voxel tile vt) = sum over its K tiles of
 //   W_hi F_hi + W_hi F_lo + W_lo F_hi (v_mfma_f32_16x16x32_bf16; W from the
@@ -786,6 +787,7 @@ hipError_t launch_vec(const T* F, const ContractArgs& a, hipStream_t st) {
 // ============================================================================
 __host__ __device__ constexpr int adj_spad(int n_s) { return (n_s + 31 + kAdjK - 1) / kAdjK * kAdjK; }
 __host__ __device__ constexpr int adj_srow(int n_s) { return adj_spad(n_s) + 8; }
+constexpr int kAdjSrow = adj_srow(kMaxSplitShells);   // one row stride for every class: LDS offsets fold into immediates
 
 __device__ __forceinline__ int adj_group_of(const AdjGroup* __restrict__ groups, int n_groups, int b) {
   int lo = 0, hi = n_groups - 1;
@@ -832,11 +834,12 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
   const int b = (int)blockIdx.x - grp.block0;
   const int xcd = b & 7, qb = b >> 3;
   const int wg = qb % grp.n_wg, kr = xcd + 8 * (qb / grp.n_wg);
-  const int ns = grp.n_s, srow = adj_srow(ns);
+  const int ns = grp.n_s;
+  constexpr int srow = kAdjSrow;
   constexpr int kThr = kAdjWaves * 64;
-  float* Ff = reinterpret_cast<float*>(smem_raw);
-  __bf16* Bh = reinterpret_cast<__bf16*>(smem_raw + (size_t)(ns + 1) * kAdjVox * 4);
+  __bf16* Bh = reinterpret_cast<__bf16*>(smem_raw);
   __bf16* Bl = Bh + kAdjVox * srow;
+  float* Ff = reinterpret_cast<float*>(smem_raw + 2 * (size_t)kAdjVox * srow * 2);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   for (int e = tid; e < kAdjVox; e += kThr) Ff[ns * kAdjVox + e] = 0.f;
   for (int e = tid; e < kAdjVox * (srow - ns); e += kThr) {
@@ -852,7 +855,7 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
   const int total = kBlk * ns * 32;
   for (long long c = kr; c < n_chunks; c += grp.n_krange) {
     __syncthreads();  // the previous chunk's reads (and the zeroing) are done
-    // stage: the chunk's four voxel blocks are contiguous in F (element e:
+    // stage: the chunk's voxel blocks are contiguous in F (element e:
     // block e / (32 n_s), shell (e / 32) % n_s, voxel e % 32); eight loads in flight
     const float* src = F + c * (long long)total;
     for (int e0 = tid; e0 < total; e0 += 8 * kThr) {
@@ -1102,7 +1105,7 @@ __global__ void k_zero16(uint4* __restrict__ dst, long long n16) {
 }  // namespace
 
 size_t adj_lds_bytes(int max_s) {
-  return (size_t)(max_s + 1) * kAdjVox * sizeof(float) + 2 * (size_t)kAdjVox * adj_srow(max_s) * sizeof(__bf16);
+  return (size_t)(max_s + 1) * kAdjVox * sizeof(float) + 2 * (size_t)kAdjVox * kAdjSrow * sizeof(__bf16);
 }
 
 hipError_t prepare_adjoint_mfma() {
