@@ -313,10 +313,11 @@ int bispec_many_layout(bispec_many_t batch, int32_t* n, int64_t* delta_off, int6
 
 /* Launch units of the batch: runs of identical consecutive members (same
  * configuration, split-bf16, no BISPEC_FLAG_AUTOTUNE; e.g. the realisations of
- * an ensemble) form cohorts whose forward transforms, shell passes and
- * reductions run as one launch per pass for all their members (cohorts are
- * split so their per-member spectra and pass intermediates stay within 8 GiB);
- * every other member is a unit of its own.  n_units (host) receives the number
+ * an ensemble) form cohorts whose forward transforms and shell passes run as
+ * one launch per pass for all their members (cohorts are split so their
+ * per-member spectra and pass intermediates stay within 8 GiB); every other
+ * member is a unit of its own.  (The contraction and the reductions of every
+ * split-bf16 member run as one launch each in any case.)  n_units (host) receives the number
  * of units, n_cohort_members (may be null) the number of members in cohorts. */
 int bispec_many_units(bispec_many_t batch, int32_t* n_units, int32_t* n_cohort_members);
 

@@ -235,10 +235,12 @@ struct bispec_many_s {
   std::vector<size_t> f_at, pm_at;     // byte offsets of member i's pieces
   int ws_n = 0, ws_blocks = 0;
   size_t ws_lds = 0;
-  hipEvent_t ev_mid = nullptr;         // the grouped contraction is done
+  // one grouped reduction of every split member's classes after the contraction
+  DevBuf red_groups;
+  int red_n = 0, red_blocks = 0;
   // cohorts: runs of m >= 2 consecutive identical split-bf16 members (the
-  // realisations of one configuration) whose forward transforms, shell passes
-  // and reductions run as one launch each (grid y = member), with a spectrum
+  // realisations of one configuration) whose forward transforms and shell
+  // passes run as one launch each (grid y = member), with a spectrum
   // and pass intermediates per member; units are the cohorts and the members
   // outside any, in member order, each run on one lane
   struct Unit {
@@ -907,14 +909,6 @@ int run_fields(bispec_plan_s& p, const RunBufs& w, const float* delta, hipStream
   return BISPEC_OK;
 }
 
-// The per-class reductions of the split-bf16 partials into B.
-int run_reduce_mfma(bispec_plan_s& p, const RunBufs& w, double* B, hipStream_t s) {
-  for (GridClass& c : p.cls)
-    HIP_TRY(launch_reduce(w.partial_mfma + c.pm_off, mfma_ranges(c), (long long)c.tile_stride * kMTileElems,
-                          c.n_tri, c.mfma_slot.as<int32_t>(), p.norm.as<double>(), c.tri_out.as<int32_t>(), B, s));
-  return BISPEC_OK;
-}
-
 // The vector (fp32) contraction and its reductions.
 int run_contract_fp32(bispec_plan_s& p, const RunBufs& w, double* B, hipStream_t s) {
   for (GridClass& c : p.cls) HIP_TRY(launch_contract_fp32(w.F + c.f_off, contract_args(c, w.partial), s));
@@ -1004,11 +998,6 @@ int run_core(bispec_plan_s& p, const RunBufs& w, const float* delta, double* B, 
   return BISPEC_OK;
 }
 
-// Enqueue a batch pass, forked from and joined back into stream s (which may
-// be capturing): each member's forward transform and shell passes (and, for
-// fp32 members, its contraction and reductions) on its lane; then one grouped
-// split-bf16 contraction of every split member's classes on s; then the split
-// members' reductions on the lanes again.
 // A cohort's forward transforms and shell passes: one launch per pass for all
 // its members (the tables of its first member serve all of them).
 int run_fields_cohort(bispec_many_s& m, const bispec_many_s::Unit& u, const float* delta, hipStream_t s) {
@@ -1030,18 +1019,11 @@ int run_fields_cohort(bispec_many_s& m, const bispec_many_s::Unit& u, const floa
   return BISPEC_OK;
 }
 
-// A cohort's reductions of its split-bf16 partials: one launch per class.
-int run_reduce_cohort(bispec_many_s& m, const bispec_many_s::Unit& u, double* B, hipStream_t s) {
-  bispec_plan_s& p = *m.plans[u.i0];
-  const long long pm_el = (long long)((m.pm_at[u.i0 + 1] - m.pm_at[u.i0]) / sizeof(double));
-  const long long b_el = m.b_off[u.i0 + 1] - m.b_off[u.i0];
-  for (GridClass& c : p.cls)
-    HIP_TRY(launch_reduce(p.partial_mfma.as<double>() + c.pm_off, mfma_ranges(c),
-                          (long long)c.tile_stride * kMTileElems, c.n_tri, c.mfma_slot.as<int32_t>(),
-                          p.norm.as<double>(), c.tri_out.as<int32_t>(), B + m.b_off[u.i0], s, false, u.m, pm_el, b_el));
-  return BISPEC_OK;
-}
-
+// Enqueue a batch pass, forked from and joined back into stream s (which may
+// be capturing): each unit's forward transforms and shell passes (and, for
+// fp32 members, their contraction and reductions) on its lane; then, on s,
+// one grouped split-bf16 contraction of every split member's classes and one
+// grouped reduction of them into B.
 int many_enqueue(bispec_many_s& m, const float* delta, double* B, hipStream_t s) {
   HIP_TRY(hipEventRecord(m.ev_fork, s));
   for (ManyLane* l : m.lanes) HIP_TRY(hipStreamWaitEvent(l->stream, m.ev_fork, 0));
@@ -1066,20 +1048,7 @@ int many_enqueue(bispec_many_s& m, const float* delta, double* B, hipStream_t s)
   if (m.ws_n > 0) {
     HIP_TRY(launch_contract_bf16x3(m.F_all.as<float>(), m.pm_all.as<double>(), m.ws_groups.as<WsGroup>(), m.ws_n,
                                    m.ws_lds, m.ws_blocks, s));
-    HIP_TRY(hipEventRecord(m.ev_mid, s));
-    for (ManyLane* l : m.lanes) HIP_TRY(hipStreamWaitEvent(l->stream, m.ev_mid, 0));
-    for (size_t k = 0; k < m.units.size(); ++k) {
-      const bispec_many_s::Unit& u = *m.units[k];
-      bispec_plan_s& p = *m.plans[u.i0];
-      if (p.precision == BISPEC_PREC_FP32) continue;
-      const hipStream_t ls = m.lanes[m.unit_lane[k]]->stream;
-      const int st = u.m > 1 ? run_reduce_cohort(m, u, B, ls) : run_reduce_mfma(p, own_bufs(p), B + m.b_off[u.i0], ls);
-      if (st) return st;
-    }
-    for (ManyLane* l : m.lanes) {
-      HIP_TRY(hipEventRecord(l->ev_join, l->stream));
-      HIP_TRY(hipStreamWaitEvent(s, l->ev_join, 0));
-    }
+    HIP_TRY(launch_reduce_grouped(m.red_groups.as<RedGroup>(), m.red_n, m.red_blocks, B, s));
   }
   return BISPEC_OK;
 }
@@ -1962,7 +1931,6 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
     hipError_t e = dalloc(m->F_all, f_total);
     if (e == hipSuccess) e = dalloc(m->pm_all, pm_total);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_mid, hipEventDisableTiming);
     if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("batch buffers: ") + hipGetErrorString(e)));
   }
   // the plans take views of their lane's workspace and of their pieces of the
@@ -1990,11 +1958,38 @@ int bispec_plan_many(const bispec_config* cfgs, int32_t n, void* hip_stream, bis
   }
   m->ws_n = (int)groups.size();
   m->ws_blocks = block;
+  // the reductions of every split member's classes, in member and class order
+  std::vector<RedGroup> red;
+  long long red_blocks = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    bispec_plan_s* p = m->plans[i];
+    if (p->precision == BISPEC_PREC_FP32) continue;
+    for (GridClass& c : p->cls) {
+      if (c.n_tri <= 0) continue;
+      RedGroup g;
+      g.partial = p->partial_mfma.as<double>() + c.pm_off;
+      g.slot = c.mfma_slot.as<int32_t>();
+      g.norm = p->norm.as<double>();
+      g.out_idx = c.tri_out.as<int32_t>();
+      g.stride = (long long)c.tile_stride * kMTileElems;
+      g.n_tri = c.n_tri;
+      g.b_off = m->b_off[i];
+      g.n_krange = mfma_ranges(c);
+      g.block0 = (int)red_blocks;
+      red_blocks += reduce_blocks(c.n_tri);
+      red.push_back(g);
+    }
+  }
+  if (red_blocks > (1LL << 30)) return fail(set_err(BISPEC_EINVAL, "batch has too many triangles for one reduction launch"));
+  m->red_n = (int)red.size();
+  m->red_blocks = (int)red_blocks;
   if (m->ws_n > 0) {
     hipError_t e = upload(m->ws_groups, groups, s);
+    if (e == hipSuccess && m->red_n > 0) e = upload(m->red_groups, red, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(set_err(BISPEC_EHIP, std::string("batch table: ") + hipGetErrorString(e)));
   }
+  if ((m->ws_n > 0) != (m->red_n > 0)) return fail(set_err(BISPEC_EINVAL, "batch tables disagree"));
   *out = m;
   return BISPEC_OK;
 }
@@ -2063,7 +2058,6 @@ int bispec_destroy_many(bispec_many_t m) {
 }  // extern "C"
 
 bispec_many_s::~bispec_many_s() {
-  if (ev_mid) (void)hipEventDestroy(ev_mid);
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);

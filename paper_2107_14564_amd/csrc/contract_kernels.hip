@@ -711,10 +711,7 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
                                                               const int32_t* __restrict__ slot,
                                                               const double* __restrict__ norm,
                                                               const int32_t* __restrict__ out_idx,
-                                                              double* __restrict__ out, int accumulate,
-                                                              long long p_stride, long long out_stride) {
-  partial += blockIdx.y * p_stride;   // member of a cohort (grid y)
-  out += blockIdx.y * out_stride;
+                                                              double* __restrict__ out, int accumulate) {
   __shared__ double part[kRedPart][kRedTri];
   const int tl = threadIdx.x % kRedTri, p = threadIdx.x / kRedTri;
   const long long t = (long long)blockIdx.x * kRedTri + tl;
@@ -732,6 +729,34 @@ __global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce(const double* __r
     const long long o = out_idx ? out_idx[t] : t;
     const double v = norm ? r * norm[o] : r;
     out[o] = accumulate ? out[o] + v : v;   // accumulate: the slabs of a streamed grid, in order
+  }
+}
+
+__global__ void __launch_bounds__(kRedTri * kRedPart) k_reduce_grouped(const RedGroup* __restrict__ groups,
+                                                                      int n_groups, double* __restrict__ B) {
+  int lo = 0, hi = n_groups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].block0 <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const RedGroup& g = groups[lo];
+  __shared__ double part[kRedPart][kRedTri];
+  const int tl = threadIdx.x % kRedTri, p = threadIdx.x / kRedTri;
+  const long long t = (long long)((int)blockIdx.x - g.block0) * kRedTri + tl;
+  double s = 0.0;
+  if (t < g.n_tri) {
+    const long long at = g.slot[t];
+    for (int k = p; k < g.n_krange; k += kRedPart) s += g.partial[(long long)k * g.stride + at];
+  }
+  part[p][tl] = s;
+  __syncthreads();
+  if (p == 0 && t < g.n_tri) {
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRedPart; ++q) r += part[q][tl];
+    const long long o = g.out_idx[t];
+    B[g.b_off + o] = r * g.norm[o];
   }
 }
 
@@ -1257,14 +1282,21 @@ hipError_t launch_gbuild(const float* F, const double* gB, const double* norm, c
   return hipGetLastError();
 }
 
+long long reduce_blocks(long long n_tri) { return (n_tri + kRedTri - 1) / kRedTri; }
+
+hipError_t launch_reduce_grouped(const RedGroup* groups_dev, int n_groups, int n_blocks, double* B, hipStream_t st) {
+  if (n_groups < 1 || n_blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_grouped, dim3((unsigned)n_blocks), dim3(kRedTri * kRedPart), 0, st, groups_dev, n_groups,
+                     B);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
-                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st, bool accumulate,
-                         int members, long long p_stride, long long out_stride) {
+                         const double* norm, const int32_t* out_idx, double* out, hipStream_t st, bool accumulate) {
   if (n_tri <= 0) return hipSuccess;
-  if (members < 1) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)((n_tri + kRedTri - 1) / kRedTri);
-  hipLaunchKernelGGL(k_reduce, dim3(blocks, (unsigned)members), dim3(kRedTri * kRedPart), 0, st, partial, n_krange,
-                     stride, n_tri, slot, norm, out_idx, out, accumulate ? 1 : 0, p_stride, out_stride);
+  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(kRedTri * kRedPart), 0, st, partial, n_krange, stride, n_tri, slot,
+                     norm, out_idx, out, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -243,11 +243,26 @@ hipError_t launch_contract4_f64(const double* F, const Quad4Args& a, hipStream_t
 hipError_t launch_fill_random(float* dst, long long n, unsigned long long seed, hipStream_t st);
 // dst[0 .. bytes) = 0 with a fill kernel (capture-safe; bytes and dst 16-byte aligned)
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
+// The reductions of many grid classes (of the members of a batch) in one
+// launch: group g turns its class's partials into results B[b_off + o] as
+// launch_reduce does with norm, slot and out_idx (same order of additions).
+struct RedGroup {
+  const double* partial = nullptr;    // the class's partials, n_krange ranges at stride
+  const int32_t* slot = nullptr;      // triangle -> element of a range
+  const double* norm = nullptr;       // indexed by result
+  const int32_t* out_idx = nullptr;   // triangle -> result of the member
+  long long stride = 0, n_tri = 0;
+  long long b_off = 0;                // the member's results at B + b_off
+  int n_krange = 0;
+  int block0 = 0;                     // first block of the group (reduce_blocks(n_tri) blocks each)
+};
+long long reduce_blocks(long long n_tri);
+hipError_t launch_reduce_grouped(const RedGroup* groups_dev, int n_groups, int n_blocks, double* B, hipStream_t st);
+
 // out[o] = norm[o] * sum_k partial[k * stride + (slot ? slot[t] : t)] with o = out_idx ? out_idx[t] : t,
-// for t < n_tri (fixed order, float64; norm may be null); accumulate: out[o] += that.
-// members > 1: a cohort, member m reading partial + m p_stride and writing out + m out_stride
+// for t < n_tri (fixed order, float64; norm may be null); accumulate: out[o] += that
 hipError_t launch_reduce(const double* partial, int n_krange, long long stride, long long n_tri, const int32_t* slot,
                          const double* norm, const int32_t* out_idx, double* out, hipStream_t st,
-                         bool accumulate = false, int members = 1, long long p_stride = 0, long long out_stride = 0);
+                         bool accumulate = false);
 
 }  // namespace bispec
