@@ -911,6 +911,9 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
         const AdjRowBlock& rb = grp.rbs[r];
         const int l8 = rb.l8, nkt = rb.nkt;
         const uint16_t* wt = grp.W + (long long)rb.w_tile * 1024 + lane * 8;
+        int jrow[4];   // this lane's rows, read before the K loop so the loads overlap it
+#pragma unroll
+        for (int v = 0; v < 4; ++v) jrow[v] = rb.j[4 * (lane >> 4) + v];
         f32x4 acc[kVt];
 #pragma unroll
         for (int vt = 0; vt < kVt; ++vt)
@@ -933,7 +936,7 @@ __global__ void __launch_bounds__(kAdjWaves * 64) k_adjoint_mfma(const float* __
         const float* fj[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int j = rb.j[4 * (lane >> 4) + v];
+          const int j = jrow[v];
           fj[v] = Ff + (j > 0 ? j - 1 : ns) * kAdjVox + (lane & 15);
         }
 #pragma unroll
