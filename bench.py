@@ -425,8 +425,37 @@ def bench_batch(args, np, torch, P):
                      "algorithmic_flop": flop},
         "plan_s": plan_s,
     }
+    if not args.no_cpu_baseline:
+        result["error_vs_oracle"] = batch_error(bp, fields, configs, out.cpu().numpy(), np)
     bp.close()
     print(json.dumps(result), flush=True)
+
+
+def batch_error(bp, fields, configs, b_all, np) -> dict:
+    """The timed batch's error against the float64 oracle on a bounded sample:
+    for the first and the last member, its bins of the six smallest first sides
+    (at most 200), on the member's full grid."""
+    from oracle import fbe
+    members = sorted({0, bp.n - 1})
+    d2 = r2 = 0.0
+    e_cond = 0.0
+    n_checked = 0
+    ntri_ok = True
+    for i in members:
+        c = configs[i]
+        tri = bp.triangles[i].numpy()
+        pick = np.where(tri[:, 0] <= tri[:, 0].min() + 5)[0][:200]
+        ref = fbe.estimate(fields[i].numpy().astype(np.float64), c["box_l"], c["dk"], tri[pick], rsd_beta=0.0,
+                           with_abs=True)
+        got = b_all[bp.b_off[i]:bp.b_off[i + 1]][pick]
+        d2 += float(np.sum((got - ref["B"]) ** 2))
+        r2 += float(np.sum(ref["B"] ** 2))
+        e_cond = max(e_cond, float(np.max(np.abs(got - ref["B"]) / ref["S"])))
+        ntri_ok = ntri_ok and bool(np.array_equal(bp.ntri[i].numpy()[pick], ref["ntri"]))
+        n_checked += len(pick)
+    return {"vs": "float64 oracle", "members": members, "n_checked": n_checked,
+            "sample": "the bins of the six smallest first sides of each sampled member (at most 200), full grid",
+            "e_norm": (d2 / r2) ** 0.5 if r2 > 0 else None, "e_cond": e_cond, "ntri_exact": ntri_ok}
 
 
 def bp_cfg(P, c):
